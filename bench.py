@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark of the selection hot path: selected factor columns per second.
+
+One step = one pass of the whole hot path over the workload: greedy
+conditional selection for every column (FP32 covariance evaluation and GEMV,
+FP64 downdates), the FP64 Theta_ss Cholesky and eq. L_col column, and the
+deterministic sum of log conditional variances (the KL data term of
+eq. obj_chol).  Inputs are resident in HBM before timing starts; ordering and
+pools are untimed set-up.
+
+Default workload: N = 100,000 points uniform in [0,1]^3, Matern 5/2,
+l = 0.05, nugget 1e-6, pools of the 256 nearest later-ordered points (uneven
+at the tail), k = 32, mixed precision.
+
+Prints ONE JSON line (rank 0, N = 1 GPU).
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "selected factor columns/s at fixed KL gap; plain vs learned-screened"
+PEAK_ALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32 = FP64 vector rate
+PEAK_HBM_GBS = 8000.0
+
+
+def eval_flops(dim: int, two_nu: int) -> int:
+    """Flops of one covariance evaluation: per dimension a subtraction and an
+    FMA (3), then sqrt, scale, exp (1 each) and the Matern polynomial."""
+    poly = {1: 1, 3: 3, 5: 5}[two_nu]
+    return 3 * dim + 3 + poly
+
+
+def column_work(C, k, dim, two_nu):
+    """Algorithmic flops and bytes of one column (numpy arrays C, k)."""
+    import numpy as np
+
+    C = np.asarray(C, np.float64)
+    kk = np.minimum(k, C)
+    fe = eval_flops(dim, two_nu)
+    evals = C + C * kk                            # initial covariances + one per candidate per pick
+    gemv = 2.0 * C * kk * (kk - 1) / 2.0          # left-looking GEMV, 2 flops per FMA
+    down = 4.0 * C * kk                           # two FP64 FMAs per candidate per pick
+    score = 2.0 * C * kk                          # cov^2 and the division
+    m = kk + 1
+    tss = fe * m * (m + 1) / 2.0 + m ** 3 / 3.0 + m * m   # Theta_ss build, Cholesky, back-substitution
+    flops = fe * evals + gemv + down + score + tss
+    # bytes: target + pool_len + pool indices read, outputs written
+    # (sel int32 k, factor fp64 k+1, log_condvar fp64, status u8)
+    byt = 8.0 + 4.0 * C + 4.0 * k + 8.0 * (k + 1) + 8.0 + 1.0
+    return flops, byt
+
+
+def cpu_baseline(w, k, seconds, threads):
+    """Time the FP64 oracle on a bounded seeded sample of the same columns."""
+    import numpy as np
+
+    import oracle
+
+    rng = np.random.default_rng(12345)
+    T = len(w.targets)
+    probe = np.sort(rng.choice(T, size=min(T, 512), replace=False))
+    t0 = time.perf_counter()
+    oracle.select_and_factor(w.points, w.kernel, w.targets[probe], w.pool[probe], w.pool_len[probe], k,
+                             nthreads=threads)
+    dt = time.perf_counter() - t0
+    m = int(min(T, max(len(probe), len(probe) * seconds / max(dt, 1e-6))))
+    idx = np.sort(rng.choice(T, size=m, replace=False))
+    t0 = time.perf_counter()
+    oracle.select_and_factor(w.points, w.kernel, w.targets[idx], w.pool[idx], w.pool_len[idx], k, nthreads=threads)
+    dt = time.perf_counter() - t0
+    return {"value": m / dt, "unit": "columns/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} of {T} columns (seeded uniform sample), FP64 C oracle with OpenMP over columns, "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=100_000)
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
+    ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
+    args = ap.parse_args()
+
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path (columns shard with no "
+              "communication; see the design notes).", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import build as b
+    if not (os.path.exists(b.LIB) and os.path.exists(b.GEO_LIB)):
+        import __graft_entry__
+        __graft_entry__.build()
+    from paper_2307_11648_amd import csel, inputs
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    print("bench: building inputs", file=sys.stderr, flush=True)
+    w = inputs.workload_plain_batched(n=args.n)
+    k = w.k
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    pts = t(w.points, torch.float64)
+    tg = t(w.targets, torch.int32)
+    pl = t(w.pool, torch.int32)
+    ln = t(w.pool_len, torch.int32)
+    T = len(w.targets)
+    out = csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, args.precision)
+    s_out = torch.empty(1, dtype=torch.float64, device=dev)
+    torch.cuda.synchronize()
+
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+
+    def step(i=None):
+        if i is not None:
+            ev[i][0].record()
+        csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, args.precision, out=out)
+        if i is not None:
+            ev[i][1].record()
+        csel.sum(out["log_condvar"], out=s_out)
+
+    graph = None
+    if args.graph:
+        # capture one step (no events inside) and check replays against eager
+        step()
+        torch.cuda.synchronize()
+        ref = {key: v.clone() for key, v in out.items()}
+        ref_s = s_out.clone()
+        cs = torch.cuda.Stream()
+        cs.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(cs):
+            step()
+        torch.cuda.current_stream().wait_stream(cs)
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph):
+            step()
+        for _ in range(2):
+            for v in out.values():
+                v.zero_()
+            graph.replay()
+            torch.cuda.synchronize()
+            for key in out:
+                assert torch.equal(out[key], ref[key]), f"graph replay differs from eager in {key}"
+            assert torch.equal(s_out, ref_s)
+
+    print("bench: warmup", file=sys.stderr, flush=True)
+    for _ in range(args.warmup):
+        graph.replay() if graph is not None else step()
+    torch.cuda.synchronize()
+
+    # timed region: K steps; inside each step the select kernel is bracketed by
+    # events on its own stream (the current stream)
+    print("bench: timing", file=sys.stderr, flush=True)
+    t_start = torch.cuda.Event(enable_timing=True)
+    t_end = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t_start.record()
+    for i in range(args.steps):
+        if graph is not None:
+            ev[i][0].record()
+            graph.replay()
+            ev[i][1].record()
+        else:
+            step(i)
+    t_end.record()
+    torch.cuda.synchronize()
+    total_ms = t_start.elapsed_time(t_end)
+    ms_step = total_ms / args.steps
+    # with a graph the per-step events bracket select + sum; the sum kernel is
+    # a single 1024-thread block over T doubles (a few microseconds)
+    kern_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in ev]))
+
+    flops, byt = column_work(w.pool_len, k, w.points.shape[1], w.kernel.two_nu)
+    flops_launch = float(np.sum(flops))
+    bytes_launch = float(np.sum(byt)) + w.points.nbytes
+    achieved = flops_launch / (kern_ms * 1e-3) / 1e12
+    st = out["status"].cpu().numpy()
+    S = float(s_out.item())
+
+    res = {
+        "metric": METRIC,
+        "value": T / (ms_step * 1e-3),
+        "unit": "columns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": f"plain greedy selection, N={args.n} uniform in [0,1]^3, Matern 5/2, l=0.05, nugget 1e-6, "
+                        f"pools of 256 nearest later points (uneven at the tail), k={k}, {args.precision}",
+            "columns": T,
+            "k": k,
+            "pool": 256,
+            "precision": args.precision,
+            "graph": bool(args.graph),
+            "sum_log_condvar": S,
+            "status_nonzero": int(np.count_nonzero(st)),
+        },
+        "roofline": {
+            "bound": "alu",
+            "kernel": "select_factor_kernel",
+            "achieved": achieved,
+            "peak": PEAK_ALU_TFLOPS,
+            "unit": "TFLOP/s",
+            "frac": achieved / PEAK_ALU_TFLOPS,
+            "traffic": None,
+            "kernel_ms": kern_ms,
+            "algorithmic_gflop_per_launch": flops_launch / 1e9,
+            "algorithmic_mb_per_launch": bytes_launch / 1e6,
+            "hbm_frac_at_algorithmic_bytes": bytes_launch / (kern_ms * 1e-3) / 1e9 / PEAK_HBM_GBS,
+        },
+    }
+    if args.cpu_seconds > 0:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        res["cpu_baseline"] = cpu_baseline(w, k, args.cpu_seconds, threads)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,133 @@
+/*
+ * csel.h -- C ABI of the greedy conditional-selection library for MI355X (gfx950).
+ *
+ * The library builds sparse inverse-Cholesky factors of kernel covariance
+ * matrices by greedy conditional selection (Huan, Guinness, Katzfuss, Owhadi,
+ * Schaefer, "Sparse inverse Cholesky factorization of dense kernel matrices by
+ * greedy conditional selection", arXiv:2307.11648).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - All array arguments are DEVICE pointers owned by the caller, unless the
+ *    comment says "host".  Nothing is freed or retained across a call.
+ *  - Work is enqueued asynchronously on `stream` (0 = the null stream);
+ *    outputs are valid once the stream is synchronized.  Calls on one stream
+ *    are ordered; the library keeps no per-call state between calls.
+ *  - Points are given in ordering-position order: "later" means a larger
+ *    index.  Coordinates are FP64, row-major [n][dim], 1 <= dim <= 3.
+ *  - Return value: CSEL_OK or a negative csel_error.  Arguments that can be
+ *    checked on the host are checked before anything is enqueued; the message
+ *    of the last failure on the calling thread is in csel_last_error().
+ *    Problems found inside a kernel (index out of range, numerical breakdown)
+ *    are not errors of the call: they are reported per column in `status`.
+ *  - Per-column status codes:
+ *      0 ok
+ *      1 stopped early: no candidate left with positive conditional variance;
+ *        the factor is built on the candidates selected so far
+ *      2 the selected covariance block was not numerically positive definite;
+ *        the column's values are NaN
+ *      3 bad input for this column (target or pool index outside [0, n),
+ *        pool_len outside [0, pool_stride]); the column is left as for status 2
+ *      4 (aggregated only) a pool index precedes a group member while factor
+ *        values were requested
+ *  - No C++ exception crosses this boundary.
+ */
+#ifndef CSEL_H
+#define CSEL_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    CSEL_OK = 0,
+    CSEL_EINVAL = -1,       /* an argument is invalid (see csel_last_error) */
+    CSEL_EHIP = -2,         /* a HIP runtime call failed */
+    CSEL_ENOMEM = -3,       /* device workspace could not be allocated */
+    CSEL_EUNSUPPORTED = -4  /* valid request outside what this build handles */
+} csel_error;
+
+enum { CSEL_FP64 = 0, CSEL_MIXED = 1 };
+
+/* Matern covariance K(x, y) = variance * m_nu(|x - y| / length_scale) with
+ * nu = two_nu / 2 in {1/2, 3/2, 5/2}, plus `nugget` on the diagonal (by
+ * index).  The paper uses the Matern family throughout (Sec. 6) without
+ * printing it; these are the textbook half-integer forms:
+ *   nu=1/2: exp(-a), a = r/l;   nu=3/2: (1+a)exp(-a), a = sqrt(3) r/l;
+ *   nu=5/2: (1+a+a^2/3)exp(-a), a = sqrt(5) r/l. */
+typedef struct {
+    int32_t two_nu;
+    double length_scale; /* > 0 */
+    double variance;     /* > 0 */
+    double nugget;       /* >= 0 */
+} csel_kernel;
+
+/* Message for the last non-OK return on the calling thread ("" if none). */
+const char *csel_last_error(void);
+
+/* ABI version, currently 1. */
+int32_t csel_version(void);
+
+/* Largest pool size and number of selections per column this build handles
+ * for csel_select_and_factor. */
+int32_t csel_max_pool(void);
+int32_t csel_max_select(void);
+
+/*
+ * csel_select_and_factor -- greedy single-target selection per column and its
+ * KL-optimal factor column.
+ *
+ * For each target column i = targets[c] (Sec. 4): the candidates are
+ * pool_idx[c*pool_stride + 0 .. pool_len[c]) (ids of later points, sorted by
+ * distance, ascending).  k_c = min(k, pool_len[c]) points are selected one at
+ * a time, each maximizing the decrease of the target's conditional variance,
+ * cov(i, j | I)^2 / var(j | I) (eq. obj_gp), with the conditional variances
+ * and covariances kept by rank-one downdates of a partial Cholesky factor
+ * (eq. cond_select; App. C.1).  A candidate stays eligible while its
+ * conditional variance exceeds 1e-12 times its prior variance.  Ties in score
+ * go to the smaller pool slot.  The column on s = [i, selected...] is then
+ * L_{s,i} = Theta_ss^{-1} e_1 / sqrt(e_1^T Theta_ss^{-1} e_1) (eq. L_col),
+ * from an FP64 Cholesky factorization of Theta_ss.
+ *
+ *   pts        [n][dim] FP64 coordinates
+ *   targets    [n_targets] int32 column ids
+ *   pool_idx   [n_targets][pool_stride] int32 candidate ids
+ *   pool_len   [n_targets] int32, 0 <= pool_len <= pool_stride <= csel_max_pool()
+ *   k          0 <= k <= csel_max_select()
+ *   precision  CSEL_FP64: everything in FP64.
+ *              CSEL_MIXED: covariance evaluation and the left-looking GEMV of
+ *              the selection in FP32; conditional variances/covariances, the
+ *              scores, Theta_ss and its Cholesky factorization in FP64.
+ * Outputs (per column c):
+ *   sel_idx    [n_targets][k] selected ids in selection order, -1 padded
+ *   factor_val [n_targets][k+1]: [0] = L_ii, [1+t] = entry of row sel_idx[t];
+ *              0 in padded slots
+ *   log_condvar[n_targets] log Theta_{ii | s_i \ i} (may be NULL); the sum
+ *              over all columns minus log det Theta is 2 KL (eq. obj_chol)
+ *   top2_gap   [n_targets][k] relative gap (s1 - s2)/s1 between the best and
+ *              second-best scores at each step, 1 with a single eligible
+ *              candidate, NaN padded (may be NULL)
+ *   status     [n_targets] per-column status (see above)
+ */
+int csel_select_and_factor(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel,
+                           int64_t n_targets, const int32_t *targets, const int32_t *pool_idx,
+                           const int32_t *pool_len, int32_t pool_stride, int32_t k, int32_t precision,
+                           int32_t *sel_idx, double *factor_val, double *log_condvar, float *top2_gap,
+                           uint8_t *status, hipStream_t stream);
+
+/*
+ * csel_sum -- deterministic FP64 sum of x[0..n) into *out (device scalar).
+ * Used for S = sum_i log Theta_{ii|s_i \ i}, the data term of the KL
+ * (eq. obj_chol).  The summation order is fixed, so results are bitwise
+ * reproducible for a given n.
+ */
+int csel_sum(const double *x, int64_t n, double *out, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* CSEL_H */

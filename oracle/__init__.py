@@ -54,6 +54,9 @@ def _load():
                                                                       _c.c_int32, _i32p, _f64p, _f64p, _f64p, _u8p,
                                                                       _c.c_int32]
     lib.orc_select_and_factor.restype = None
+    lib.orc_replay_one.argtypes = [_f64p, _c.c_int32] + kern + [_c.c_int32, _i32p, _c.c_int32, _c.c_int32, _i32p,
+                                                               _f64p, _f64p, _f64p, _f64p]
+    lib.orc_replay_one.restype = _c.c_int
     lib.orc_multi_one.argtypes = [_f64p, _c.c_int32] + kern + [_i32p, _c.c_int32, _i32p, _c.c_int32, _c.c_int32,
                                                               _i32p, _f64p, _f64p, _f64p, _f64p]
     lib.orc_multi_one.restype = _c.c_int
@@ -123,6 +126,26 @@ def select_one(x, kernel, target: int, pool, k: int) -> dict:
                                 _p(cov, _f64p))
     return {"sel": sel[:k], "gap": gap[:k], "factor": fac, "log_condvar": float(lcv[0]), "var": var[:C],
             "cov": cov[:C], "status": int(st)}
+
+
+def replay_one(x, kernel, target: int, pool, k: int, forced) -> dict:
+    """Replay another run's selection sequence ``forced`` (ids, -1 padded) in
+    FP64: per step the best valid score, the forced pick's score and the
+    target's conditional variance before the step, and the eq. L_col column on
+    [target, forced...].  Status 5: a forced pick was not
+    a valid candidate."""
+    x = _pts(x)
+    pool = np.ascontiguousarray(pool, dtype=np.int32)
+    forced = np.ascontiguousarray(forced, dtype=np.int32)
+    best = np.empty(max(2 * k, 1), np.float64)
+    pick = np.empty(max(k, 1), np.float64)
+    fac = np.empty(k + 1, np.float64)
+    lcv = np.empty(1, np.float64)
+    st = _load().orc_replay_one(_p(x, _f64p), x.shape[1], *_kargs(kernel), int(target), _p(pool, _i32p), len(pool),
+                                k, _p(forced, _i32p), _p(best, _f64p), _p(pick, _f64p), _p(fac, _f64p),
+                                _p(lcv, _f64p))
+    return {"best": best[:k], "pick": pick[:k], "target_var": best[k:2 * k], "factor": fac,
+            "log_condvar": float(lcv[0]), "status": int(st)}
 
 
 def select_and_factor(x, kernel, targets, pool, pool_len, k: int, nthreads: int = 0) -> dict:

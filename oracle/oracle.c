@@ -125,8 +125,13 @@ static int lcol(const orc_cov *c, const int32_t *s, int m, double *vals, double 
  *   logcv         log Theta_{ii | s_i \ i}
  *   var_out[C]    (optional) conditional variances of the pool after selection
  * Returns status. */
-int orc_select_column(const orc_cov *c, int32_t i, const int32_t *pool, int32_t C, int32_t k, int32_t *sel,
-                      double *gap, double *factor, double *logcv, double *var_out, double *cov_out) {
+/* When `forced` is given, step t takes forced[t] (a pool id; -1 ends the
+ * run) instead of the argmax and records, in FP64, the best score over valid
+ * candidates (best_out[t]) and the forced pick's score (pick_out[t]): a replay
+ * of another run's selection under exact arithmetic. */
+static int select_column_impl(const orc_cov *c, int32_t i, const int32_t *pool, int32_t C, int32_t k, int32_t *sel,
+                              double *gap, double *factor, double *logcv, double *var_out, double *cov_out,
+                              const int32_t *forced, double *best_out, double *pick_out) {
     int32_t R = C + 1;
     int32_t kk = k < C ? k : C;
     double *L = (double *)calloc((size_t)R * (kk > 0 ? kk : 1), sizeof(double));
@@ -159,6 +164,18 @@ int orc_select_column(const orc_cov *c, int32_t i, const int32_t *pool, int32_t 
             if (sc > s1) { s2 = s1; s1 = sc; best = j; }
             else if (sc > s2) s2 = sc;
         }
+        if (forced) {
+            /* replay: take the given pick if it is a valid candidate */
+            int32_t f = forced[t], fj = -1;
+            if (f < 0) break;
+            for (int32_t j = 0; j < C; ++j)
+                if (pool[j] == f && !taken[j] && var[j] > 1e-12 * prior[j]) fj = j;
+            if (fj < 0) { status = 5; break; }
+            best_out[t] = s1;
+            pick_out[t] = cov[fj] * cov[fj] / var[fj];
+            best_out[k + t] = var[C]; /* the target's conditional variance before this step */
+            best = fj;
+        }
         if (nvalid == 0) { status = 1; break; }
         gap[t] = (nvalid == 1) ? 1.0 : (s1 == 0.0 ? 0.0 : (s1 - s2) / s1);
         /* new column of the partial Cholesky factor by left-looking (eq. cond_select) */
@@ -190,6 +207,27 @@ int orc_select_column(const orc_cov *c, int32_t i, const int32_t *pool, int32_t 
     if (st) status = st;
     free(s); free(L); free(var); free(prior); free(cov); free(u); free(taken); free(row_id);
     return status;
+}
+
+int orc_select_column(const orc_cov *c, int32_t i, const int32_t *pool, int32_t C, int32_t k, int32_t *sel,
+                      double *gap, double *factor, double *logcv, double *var_out, double *cov_out) {
+    return select_column_impl(c, i, pool, C, k, sel, gap, factor, logcv, var_out, cov_out, NULL, NULL, NULL);
+}
+
+/* Replay of a given selection sequence (see select_column_impl); the factor
+ * and log_condvar are eq. L_col on [i, forced...].  Status 5 marks a forced
+ * pick that is not a valid candidate. */
+int orc_replay_one(const double *x, int32_t d, int32_t two_nu, double ell, double s2, double nugget, int32_t target,
+                   const int32_t *pool, int32_t C, int32_t k, const int32_t *forced, double *best_out,
+                   double *pick_out, double *factor, double *logcv) {
+    orc_cov c = {x, d, two_nu, ell, s2, nugget};
+    int32_t *sel = (int32_t *)malloc(sizeof(int32_t) * (k > 0 ? k : 1));
+    double *gap = (double *)malloc(sizeof(double) * (k > 0 ? k : 1));
+    for (int32_t t = 0; t < k; ++t) { best_out[t] = NAN; best_out[k + t] = NAN; pick_out[t] = NAN; }
+    int st = select_column_impl(&c, target, pool, C, k, sel, gap, factor, logcv, NULL, NULL, forced, best_out,
+                                pick_out);
+    free(sel); free(gap);
+    return st;
 }
 
 void orc_select_and_factor(const double *x, int32_t d, int32_t two_nu, double ell, double s2, double nugget,

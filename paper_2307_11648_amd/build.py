@@ -20,13 +20,20 @@ LIB = os.path.join(PKG, "libcsel.so")
 GEO_SRC = os.path.join(PKG, "inputs", "geometry.c")
 GEO_LIB = os.path.join(PKG, "inputs", "libcsel_geometry.so")
 
-HIP_SOURCES = ["abi.cpp", "select.hip", "aggregate.hip", "apply.hip", "mlp.hip"]
+# (source, extra defines): the single-target kernel families compile as
+# separate objects so the build runs in parallel.
+HIP_UNITS = [("abi.cpp", []), ("select.hip", [])] + [
+    ("select_inst.hip", [f"-DCSEL_SEL_T={t}", f"-DCSEL_SEL_NU={nu}"])
+    for t in ("float", "double") for nu in (1, 3, 5)
+] + [(s, []) for s in ("aggregate.hip", "apply.hip", "mlp.hip")]
 
 HIPCC_FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions are kept out of every kernel
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-fvisibility=hidden", "-ffp-contract=fast",
+    # the pick loops are unrolled in full so every partial-factor index is static
+    "-mllvm", "-pragma-unroll-threshold=1000000",
     "-Wno-unused-command-line-argument",
 ]
 
@@ -44,15 +51,31 @@ def build_geometry() -> str:
     return GEO_LIB
 
 
-def hip_sources():
-    return [os.path.join(CSRC, s) for s in HIP_SOURCES if os.path.exists(os.path.join(CSRC, s))]
+def hip_units():
+    return [(os.path.join(CSRC, src), defs) for src, defs in HIP_UNITS if os.path.exists(os.path.join(CSRC, src))]
 
 
-def build_hip(extra_flags=None) -> str:
+def build_hip(extra_flags=None, jobs=None) -> str:
+    """Compile every unit to an object (in parallel), then link libcsel.so."""
+    from concurrent.futures import ThreadPoolExecutor
+
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+    objdir = os.path.join(PKG, "_build")
+    os.makedirs(objdir, exist_ok=True)
+    units = hip_units()
+    jobs = jobs or int(os.environ.get("MAX_JOBS", "0") or 0) or min(16, os.cpu_count() or 4)
+
+    def compile_one(u):
+        src, defs = u
+        tag = "_".join(d.split("=")[-1] for d in defs)
+        obj = os.path.join(objdir, os.path.basename(src) + (("." + tag) if tag else "") + ".o")
+        _run([hipcc] + HIPCC_FLAGS + (extra_flags or []) + defs + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
+        return obj
+
+    with ThreadPoolExecutor(max_workers=jobs) as ex:
+        objs = list(ex.map(compile_one, units))
     tmp = LIB + ".tmp"
-    cmd = [hipcc] + HIPCC_FLAGS + (extra_flags or []) + ["-I", INCLUDE, "-I", CSRC, "-o", tmp] + hip_sources()
-    _run(cmd)
+    _run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs)
     os.replace(tmp, LIB)
     return LIB
 

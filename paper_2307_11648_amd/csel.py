@@ -1,0 +1,137 @@
+"""Python binding of libcsel (ctypes).  Argument marshalling only: every step
+of the hot path runs in the library's HIP kernels; torch supplies device
+memory and the current stream.  There is no CPU fallback: a missing library
+or a non-GPU tensor is an error.
+
+Entry points mirror include/csel.h:
+    select_and_factor  -- greedy single-target selection + eq. L_col columns
+    sum                -- deterministic FP64 sum (KL data term)
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcsel.so")
+_lib = None
+
+_c = ctypes
+_vp = ctypes.c_void_p
+
+CSEL_FP64 = 0
+CSEL_MIXED = 1
+_PREC = {"fp64": CSEL_FP64, "mixed": CSEL_MIXED}
+
+
+class CselError(RuntimeError):
+    """A non-OK return of the C ABI, with csel_last_error()'s message."""
+
+    def __init__(self, code, msg):
+        super().__init__(f"csel error {code}: {msg}")
+        self.code = code
+
+
+class KernelParams(ctypes.Structure):
+    _fields_ = [("two_nu", ctypes.c_int32), ("length_scale", ctypes.c_double), ("variance", ctypes.c_double),
+                ("nugget", ctypes.c_double)]
+
+
+def kernel_struct(kernel) -> KernelParams:
+    return KernelParams(int(kernel.two_nu), float(kernel.length_scale), float(kernel.variance), float(kernel.nugget))
+
+
+def load():
+    """Load libcsel.so (built in-tree by paper_2307_11648_amd.build)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"{LIB_PATH} is missing: build it with paper_2307_11648_amd.build.build_hip()")
+    lib = ctypes.CDLL(LIB_PATH)
+    lib.csel_last_error.restype = ctypes.c_char_p
+    lib.csel_version.restype = ctypes.c_int32
+    lib.csel_max_pool.restype = ctypes.c_int32
+    lib.csel_max_select.restype = ctypes.c_int32
+    lib.csel_select_and_factor.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64,
+                                           _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp,
+                                           _vp, _vp]
+    lib.csel_select_and_factor.restype = ctypes.c_int
+    lib.csel_sum.argtypes = [_vp, _c.c_int64, _vp, _vp]
+    lib.csel_sum.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def _check(rc):
+    if rc != 0:
+        raise CselError(rc, load().csel_last_error().decode())
+
+
+def _dev(t: torch.Tensor, dtype, name):
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise ValueError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else t.data_ptr()
+
+
+def _stream(stream):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def select_and_factor(points, kernel, targets, pool, pool_len, k: int, precision: str = "fp64",
+                      want_gap: bool = False, out: dict | None = None, stream=None) -> dict:
+    """Greedy selection + factor columns for every target (csel_select_and_factor).
+
+    points [n, dim] float64, targets [T] int32, pool [T, stride] int32,
+    pool_len [T] int32 -- all on the GPU.  Returns a dict of GPU tensors:
+    sel [T, k] int32, factor [T, k+1] float64, log_condvar [T] float64,
+    status [T] uint8 and, if want_gap, gap [T, k] float32.  Pass `out` (same
+    keys) to reuse buffers."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    _dev(targets, torch.int32, "targets")
+    _dev(pool, torch.int32, "pool")
+    _dev(pool_len, torch.int32, "pool_len")
+    if points.dim() != 2:
+        raise ValueError("points must be [n, dim]")
+    T = targets.shape[0]
+    stride = pool.shape[1] if pool.dim() == 2 else 0
+    dev = points.device
+    if out is None:
+        out = {
+            "sel": torch.empty((T, k), dtype=torch.int32, device=dev),
+            "factor": torch.empty((T, k + 1), dtype=torch.float64, device=dev),
+            "log_condvar": torch.empty(T, dtype=torch.float64, device=dev),
+            "status": torch.empty(T, dtype=torch.uint8, device=dev),
+        }
+        if want_gap:
+            out["gap"] = torch.empty((T, k), dtype=torch.float32, device=dev)
+    kp = kernel_struct(kernel)
+    rc = lib.csel_select_and_factor(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), T,
+                                    targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride, int(k),
+                                    _PREC[precision], _ptr(out["sel"]), _ptr(out["factor"]),
+                                    _ptr(out.get("log_condvar")), _ptr(out.get("gap")), _ptr(out["status"]),
+                                    _stream(stream))
+    _check(rc)
+    return out
+
+
+def sum(x, out=None, stream=None):
+    """Deterministic FP64 sum of a GPU float64 vector (csel_sum) -> 1-element tensor."""
+    lib = load()
+    _dev(x, torch.float64, "x")
+    if out is None:
+        out = torch.empty(1, dtype=torch.float64, device=x.device)
+    _check(lib.csel_sum(x.data_ptr(), x.numel(), out.data_ptr(), _stream(stream)))
+    return out

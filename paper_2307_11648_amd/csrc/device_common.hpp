@@ -1,0 +1,147 @@
+// device_common.hpp -- wave-level building blocks shared by the CDNA4 kernels.
+//
+// Everything here is written for wave64 (gfx950): lane masks, DPP controls and
+// readlane broadcasts assume 64 lanes per wavefront.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace csel {
+
+constexpr int kWave = 64;
+
+__device__ __forceinline__ int lane_id() { return __lane_id(); }
+
+// ---------------------------------------------------------------------------
+// uniform broadcasts (the source lane index must be wave-uniform)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float bcast(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+__device__ __forceinline__ int32_t bcast(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+__device__ __forceinline__ double bcast(double v, int lane) {
+    int64_t b = __double_as_longlong(v);
+    int32_t lo = __builtin_amdgcn_readlane((int32_t)(b & 0xffffffff), lane);
+    int32_t hi = __builtin_amdgcn_readlane((int32_t)(b >> 32), lane);
+    return __longlong_as_double(((int64_t)(uint32_t)lo) | ((int64_t)hi << 32));
+}
+__device__ __forceinline__ uint64_t bcast(uint64_t v, int lane) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)v, lane);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int32_t)(uint32_t)(v >> 32), lane);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// ---------------------------------------------------------------------------
+// DPP moves within rows of 16 lanes (all source lanes valid for these controls)
+// ---------------------------------------------------------------------------
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+constexpr int kDppRowRor4 = 0x124;  // row_ror:4
+constexpr int kDppRowRor8 = 0x128;  // row_ror:8
+
+template <int CTRL>
+__device__ __forceinline__ uint64_t dpp64(uint64_t v) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)(uint32_t)v, CTRL, 0xF, 0xF, false);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)(uint32_t)(v >> 32), CTRL, 0xF, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
+
+// Top-two of distinct 64-bit keys; 0 means "no candidate".
+struct Top2 {
+    uint64_t k1, k2;
+};
+
+__device__ __forceinline__ Top2 merge(Top2 a, Top2 b) {
+    Top2 r;
+    r.k1 = a.k1 > b.k1 ? a.k1 : b.k1;
+    uint64_t lo = a.k1 > b.k1 ? b.k1 : a.k1;
+    uint64_t s = a.k2 > b.k2 ? a.k2 : b.k2;
+    r.k2 = lo > s ? lo : s;
+    return r;
+}
+
+__device__ __forceinline__ void insert(Top2 &a, uint64_t key) {
+    if (key > a.k1) {
+        a.k2 = a.k1;
+        a.k1 = key;
+    } else if (key > a.k2) {
+        a.k2 = key;
+    }
+}
+
+// Wave-wide top-two over disjoint per-lane sets; the result is uniform.
+// Inside each row of 16 lanes: two quad butterflies and two row rotations
+// (every step merges disjoint sets); across the four rows: readlane.
+__device__ __forceinline__ Top2 wave_top2(Top2 v) {
+    Top2 o;
+    o.k1 = dpp64<kDppQuadXor1>(v.k1); o.k2 = dpp64<kDppQuadXor1>(v.k2); v = merge(v, o);
+    o.k1 = dpp64<kDppQuadXor2>(v.k1); o.k2 = dpp64<kDppQuadXor2>(v.k2); v = merge(v, o);
+    o.k1 = dpp64<kDppRowRor4>(v.k1); o.k2 = dpp64<kDppRowRor4>(v.k2); v = merge(v, o);
+    o.k1 = dpp64<kDppRowRor8>(v.k1); o.k2 = dpp64<kDppRowRor8>(v.k2); v = merge(v, o);
+    Top2 r0 = {bcast(v.k1, 0), bcast(v.k2, 0)};
+    Top2 r1 = {bcast(v.k1, 16), bcast(v.k2, 16)};
+    Top2 r2 = {bcast(v.k1, 32), bcast(v.k2, 32)};
+    Top2 r3 = {bcast(v.k1, 48), bcast(v.k2, 48)};
+    return merge(merge(r0, r1), merge(r2, r3));
+}
+
+// Wave-wide max of a 64-bit key (uniform result).
+__device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
+    uint64_t o;
+    o = dpp64<kDppQuadXor1>(v); v = v > o ? v : o;
+    o = dpp64<kDppQuadXor2>(v); v = v > o ? v : o;
+    o = dpp64<kDppRowRor4>(v); v = v > o ? v : o;
+    o = dpp64<kDppRowRor8>(v); v = v > o ? v : o;
+    uint64_t a = bcast(v, 0), b = bcast(v, 16), c = bcast(v, 32), d = bcast(v, 48);
+    a = a > b ? a : b;
+    c = c > d ? c : d;
+    return a > c ? a : c;
+}
+
+// ---------------------------------------------------------------------------
+// Selection keys: a non-negative FP64 score with its low kSlotBits mantissa
+// bits replaced by (kSlotMax - slot).  Larger key = larger score, then
+// smaller slot.  Any eligible candidate has key >= 1; 0 = none.
+// ---------------------------------------------------------------------------
+constexpr int kSlotBits = 13;
+constexpr uint64_t kSlotMask = (1ull << kSlotBits) - 1;
+constexpr int kSlotMax = (1 << kSlotBits) - 1;  // slots 0 .. kSlotMax-1
+
+__device__ __forceinline__ uint64_t make_key(double score, int slot) {
+    uint64_t b = (uint64_t)__double_as_longlong(score);
+    return (b & ~kSlotMask) | (uint64_t)(kSlotMax - slot);
+}
+__device__ __forceinline__ int key_slot(uint64_t key) { return kSlotMax - (int)(key & kSlotMask); }
+__device__ __forceinline__ double key_score(uint64_t key) {
+    return __longlong_as_double((long long)(key & ~kSlotMask));
+}
+
+// ---------------------------------------------------------------------------
+// Matern kernels (half-integer smoothness).  `c` = sqrt(2 nu) / length_scale.
+// ---------------------------------------------------------------------------
+template <int TWO_NU>
+__device__ __forceinline__ float matern_f32(float r, float c, float s2) {
+    const float a = c * r;
+    const float e = __expf(-a);
+    if constexpr (TWO_NU == 1) return s2 * e;
+    if constexpr (TWO_NU == 3) return s2 * (1.0f + a) * e;
+    return s2 * (1.0f + a + a * a * (1.0f / 3.0f)) * e;
+}
+
+template <int TWO_NU>
+__device__ __forceinline__ double matern_f64(double r, double c, double s2) {
+    const double a = c * r;
+    const double e = exp(-a);
+    if constexpr (TWO_NU == 1) return s2 * e;
+    if constexpr (TWO_NU == 3) return s2 * (1.0 + a) * e;
+    return s2 * (1.0 + a + a * a * (1.0 / 3.0)) * e;
+}
+
+__device__ __forceinline__ double matern_f64_rt(int two_nu, double r, double c, double s2) {
+    if (two_nu == 1) return matern_f64<1>(r, c, s2);
+    if (two_nu == 3) return matern_f64<3>(r, c, s2);
+    return matern_f64<5>(r, c, s2);
+}
+
+}  // namespace csel

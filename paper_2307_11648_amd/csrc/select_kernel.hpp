@@ -1,0 +1,294 @@
+// select_kernel.hpp -- single-target greedy selection + KL-optimal factor column.
+//
+// Schedule: one wavefront per target column (4 columns per 256-thread block).
+// The candidate pool (C <= 64*RPL) is spread over the 64 lanes, RPL rows per
+// lane (pool slot j = rr*64 + lane).  Each lane keeps, for its rows:
+//   - the coordinate offset from the target (FP32 or FP64),
+//   - the tracked conditional variance and covariance with the target (FP64),
+//   - its row of the partial Cholesky factor, L[rr][0..KMAX) (FP32 or FP64),
+// all in VGPRs: the pick loop is fully unrolled so every index into L is static.
+//
+// One pick (Sec. 3.1, eq. cond_select / eq. obj_gp; App. C.1):
+//   score = cov^2 / var (FP64) -> wave top-two via DPP -> the winner's factor
+//   row, offset, var and cov are broadcast with readlane -> every lane
+//   evaluates Theta(row, winner), subtracts the GEMV L[row] . L[winner] and
+//   scales by 1/sqrt(var_winner) -> FP64 rank-one downdate of var and cov.
+// The target's own factor row is never formed: its entry for pick t is
+// cov_winner / sqrt(var_winner), the quantity eq. cond_select defines.
+//
+// Factor column (eq. L_col): lanes 0..s-1 hold the selected points and lane s
+// the target.  Theta' = Theta over [selected..., target] is built in FP64
+// (lane r owns row r), factored by a right-looking Cholesky with readlane
+// broadcasts, and L_{s,i} follows from one back-substitution with the last
+// unit vector: with Theta' = R R^T, Theta'^{-1} e_last = R^{-T} e_last / R_ll.
+
+#pragma once
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace csel {
+
+template <typename T, int TWO_NU>
+__device__ __forceinline__ T matern(T r, T c, T s2) {
+    if constexpr (sizeof(T) == 4) return matern_f32<TWO_NU>(r, c, s2);
+    else return matern_f64<TWO_NU>(r, c, s2);
+}
+
+constexpr int kSelWavesPerBlock = 4;
+
+template <typename T, int TWO_NU, int RPL, int KMAX>
+__global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
+    static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
+    __shared__ double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
+
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
+    if (col >= p.n_targets) return;
+
+    const int kout = p.k;
+    int32_t* sel_out = p.sel + col * kout;
+    double* fac_out = p.fac + col * (kout + 1);
+
+    const int32_t tgt = __builtin_amdgcn_readfirstlane(p.targets[col]);
+    const int32_t C = __builtin_amdgcn_readfirstlane(p.pool_len[col]);
+    const int dim = p.dim;
+
+    // ---- stage the pool ------------------------------------------------
+    bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > p.stride || C > RPL * kWave;
+    double xi[3] = {0.0, 0.0, 0.0};
+    T dx[RPL][3];
+    double var[RPL], cov[RPL];
+    int32_t pid[RPL];
+    uint32_t live = 0;
+    const T cnu = (T)p.c_nu, s2 = (T)p.s2;
+    const double prior = p.s2 + p.nugget;
+    const double thr = 1e-12 * prior;
+    if (!bad) {
+        for (int d = 0; d < dim; ++d) xi[d] = p.pts[(int64_t)tgt * dim + d];
+    }
+    bool bad_idx = false;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+        const int j = rr * kWave + lane;
+        pid[rr] = -1;
+        dx[rr][0] = dx[rr][1] = dx[rr][2] = (T)0;
+        var[rr] = 0.0;
+        cov[rr] = 0.0;
+        if (!bad && j < C) {
+            const int32_t q = p.pool[col * p.stride + j];
+            if (q < 0 || (int64_t)q >= p.n) {
+                bad_idx = true;
+            } else {
+                pid[rr] = q;
+                for (int d = 0; d < dim; ++d) dx[rr][d] = (T)(p.pts[(int64_t)q * dim + d] - xi[d]);
+                live |= 1u << rr;
+            }
+        }
+        const T r = sqrt(dx[rr][0] * dx[rr][0] + dx[rr][1] * dx[rr][1] + dx[rr][2] * dx[rr][2]);
+        cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
+        var[rr] = prior;
+    }
+    bad = bad || __any(bad_idx);
+    if (bad) {
+        for (int r = lane; r < kout; r += kWave) {
+            sel_out[r] = -1;
+            fac_out[1 + r] = __builtin_nan("");
+            if (p.gap) p.gap[col * kout + r] = __builtin_nanf("");
+        }
+        if (lane == 0) {
+            fac_out[0] = __builtin_nan("");
+            if (p.logcv) p.logcv[col] = __builtin_nan("");
+            p.status[col] = 3;
+        }
+        return;
+    }
+
+    // ---- greedy selection ------------------------------------------------
+    const int kk = min(kout, C);
+    const T nug = (T)p.nugget;
+    T L[RPL][KMAX];
+    int32_t my_sel = -1;
+    float my_gap = __builtin_nanf("");
+    int nsel = 0;
+    int st = 0;
+    bool stopped = false;
+#pragma unroll
+    for (int t = 0; t < KMAX; ++t) {
+        if (t < kk && !stopped) {
+            Top2 loc = {0ull, 0ull};
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) {
+                if (((live >> rr) & 1u) && var[rr] > thr) {
+                    const double sc = cov[rr] * cov[rr] / var[rr];
+                    insert(loc, make_key(sc, rr * kWave + lane));
+                }
+            }
+            const Top2 w = wave_top2(loc);
+            if (w.k1 == 0ull) {
+                st = 1;
+                stopped = true;
+            } else {
+                const int slot = key_slot(w.k1);
+                const int rs = slot >> 6;
+                const int ls = slot & (kWave - 1);
+                const double sa = key_score(w.k1), sb = key_score(w.k2);
+                const float g = (w.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
+
+                // broadcast the winner's row
+                T Lk[KMAX];
+                T dk0 = (T)0, dk1 = (T)0, dk2 = (T)0;
+                double vk = 1.0, ck = 0.0;
+                int32_t idk = -1;
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    if (rr == rs) {
+#pragma unroll
+                        for (int q = 0; q < t; ++q) Lk[q] = bcast(L[rr][q], ls);
+                        dk0 = bcast(dx[rr][0], ls);
+                        dk1 = bcast(dx[rr][1], ls);
+                        dk2 = bcast(dx[rr][2], ls);
+                        vk = bcast(var[rr], ls);
+                        ck = bcast(cov[rr], ls);
+                        idk = bcast(pid[rr], ls);
+                    }
+                }
+                const double inv_sd = 1.0 / sqrt(vk);
+                const double ui = ck * inv_sd;
+                const T inv_sd_t = (T)inv_sd;
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
+                    const T r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    T acc = matern<T, TWO_NU>(r, cnu, s2);
+                    if (pid[rr] == idk) acc += nug;
+#pragma unroll
+                    for (int q = 0; q < t; ++q) acc -= L[rr][q] * Lk[q];
+                    const T u = acc * inv_sd_t;
+                    L[rr][t] = u;
+                    const double ud = (double)u;
+                    var[rr] -= ud * ud;
+                    cov[rr] -= ud * ui;
+                }
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr)
+                    if (rr == rs && lane == ls) live &= ~(1u << rr);
+                if (lane == t) {
+                    my_sel = idk;
+                    my_gap = g;
+                }
+                nsel = t + 1;
+            }
+        }
+    }
+
+    // ---- factor column: Theta' over [selected..., target], FP64 ------------
+    const int M = nsel + 1;
+    const int32_t my_id = lane < nsel ? my_sel : (lane == nsel ? tgt : -1);
+    double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0;
+    if (my_id >= 0) {
+        xr0 = p.pts[(int64_t)my_id * dim + 0];
+        if (dim > 1) xr1 = p.pts[(int64_t)my_id * dim + 1];
+        if (dim > 2) xr2 = p.pts[(int64_t)my_id * dim + 2];
+    }
+    const double cnu64 = p.c_nu, s264 = p.s2, nug64 = p.nugget;
+    double a[KMAX + 1];
+#pragma unroll
+    for (int c = 0; c <= KMAX; ++c) {
+        if (c >= M) continue;
+        const double y0 = bcast(xr0, c), y1 = bcast(xr1, c), y2 = bcast(xr2, c);
+        const int32_t idc = bcast(my_id, c);
+        const double e0 = xr0 - y0, e1 = xr1 - y1, e2 = xr2 - y2;
+        a[c] = matern_f64<TWO_NU>(sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnu64, s264) + (my_id == idc ? nug64 : 0.0);
+    }
+    bool pd = true;
+#pragma unroll
+    for (int j = 0; j <= KMAX; ++j) {
+        if (j >= M || !pd) continue;
+        const double piv = bcast(a[j], j);
+        if (!(piv > 0.0)) {
+            pd = false;
+            continue;
+        }
+        const double dj = sqrt(piv);
+        const double inv = 1.0 / dj;
+        if (lane > j) a[j] *= inv;
+        else if (lane == j) a[j] = dj;
+#pragma unroll
+        for (int c = j + 1; c <= KMAX; ++c) {
+            if (c >= M) continue;
+            const double lc = bcast(a[j], c);
+            if (lane >= c) a[c] -= a[j] * lc;
+        }
+    }
+
+    double y = 0.0;
+    if (pd) {
+        // rows of R to LDS (lane r writes row r), then back-substitution
+        double(*R)[KMAX + 2] = sh_r[wib];
+        if (lane < M) {
+#pragma unroll
+            for (int c = 0; c <= KMAX; ++c)
+                if (c <= lane) R[lane][c] = a[c];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const int l = nsel;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = KMAX; c >= 0; --c) {
+            if (c > l) continue;
+            const double rcc = bcast(a[c], c);
+            double yc;
+            if (c == l) {
+                yc = 1.0 / rcc;
+                if (lane == 0 && p.logcv) p.logcv[col] = 2.0 * log(rcc);
+            } else {
+                yc = -bcast(acc, c) / rcc;
+            }
+            if (lane == c) y = yc;
+            if (lane < c) acc += R[c][lane] * yc;
+        }
+    } else {
+        st = 2;
+        y = __builtin_nan("");
+        if (lane == 0 && p.logcv) p.logcv[col] = __builtin_nan("");
+    }
+    if (lane < kout) {
+        sel_out[lane] = lane < nsel ? my_sel : -1;
+        fac_out[1 + lane] = lane < nsel ? y : (pd ? 0.0 : __builtin_nan(""));
+        if (p.gap) p.gap[col * kout + lane] = my_gap;
+    }
+    if (lane == nsel) fac_out[0] = y;
+    if (lane == 0) p.status[col] = (uint8_t)st;
+}
+
+template <typename T, int TWO_NU, int RPL, int KMAX>
+static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
+    const int64_t blocks = (a.n_targets + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
+    hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+template <typename T, int TWO_NU>
+static hipError_t launch_nu_impl(const SelectArgs& a, int rpl, int kmax, hipStream_t s) {
+    if (kmax == 16) {
+        switch (rpl) {
+            case 1: return launch_one<T, TWO_NU, 1, 16>(a, s);
+            case 2: return launch_one<T, TWO_NU, 2, 16>(a, s);
+            case 4: return launch_one<T, TWO_NU, 4, 16>(a, s);
+            case 8: return launch_one<T, TWO_NU, 8, 16>(a, s);
+        }
+    } else if (kmax == 32) {
+        switch (rpl) {
+            case 1: return launch_one<T, TWO_NU, 1, 32>(a, s);
+            case 2: return launch_one<T, TWO_NU, 2, 32>(a, s);
+            case 4: return launch_one<T, TWO_NU, 4, 32>(a, s);
+            case 8: return launch_one<T, TWO_NU, 8, 32>(a, s);
+        }
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace csel

@@ -1,0 +1,93 @@
+"""Parity helpers: compare GPU outputs with the FP64 oracle.
+
+Where several greedy runs are correct (near-ties), only what is unique is
+compared: the selection must agree on every decisive step (oracle top-two
+relative gap above a threshold) up to the first non-decisive step of that
+column; factor values are compared on columns whose whole selection agrees.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+
+def decisive_prefix(gap_row, thr):
+    """Number of leading steps whose oracle top-two gap exceeds thr."""
+    g = np.asarray(gap_row, dtype=np.float64)
+    bad = np.where(~(g > thr))[0]
+    return len(g) if len(bad) == 0 else int(bad[0])
+
+
+def compare_single(gpu: dict, orc: dict, thr: float, factor_rtol: float, logcv_atol: float):
+    """Returns a report dict; raises AssertionError on a parity violation.
+
+    gpu/orc: numpy dicts with sel [T,k], factor [T,k+1], log_condvar [T],
+    status [T]; orc also has gap [T,k] (float64, NaN padded)."""
+    T, k = orc["sel"].shape
+    assert gpu["sel"].shape == (T, k)
+    np.testing.assert_array_equal(gpu["status"], orc["status"])
+    n_match = n_decisive = 0
+    worst_fac = 0.0
+    worst_lcv = 0.0
+    mismatched = []
+    for t in range(T):
+        if orc["status"][t] >= 2:
+            continue
+        p = decisive_prefix(orc["gap"][t], thr)
+        # compare the decisive prefix; the step at p itself may go either way
+        if not np.array_equal(gpu["sel"][t, :p], orc["sel"][t, :p]):
+            raise AssertionError(f"column {t}: decisive selection differs\n gpu {gpu['sel'][t]}\n orc {orc['sel'][t]}"
+                                 f"\n gap {orc['gap'][t]}")
+        nsel = int(np.sum(orc["sel"][t] >= 0))
+        if p >= nsel:
+            n_decisive += 1
+        if np.array_equal(gpu["sel"][t], orc["sel"][t]):
+            n_match += 1
+            a = gpu["factor"][t, : nsel + 1]
+            b = orc["factor"][t, : nsel + 1]
+            e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+            worst_fac = max(worst_fac, e)
+            worst_lcv = max(worst_lcv, abs(float(gpu["log_condvar"][t]) - float(orc["log_condvar"][t])))
+        else:
+            mismatched.append(t)
+    assert worst_fac <= factor_rtol, f"factor column error {worst_fac:.3e} > {factor_rtol:.1e}"
+    assert worst_lcv <= logcv_atol, f"log condvar error {worst_lcv:.3e} > {logcv_atol:.1e}"
+    return {"columns": T, "identical": n_match, "fully_decisive": n_decisive, "worst_factor_rel": worst_fac,
+            "worst_logcv_abs": worst_lcv, "mismatched": mismatched}
+
+
+def kl_rel_error(S_gpu: float, S_orc: float, logdet: float) -> float:
+    """Relative error of KL = (S - logdet)/2 given the two data terms S."""
+    kl = 0.5 * (S_orc - logdet)
+    return abs(0.5 * (S_gpu - S_orc)) / abs(kl)
+
+
+def replay_check(gpu: dict, points, kernel, targets, pool, pool_len, k, cols, tau: float, factor_rtol: float):
+    """Replay the GPU's own selection of each column in ``cols`` in FP64.
+
+    Every GPU pick must be a valid candidate whose exact score (the decrease
+    of the target's conditional variance it brings, eq. obj_gp) falls short of
+    the best exact score by at most tau times the target's current
+    conditional variance -- i.e. each step loses at most a fraction tau of
+    the variance, so log Theta_ii|s moves by at most ~tau per step -- and the
+    GPU's factor column must equal eq. L_col on its own selected set.  Returns
+    the largest normalised shortfall seen and the worst factor error."""
+    import oracle
+
+    worst_short = 0.0
+    worst_fac = 0.0
+    for t in cols:
+        sel = gpu["sel"][t]
+        r = oracle.replay_one(points, kernel, int(targets[t]), pool[t, : pool_len[t]], k, sel)
+        assert r["status"] != 5, f"column {t}: a GPU pick is not a valid candidate"
+        n = int(np.sum(sel >= 0))
+        for s in range(n):
+            short = (r["best"][s] - r["pick"][s]) / r["target_var"][s]
+            worst_short = max(worst_short, short)
+            assert short <= tau, (f"column {t} step {s}: pick score {r['pick'][s]} vs best {r['best'][s]}, "
+                                  f"target variance {r['target_var'][s]}")
+        a = gpu["factor"][t, : n + 1]
+        b = r["factor"][: n + 1]
+        e = float(np.max(np.abs(a - b)) / np.max(np.abs(b)))
+        worst_fac = max(worst_fac, e)
+        assert e <= factor_rtol, f"column {t}: factor error {e:.3e} on its own selected set"
+    return worst_short, worst_fac

@@ -100,6 +100,25 @@ def test_selection_matches_brute_force(seed):
     assert math.exp(r["log_condvar"]) == pytest.approx(_cond_var(th, i, S), rel=1e-10)
 
 
+def test_replay_of_own_selection_is_exact():
+    """Replaying the oracle's own picks reproduces its scores and columns."""
+    w = inputs.workload_plain_fp64(n=300, seed=6)
+    r = oracle.select_and_factor(w.points, w.kernel, w.targets, w.pool, w.pool_len, 10)
+    for t in range(0, 280, 13):
+        p = w.pool[t, : w.pool_len[t]]
+        rp = oracle.replay_one(w.points, w.kernel, int(w.targets[t]), p, 10, r["sel"][t])
+        n = int(np.sum(r["sel"][t] >= 0))
+        np.testing.assert_array_equal(rp["pick"][:n], rp["best"][:n])
+        np.testing.assert_allclose(rp["factor"], r["factor"][t], rtol=1e-13, atol=0)
+        # forcing a different (valid) first pick lowers that step's score
+        if n >= 2:
+            forced = r["sel"][t].copy()
+            forced[0], forced[1] = forced[1], forced[0]
+            rq = oracle.replay_one(w.points, w.kernel, int(w.targets[t]), p, 10, forced)
+            assert rq["status"] != 5
+            assert rq["pick"][0] < rq["best"][0]
+
+
 def test_first_pick_is_nearest_and_prefix_consistent():
     w = inputs.workload_plain_fp64(n=400, seed=11)
     r16 = oracle.select_and_factor(w.points, w.kernel, w.targets, w.pool, w.pool_len, 16)
