@@ -30,6 +30,8 @@
  *        pool_len outside [0, pool_stride]); the column is left as for status 2
  *      4 (aggregated only) a pool index precedes a group member while factor
  *        values were requested
+ *      5 (aggregated only) the aggregated pattern exceeds the factor block
+ *        size; the selection outputs are valid, the columns are not written
  *  - No C++ exception crosses this boundary.
  */
 #ifndef CSEL_H
@@ -117,6 +119,96 @@ int csel_select_and_factor(const double *pts, int64_t n, int32_t dim, const csel
                            const int32_t *pool_len, int32_t pool_stride, int32_t k, int32_t precision,
                            int32_t *sel_idx, double *factor_val, double *log_condvar, float *top2_gap,
                            uint8_t *status, hipStream_t stream);
+
+/*
+ * csel_aggregated_workspace_size -- bytes of device workspace that
+ * csel_aggregated_select needs for these sizes (-1 with csel_last_error set if
+ * the sizes are not supported).  The workspace holds the two partial Cholesky
+ * factors of the groups in flight; its contents need no initialization and
+ * are scratch after the call.
+ */
+int64_t csel_aggregated_workspace_size(int64_t n_groups, int32_t pool_stride, int32_t max_members, int32_t k,
+                                       int32_t precision);
+
+/* Largest aggregated pattern |s_g| = members + selected for which
+ * csel_aggregated_select can build the member columns (status 5 beyond). */
+int32_t csel_aggregated_max_block(void);
+
+/*
+ * csel_aggregated_select -- multi-target greedy selection for groups of
+ * columns (supernodes) sharing one sparsity set, with the aggregated factor
+ * columns and/or GP posterior variances.
+ *
+ * For group g with targets T = members[group_ptr[g] .. group_ptr[g+1]) and
+ * candidates pool_idx[g*pool_stride + 0 .. pool_len[g]), k_g = min(k,
+ * pool_len[g]) points are selected one at a time, each maximizing the
+ * decrease of log det Theta_{TT | I} (D-optimal design, eq. greedy_mult):
+ * log Theta_{jj | I, T} - log Theta_{jj | I}, computed as the score
+ * 1 - var2_j / var1_j from two partial Cholesky factors -- one conditioned on
+ * the targets first and then on the selected points, one on the selected
+ * points only (Sec. 5.2; App. C.2).  Eligibility and ties as in
+ * csel_select_and_factor (both conditional variances above 1e-12 times the
+ * prior).
+ *
+ *   members      [sum m] int32 target ids, ascending within each group
+ *   group_ptr    [n_groups+1] int32 CSR offsets, 1 <= m_g <= max_members
+ *   max_members  bound on every m_g (groups above it get status 3)
+ *   pool_idx     [n_groups][pool_stride] int32 candidate ids, pool_len [n_groups]
+ *   k            0 <= k <= 256; pool_stride + max_members <= 4096
+ *   precision    CSEL_FP64, or CSEL_MIXED (FP32 covariance evaluation and
+ *                GEMVs, FP64 conditional variances and factor columns)
+ *   workspace    device scratch of csel_aggregated_workspace_size() bytes
+ * Outputs:
+ *   sel_idx      [n_groups][k] selected ids in selection order, -1 padded
+ *   top2_gap     [n_groups][k] relative top-two score gap per step (may be NULL)
+ *   group_logdet [n_groups] log det Theta_{TT | selected} tracked during the
+ *                selection; with adjacent groups this is the group's KL term
+ *                (eq. obj_mult) (may be NULL)
+ *   post_var     [sum m] Theta_qq | selected for every target: the posterior
+ *                variances of GP prediction at the targets given the selected
+ *                training points (Alg. infer_select) (may be NULL)
+ *   factor_val   (may be NULL) aggregated factor columns: member q gets
+ *                s_q = {j in sort(T u selected) : j >= q} and the eq. L_col
+ *                column on s_q, computed for the whole group from one reverse
+ *                Cholesky factorization of Theta over sort(T u selected) in
+ *                FP64 (App. A.4, eq. L_precision).  Requires every pool id to
+ *                exceed every member id of its group (status 4 otherwise).
+ *                Member a (0-based within its group of m_g members) owns the
+ *                slots [val_ptr[a], val_ptr[a+1]) of factor_rows (row ids,
+ *                ascending) and factor_val, which must hold m_g - a + k_g
+ *                entries; unused trailing slots get row -1, value 0.
+ *   member_log_condvar [sum m] log Theta_{qq | s_q \ q} (with factor_val)
+ *   status       [n_groups] per-group status: 0, 1 (stopped early), 2 (block
+ *                not positive definite), 3 (bad input), 4 (pool precedes a
+ *                member with factor output), 5 (pattern larger than
+ *                csel_aggregated_max_block(); selection outputs are valid)
+ */
+int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_groups,
+                           const int32_t *group_ptr, const int32_t *members, int32_t max_members,
+                           const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride, int32_t k,
+                           int32_t precision, void *workspace, int64_t workspace_bytes, int32_t *sel_idx,
+                           float *top2_gap, double *group_logdet, double *post_var, const int64_t *val_ptr,
+                           int32_t *factor_rows, double *factor_val, double *member_log_condvar, uint8_t *status,
+                           hipStream_t stream);
+
+/*
+ * csel_apply_factor -- product with a sparse lower-triangular factor L in CSC
+ * form, the way the factor is used once built (L L^T ~ Theta^{-1}; e.g. as a
+ * preconditioner, Sec. 6.3).
+ *
+ *   n          number of columns (= rows) of L
+ *   col_ptr    [n+1] int64 offsets into row_idx / val
+ *   row_idx    [nnz] int32 row of each entry; entries with a negative row (or
+ *              a row >= n) are skipped, so the padded [T][k+1] layout of
+ *              csel_select_and_factor can be passed with col_ptr[j] = j*(k+1)
+ *   val        [nnz] FP64 values
+ *   transpose  1: y = L^T x (per-column gather, deterministic)
+ *              0: y = L x (per-column scatter with FP64 atomics; the order of
+ *                 the additions, and so the last bits, may vary between runs)
+ *   x, y       [n] FP64; must not alias
+ */
+int csel_apply_factor(int64_t n, const int64_t *col_ptr, const int32_t *row_idx, const double *val,
+                      int32_t transpose, const double *x, double *y, hipStream_t stream);
 
 /*
  * csel_sum -- deterministic FP64 sum of x[0..n) into *out (device scalar).

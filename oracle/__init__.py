@@ -60,6 +60,9 @@ def _load():
     lib.orc_multi_one.argtypes = [_f64p, _c.c_int32] + kern + [_i32p, _c.c_int32, _i32p, _c.c_int32, _c.c_int32,
                                                               _i32p, _f64p, _f64p, _f64p, _f64p]
     lib.orc_multi_one.restype = _c.c_int
+    lib.orc_multi_replay_one.argtypes = [_f64p, _c.c_int32] + kern + [_i32p, _c.c_int32, _i32p, _c.c_int32,
+                                                                     _c.c_int32, _i32p, _f64p, _f64p, _f64p, _f64p]
+    lib.orc_multi_replay_one.restype = _c.c_int
     lib.orc_aggregated_one.argtypes = [_f64p, _c.c_int32] + kern + [_i32p, _c.c_int32, _i32p, _c.c_int32, _i32p,
                                                                    _f64p, _f64p, _u8p]
     lib.orc_aggregated_one.restype = _c.c_int64
@@ -187,6 +190,26 @@ def multi_one(x, kernel, members, pool, k: int) -> dict:
                                _p(sel, _i32p), _p(gap, _f64p), _p(ld, _f64p), _p(pv, _f64p), _p(v1, _f64p))
     return {"sel": sel[:k], "gap": gap[:k], "logdet": float(ld[0]), "post_var": pv, "var1_targets": v1,
             "status": int(st)}
+
+
+def multi_replay_one(x, kernel, members, pool, k: int, forced) -> dict:
+    """Replay a multi-target selection sequence in FP64: per step the best
+    valid score and the forced pick's score (1 - var2/var1), the log det of
+    the targets' conditional covariance and the posterior variances after the
+    forced sequence.  Status 5: a forced pick was not a valid candidate."""
+    x = _pts(x)
+    T = np.ascontiguousarray(members, dtype=np.int32)
+    pool = np.ascontiguousarray(pool, dtype=np.int32)
+    forced = np.ascontiguousarray(forced, dtype=np.int32)
+    m = len(T)
+    best = np.empty(max(k, 1), np.float64)
+    pick = np.empty(max(k, 1), np.float64)
+    ld = np.empty(1, np.float64)
+    pv = np.empty(m, np.float64)
+    st = _load().orc_multi_replay_one(_p(x, _f64p), x.shape[1], *_kargs(kernel), _p(T, _i32p), m, _p(pool, _i32p),
+                                      len(pool), k, _p(forced, _i32p), _p(best, _f64p), _p(pick, _f64p),
+                                      _p(ld, _f64p), _p(pv, _f64p))
+    return {"best": best[:k], "pick": pick[:k], "logdet": float(ld[0]), "post_var": pv, "status": int(st)}
 
 
 def aggregated_columns(x, kernel, members, sel) -> dict:

@@ -268,8 +268,9 @@ int orc_select_one(const double *x, int32_t d, int32_t two_nu, double ell, doubl
  *   post_var[m]         Theta_qq | sel by the direct formula of Alg. infer_select
  *   var1_tgt[m]         the factor-A target rows (same quantity, tracked)
  * Returns status (0, 1 early stop). */
-int orc_multi_select(const orc_cov *c, const int32_t *T, int32_t m, const int32_t *pool, int32_t C, int32_t k,
-                     int32_t *sel, double *gap, double *logdet, double *post_var, double *var1_tgt) {
+static int multi_select_impl(const orc_cov *c, const int32_t *T, int32_t m, const int32_t *pool, int32_t C,
+                             int32_t k, int32_t *sel, double *gap, double *logdet, double *post_var,
+                             double *var1_tgt, const int32_t *forced, double *best_out, double *pick_out) {
     int32_t R = C + m;
     int32_t kk = k < C ? k : C;
     int32_t wa = kk > 0 ? kk : 1, wb = m + kk;
@@ -313,9 +314,24 @@ int orc_multi_select(const orc_cov *c, const int32_t *T, int32_t m, const int32_
         for (int32_t j = 0; j < C; ++j) {
             if (taken[j] || !(var1[j] > 1e-12 * prior[j]) || !(var2[j] > 1e-12 * prior[j])) continue;
             ++nvalid;
+            /* conditioning on more points never raises a variance, so
+             * var2 <= var1 and the score is >= 0 in exact arithmetic;
+             * rounding below 0 is clamped (eq. greedy_mult) */
             double sc = 1.0 - var2[j] / var1[j];
+            if (sc < 0.0) sc = 0.0;
             if (sc > s1) { s2 = s1; s1 = sc; best = j; }
             else if (sc > s2) s2 = sc;
+        }
+        if (forced) {
+            /* replay: take the given pick if it is a valid candidate */
+            int32_t f = forced[t], fj = -1;
+            if (f < 0) break;
+            for (int32_t j = 0; j < C; ++j)
+                if (pool[j] == f && !taken[j] && var1[j] > 1e-12 * prior[j] && var2[j] > 1e-12 * prior[j]) fj = j;
+            if (fj < 0) { status = 5; break; }
+            best_out[t] = s1;
+            pick_out[t] = fmax(0.0, 1.0 - var2[fj] / var1[fj]);
+            best = fj;
         }
         if (nvalid == 0) { status = 1; break; }
         gap[t] = (nvalid == 1) ? 1.0 : (s1 == 0.0 ? 0.0 : (s1 - s2) / s1);
@@ -363,6 +379,27 @@ int orc_multi_select(const orc_cov *c, const int32_t *T, int32_t m, const int32_
     }
     free(A); free(B); free(var1); free(var2); free(prior); free(u1); free(u2); free(taken); free(row_id);
     return status;
+}
+
+int orc_multi_select(const orc_cov *c, const int32_t *T, int32_t m, const int32_t *pool, int32_t C, int32_t k,
+                     int32_t *sel, double *gap, double *logdet, double *post_var, double *var1_tgt) {
+    return multi_select_impl(c, T, m, pool, C, k, sel, gap, logdet, post_var, var1_tgt, NULL, NULL, NULL);
+}
+
+/* Replay of a given multi-target selection: per step the best valid score
+ * and the forced pick's score (1 - var2/var1, FP64); logdet and post_var as
+ * for the forced sequence.  Status 5: a forced pick was not valid. */
+int orc_multi_replay_one(const double *x, int32_t d, int32_t two_nu, double ell, double s2, double nugget,
+                         const int32_t *T, int32_t m, const int32_t *pool, int32_t C, int32_t k,
+                         const int32_t *forced, double *best_out, double *pick_out, double *logdet,
+                         double *post_var) {
+    orc_cov c = {x, d, two_nu, ell, s2, nugget};
+    int32_t *sel = (int32_t *)malloc(sizeof(int32_t) * (k > 0 ? k : 1));
+    double *gap = (double *)malloc(sizeof(double) * (k > 0 ? k : 1));
+    for (int32_t t = 0; t < k; ++t) { best_out[t] = NAN; pick_out[t] = NAN; }
+    int st = multi_select_impl(&c, T, m, pool, C, k, sel, gap, logdet, post_var, NULL, forced, best_out, pick_out);
+    free(sel); free(gap);
+    return st;
 }
 
 static int cmp_i32(const void *a, const void *b) {
@@ -447,16 +484,19 @@ int64_t orc_aggregated_one(const double *x, int32_t d, int32_t two_nu, double el
 /* ------------------------------------------------------------------------ */
 void orc_apply_factor(int64_t n, const int64_t *col_ptr, const int32_t *row_idx, const double *val, int32_t transpose,
                       const double *xin, double *y) {
+    /* entries whose row lies outside [0, n) are padding and are skipped */
     if (transpose) {
         for (int64_t j = 0; j < n; ++j) {
             double s = 0.0;
-            for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p) s += val[p] * xin[row_idx[p]];
+            for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p)
+                if (row_idx[p] >= 0 && row_idx[p] < n) s += val[p] * xin[row_idx[p]];
             y[j] = s;
         }
     } else {
         for (int64_t r = 0; r < n; ++r) y[r] = 0.0;
         for (int64_t j = 0; j < n; ++j)
-            for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p) y[row_idx[p]] += val[p] * xin[j];
+            for (int64_t p = col_ptr[j]; p < col_ptr[j + 1]; ++p)
+                if (row_idx[p] >= 0 && row_idx[p] < n) y[row_idx[p]] += val[p] * xin[j];
     }
 }
 

@@ -5,6 +5,8 @@ or a non-GPU tensor is an error.
 
 Entry points mirror include/csel.h:
     select_and_factor  -- greedy single-target selection + eq. L_col columns
+    aggregated_select  -- multi-target selection, aggregated columns, GP posterior variances
+    apply_factor       -- y = L^T x or y = L x with the sparse factor
     sum                -- deterministic FP64 sum (KL data term)
 """
 from __future__ import annotations
@@ -59,6 +61,15 @@ def load():
                                            _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp,
                                            _vp, _vp]
     lib.csel_select_and_factor.restype = ctypes.c_int
+    lib.csel_apply_factor.argtypes = [_c.c_int64, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp]
+    lib.csel_apply_factor.restype = ctypes.c_int
+    lib.csel_aggregated_workspace_size.argtypes = [_c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32]
+    lib.csel_aggregated_workspace_size.restype = ctypes.c_int64
+    lib.csel_aggregated_max_block.restype = ctypes.c_int32
+    lib.csel_aggregated_select.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64,
+                                           _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
+                                           _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_aggregated_select.restype = ctypes.c_int
     lib.csel_sum.argtypes = [_vp, _c.c_int64, _vp, _vp]
     lib.csel_sum.restype = ctypes.c_int
     _lib = lib
@@ -125,6 +136,95 @@ def select_and_factor(points, kernel, targets, pool, pool_len, k: int, precision
                                     _stream(stream))
     _check(rc)
     return out
+
+
+def aggregated_val_ptr(group_ptr, pool_len, k: int):
+    """Offsets of the aggregated member columns (layout glue): member a of a
+    group with m members and min(k, pool_len) selections owns m - a + that
+    many values, rows ascending."""
+    gp = group_ptr.to(torch.int64)
+    m = gp[1:] - gp[:-1]
+    ns = torch.clamp(pool_len.to(torch.int64), max=k)
+    g_of = torch.repeat_interleave(torch.arange(len(m), device=gp.device), m)
+    a = torch.arange(int(gp[-1].item()), device=gp.device) - gp[:-1][g_of]
+    sizes = m[g_of] - a + ns[g_of]
+    vp = torch.zeros(len(sizes) + 1, dtype=torch.int64, device=gp.device)
+    vp[1:] = torch.cumsum(sizes, 0)
+    return vp
+
+
+def aggregated_select(points, kernel, group_ptr, members, max_members: int, pool, pool_len, k: int,
+                      precision: str = "mixed", want_factor: bool = False, want_post_var: bool = False,
+                      want_gap: bool = False, out: dict | None = None, workspace=None, stream=None) -> dict:
+    """Multi-target (aggregated) greedy selection (csel_aggregated_select).
+
+    group_ptr [G+1] int32 CSR offsets into members [sum m] int32; pool [G,
+    stride] int32, pool_len [G] int32.  Returns GPU tensors: sel [G, k],
+    logdet [G], status [G]; with want_post_var post_var [sum m]; with
+    want_factor val_ptr, rows, vals, member_log_condvar; with want_gap gap."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    for t, nm in ((group_ptr, "group_ptr"), (members, "members"), (pool, "pool"), (pool_len, "pool_len")):
+        _dev(t, torch.int32, nm)
+    G = group_ptr.numel() - 1
+    stride = pool.shape[1] if pool.dim() == 2 else 0
+    dev = points.device
+    nm_total = members.numel()
+    if out is None:
+        out = {"sel": torch.empty((G, k), dtype=torch.int32, device=dev),
+               "logdet": torch.empty(G, dtype=torch.float64, device=dev),
+               "status": torch.empty(G, dtype=torch.uint8, device=dev)}
+        if want_gap:
+            out["gap"] = torch.empty((G, k), dtype=torch.float32, device=dev)
+        if want_post_var:
+            out["post_var"] = torch.empty(nm_total, dtype=torch.float64, device=dev)
+        if want_factor:
+            vp = aggregated_val_ptr(group_ptr, pool_len, k)
+            nnz = int(vp[-1].item())
+            out.update(val_ptr=vp, rows=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                       vals=torch.empty(max(nnz, 1), dtype=torch.float64, device=dev),
+                       member_log_condvar=torch.empty(nm_total, dtype=torch.float64, device=dev))
+    prec = _PREC[precision]
+    need = lib.csel_aggregated_workspace_size(G, stride, int(max_members), int(k), prec)
+    if need < 0:
+        _check(-1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    out["workspace"] = workspace
+    kp = kernel_struct(kernel)
+    rc = lib.csel_aggregated_select(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), G,
+                                    group_ptr.data_ptr(), members.data_ptr(), int(max_members), pool.data_ptr(),
+                                    pool_len.data_ptr(), stride, int(k), prec, workspace.data_ptr(),
+                                    workspace.numel(), _ptr(out["sel"]), _ptr(out.get("gap")),
+                                    _ptr(out.get("logdet")), _ptr(out.get("post_var")), _ptr(out.get("val_ptr")),
+                                    _ptr(out.get("rows")), _ptr(out.get("vals")),
+                                    _ptr(out.get("member_log_condvar")), _ptr(out["status"]), _stream(stream))
+    _check(rc)
+    return out
+
+
+def apply_factor(col_ptr, row_idx, val, x, transpose: bool, out=None, stream=None):
+    """y = L^T x (transpose) or y = L x for L in CSC form (csel_apply_factor)."""
+    lib = load()
+    _dev(col_ptr, torch.int64, "col_ptr")
+    _dev(row_idx, torch.int32, "row_idx")
+    _dev(val, torch.float64, "val")
+    _dev(x, torch.float64, "x")
+    n = col_ptr.numel() - 1
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=x.device)
+    _check(lib.csel_apply_factor(n, col_ptr.data_ptr(), row_idx.data_ptr(), val.data_ptr(), int(bool(transpose)),
+                                 x.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def single_target_csc(targets, sel, factor):
+    """CSC view of select_and_factor outputs for targets 0..n-1 in order:
+    column i holds [i, sel[i]...] with factor[i] (layout glue, no arithmetic)."""
+    T, k = sel.shape
+    rows = torch.cat([targets.view(T, 1), sel], dim=1).contiguous().view(-1)
+    col_ptr = torch.arange(T + 1, dtype=torch.int64, device=sel.device) * (k + 1)
+    return col_ptr, rows, factor.contiguous().view(-1)
 
 
 def sum(x, out=None, stream=None):

@@ -110,3 +110,105 @@ CSEL_API int csel_sum(const double* x, int64_t n, double* out, hipStream_t strea
     if (e != hipSuccess) return hip_fail(e, "sum launch");
     return CSEL_OK;
 }
+
+CSEL_API int csel_apply_factor(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val,
+                               int32_t transpose, const double* x, double* y, hipStream_t stream) {
+    g_err[0] = 0;
+    if (n < 0) return fail(CSEL_EINVAL, "n must be >= 0");
+    if (transpose != 0 && transpose != 1) return fail(CSEL_EINVAL, "transpose must be 0 or 1");
+    if (n == 0) return CSEL_OK;
+    if (!col_ptr || !x || !y) return fail(CSEL_EINVAL, "a required array is NULL");
+    if (x == y) return fail(CSEL_EINVAL, "x and y must not alias");
+    hipError_t e = csel::launch_apply(n, col_ptr, row_idx, val, transpose, x, y, stream);
+    if (e != hipSuccess) return hip_fail(e, "apply_factor launch");
+    return CSEL_OK;
+}
+
+namespace {
+constexpr int kAggMaxPool = 4096;
+constexpr int kAggMaxMembers = 256;
+constexpr int kAggMaxSelect = 256;
+
+int check_agg(int64_t n_groups, int32_t pool_stride, int32_t max_members, int32_t k, int32_t precision) {
+    if (n_groups < 0) return fail(CSEL_EINVAL, "n_groups must be >= 0");
+    if (pool_stride < 0 || pool_stride > kAggMaxPool)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [0, %d] (got %d)", kAggMaxPool, pool_stride);
+    if (max_members < 1 || max_members > kAggMaxMembers)
+        return fail(CSEL_EUNSUPPORTED, "max_members must be in [1, %d] (got %d)", kAggMaxMembers, max_members);
+    if (k < 0 || k > kAggMaxSelect) return fail(CSEL_EUNSUPPORTED, "k must be in [0, %d] (got %d)", kAggMaxSelect, k);
+    if (pool_stride + max_members > 4096)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride + max_members must be <= 4096");
+    if (precision != CSEL_FP64 && precision != CSEL_MIXED)
+        return fail(CSEL_EINVAL, "precision must be CSEL_FP64 or CSEL_MIXED");
+    return CSEL_OK;
+}
+}  // namespace
+
+CSEL_API int64_t csel_aggregated_workspace_size(int64_t n_groups, int32_t pool_stride, int32_t max_members, int32_t k,
+                                                int32_t precision) {
+    g_err[0] = 0;
+    if (check_agg(n_groups, pool_stride, max_members, k, precision)) return -1;
+    return csel::plan_aggregated(n_groups, pool_stride, max_members, k, precision).ws_bytes;
+}
+
+CSEL_API int32_t csel_aggregated_max_block(void) { return csel::agg_factor_max_m(); }
+
+CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                    int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
+                                    int32_t max_members, const int32_t* pool_idx, const int32_t* pool_len,
+                                    int32_t pool_stride, int32_t k, int32_t precision, void* workspace,
+                                    int64_t workspace_bytes, int32_t* sel_idx, float* top2_gap,
+                                    double* group_logdet, double* post_var, const int64_t* val_ptr,
+                                    int32_t* factor_rows, double* factor_val, double* member_log_condvar,
+                                    uint8_t* status, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    rc = check_agg(n_groups, pool_stride, max_members, k, precision);
+    if (rc) return rc;
+    if (n_groups == 0) return CSEL_OK;
+    const bool want_factor = factor_val != nullptr;
+    if (!pts || !group_ptr || !members || !pool_len || !status || (k > 0 && !sel_idx) ||
+        (pool_stride > 0 && !pool_idx))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    if (want_factor && (!val_ptr || !factor_rows))
+        return fail(CSEL_EINVAL, "factor output needs val_ptr, factor_rows and factor_val");
+    const csel::AggPlan pl = csel::plan_aggregated(n_groups, pool_stride, max_members, k, precision);
+    if (!workspace || workspace_bytes < pl.ws_bytes)
+        return fail(CSEL_EINVAL, "workspace must hold csel_aggregated_workspace_size() = %lld bytes",
+                    (long long)pl.ws_bytes);
+    csel::AggArgs a;
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.s2 = kernel->variance;
+    a.nugget = kernel->nugget;
+    a.n_groups = n_groups;
+    a.group_ptr = group_ptr;
+    a.members = members;
+    a.max_members = max_members;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    a.k = k;
+    a.later_only = want_factor ? 1 : 0;
+    a.ws = workspace;
+    a.slab_elems = pl.slab_elems;
+    a.rmax = pl.rmax;
+    a.sel = sel_idx;
+    a.gap = top2_gap;
+    a.logdet = group_logdet;
+    a.post_var = post_var;
+    a.status = status;
+    a.val_ptr = val_ptr;
+    a.fac_rows = factor_rows;
+    a.fac_val = factor_val;
+    a.member_logcv = member_log_condvar;
+    hipError_t e = csel::launch_aggregated(a, pl, precision, want_factor, stream);
+    if (e != hipSuccess) return hip_fail(e, "aggregated_select launch");
+    return CSEL_OK;
+}

@@ -1,0 +1,456 @@
+// aggregate.hip -- multi-target (aggregated / supernodal) greedy selection and
+// the aggregated factor columns.
+//
+// Selection (Sec. 5.2, eq. greedy_mult; App. C.2): for a group of targets T
+// and a candidate pool P, two partial Cholesky factors are kept over the rows
+// R = P u T:
+//   factor B conditions on the targets first (m columns, left-looking), then
+//            on every selected point: var2_j = Theta_jj | T, I
+//   factor A conditions on the selected points only: var1_j = Theta_jj | I
+// and each pick maximizes 1 - var2_j / var1_j, the monotone form of the
+// log-determinant decrease log var2 - log var1 of eq. greedy_mult.
+//
+// Schedule: one workgroup per group (grid-stride over groups).  Rows are
+// spread over the threads (row r = i*NT + tid, RPT rows per thread, static),
+// each thread keeping its rows' coordinates and FP64 var1/var2 in registers.
+// The factors live column-major in a per-workgroup slab of the workspace
+// (A[q*rmax + r], B[q*rmax + r]), so the per-pick GEMVs read coalesced
+// columns; for the group sizes of interest the slab stays in L2/MALL.
+// A pick is: per-thread top-two -> wave top-two (DPP) -> LDS -> workgroup
+// top-two; the winner's factor rows are staged in LDS; every thread then
+// evaluates Theta(row, winner), runs the two GEMVs and the FP64 downdates.
+//
+// Aggregated columns (Sec. 5.1; App. A.4, eq. L_precision): with
+// s_g = sort(T u selected), U = P chol(P Theta_sg P) P is upper triangular and
+// L = U^{-T}; member q's column is L[:, p_q], nonzero on the suffix of s_g
+// that starts at q.  A second kernel builds the reversed Theta_sg in packed
+// LDS (FP64), factors it right-looking (one barrier per column) and solves
+// one column per wavefront with readlane broadcasts.
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace csel {
+
+template <typename T>
+__device__ __forceinline__ T matern_any(int two_nu, T r, T c, T s2) {
+    if constexpr (sizeof(T) == 4) {
+        if (two_nu == 1) return matern_f32<1>(r, c, s2);
+        if (two_nu == 3) return matern_f32<3>(r, c, s2);
+        return matern_f32<5>(r, c, s2);
+    } else {
+        return matern_f64_rt(two_nu, r, c, s2);
+    }
+}
+
+constexpr int kAggMaxWaves = 16;
+
+template <typename T, int RPT>
+__global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
+    extern __shared__ __align__(16) unsigned char agg_smem[];
+    // LDS layout: wave top-two [16], winner scalars, winner A row [k], B row [mmax+k]
+    Top2* wtop = reinterpret_cast<Top2*>(agg_smem);
+    double* wsc = reinterpret_cast<double*>(agg_smem + sizeof(Top2) * kAggMaxWaves);  // var1, var2, x0..x2
+    int32_t* wid = reinterpret_cast<int32_t*>(wsc + 6);
+    T* rowA = reinterpret_cast<T*>(agg_smem + sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double));
+    T* rowB = rowA + p.k;
+
+    const int tid = threadIdx.x;
+    const int NT = blockDim.x;
+    const int lane = lane_id();
+    const int wave = tid >> 6;
+    const int nwaves = NT >> 6;
+    const int rmax = p.rmax;
+    T* slabA = reinterpret_cast<T*>(p.ws) + (int64_t)blockIdx.x * p.slab_elems;
+    T* slabB = slabA + (int64_t)p.k * rmax;
+    const T cnu = (T)p.c_nu, s2 = (T)p.s2;
+    const double prior = p.s2 + p.nugget;
+    const double thr = 1e-12 * prior;
+    const int dim = p.dim;
+
+    for (int64_t g = blockIdx.x; g < p.n_groups; g += gridDim.x) {
+        const int32_t b0 = p.group_ptr[g];
+        const int32_t m = p.group_ptr[g + 1] - b0;
+        const int32_t C = p.pool_len[g];
+        int32_t* sel_out = p.sel + g * p.k;
+        // ---- validate (uniform) ------------------------------------------
+        bool bad = m < 1 || m > p.max_members || C < 0 || C > p.stride;
+        const int R = bad ? 0 : C + m;
+        // stage my rows
+        int32_t rid[RPT];
+        double x0[RPT], x1[RPT], x2[RPT], v1[RPT], v2[RPT];
+        uint32_t live = 0;  // candidate rows not yet taken
+        bool my_bad = false;
+        int32_t my_max_member = -1;
+#pragma unroll
+        for (int i = 0; i < RPT; ++i) {
+            const int r = i * NT + tid;
+            rid[i] = -1;
+            x0[i] = x1[i] = x2[i] = 0.0;
+            v1[i] = v2[i] = prior;
+            if (r < R) {
+                const int32_t id = r < C ? p.pool[g * p.stride + r] : p.members[b0 + (r - C)];
+                if (id < 0 || (int64_t)id >= p.n) {
+                    my_bad = true;
+                } else {
+                    rid[i] = id;
+                    x0[i] = p.pts[(int64_t)id * dim];
+                    if (dim > 1) x1[i] = p.pts[(int64_t)id * dim + 1];
+                    if (dim > 2) x2[i] = p.pts[(int64_t)id * dim + 2];
+                    if (r < C) live |= 1u << i;
+                }
+            }
+        }
+        // later-only check needs the largest member id: members are few, every
+        // thread scans them (uniform result)
+        if (!bad && p.later_only) {
+            for (int q = 0; q < m; ++q) my_max_member = max(my_max_member, p.members[b0 + q]);
+        }
+        bool my_early = false;
+        if (p.later_only) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (((live >> i) & 1u) && rid[i] <= my_max_member) my_early = true;
+        }
+        bad = __syncthreads_or(bad || my_bad);
+        const bool early = __syncthreads_or(my_early);
+        if (bad || early) {
+            for (int t = tid; t < p.k; t += NT) {
+                sel_out[t] = -1;
+                if (p.gap) p.gap[g * p.k + t] = __builtin_nanf("");
+            }
+            if (tid == 0) {
+                if (p.logdet) p.logdet[g] = __builtin_nan("");
+                p.status[g] = bad ? 3 : 4;
+            }
+            if (p.post_var && !bad)
+                for (int q = tid; q < m; q += NT) p.post_var[b0 + q] = __builtin_nan("");
+            __syncthreads();
+            continue;
+        }
+
+        // ---- factor B over the targets (left-looking, Sec. 5.2) -------------
+        double ldT = 0.0;
+        for (int c = 0; c < m; ++c) {
+            const int prow = C + c;
+            // the previous column's writes (slab, LDS reads) complete first
+            __syncthreads();
+            // owner publishes the pivot's var2 and coordinates
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (i * NT + tid == prow) {
+                    wsc[1] = v2[i];
+                    wsc[2] = x0[i];
+                    wsc[3] = x1[i];
+                    wsc[4] = x2[i];
+                    wid[0] = rid[i];
+                }
+            for (int q = tid; q < c; q += NT) rowB[q] = slabB[(int64_t)q * rmax + prow];
+            __syncthreads();
+            const double piv = wsc[1];
+            const double y0 = wsc[2], y1 = wsc[3], y2 = wsc[4];
+            const int32_t idw = wid[0];
+            ldT += log(piv);
+            const double inv_sd = 1.0 / sqrt(piv);
+            const T inv_sd_t = (T)inv_sd;
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = i * NT + tid;
+                if (r < R) {
+                    const T e0 = (T)(x0[i] - y0), e1 = (T)(x1[i] - y1), e2 = (T)(x2[i] - y2);
+                    T acc = matern_any<T>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnu, s2);
+                    if (rid[i] == idw) acc += (T)p.nugget;
+                    for (int q = 0; q < c; ++q) acc -= slabB[(int64_t)q * rmax + r] * rowB[q];
+                    const T u = acc * inv_sd_t;
+                    slabB[(int64_t)c * rmax + r] = u;
+                    const double ud = (double)u;
+                    v2[i] -= ud * ud;
+                }
+            }
+        }
+
+        // ---- greedy multi-target selection ---------------------------------
+        const int kk = min(p.k, C);
+        double ld = 0.0;
+        int nsel = 0;
+        int st = 0;
+        for (int t = 0; t < kk; ++t) {
+            Top2 loc = {0ull, 0ull};
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                // conditioning on the targets never raises a variance (var2 <= var1),
+                // so the score is >= 0; rounding can push it below, and a negative
+                // double would compare as a huge key
+                if (((live >> i) & 1u) && v1[i] > thr && v2[i] > thr)
+                    insert(loc, make_key(fmax(0.0, 1.0 - v2[i] / v1[i]), i * NT + tid));
+            }
+            const Top2 wv = wave_top2(loc);
+            if (lane == 0) wtop[wave] = wv;
+            __syncthreads();  // also orders the previous pick's column writes before the staging below
+            Top2 w = wtop[0];
+            for (int q = 1; q < nwaves; ++q) w = merge(w, wtop[q]);
+            if (w.k1 == 0ull) {
+                st = 1;
+                break;
+            }
+            const int slot = key_slot(w.k1);
+#pragma unroll
+            for (int i = 0; i < RPT; ++i)
+                if (i * NT + tid == slot) {
+                    wsc[0] = v1[i];
+                    wsc[1] = v2[i];
+                    wsc[2] = x0[i];
+                    wsc[3] = x1[i];
+                    wsc[4] = x2[i];
+                    wid[0] = rid[i];
+                    live &= ~(1u << i);
+                }
+            for (int q = tid; q < t; q += NT) rowA[q] = slabA[(int64_t)q * rmax + slot];
+            for (int q = tid; q < m + t; q += NT) rowB[q] = slabB[(int64_t)q * rmax + slot];
+            __syncthreads();
+            const double w1 = wsc[0], w2 = wsc[1];
+            const double y0 = wsc[2], y1 = wsc[3], y2 = wsc[4];
+            const int32_t idw = wid[0];
+            ld += log(w2) - log(w1);
+            if (tid == 0) {
+                sel_out[t] = idw;
+                if (p.gap) {
+                    const double sa = key_score(w.k1), sb = key_score(w.k2);
+                    p.gap[g * p.k + t] = (w.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
+                }
+            }
+            const T inv1 = (T)(1.0 / sqrt(w1)), inv2 = (T)(1.0 / sqrt(w2));
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = i * NT + tid;
+                if (r < R) {
+                    const T e0 = (T)(x0[i] - y0), e1 = (T)(x1[i] - y1), e2 = (T)(x2[i] - y2);
+                    T th = matern_any<T>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnu, s2);
+                    if (rid[i] == idw) th += (T)p.nugget;
+                    T a = th, bb = th;
+                    for (int q = 0; q < t; ++q) a -= slabA[(int64_t)q * rmax + r] * rowA[q];
+                    for (int q = 0; q < m + t; ++q) bb -= slabB[(int64_t)q * rmax + r] * rowB[q];
+                    const T u1 = a * inv1, u2 = bb * inv2;
+                    slabA[(int64_t)t * rmax + r] = u1;
+                    slabB[(int64_t)(m + t) * rmax + r] = u2;
+                    const double d1 = (double)u1, d2 = (double)u2;
+                    v1[i] -= d1 * d1;
+                    v2[i] -= d2 * d2;
+                }
+            }
+            nsel = t + 1;
+        }
+        // ---- outputs ----------------------------------------------------------
+        for (int t = nsel + tid; t < p.k; t += NT) {
+            sel_out[t] = -1;
+            if (p.gap) p.gap[g * p.k + t] = __builtin_nanf("");
+        }
+        if (tid == 0) {
+            if (p.logdet) p.logdet[g] = ldT + ld;
+            p.status[g] = (uint8_t)st;
+        }
+        if (p.post_var) {
+#pragma unroll
+            for (int i = 0; i < RPT; ++i) {
+                const int r = i * NT + tid;
+                if (r >= C && r < R) p.post_var[b0 + (r - C)] = v1[i];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// aggregated factor columns (FP64)
+// ---------------------------------------------------------------------------
+constexpr int kAggFacMaxM = 96;  // |s_g| = m + selected
+constexpr int kAggFacThreads = 256;
+
+__host__ __device__ constexpr int tri(int i) { return i * (i + 1) / 2; }
+
+__global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
+    __shared__ double A[tri(kAggFacMaxM + 1)];  // reversed Theta_sg, packed lower, then its Cholesky factor
+    __shared__ int32_t sg[kAggFacMaxM];
+    __shared__ int32_t bad_piv;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid >> 6;
+    const int64_t g = blockIdx.x;
+    if (g >= p.n_groups) return;
+    if (p.status[g] >= 2) return;  // nothing to build (values were left untouched)
+    const int32_t b0 = p.group_ptr[g];
+    const int32_t m = p.group_ptr[g + 1] - b0;
+    const int32_t* sel = p.sel + g * p.k;
+    int nsel = 0;
+    while (nsel < p.k && sel[nsel] >= 0) ++nsel;
+    const int M = m + nsel;
+    if (M > kAggFacMaxM) {
+        if (tid == 0) p.status[g] = 5;
+        return;
+    }
+    // s_g sorted ascending: rank sort (ids are distinct)
+    for (int a = tid; a < M; a += kAggFacThreads) {
+        const int32_t v = a < m ? p.members[b0 + a] : sel[a - m];
+        int rank = 0;
+        for (int c = 0; c < M; ++c) {
+            const int32_t w = c < m ? p.members[b0 + c] : sel[c - m];
+            rank += (w < v);
+        }
+        sg[rank] = v;
+    }
+    if (tid == 0) bad_piv = 0;
+    __syncthreads();
+    // reversed order: index i' = M-1-i; packed lower entries (i', c') with c' <= i'
+    const double cnu = p.c_nu;
+    const int dim = p.dim;
+    for (int e = tid; e < tri(M); e += kAggFacThreads) {
+        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        while (tri(i + 1) <= e) ++i;
+        while (tri(i) > e) --i;
+        const int c = e - tri(i);
+        const int32_t a = sg[M - 1 - i], bq = sg[M - 1 - c];
+        double s = 0.0;
+        for (int d = 0; d < dim; ++d) {
+            const double df = p.pts[(int64_t)a * dim + d] - p.pts[(int64_t)bq * dim + d];
+            s += df * df;
+        }
+        A[e] = matern_f64_rt(p.two_nu, sqrt(s), cnu, p.s2) + (a == bq ? p.nugget : 0.0);
+    }
+    __syncthreads();
+    // right-looking Cholesky, one barrier per column: in step j the column j-1
+    // is scaled while the trailing block takes the rank-one update of column j
+    for (int j = 0; j <= M; ++j) {
+        if (j > 0) {
+            const double djm = sqrt(A[tri(j - 1) + j - 1]);
+            for (int i = j + tid; i < M; i += kAggFacThreads) A[tri(i) + j - 1] /= djm;
+        }
+        if (j < M) {
+            const double piv = A[tri(j) + j];
+            if (!(piv > 0.0)) {
+                if (tid == 0) bad_piv = 1;
+            } else {
+                const int nt = M - 1 - j;  // trailing size
+                for (int e = tid; e < tri(nt); e += kAggFacThreads) {
+                    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+                    while (tri(i + 1) <= e) ++i;
+                    while (tri(i) > e) --i;
+                    const int c = e - tri(i);
+                    const int ii = j + 1 + i, cc = j + 1 + c;
+                    A[tri(ii) + cc] -= A[tri(ii) + j] * A[tri(cc) + j] / piv;
+                }
+            }
+        }
+        __syncthreads();
+        if (bad_piv) break;
+    }
+    for (int j = tid; j < M; j += kAggFacThreads) A[tri(j) + j] = bad_piv ? 0.0 : sqrt(A[tri(j) + j]);
+    __syncthreads();
+    // member columns: member at sorted position pos -> reversed index jr = M-1-pos;
+    // z = R^{-T} e_jr (entries z_i, i <= jr): column-oriented back-substitution.
+    const int nw = kAggFacThreads / kWave;
+    for (int a = wave; a < m; a += nw) {
+        const int32_t q = p.members[b0 + a];
+        int pos = 0;
+        while (sg[pos] != q) ++pos;
+        const int jr = M - 1 - pos;
+        double* vals = p.fac_val + p.val_ptr[b0 + a];
+        int32_t* rows = p.fac_rows + p.val_ptr[b0 + a];
+        const int len = M - pos;
+        if (bad_piv) {
+            for (int l = lane; l < len; l += kWave) {
+                vals[l] = __builtin_nan("");
+                rows[l] = sg[pos + l];
+            }
+            if (lane == 0 && p.member_logcv) p.member_logcv[b0 + a] = __builtin_nan("");
+            continue;
+        }
+        // lanes own reversed indices i = lane and lane + 64 (M <= 128)
+        double acc0 = 0.0, acc1 = 0.0, z0 = 0.0, z1 = 0.0;
+        for (int l = jr; l >= 0; --l) {
+            const double rll = A[tri(l) + l];
+            double zl;
+            if (l == jr) {
+                zl = 1.0 / rll;
+            } else {
+                const double al = (l < kWave) ? bcast(acc0, l) : bcast(acc1, l - kWave);
+                zl = -al / rll;
+            }
+            if (lane == l) z0 = zl;
+            if (lane + kWave == l) z1 = zl;
+            // rows i < l take R[l][i] * z_l
+            if (lane < l) acc0 += A[tri(l) + lane] * zl;
+            if (lane + kWave < l) acc1 += A[tri(l) + lane + kWave] * zl;
+        }
+        // reversed index i -> original position M-1-i -> output slot (M-1-i) - pos
+        if (lane <= jr) {
+            const int o = (M - 1 - lane) - pos;
+            vals[o] = z0;
+            rows[o] = sg[M - 1 - lane];
+        }
+        if (lane + kWave <= jr) {
+            const int o = (M - 1 - lane - kWave) - pos;
+            vals[o] = z1;
+            rows[o] = sg[M - 1 - lane - kWave];
+        }
+        if (lane == 0 && p.member_logcv) p.member_logcv[b0 + a] = 2.0 * log(A[tri(jr) + jr]);
+        // pad the member's slot range if fewer points were selected than budgeted
+        const int64_t budget = p.val_ptr[b0 + a + 1] - p.val_ptr[b0 + a];
+        for (int64_t l = len + lane; l < budget; l += kWave) {
+            vals[l] = 0.0;
+            rows[l] = -1;
+        }
+    }
+    if (tid == 0 && bad_piv) p.status[g] = 2;
+}
+
+template <typename T, int RPT>
+static hipError_t launch_sel(const AggArgs& a, int nt, unsigned grid, size_t smem, hipStream_t s) {
+    auto kern = agg_select_kernel<T, RPT>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), smem, s, a);
+    return hipGetLastError();
+}
+
+AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision) {
+    AggPlan pl;
+    pl.rmax = stride + max_members;
+    pl.rpt = (pl.rmax + 1023) / 1024;
+    pl.rpt = pl.rpt <= 1 ? 1 : pl.rpt <= 2 ? 2 : 4;
+    pl.threads = std::min(1024, std::max(64, ((pl.rmax + pl.rpt - 1) / pl.rpt + 63) / 64 * 64));
+    const int64_t elem = precision == 0 ? 8 : 4;
+    pl.slab_elems = ((int64_t)k + max_members + k) * pl.rmax;
+    pl.slab_elems = (pl.slab_elems + 63) / 64 * 64;
+    // enough slots to fill the chip several times over, capped by the group count
+    pl.slots = (int)std::min<int64_t>(n_groups, 1024);
+    if (pl.slots < 1) pl.slots = 1;
+    pl.ws_bytes = pl.slab_elems * elem * pl.slots;
+    pl.smem = sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double) + ((size_t)k + max_members + k) * elem;
+    return pl;
+}
+
+hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s) {
+    if (a.n_groups == 0) return hipSuccess;
+    hipError_t e;
+    const unsigned grid = (unsigned)pl.slots;
+    if (precision == 0) {
+        e = pl.rpt == 1 ? launch_sel<double, 1>(a, pl.threads, grid, pl.smem, s)
+            : pl.rpt == 2 ? launch_sel<double, 2>(a, pl.threads, grid, pl.smem, s)
+                          : launch_sel<double, 4>(a, pl.threads, grid, pl.smem, s);
+    } else {
+        e = pl.rpt == 1 ? launch_sel<float, 1>(a, pl.threads, grid, pl.smem, s)
+            : pl.rpt == 2 ? launch_sel<float, 2>(a, pl.threads, grid, pl.smem, s)
+                          : launch_sel<float, 4>(a, pl.threads, grid, pl.smem, s);
+    }
+    if (e != hipSuccess) return e;
+    if (want_factor) {
+        hipLaunchKernelGGL(agg_factor_kernel, dim3((unsigned)a.n_groups), dim3(kAggFacThreads), 0, s, a);
+        e = hipGetLastError();
+    }
+    return e;
+}
+
+int agg_factor_max_m() { return kAggFacMaxM; }
+
+}  // namespace csel

@@ -102,7 +102,8 @@ __device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
 // ---------------------------------------------------------------------------
 // Selection keys: a non-negative FP64 score with its low kSlotBits mantissa
 // bits replaced by (kSlotMax - slot).  Larger key = larger score, then
-// smaller slot.  Any eligible candidate has key >= 1; 0 = none.
+// smaller slot.  Any eligible candidate has key >= 1; 0 = none.  The score
+// must be >= 0 (+0.0): the bits of a negative double compare as huge keys.
 // ---------------------------------------------------------------------------
 constexpr int kSlotBits = 13;
 constexpr uint64_t kSlotMask = (1ull << kSlotBits) - 1;

@@ -1,0 +1,211 @@
+"""GPU parity of csel_aggregated_select (multi-target selection, aggregated
+columns, GP posterior variances) and csel_apply_factor against the oracle."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from paper_2307_11648_amd import csel, inputs
+from parity import decisive_prefix
+
+pytestmark = pytest.mark.gpu
+
+THR = 1e-6
+# Mixed precision: a GPU pick may lose at most this much log-determinant
+# (log(1 - s_pick) - log(1 - s_best), exact FP64 scores on the GPU's own path)
+# per step; FP32 covariances perturb 1 - var2/var1 by about u32 * prior / var2.
+TAU_LOGDET = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    csel.load()
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+def run_gpu(w, k, precision, want_factor=True, want_post_var=True, max_members=None, pool=None, members=None):
+    mm = int(np.max(np.diff(w.group_ptr))) if max_members is None else max_members
+    out = csel.aggregated_select(_t(w.points, torch.float64), w.kernel, _t(w.group_ptr, torch.int32),
+                                 _t(w.members if members is None else members, torch.int32), mm,
+                                 _t(w.pool if pool is None else pool, torch.int32), _t(w.pool_len, torch.int32), k,
+                                 precision, want_factor=want_factor, want_post_var=want_post_var, want_gap=True)
+    torch.cuda.synchronize()
+    return {key: v.cpu().numpy() for key, v in out.items() if key != "workspace"}
+
+
+@pytest.fixture(scope="module")
+def agg_small():
+    return inputs.workload_aggregated(n=6000, seed=31, C=128, k=24, mmin=4, mmax=12)
+
+
+def _compare_groups(g, o, w, thr, check_values=True, vtol=1e-5):
+    G = len(w.group_ptr) - 1
+    np.testing.assert_array_equal(g["status"], o["status"])
+    same = 0
+    worst = 0.0
+    for gi in range(G):
+        if o["status"][gi] >= 2:
+            continue
+        p = decisive_prefix(o["gap"][gi], thr)
+        assert np.array_equal(g["sel"][gi, :p], o["sel"][gi, :p]), f"group {gi}: decisive picks differ"
+        if not np.array_equal(g["sel"][gi], o["sel"][gi]):
+            continue
+        same += 1
+        assert g["logdet"][gi] == pytest.approx(o["logdet"][gi], rel=1e-9 if thr == THR else 1e-3, abs=1e-9)
+        if check_values:
+            b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+            for a in range(b, e):
+                gv = g["vals"][g["val_ptr"][a]:g["val_ptr"][a + 1]]
+                ov = o["vals"][o["val_ptr"][a]:o["val_ptr"][a + 1]]
+                gr = g["rows"][g["val_ptr"][a]:g["val_ptr"][a + 1]]
+                orr = o["rows"][o["val_ptr"][a]:o["val_ptr"][a + 1]]
+                n = len(ov)
+                assert np.array_equal(gr[:n], orr)
+                err = float(np.max(np.abs(gv[:n] - ov)) / np.max(np.abs(ov)))
+                worst = max(worst, err)
+                assert err <= vtol, f"group {gi} member {a}: column error {err}"
+    return same, worst
+
+
+def test_aggregated_fp64_parity(agg_small):
+    print("case: aggregated fp64 n=6000 C=128 k=24 m=4..12", flush=True)
+    w = agg_small
+    g = run_gpu(w, w.k, "fp64")
+    o = oracle.aggregated_select(w.points, w.kernel, w.group_ptr, w.members, w.pool, w.pool_len, w.k,
+                                 want_factor=True, want_post_var=True)
+    same, worst = _compare_groups(g, o, w, THR)
+    G = len(w.group_ptr) - 1
+    print(f"fp64: {same} of {G} groups identical, worst column error {worst:.2e}")
+    assert same >= 0.97 * G
+    np.testing.assert_allclose(g["member_log_condvar"], o["member_log_condvar"], rtol=1e-8, atol=1e-9)
+    # telescoping (eq. obj_mult): member log condvars sum to the tracked log det
+    for gi in range(G):
+        b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+        assert np.sum(g["member_log_condvar"][b:e]) == pytest.approx(g["logdet"][gi], rel=1e-8, abs=1e-8)
+    np.testing.assert_allclose(g["post_var"], o["post_var"], rtol=1e-7, atol=1e-12)
+
+
+def test_aggregated_mixed_replay(agg_small):
+    print("case: aggregated mixed n=6000 C=128 k=24 m=4..12", flush=True)
+    w = agg_small
+    g = run_gpu(w, w.k, "mixed")
+    G = len(w.group_ptr) - 1
+    worst_loss = 0.0
+    worst_val = 0.0
+    for gi in range(G):
+        b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+        T = w.members[b:e]
+        pool = w.pool[gi, : w.pool_len[gi]]
+        r = oracle.multi_replay_one(w.points, w.kernel, T, pool, w.k, g["sel"][gi])
+        assert r["status"] != 5, f"group {gi}: a GPU pick is not a valid candidate"
+        n = int(np.sum(g["sel"][gi] >= 0))
+        for s in range(n):
+            loss = math.log1p(-r["pick"][s]) - math.log1p(-r["best"][s])
+            worst_loss = max(worst_loss, loss)
+            assert loss <= TAU_LOGDET, f"group {gi} step {s}: log det loss {loss}"
+        cols = oracle.aggregated_columns(w.points, w.kernel, T, g["sel"][gi])
+        for a in range(b, e):
+            gv = g["vals"][g["val_ptr"][a]:g["val_ptr"][a + 1]]
+            off = sum(len(T) - q + n for q in range(a - b))
+            ov = cols["vals"][off: off + len(T) - (a - b) + n]
+            err = float(np.max(np.abs(gv[: len(ov)] - ov)) / np.max(np.abs(ov)))
+            worst_val = max(worst_val, err)
+            assert err <= 1e-3
+        # mixed tracked log det vs FP64 log det on the same selection
+        assert g["logdet"][gi] == pytest.approx(r["logdet"], rel=1e-3, abs=1e-3)
+    print(f"mixed: worst per-step log det loss {worst_loss:.2e}, worst column error {worst_val:.2e}")
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_gp_posterior_variance(precision):
+    """GP prediction batches: training points uniform in [0,1]^2, 4 spatial
+    batches of 64 prediction points, Matern 5/2, l = 0.03, pools of the 512
+    training points nearest to any batch member, k = 64 (reduced sizes)."""
+    print(f"case: gp n_train=20000 m=64 C=512 k=64 {precision}", flush=True)
+    w = inputs.workload_gp(n_train=20000, n_pred=256, C=512, k=64, n_strips=2, per_strip=2)
+    g = run_gpu(w, w.k, precision, want_factor=False)
+    G = len(w.group_ptr) - 1
+    if precision == "fp64":
+        o = oracle.aggregated_select(w.points, w.kernel, w.group_ptr, w.members, w.pool, w.pool_len, w.k,
+                                     want_factor=False, want_post_var=True)
+        same, _ = _compare_groups(g, o, w, THR, check_values=False)
+        assert same >= G - 1
+        for gi in range(G):
+            if np.array_equal(g["sel"][gi], o["sel"][gi]):
+                b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+                np.testing.assert_allclose(g["post_var"][b:e], o["post_var"][b:e], rtol=1e-7, atol=1e-13)
+    else:
+        # 64 clustered targets under a smooth kernel drive var2 / prior to
+        # 1e-4..1e-5, where the FP32 absolute error u32 * prior * sqrt(m + t)
+        # becomes a 1e-2-level relative error of var2: the per-step log det
+        # loss and the posterior variances carry errors of that size in mixed
+        # precision (FP64 is exact, see the fp64 case).
+        tau = 5e-2
+        worst = worst_loss = 0.0
+        for gi in range(G):
+            b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+            r = oracle.multi_replay_one(w.points, w.kernel, w.members[b:e], w.pool[gi, : w.pool_len[gi]], w.k,
+                                        g["sel"][gi])
+            assert r["status"] != 5
+            n = int(np.sum(g["sel"][gi] >= 0))
+            for s in range(n):
+                loss = math.log1p(-r["pick"][s]) - math.log1p(-r["best"][s])
+                worst_loss = max(worst_loss, loss)
+                assert loss <= tau
+            err = np.max(np.abs(g["post_var"][b:e] - r["post_var"]) / r["post_var"])
+            worst = max(worst, float(err))
+        o = oracle.aggregated_select(w.points, w.kernel, w.group_ptr, w.members, w.pool, w.pool_len, w.k,
+                                     want_factor=False, want_post_var=True)
+        err_o = float(np.max(np.abs(g["post_var"] - o["post_var"]) / o["post_var"]))
+        print(f"mixed: worst per-step log det loss {worst_loss:.2e}; posterior-variance relative error "
+              f"{worst:.2e} on the GPU's selection, {err_o:.2e} against the FP64 oracle's own run")
+        assert worst <= tau
+
+
+def test_aggregated_status_codes(agg_small):
+    print("case: aggregated status codes", flush=True)
+    w = agg_small
+    # a pool that reaches before the group's last member -> status 4 with factor output
+    pool = w.pool.copy()
+    pool[0, 0] = w.members[w.group_ptr[0]]
+    g = run_gpu(w, w.k, "fp64", pool=pool)
+    assert g["status"][0] == 4 and np.all(g["sel"][0] == -1)
+    assert np.all(g["status"][1:] <= 1)
+    # the same pool without factor output is a valid multi-target problem
+    g2 = run_gpu(w, w.k, "fp64", pool=pool, want_factor=False)
+    assert g2["status"][0] in (0, 1)
+    # group larger than max_members -> status 3 for that group only
+    m = np.diff(w.group_ptr)
+    g3 = run_gpu(w, w.k, "fp64", max_members=int(m.min()))
+    assert np.all((g3["status"] == 3) == (m > m.min()))
+    # aggregated pattern beyond the block size -> status 5, selection still valid
+    w5 = inputs.workload_aggregated(n=4000, seed=5, C=128, k=80, mmin=20, mmax=24)
+    g5 = run_gpu(w5, 80, "fp64")
+    assert np.all(g5["status"][np.diff(w5.group_ptr) + np.minimum(80, w5.pool_len) > 96] == 5)
+
+
+def test_apply_factor():
+    print("case: apply_factor", flush=True)
+    w = inputs.workload_plain_fp64(n=2000, seed=8)
+    pts = _t(w.points, torch.float64)
+    out = csel.select_and_factor(pts, w.kernel, _t(w.targets, torch.int32), _t(w.pool, torch.int32),
+                                 _t(w.pool_len, torch.int32), 16, "fp64")
+    cp, rows, vals = csel.single_target_csc(_t(w.targets, torch.int32), out["sel"], out["factor"])
+    x = torch.from_numpy(np.random.default_rng(1).standard_normal(2000)).cuda()
+    ylt = csel.apply_factor(cp, rows, vals, x, True)
+    yl = csel.apply_factor(cp, rows, vals, x, False)
+    torch.cuda.synchronize()
+    cp_n, rows_n, vals_n = cp.cpu().numpy(), rows.cpu().numpy(), vals.cpu().numpy()
+    xn = x.cpu().numpy()
+    np.testing.assert_allclose(ylt.cpu().numpy(), oracle.apply_factor(cp_n, rows_n, vals_n, xn, True), rtol=1e-12,
+                               atol=1e-10)
+    np.testing.assert_allclose(yl.cpu().numpy(), oracle.apply_factor(cp_n, rows_n, vals_n, xn, False), rtol=1e-12,
+                               atol=1e-10)
+    # L^T x is deterministic
+    assert torch.equal(ylt, csel.apply_factor(cp, rows, vals, x, True))
