@@ -55,6 +55,29 @@ def column_work(C, k, dim, two_nu):
     return flops, byt
 
 
+def group_work(group_ptr, pool_len, k, dim, two_nu, want_factor):
+    """Algorithmic flops and bytes of one aggregated group (numpy arrays)."""
+    import numpy as np
+
+    m = np.diff(np.asarray(group_ptr, np.float64))
+    C = np.asarray(pool_len, np.float64)
+    kk = np.minimum(k, C)
+    R = C + m
+    fe = eval_flops(dim, two_nu)
+    # target conditioning: m left-looking columns over all rows
+    init = fe * R * m + 2.0 * R * m * (m - 1) / 2.0 + 2.0 * R * m
+    # picks: one evaluation, GEMV over the A (t) and B (m + t) columns, two FP64 downdates, score
+    picks = fe * R * kk + 2.0 * R * (kk * (kk - 1) / 2.0 + m * kk + kk * (kk - 1) / 2.0) + 4.0 * R * kk + 3.0 * C * kk
+    flops = init + picks
+    if want_factor:
+        M = m + kk
+        flops = flops + fe * M * (M + 1) / 2.0 + M ** 3 / 3.0 + m * M * M
+    byt = 8.0 + 4.0 * C + 4.0 * m + 4.0 * k + 8.0 + 1.0 + 8.0 * m
+    if want_factor:
+        byt = byt + 12.0 * (m * (m + 1) / 2.0 + m * kk) + 8.0 * m
+    return flops, byt
+
+
 def cpu_baseline(w, k, seconds, threads):
     """Time the FP64 oracle on a bounded seeded sample of the same columns."""
     import numpy as np
@@ -78,13 +101,114 @@ def cpu_baseline(w, k, seconds, threads):
                       f"{dt:.1f} s"}
 
 
+def cpu_baseline_groups(w, k, seconds, threads, want_factor, want_post_var):
+    """Time the FP64 oracle on a bounded seeded sample of the groups."""
+    import numpy as np
+
+    import oracle
+
+    rng = np.random.default_rng(12345)
+    G = len(w.group_ptr) - 1
+
+    def run(idx):
+        gp = np.zeros(len(idx) + 1, np.int32)
+        sizes = np.diff(w.group_ptr)[idx]
+        gp[1:] = np.cumsum(sizes)
+        mem = np.concatenate([w.members[w.group_ptr[g]:w.group_ptr[g + 1]] for g in idx])
+        t0 = time.perf_counter()
+        oracle.aggregated_select(w.points, w.kernel, gp, mem, w.pool[idx], w.pool_len[idx], k,
+                                 want_factor=want_factor, want_post_var=want_post_var, nthreads=threads)
+        return time.perf_counter() - t0, int(sizes.sum())
+
+    probe = np.sort(rng.choice(G, size=min(G, 64), replace=False))
+    dt, _ = run(probe)
+    m = int(min(G, max(len(probe), len(probe) * seconds / max(dt, 1e-6))))
+    idx = np.sort(rng.choice(G, size=m, replace=False))
+    dt, cols = run(idx)
+    return {"value": cols / dt, "unit": "columns/s", "cores": threads, "kind": "oracle",
+            "sample": f"{m} of {G} groups ({cols} member columns, seeded uniform sample), FP64 C oracle with "
+                      f"OpenMP over groups, {dt:.1f} s"}
+
+
+def bench_groups(args):
+    """Aggregated (supernodal) selection or GP prediction batches."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs
+
+    print("bench: building inputs", file=sys.stderr, flush=True)
+    if args.workload == "aggregated":
+        w = inputs.workload_aggregated(n=args.n or 1_000_000)
+        want_factor, want_post_var = True, False
+        desc = (f"aggregated selection, N={len(w.points)} uniform in [0,1]^2, Matern 1/2, l=0.02, supernodes of "
+                f"m uniform in 8..32, union pools of 512 later points, k=64, {args.precision}, member columns")
+    else:
+        w = inputs.workload_gp(n_train=args.n or 500_000)
+        want_factor, want_post_var = False, True
+        desc = (f"GP prediction, {w.meta['n_train']} training points uniform in [0,1]^2, 4096 prediction points "
+                f"in 64 batches of 64, Matern 5/2, l=0.03, pools of 2048, k=128, {args.precision}, "
+                f"posterior variances")
+    k = w.k
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    pts = t(w.points, torch.float64)
+    gp_t, mem_t = t(w.group_ptr, torch.int32), t(w.members, torch.int32)
+    pl, ln = t(w.pool, torch.int32), t(w.pool_len, torch.int32)
+    mm = int(np.max(np.diff(w.group_ptr)))
+    out = csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, args.precision,
+                                 want_factor=want_factor, want_post_var=want_post_var)
+    torch.cuda.synchronize()
+    ws = out["workspace"]
+
+    def step():
+        csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, args.precision,
+                               want_factor=want_factor, want_post_var=want_post_var, out=out, workspace=ws)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(args.steps)]
+    for i in range(args.steps):
+        ev[i][0].record()
+        step()
+        ev[i][1].record()
+    torch.cuda.synchronize()
+    times = [a.elapsed_time(b_) for a, b_ in ev]
+    ms = float(np.mean(times))
+    cols = len(w.members)
+    flops, byt = group_work(w.group_ptr, w.pool_len, k, w.points.shape[1], w.kernel.two_nu, want_factor)
+    achieved = float(np.sum(flops)) / (ms * 1e-3) / 1e12
+    st = out["status"].cpu().numpy()
+    res = {
+        "metric": METRIC, "value": cols / (ms * 1e-3), "unit": "columns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": desc, "groups": len(w.group_ptr) - 1, "columns": cols, "k": k,
+                   "status_counts": {int(v): int((st == v).sum()) for v in np.unique(st)}},
+        "roofline": {"bound": "alu", "kernel": "agg_select_kernel (+ agg_factor_kernel)", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": None, "kernel_ms": ms,
+                     "algorithmic_gflop_per_launch": float(np.sum(flops)) / 1e9,
+                     "algorithmic_mb_per_launch": float(np.sum(byt)) / 1e6},
+    }
+    if args.cpu_seconds > 0:
+        print("bench: cpu baseline", file=sys.stderr, flush=True)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        res["cpu_baseline"] = cpu_baseline_groups(w, k, args.cpu_seconds, threads, want_factor, want_post_var)
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=100_000)
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "aggregated", "gp"])
+    ap.add_argument("--n", type=int, default=0, help="number of points (0 = the workload's full size)")
+    ap.add_argument("--precision", default="", choices=["", "mixed", "fp64"],
+                    help="default: mixed, except fp64 for the GP workload (its conditional variances fall "
+                         "below the FP32 error floor)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
     ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
     args = ap.parse_args()
@@ -104,6 +228,11 @@ def main():
     from paper_2307_11648_amd import csel, inputs
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
+    if not args.precision:
+        args.precision = "fp64" if args.workload == "gp" else "mixed"
+    if args.workload != "plain":
+        return bench_groups(args)
+    args.n = args.n or 100_000
     print("bench: building inputs", file=sys.stderr, flush=True)
     w = inputs.workload_plain_batched(n=args.n)
     k = w.k
