@@ -211,6 +211,92 @@ int csel_apply_factor(int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
                       int32_t transpose, const double *x, double *y, hipStream_t stream);
 
 /*
+ * csel_select_and_factor_list -- csel_select_and_factor restricted to the
+ * columns col_list[0 .. *col_count) (device int32 list and count), e.g. the
+ * fallback columns reported by csel_screen.  Array arguments are indexed by
+ * column exactly as in csel_select_and_factor; only listed columns are
+ * written.  max_cols bounds *col_count (the launch covers max_cols columns,
+ * listed entries beyond *col_count are ignored), so the call needs no host
+ * synchronization.
+ */
+int csel_select_and_factor_list(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel,
+                                int64_t n_targets, const int32_t *targets, const int32_t *pool_idx,
+                                const int32_t *pool_len, int32_t pool_stride, int32_t k, int32_t precision,
+                                const int32_t *col_list, const int32_t *col_count, int64_t max_cols,
+                                int32_t *sel_idx, double *factor_val, double *log_condvar, float *top2_gap,
+                                uint8_t *status, hipStream_t stream);
+
+/*
+ * Learned candidate screen (not part of the paper).  An MLP scores every
+ * candidate of a column from 16 geometric features; the `keep` best are
+ * kept, and the exact greedy selection of csel_select_and_factor runs on the
+ * kept candidates.  The MLP is 16 -> 64 -> 64 -> 1 with ReLU, evaluated with
+ * BF16 inputs, weights and first-layer activations on MFMA, FP32
+ * accumulation and FP32 biases.  Parameters are one FP32 vector of
+ * csel_mlp_num_params() values, W1[16][64], b1[64], W2[64][64], b2[64],
+ * w3[64], b3, plus its BF16 copy (uint16 bit patterns, same indexing).
+ *
+ * Features of candidate j at pool slot s of target i (d = x_j - x_i, r = |d|,
+ * slot 0 nearest): log(r/r_0), s/C, K(r)/variance, r/length_scale,
+ * r_0/length_scale, cos(d, d_0), the smallest distance from x_j to one of the
+ * 8 nearest candidates over r, the fraction of those 8 that are closer than
+ * j within a 0.7-cosine cone, K(|x_j - x_{p0}|)/variance, the target-variance
+ * decrease j would bring after the nearest candidate is selected (eq.
+ * obj_gp), [s == 0], log(1+s)/log(1+C), and 4 zeros.
+ */
+int32_t csel_mlp_num_params(void);
+
+/* Features [n_targets][pool_stride][16] (FP32) of every pool slot < pool_len. */
+int csel_screen_features(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_targets,
+                         const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len,
+                         int32_t pool_stride, float *features, hipStream_t stream);
+
+/*
+ * csel_screen -- per column: features, MLP logits, the `keep` largest logits
+ * (ties to the smaller slot), written as candidate ids in slot (distance)
+ * order to kept_idx [n_targets][keep] (-1 padded), kept_len [n_targets].
+ * Columns with pool_len <= keep keep their whole pool.  fallback[c] = 1 when
+ * the dropped candidates' summed sigmoid(logit) (their expected number of
+ * selections) exceeds fallback_threshold; such columns should be selected on
+ * their full pool, and when fallback_list/fallback_count are given their
+ * indices are appended there (count reset by this call; list order is not
+ * deterministic).  fallback = 3 marks bad input.  logits [n_targets]
+ * [pool_stride] is optional.  pool_stride <= 512.
+ */
+int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_targets,
+                const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride,
+                const float *params, const uint16_t *params_bf16, int32_t keep, float fallback_threshold,
+                int32_t *kept_idx, int32_t *kept_len, uint8_t *fallback, float *logits, int32_t *fallback_list,
+                int32_t *fallback_count, hipStream_t stream);
+
+/* MLP logits [n_rows] of feature rows x [n_rows][16]. */
+int csel_mlp_forward(const float *params, const uint16_t *params_bf16, const float *x, int64_t n_rows,
+                     float *logits, hipStream_t stream);
+
+/* Workspace bytes for csel_mlp_grad. */
+int64_t csel_mlp_grad_workspace_size(int64_t n_rows);
+
+/*
+ * csel_mlp_grad -- mean weighted binary cross-entropy with logits over the
+ * rows (weight pos_weight on label 1, 1 on label 0) and its gradient with
+ * respect to the parameters: grad [csel_mlp_num_params() + 1], the last entry
+ * being the summed (not averaged) weighted loss.  Forward as in csel_screen;
+ * backward with BF16 MFMA operands and FP32 accumulation; per-wave partial
+ * gradients are summed in a fixed order (deterministic).
+ */
+int csel_mlp_grad(const float *params, const uint16_t *params_bf16, const float *x, const uint8_t *labels,
+                  int64_t n_rows, float pos_weight, void *workspace, int64_t workspace_bytes, float *grad,
+                  hipStream_t stream);
+
+/* One Adam step (Kingma & Ba) on the FP32 parameters, step counted from 1;
+ * m and v are the FP32 moment buffers; refreshes the BF16 copy. */
+int csel_mlp_adam(float *params, uint16_t *params_bf16, const float *grad, float *m, float *v, int32_t n_params,
+                  float lr, float beta1, float beta2, float eps, int32_t step, hipStream_t stream);
+
+/* BF16 copy (round to nearest even) of the FP32 parameters. */
+int csel_mlp_to_bf16(const float *params, uint16_t *params_bf16, int32_t n_params, hipStream_t stream);
+
+/*
  * csel_sum -- deterministic FP64 sum of x[0..n) into *out (device scalar).
  * Used for S = sum_i log Theta_{ii|s_i \ i}, the data term of the KL
  * (eq. obj_chol).  The summation order is fixed, so results are bitwise

@@ -1,0 +1,184 @@
+"""Oracle of the learned candidate screen: per-candidate features and the MLP.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).  Plain numpy, FP64.
+
+The screen is not part of the paper: it prunes a column's candidate pool to
+the `keep` candidates an MLP scores highest, before the exact greedy
+selection of Sec. 3.1 runs on the kept candidates.  Features describe a
+candidate j of target i (pool sorted by distance, slot s, nearest slot 0):
+
+  f0  log(r_s / r_0)                  f6  min_{l<8, l!=s} |x_j - x_l| / r_s
+  f1  s / C                           f7  #{l<8, l!=s : r_l < r_s, cos(d_s, d_l) > 0.7} / 8
+  f2  K(r_s) / var  (correlation)     f8  K(|x_j - x_{p0}|) / var
+  f3  r_s / length_scale              f9  step-1 score: the variance decrease of
+  f4  r_0 / length_scale                  the target from j after the nearest
+  f5  cos(d_s, d_0)                       candidate is selected (eq. obj_gp), / prior
+                                      f10 [s == 0]
+                                      f11 log(1 + s) / log(1 + C)
+  f12..f15 = 0
+with d_s = x_{p_s} - x_i, r_s = |d_s|, guarded against zero distances.
+
+MLP: 16 -> 64 -> 64 -> 1 with ReLU.  The GPU computes it with BF16 inputs,
+BF16 weights and BF16 first-layer activations (MFMA operands) and FP32
+accumulation; `mlp_forward(..., bf16=True)` evaluates the same rounded
+quantities in FP64 so the two sides differ only by accumulation order.
+Parameters are one FP32 vector: W1[16][64], b1[64], W2[64][64], b2[64],
+w3[64], b3 (5313 values).
+"""
+from __future__ import annotations
+
+import numpy as np
+
+F = 16
+H = 64
+N_PARAMS = F * H + H + H * H + H + H + 1
+OFF_W1, OFF_B1 = 0, F * H
+OFF_W2 = OFF_B1 + H
+OFF_B2 = OFF_W2 + H * H
+OFF_W3 = OFF_B2 + H
+OFF_B3 = OFF_W3 + H
+
+
+def unpack(p):
+    p = np.asarray(p, np.float64)
+    W1 = p[OFF_W1:OFF_B1].reshape(F, H)
+    b1 = p[OFF_B1:OFF_W2]
+    W2 = p[OFF_W2:OFF_B2].reshape(H, H)
+    b2 = p[OFF_B2:OFF_W3]
+    w3 = p[OFF_W3:OFF_B3]
+    b3 = p[OFF_B3]
+    return W1, b1, W2, b2, w3, b3
+
+
+def bf16_round(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    a = np.asarray(x, np.float32)
+    b = a.view(np.uint32).astype(np.uint64)
+    b = (b + 0x7FFF + ((b >> 16) & 1)) & 0xFFFF0000
+    return b.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def matern_corr(two_nu, a):
+    if two_nu == 1:
+        return np.exp(-a)
+    if two_nu == 3:
+        return (1 + a) * np.exp(-a)
+    return (1 + a + a * a / 3.0) * np.exp(-a)
+
+
+def features(x, kernel, target, pool):
+    """Features [C, 16] (FP64) of the candidates `pool` (sorted by distance)."""
+    x = np.asarray(x, np.float64)
+    pool = np.asarray(pool)
+    C = len(pool)
+    out = np.zeros((C, F))
+    if C == 0:
+        return out
+    ell = float(kernel.length_scale)
+    c = np.sqrt(float(kernel.two_nu)) / ell
+    tiny = 1e-9 * ell
+    a_diag = 1.0 + float(kernel.nugget) / float(kernel.variance)
+    xi = x[target]
+    d = x[pool] - xi
+    r = np.sqrt(np.sum(d * d, axis=1))
+    r0 = max(r[0], tiny)
+    rs = np.maximum(r, tiny)
+    s = np.arange(C)
+    out[:, 0] = np.log(rs / r0)
+    out[:, 1] = s / C
+    rho_i = matern_corr(kernel.two_nu, c * r)
+    out[:, 2] = rho_i
+    out[:, 3] = r / ell
+    out[:, 4] = r[0] / ell
+    cos0 = (d @ d[0]) / (rs * r0)
+    out[:, 5] = np.where(r > 0, cos0, 1.0)
+    near = min(8, C)
+    for j in range(C):
+        best = np.inf
+        cnt = 0
+        for l in range(near):
+            if l == j:
+                continue
+            dl = np.sqrt(np.sum((x[pool[j]] - x[pool[l]]) ** 2))
+            best = min(best, dl / rs[j])
+            if r[l] < r[j] and (d[j] @ d[l]) / (rs[j] * max(r[l], tiny)) > 0.7:
+                cnt += 1
+        out[j, 6] = best if np.isfinite(best) else 0.0
+        out[j, 7] = cnt / 8.0
+    dj0 = np.sqrt(np.sum((x[pool] - x[pool[0]]) ** 2, axis=1))
+    rho_j0 = matern_corr(kernel.two_nu, c * dj0)
+    rho_j0[0] = a_diag
+    out[:, 8] = matern_corr(kernel.two_nu, c * dj0)
+    cov1 = rho_i - rho_i[0] * rho_j0 / a_diag
+    var1 = a_diag - rho_j0 * rho_j0 / a_diag
+    f9 = np.where(var1 > 1e-12 * a_diag, cov1 * cov1 / np.maximum(var1, 1e-300) / a_diag, 0.0)
+    f9[0] = 1.0
+    out[:, 9] = f9
+    out[0, 10] = 1.0
+    out[:, 11] = np.log1p(s) / np.log1p(C)
+    return out
+
+
+def mlp_forward(X, p, bf16=True):
+    """Logits [N] and the intermediate activations (FP64)."""
+    W1, b1, W2, b2, w3, b3 = unpack(p)
+    X = np.asarray(X, np.float64)
+    if bf16:
+        X, W1, W2, w3 = bf16_round(X), bf16_round(W1), bf16_round(W2), bf16_round(w3)
+    Z1 = X @ W1 + b1
+    H1 = np.maximum(Z1, 0.0)
+    H1q = bf16_round(H1) if bf16 else H1
+    Z2 = H1q @ W2 + b2
+    H2 = np.maximum(Z2, 0.0)
+    z = H2 @ w3 + b3
+    return z, {"X": X, "W1": W1, "W2": W2, "w3": w3, "H1": H1, "H1q": H1q, "H2": H2}
+
+
+def bce_loss_and_grad(X, y, p, pos_weight=1.0, bf16=True):
+    """Mean weighted BCE-with-logits over the rows and its gradient with
+    respect to the FP32 parameter vector (backpropagated through the same
+    rounded forward quantities)."""
+    y = np.asarray(y, np.float64)
+    z, a = mlp_forward(X, p, bf16)
+    N = len(y)
+    wgt = np.where(y > 0.5, pos_weight, 1.0)
+    # log(1 + exp(-|z|)) form of the BCE
+    loss = wgt * (np.maximum(z, 0) - z * y + np.log1p(np.exp(-np.abs(z))))
+    sig = 1.0 / (1.0 + np.exp(-z))
+    dz = wgt * (sig - y) / N
+    g = np.zeros(N_PARAMS)
+    H2, H1q, H1 = a["H2"], a["H1q"], a["H1"]
+    g[OFF_W3:OFF_B3] = H2.T @ dz
+    g[OFF_B3] = dz.sum()
+    dH2 = np.outer(dz, a["w3"]) * (H2 > 0)
+    g[OFF_W2:OFF_B2] = (H1q.T @ dH2).ravel()
+    g[OFF_B2:OFF_W3] = dH2.sum(axis=0)
+    dH1 = (dH2 @ a["W2"].T) * (H1 > 0)
+    g[OFF_W1:OFF_B1] = (a["X"].T @ dH1).ravel()
+    g[OFF_B1:OFF_W2] = dH1.sum(axis=0)
+    return float(loss.sum() / N), g
+
+
+def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba) in FP64; returns new p, m, v."""
+    m = beta1 * m + (1 - beta1) * g
+    v = beta2 * v + (1 - beta2) * g * g
+    mh = m / (1 - beta1 ** step)
+    vh = v / (1 - beta2 ** step)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def screen_keep(logits, pool_len, keep, fallback_threshold=0.5):
+    """Kept slots (ascending) of one column: the `keep` largest logits, ties to
+    the smaller slot; and the fallback flag: the expected number of true
+    selections among the dropped candidates, sum sigmoid(logit), exceeds the
+    threshold."""
+    z = np.asarray(logits[:pool_len], np.float64)
+    C = len(z)
+    if C <= keep:
+        return np.arange(C), False
+    order = sorted(range(C), key=lambda s: (-z[s], s))
+    kept = np.sort(np.array(order[:keep]))
+    dropped = np.array(order[keep:])
+    fb = float(np.sum(1.0 / (1.0 + np.exp(-z[dropped])))) > fallback_threshold
+    return kept, fb

@@ -25,7 +25,7 @@ GEO_LIB = os.path.join(PKG, "inputs", "libcsel_geometry.so")
 HIP_UNITS = [("abi.cpp", []), ("select.hip", [])] + [
     ("select_inst.hip", [f"-DCSEL_SEL_T={t}", f"-DCSEL_SEL_NU={nu}"])
     for t in ("float", "double") for nu in (1, 3, 5)
-] + [(s, []) for s in ("aggregate.hip", "apply.hip", "mlp.hip")]
+] + [(s, []) for s in ("aggregate.hip", "apply.hip", "screen.hip")]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

@@ -70,6 +70,29 @@ def load():
                                            _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                            _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.csel_aggregated_select.restype = ctypes.c_int
+    lib.csel_select_and_factor_list.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams),
+                                                _c.c_int64, _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
+                                                _vp, _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_select_and_factor_list.restype = ctypes.c_int
+    lib.csel_mlp_num_params.restype = ctypes.c_int32
+    lib.csel_screen_features.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64,
+                                         _vp, _vp, _vp, _c.c_int32, _vp, _vp]
+    lib.csel_screen_features.restype = ctypes.c_int
+    lib.csel_screen.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64, _vp, _vp,
+                                _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_float, _vp, _vp, _vp, _vp, _vp, _vp,
+                                _vp]
+    lib.csel_screen.restype = ctypes.c_int
+    lib.csel_mlp_forward.argtypes = [_vp, _vp, _vp, _c.c_int64, _vp, _vp]
+    lib.csel_mlp_forward.restype = ctypes.c_int
+    lib.csel_mlp_grad_workspace_size.argtypes = [_c.c_int64]
+    lib.csel_mlp_grad_workspace_size.restype = ctypes.c_int64
+    lib.csel_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_float, _vp, _c.c_int64, _vp, _vp]
+    lib.csel_mlp_grad.restype = ctypes.c_int
+    lib.csel_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, _c.c_int32, _c.c_float, _c.c_float, _c.c_float,
+                                  _c.c_float, _c.c_int32, _vp]
+    lib.csel_mlp_adam.restype = ctypes.c_int
+    lib.csel_mlp_to_bf16.argtypes = [_vp, _vp, _c.c_int32, _vp]
+    lib.csel_mlp_to_bf16.restype = ctypes.c_int
     lib.csel_sum.argtypes = [_vp, _c.c_int64, _vp, _vp]
     lib.csel_sum.restype = ctypes.c_int
     _lib = lib
@@ -136,6 +159,116 @@ def select_and_factor(points, kernel, targets, pool, pool_len, k: int, precision
                                     _stream(stream))
     _check(rc)
     return out
+
+
+def select_and_factor_list(points, kernel, targets, pool, pool_len, k: int, precision: str, col_list, col_count,
+                           max_cols: int, out: dict, stream=None) -> dict:
+    """csel_select_and_factor on the listed columns only, writing into `out`
+    (the dict returned by select_and_factor for the same targets)."""
+    lib = load()
+    _dev(col_list, torch.int32, "col_list")
+    _dev(col_count, torch.int32, "col_count")
+    T = targets.shape[0]
+    stride = pool.shape[1] if pool.dim() == 2 else 0
+    kp = kernel_struct(kernel)
+    rc = lib.csel_select_and_factor_list(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), T,
+                                         targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride, int(k),
+                                         _PREC[precision], col_list.data_ptr(), col_count.data_ptr(), int(max_cols),
+                                         _ptr(out["sel"]), _ptr(out["factor"]), _ptr(out.get("log_condvar")),
+                                         _ptr(out.get("gap")), _ptr(out["status"]), _stream(stream))
+    _check(rc)
+    return out
+
+
+# --------------------------------------------------------------------------
+# learned screen
+# --------------------------------------------------------------------------
+def mlp_num_params() -> int:
+    return int(load().csel_mlp_num_params())
+
+
+def mlp_to_bf16(params, out=None, stream=None):
+    """BF16 copy (as int16 bit patterns) of FP32 parameters."""
+    lib = load()
+    _dev(params, torch.float32, "params")
+    if out is None:
+        out = torch.empty(params.numel(), dtype=torch.int16, device=params.device)
+    _check(lib.csel_mlp_to_bf16(params.data_ptr(), out.data_ptr(), params.numel(), _stream(stream)))
+    return out
+
+
+def screen_features(points, kernel, targets, pool, pool_len, stream=None):
+    """Features [T, stride, 16] float32 of every pool slot (zeros past pool_len)."""
+    lib = load()
+    T = targets.shape[0]
+    stride = pool.shape[1]
+    feats = torch.zeros((T, stride, 16), dtype=torch.float32, device=points.device)
+    kp = kernel_struct(kernel)
+    _check(lib.csel_screen_features(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), T,
+                                    targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride,
+                                    feats.data_ptr(), _stream(stream)))
+    return feats
+
+
+def screen(points, kernel, targets, pool, pool_len, params, params_bf16, keep: int, fallback_threshold=0.5,
+           want_logits=False, out=None, stream=None) -> dict:
+    """csel_screen: kept [T, keep] ids in distance order, kept_len [T],
+    fallback [T] u8, fallback_list [T] int32 with fallback_count [1]."""
+    lib = load()
+    _dev(params, torch.float32, "params")
+    T = targets.shape[0]
+    stride = pool.shape[1]
+    dev = points.device
+    if out is None:
+        out = {"kept": torch.empty((T, keep), dtype=torch.int32, device=dev),
+               "kept_len": torch.empty(T, dtype=torch.int32, device=dev),
+               "fallback": torch.empty(T, dtype=torch.uint8, device=dev),
+               "fallback_list": torch.empty(max(T, 1), dtype=torch.int32, device=dev),
+               "fallback_count": torch.empty(1, dtype=torch.int32, device=dev)}
+        if want_logits:
+            out["logits"] = torch.zeros((T, stride), dtype=torch.float32, device=dev)
+    kp = kernel_struct(kernel)
+    _check(lib.csel_screen(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), T,
+                           targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride, params.data_ptr(),
+                           params_bf16.data_ptr(), int(keep), float(fallback_threshold), out["kept"].data_ptr(),
+                           out["kept_len"].data_ptr(), out["fallback"].data_ptr(), _ptr(out.get("logits")),
+                           out["fallback_list"].data_ptr(), out["fallback_count"].data_ptr(), _stream(stream)))
+    return out
+
+
+def mlp_forward(params, params_bf16, x, out=None, stream=None):
+    lib = load()
+    _dev(x, torch.float32, "x")
+    n = x.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float32, device=x.device)
+    _check(lib.csel_mlp_forward(params.data_ptr(), params_bf16.data_ptr(), x.data_ptr(), n, out.data_ptr(),
+                                _stream(stream)))
+    return out
+
+
+def mlp_grad(params, params_bf16, x, labels, pos_weight: float, grad=None, workspace=None, stream=None):
+    """Gradient [P+1] (last = summed weighted loss) of the mean weighted BCE."""
+    lib = load()
+    _dev(x, torch.float32, "x")
+    _dev(labels, torch.uint8, "labels")
+    n = x.shape[0]
+    need = lib.csel_mlp_grad_workspace_size(n)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 4), dtype=torch.uint8, device=x.device)
+    if grad is None:
+        grad = torch.empty(mlp_num_params() + 1, dtype=torch.float32, device=x.device)
+    _check(lib.csel_mlp_grad(params.data_ptr(), params_bf16.data_ptr(), x.data_ptr(), labels.data_ptr(), n,
+                             float(pos_weight), workspace.data_ptr(), workspace.numel(), grad.data_ptr(),
+                             _stream(stream)))
+    return grad, workspace
+
+
+def mlp_adam(params, params_bf16, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+    lib = load()
+    _check(lib.csel_mlp_adam(params.data_ptr(), params_bf16.data_ptr(), grad.data_ptr(), m.data_ptr(),
+                             v.data_ptr(), params.numel(), float(lr), float(beta1), float(beta2), float(eps),
+                             int(step), _stream(stream)))
 
 
 def aggregated_val_ptr(group_ptr, pool_len, k: int):

@@ -95,6 +95,9 @@ CSEL_API int csel_select_and_factor(const double* pts, int64_t n, int32_t dim, c
     a.logcv = log_condvar;
     a.gap = top2_gap;
     a.status = status;
+    a.col_list = nullptr;
+    a.col_count = nullptr;
+    a.n_waves = n_targets;
     const int rpl = pool_stride <= 64 ? 1 : pool_stride <= 128 ? 2 : pool_stride <= 256 ? 4 : 8;
     const int kmax = k <= 16 ? 16 : 32;
     hipError_t e = csel::launch_select_factor(a, precision, rpl, kmax, stream);
@@ -210,5 +213,226 @@ CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, c
     a.member_logcv = member_log_condvar;
     hipError_t e = csel::launch_aggregated(a, pl, precision, want_factor, stream);
     if (e != hipSuccess) return hip_fail(e, "aggregated_select launch");
+    return CSEL_OK;
+}
+
+CSEL_API int csel_select_and_factor_list(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                         int64_t n_targets, const int32_t* targets, const int32_t* pool_idx,
+                                         const int32_t* pool_len, int32_t pool_stride, int32_t k, int32_t precision,
+                                         const int32_t* col_list, const int32_t* col_count, int64_t max_cols,
+                                         int32_t* sel_idx, double* factor_val, double* log_condvar,
+                                         float* top2_gap, uint8_t* status, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_targets < 0 || max_cols < 0) return fail(CSEL_EINVAL, "n_targets and max_cols must be >= 0");
+    if (pool_stride < 0 || pool_stride > kMaxPool)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [0, %d] (got %d)", kMaxPool, pool_stride);
+    if (k < 0 || k > kMaxSelect) return fail(CSEL_EUNSUPPORTED, "k must be in [0, %d] (got %d)", kMaxSelect, k);
+    if (precision != CSEL_FP64 && precision != CSEL_MIXED)
+        return fail(CSEL_EINVAL, "precision must be CSEL_FP64 or CSEL_MIXED");
+    if (n_targets == 0 || max_cols == 0) return CSEL_OK;
+    if (!col_list || !col_count) return fail(CSEL_EINVAL, "col_list and col_count are required");
+    if (!pts || !targets || !pool_len || !status || !factor_val || (k > 0 && !sel_idx) ||
+        (pool_stride > 0 && !pool_idx))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    csel::SelectArgs a;
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.s2 = kernel->variance;
+    a.nugget = kernel->nugget;
+    a.n_targets = n_targets;
+    a.targets = targets;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    a.k = k;
+    a.sel = sel_idx;
+    a.fac = factor_val;
+    a.logcv = log_condvar;
+    a.gap = top2_gap;
+    a.status = status;
+    a.col_list = col_list;
+    a.col_count = col_count;
+    const int rpl = pool_stride <= 64 ? 1 : pool_stride <= 128 ? 2 : pool_stride <= 256 ? 4 : 8;
+    const int kmax = k <= 16 ? 16 : 32;
+    // the grid covers max_cols list entries; waves beyond *col_count exit at once
+    a.n_waves = max_cols;
+    hipError_t e = csel::launch_select_factor(a, precision, rpl, kmax, stream);
+    if (e != hipSuccess) return hip_fail(e, "select_and_factor_list launch");
+    return CSEL_OK;
+}
+
+namespace {
+constexpr int kScreenMaxPool = 512;
+}
+
+static int screen_common(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel, int64_t n_targets,
+                         const int32_t* targets, const int32_t* pool_idx, const int32_t* pool_len,
+                         int32_t pool_stride, csel::ScreenArgs& a) {
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_targets < 0) return fail(CSEL_EINVAL, "n_targets must be >= 0");
+    if (pool_stride < 1 || pool_stride > kScreenMaxPool)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [1, %d] (got %d)", kScreenMaxPool, pool_stride);
+    if (n_targets > 0 && (!pts || !targets || !pool_idx || !pool_len))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    a = csel::ScreenArgs{};
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.s2 = kernel->variance;
+    a.nugget = kernel->nugget;
+    a.ell = kernel->length_scale;
+    a.n_targets = n_targets;
+    a.targets = targets;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    return CSEL_OK;
+}
+
+static int screen_rpl(int32_t stride) { return stride <= 64 ? 1 : stride <= 128 ? 2 : stride <= 256 ? 4 : 8; }
+
+CSEL_API int32_t csel_mlp_num_params(void) { return csel::mlp_nparams(); }
+
+CSEL_API int csel_screen_features(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                  int64_t n_targets, const int32_t* targets, const int32_t* pool_idx,
+                                  const int32_t* pool_len, int32_t pool_stride, float* features,
+                                  hipStream_t stream) {
+    g_err[0] = 0;
+    csel::ScreenArgs a;
+    int rc = screen_common(pts, n, dim, kernel, n_targets, targets, pool_idx, pool_len, pool_stride, a);
+    if (rc) return rc;
+    if (n_targets == 0) return CSEL_OK;
+    if (!features) return fail(CSEL_EINVAL, "features is NULL");
+    a.mode = 1;
+    a.feats = features;
+    a.keep = 1;
+    a.kept = nullptr;
+    a.kept_len = nullptr;
+    a.fallback = nullptr;
+    hipError_t e = csel::launch_screen(a, screen_rpl(pool_stride), stream);
+    if (e != hipSuccess) return hip_fail(e, "screen_features launch");
+    return CSEL_OK;
+}
+
+CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel, int64_t n_targets,
+                         const int32_t* targets, const int32_t* pool_idx, const int32_t* pool_len,
+                         int32_t pool_stride, const float* params, const uint16_t* params_bf16, int32_t keep,
+                         float fallback_threshold, int32_t* kept_idx, int32_t* kept_len, uint8_t* fallback,
+                         float* logits, int32_t* fallback_list, int32_t* fallback_count, hipStream_t stream) {
+    g_err[0] = 0;
+    csel::ScreenArgs a;
+    int rc = screen_common(pts, n, dim, kernel, n_targets, targets, pool_idx, pool_len, pool_stride, a);
+    if (rc) return rc;
+    if (keep < 1 || keep > pool_stride) return fail(CSEL_EINVAL, "keep must be in [1, pool_stride]");
+    if (!(fallback_threshold >= 0.0f)) return fail(CSEL_EINVAL, "fallback_threshold must be >= 0");
+    if ((fallback_list == nullptr) != (fallback_count == nullptr))
+        return fail(CSEL_EINVAL, "fallback_list and fallback_count go together");
+    if (n_targets == 0) {
+        if (fallback_count) {
+            hipError_t e = csel::launch_fill_i32(fallback_count, 1, 0, stream);
+            if (e != hipSuccess) return hip_fail(e, "fill launch");
+        }
+        return CSEL_OK;
+    }
+    if (!params || !params_bf16 || !kept_idx || !kept_len || !fallback)
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    a.params = params;
+    a.params_bf16 = params_bf16;
+    a.keep = keep;
+    a.fb_thr = fallback_threshold;
+    a.mode = 0;
+    a.logits = logits;
+    a.kept = kept_idx;
+    a.kept_len = kept_len;
+    a.fallback = fallback;
+    a.fb_list = fallback_list;
+    a.fb_count = fallback_count;
+    if (fallback_count) {
+        hipError_t e = csel::launch_fill_i32(fallback_count, 1, 0, stream);
+        if (e != hipSuccess) return hip_fail(e, "fill launch");
+    }
+    hipError_t e = csel::launch_screen(a, screen_rpl(pool_stride), stream);
+    if (e != hipSuccess) return hip_fail(e, "screen launch");
+    return CSEL_OK;
+}
+
+CSEL_API int64_t csel_mlp_grad_workspace_size(int64_t n_rows) {
+    g_err[0] = 0;
+    if (n_rows < 0) return fail(CSEL_EINVAL, "n_rows must be >= 0");
+    return csel::mlp_grad_nparts(n_rows) * (int64_t)(csel::mlp_nparams() + 1) * (int64_t)sizeof(float);
+}
+
+CSEL_API int csel_mlp_forward(const float* params, const uint16_t* params_bf16, const float* x, int64_t n_rows,
+                              float* logits, hipStream_t stream) {
+    g_err[0] = 0;
+    if (n_rows < 0) return fail(CSEL_EINVAL, "n_rows must be >= 0");
+    if (n_rows == 0) return CSEL_OK;
+    if (!params || !params_bf16 || !x || !logits) return fail(CSEL_EINVAL, "a required array is NULL");
+    csel::MlpTrainArgs a{};
+    a.params = params;
+    a.params_bf16 = params_bf16;
+    a.x = x;
+    a.n_rows = n_rows;
+    hipError_t e = csel::launch_mlp_forward(a, logits, stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp_forward launch");
+    return CSEL_OK;
+}
+
+CSEL_API int csel_mlp_grad(const float* params, const uint16_t* params_bf16, const float* x, const uint8_t* labels,
+                           int64_t n_rows, float pos_weight, void* workspace, int64_t workspace_bytes, float* grad,
+                           hipStream_t stream) {
+    g_err[0] = 0;
+    if (n_rows < 0) return fail(CSEL_EINVAL, "n_rows must be >= 0");
+    if (!(pos_weight > 0.0f)) return fail(CSEL_EINVAL, "pos_weight must be > 0");
+    if (!params || !params_bf16 || !grad || (n_rows > 0 && (!x || !labels)))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    const int64_t need = csel::mlp_grad_nparts(n_rows) * (int64_t)(csel::mlp_nparams() + 1) * (int64_t)sizeof(float);
+    if (need > 0 && (!workspace || workspace_bytes < need))
+        return fail(CSEL_EINVAL, "workspace must hold csel_mlp_grad_workspace_size() = %lld bytes", (long long)need);
+    csel::MlpTrainArgs a{};
+    a.params = params;
+    a.params_bf16 = params_bf16;
+    a.x = x;
+    a.y = labels;
+    a.n_rows = n_rows;
+    a.pos_weight = pos_weight;
+    a.inv_n = n_rows > 0 ? 1.0f / (float)n_rows : 0.0f;
+    a.partials = reinterpret_cast<float*>(workspace);
+    hipError_t e = csel::launch_mlp_grad(a, grad, stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp_grad launch");
+    return CSEL_OK;
+}
+
+CSEL_API int csel_mlp_adam(float* params, uint16_t* params_bf16, const float* grad, float* m, float* v,
+                           int32_t n_params, float lr, float beta1, float beta2, float eps, int32_t step,
+                           hipStream_t stream) {
+    g_err[0] = 0;
+    if (n_params != csel::mlp_nparams()) return fail(CSEL_EINVAL, "n_params must be csel_mlp_num_params()");
+    if (step < 1) return fail(CSEL_EINVAL, "step counts from 1");
+    if (!params || !params_bf16 || !grad || !m || !v) return fail(CSEL_EINVAL, "a required array is NULL");
+    hipError_t e = csel::launch_adam(params, params_bf16, grad, m, v, n_params, lr, beta1, beta2, eps, step, stream);
+    if (e != hipSuccess) return hip_fail(e, "adam launch");
+    return CSEL_OK;
+}
+
+CSEL_API int csel_mlp_to_bf16(const float* params, uint16_t* params_bf16, int32_t n_params, hipStream_t stream) {
+    g_err[0] = 0;
+    if (n_params < 0) return fail(CSEL_EINVAL, "n_params must be >= 0");
+    if (n_params == 0) return CSEL_OK;
+    if (!params || !params_bf16) return fail(CSEL_EINVAL, "a required array is NULL");
+    hipError_t e = csel::launch_to_bf16(params, params_bf16, n_params, stream);
+    if (e != hipSuccess) return hip_fail(e, "to_bf16 launch");
     return CSEL_OK;
 }

@@ -76,6 +76,18 @@ __global__ __launch_bounds__(256) void apply_l_kernel(int64_t n, const int64_t* 
     }
 }
 
+__global__ __launch_bounds__(256) void fill_i32_kernel(int32_t* __restrict__ x, int64_t n, int32_t v) {
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        x[i] = v;
+}
+
+hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    const unsigned b = (unsigned)std::min<int64_t>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(fill_i32_kernel, dim3(b), dim3(256), 0, s, x, n, v);
+    return hipGetLastError();
+}
+
 hipError_t launch_apply(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val, int transpose,
                         const double* x, double* y, hipStream_t s) {
     if (n == 0) return hipSuccess;

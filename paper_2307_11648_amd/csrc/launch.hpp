@@ -26,7 +26,60 @@ struct SelectArgs {
     double* logcv;
     float* gap;
     uint8_t* status;
+    // optional indirection: run only columns col_list[0 .. *col_count)
+    const int32_t* col_list;
+    const int32_t* col_count;
+    int64_t n_waves;  // waves launched: n_targets, or the list capacity
 };
+
+struct ScreenArgs {
+    const double* pts;
+    int64_t n;
+    int32_t dim;
+    int32_t two_nu;
+    double c_nu;
+    double s2;
+    double nugget;
+    double ell;
+    int64_t n_targets;
+    const int32_t* targets;
+    const int32_t* pool;
+    const int32_t* pool_len;
+    int32_t stride;
+    const float* params;
+    const uint16_t* params_bf16;
+    int32_t keep;
+    float fb_thr;
+    int32_t mode;  // 0 screen, 1 features only
+    float* feats;
+    float* logits;
+    int32_t* kept;
+    int32_t* kept_len;
+    uint8_t* fallback;
+    int32_t* fb_list;
+    int32_t* fb_count;
+};
+
+struct MlpTrainArgs {
+    const float* params;
+    const uint16_t* params_bf16;
+    const float* x;
+    const uint8_t* y;
+    int64_t n_rows;
+    float pos_weight;
+    float inv_n;
+    float* partials;
+};
+
+hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s);
+int mlp_nparams();
+int64_t mlp_grad_nparts(int64_t n_rows);
+hipError_t launch_mlp_grad(const MlpTrainArgs& a, float* grad, hipStream_t s);
+hipError_t launch_mlp_forward(const MlpTrainArgs& a, float* z, hipStream_t s);
+hipError_t launch_adam(float* p, uint16_t* pb, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s);
+hipError_t launch_to_bf16(const float* p, uint16_t* pb, int n, hipStream_t s);
+hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
 
 struct AggArgs {
     const double* pts;

@@ -1,0 +1,589 @@
+// screen.hip -- learned candidate screen: per-candidate features, a BF16 MLP
+// on MFMA (FP32 accumulation), top-`keep` selection and the fallback flag;
+// plus the MLP's training kernels (forward + backward, Adam).
+//
+// Not part of the paper: the screen prunes a column's pool (sorted by
+// distance) to the candidates an MLP scores highest, and the exact greedy
+// selection (Sec. 3.1) then runs on the kept candidates.  Columns whose
+// dropped candidates carry too much predicted probability fall back to the
+// full pool.
+//
+// MLP 16 -> 64 -> 64 -> 1 (ReLU).  Computed transposed so the MFMA output of
+// one layer is directly the B operand of the next: H^T = W^T X^T with
+// v_mfma_f32_16x16x16_bf16 tiles (A: weights, 16 hidden x 16 k; B: 16 k x 16
+// candidates; D: 16 hidden x 16 candidates).  Lane l of a 16x16x16 MFMA holds
+// A[l%16][4(l/16)+i], B[4(l/16)+i][l%16] and D[4(l/16)+i][l%16], i = 0..3.
+// The last layer (64 -> 1) is a VALU dot product plus a cross-row sum.
+//
+// Parameters: one FP32 vector W1[16][64], b1[64], W2[64][64], b2[64],
+// w3[64], b3 and its BF16 copy (same indexing); weights enter the MFMAs in
+// BF16, biases stay FP32.
+#include <algorithm>
+
+#include "device_common.hpp"
+#include "launch.hpp"
+
+namespace csel {
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+constexpr int kF = 16, kH = 64;
+constexpr int kOffW1 = 0, kOffB1 = kF * kH, kOffW2 = kOffB1 + kH, kOffB2 = kOffW2 + kH * kH;
+constexpr int kOffW3 = kOffB2 + kH, kOffB3 = kOffW3 + kH, kNParams = kOffB3 + 1;
+
+// round to the nearest bfloat16, ties to even (inputs are finite)
+__device__ __forceinline__ uint16_t bf16_bits(float x) {
+    uint32_t b = __float_as_uint(x);
+    b += 0x7FFFu + ((b >> 16) & 1u);
+    return (uint16_t)(b >> 16);
+}
+__device__ __forceinline__ float bf16_to_f32(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+__device__ __forceinline__ float corr(int two_nu, float a) {
+    const float e = __expf(-a);
+    if (two_nu == 1) return e;
+    if (two_nu == 3) return (1.0f + a) * e;
+    return (1.0f + a + a * a * (1.0f / 3.0f)) * e;
+}
+
+// MLP weights in MFMA operand layout, held in registers by every wave
+struct MlpRegs {
+    short4_t a1[4];       // W1^T tile h: lane (hid 16h + l%16, feat 4g+i)
+    short4_t a2[4][4];    // W2^T tile (h2, h): lane (out 16h2 + l%16, in 16h + 4g + i)
+    float b1[4][4];       // b1[16h + 4g + i]
+    float b2[4][4];
+    float w3[4][4];       // bf16-rounded w3[16h + 4g + i]
+    float b3;
+};
+
+__device__ __forceinline__ void load_mlp(MlpRegs& R, const float* __restrict__ p, const uint16_t* __restrict__ pb,
+                                         int lane) {
+    const int c = lane & 15, g = lane >> 4;
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            R.a1[h][i] = (short)pb[kOffW1 + (4 * g + i) * kH + 16 * h + c];
+            R.b1[h][i] = p[kOffB1 + 16 * h + 4 * g + i];
+            R.b2[h][i] = p[kOffB2 + 16 * h + 4 * g + i];
+            R.w3[h][i] = bf16_to_f32(pb[kOffW3 + 16 * h + 4 * g + i]);
+        }
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                R.a2[h2][h][i] = (short)pb[kOffW2 + (16 * h + 4 * g + i) * kH + 16 * h2 + c];
+    }
+    R.b3 = p[kOffB3];
+}
+
+// Forward for one tile of 16 candidates; xb = B operand (feat 4g+i of candidate l%16).
+// Returns the logit of candidate l%16 (identical in the four lanes that share it);
+// optionally exposes H1 (bf16 operand form) and H2 (fp32) for the backward pass.
+__device__ __forceinline__ float mlp_tile(const MlpRegs& R, short4_t xb, short4_t* h1q_out, float4_t* h2_out) {
+    short4_t h1q[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[h], xb, acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) h1q[h][i] = (short)bf16_bits(fmaxf(acc[i] + R.b1[h][i], 0.0f));
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2) {
+        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int h = 0; h < 4; ++h) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[h2][h], h1q[h], acc, 0, 0, 0);
+        float4_t hv;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            hv[i] = fmaxf(acc[i] + R.b2[h2][i], 0.0f);
+            part += hv[i] * R.w3[h2][i];
+        }
+        if (h2_out) h2_out[h2] = hv;
+    }
+    if (h1q_out)
+#pragma unroll
+        for (int h = 0; h < 4; ++h) h1q_out[h] = h1q[h];
+    // the four lane groups (l/16) hold disjoint hidden units of the same candidate
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    return part + R.b3;
+}
+
+// ---------------------------------------------------------------------------
+// features of one candidate (FP32); see the feature list in the header
+// ---------------------------------------------------------------------------
+struct NearInfo {
+    float d0[3], r0, dl[8][3], rl[8];
+    int nnear;
+};
+
+__device__ __forceinline__ void candidate_features(const ScreenArgs& p, int C, int s, const float d[3], float r,
+                                                   const float xj_rel0[3], const NearInfo& nb, float f[kF]) {
+    const float ell = (float)p.ell;
+    const float cnu = (float)p.c_nu;
+    const float tiny = 1e-9f * ell;
+    const float adiag = 1.0f + (float)(p.nugget / p.s2);
+    const float r0 = fmaxf(nb.r0, tiny);
+    const float rs = fmaxf(r, tiny);
+    f[0] = __logf(rs / r0);
+    f[1] = (float)s / (float)C;
+    const float rho_i = corr(p.two_nu, cnu * r);
+    f[2] = rho_i;
+    f[3] = r / ell;
+    f[4] = nb.r0 / ell;
+    const float dot0 = d[0] * nb.d0[0] + d[1] * nb.d0[1] + d[2] * nb.d0[2];
+    f[5] = r > 0.0f ? dot0 / (rs * r0) : 1.0f;
+    float best = INFINITY, cnt = 0.0f;
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        if (l < nb.nnear && l != s) {
+            const float e0 = d[0] - nb.dl[l][0], e1 = d[1] - nb.dl[l][1], e2 = d[2] - nb.dl[l][2];
+            best = fminf(best, sqrtf(e0 * e0 + e1 * e1 + e2 * e2) / rs);
+            const float dl = d[0] * nb.dl[l][0] + d[1] * nb.dl[l][1] + d[2] * nb.dl[l][2];
+            if (nb.rl[l] < r && dl / (rs * fmaxf(nb.rl[l], tiny)) > 0.7f) cnt += 1.0f;
+        }
+    }
+    f[6] = best < INFINITY ? best : 0.0f;
+    f[7] = cnt * 0.125f;
+    const float dj0 = sqrtf(xj_rel0[0] * xj_rel0[0] + xj_rel0[1] * xj_rel0[1] + xj_rel0[2] * xj_rel0[2]);
+    const float rho_j0c = corr(p.two_nu, cnu * dj0);
+    f[8] = rho_j0c;
+    const float rho_j0 = s == 0 ? adiag : rho_j0c;
+    const float rho_i0 = corr(p.two_nu, cnu * nb.r0);
+    const float cov1 = rho_i - rho_i0 * rho_j0 / adiag;
+    const float var1 = adiag - rho_j0 * rho_j0 / adiag;
+    f[9] = s == 0 ? 1.0f : (var1 > 1e-12f * adiag ? cov1 * cov1 / var1 / adiag : 0.0f);
+    f[10] = s == 0 ? 1.0f : 0.0f;
+    f[11] = __logf(1.0f + (float)s) / __logf(1.0f + (float)C);
+#pragma unroll
+    for (int q = 12; q < kF; ++q) f[q] = 0.0f;
+}
+
+constexpr int kScrWaves = 2;
+
+// One wave per column.  RPL = candidates per lane (pool <= 64*RPL).
+template <int RPL>
+__global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
+    constexpr int MAXC = 64 * RPL;
+    __shared__ __align__(16) uint16_t sh_x[kScrWaves][MAXC][kF];
+    __shared__ float sh_z[kScrWaves][MAXC];
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    const int64_t col = (int64_t)blockIdx.x * kScrWaves + wib;
+    if (col >= p.n_targets) return;
+    const int32_t tgt = __builtin_amdgcn_readfirstlane(p.targets[col]);
+    int32_t C = __builtin_amdgcn_readfirstlane(p.pool_len[col]);
+    const bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > p.stride || C > MAXC;
+    if (bad) C = 0;
+    const int dim = p.dim;
+    double xi[3] = {0.0, 0.0, 0.0};
+    if (!bad)
+        for (int q = 0; q < dim; ++q) xi[q] = p.pts[(int64_t)tgt * dim + q];
+    // my candidates: offsets from the target
+    float d[RPL][3], r[RPL];
+    int32_t id[RPL];
+    bool my_bad = false;
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+        const int s = rr * 64 + lane;
+        d[rr][0] = d[rr][1] = d[rr][2] = 0.0f;
+        r[rr] = 0.0f;
+        id[rr] = -1;
+        if (s < C) {
+            const int32_t q = p.pool[col * p.stride + s];
+            if (q < 0 || (int64_t)q >= p.n) {
+                my_bad = true;
+            } else {
+                id[rr] = q;
+                for (int c = 0; c < dim; ++c) d[rr][c] = (float)(p.pts[(int64_t)q * dim + c] - xi[c]);
+                r[rr] = sqrtf(d[rr][0] * d[rr][0] + d[rr][1] * d[rr][1] + d[rr][2] * d[rr][2]);
+            }
+        }
+    }
+    if (__any(my_bad) || bad) {
+        if (lane == 0 && p.mode == 0) {
+            p.kept_len[col] = 0;
+            p.fallback[col] = 3;
+        }
+        return;
+    }
+    // the nearest eight candidates (slots 0..7 live in lanes 0..7, rr = 0)
+    NearInfo nb;
+    nb.nnear = min(8, C);
+    nb.d0[0] = bcast(d[0][0], 0);
+    nb.d0[1] = bcast(d[0][1], 0);
+    nb.d0[2] = bcast(d[0][2], 0);
+    nb.r0 = bcast(r[0], 0);
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        nb.dl[l][0] = bcast(d[0][0], l);
+        nb.dl[l][1] = bcast(d[0][1], l);
+        nb.dl[l][2] = bcast(d[0][2], l);
+        nb.rl[l] = bcast(r[0], l);
+    }
+    // features -> LDS (bf16), optionally -> global (fp32)
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+        const int s = rr * 64 + lane;
+        float f[kF];
+        if (s < C) {
+            const float rel0[3] = {d[rr][0] - nb.d0[0], d[rr][1] - nb.d0[1], d[rr][2] - nb.d0[2]};
+            candidate_features(p, C, s, d[rr], r[rr], rel0, nb, f);
+        } else {
+#pragma unroll
+            for (int q = 0; q < kF; ++q) f[q] = 0.0f;
+        }
+#pragma unroll
+        for (int q = 0; q < kF; ++q) sh_x[wib][s][q] = bf16_bits(f[q]);
+        if (p.feats && s < C)
+#pragma unroll
+            for (int q = 0; q < kF; ++q) p.feats[(col * p.stride + s) * kF + q] = f[q];
+    }
+    if (p.mode == 1) return;  // features only
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // MLP over tiles of 16 candidates
+    MlpRegs R;
+    load_mlp(R, p.params, p.params_bf16, lane);
+    const int ntiles = (C + 15) >> 4;
+    const int cl = lane & 15, g = lane >> 4;
+    for (int tile = 0; tile < ntiles; ++tile) {
+        const int s = tile * 16 + cl;
+        short4_t xb;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xb[i] = (short)sh_x[wib][s][4 * g + i];
+        const float z = mlp_tile(R, xb, nullptr, nullptr);
+        if (g == 0) sh_z[wib][s] = z;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // keys: monotone logit bits, then the smaller slot
+    uint64_t key[RPL];
+    float zz[RPL];
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+        const int s = rr * 64 + lane;
+        zz[rr] = s < C ? sh_z[wib][s] : 0.0f;
+        const uint32_t b = __float_as_uint(zz[rr]);
+        const uint32_t mono = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+        key[rr] = s < C ? (((uint64_t)mono << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)s)) : 0ull;
+        if (p.logits && s < C) p.logits[col * p.stride + s] = zz[rr];
+    }
+    const int keep = p.keep;
+    uint64_t thr = 0;  // kept = key >= thr
+    bool fb = false;
+    if (C > keep) {
+        // bisection for the keep-th largest key
+        uint64_t lo = 0, hi = ~0ull;
+        while (lo < hi) {
+            const uint64_t mid = lo + (hi - lo) / 2 + 1;
+            int cnt = 0;
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) cnt += __popcll(__ballot(key[rr] >= mid));
+            if (cnt >= keep) lo = mid;
+            else hi = mid - 1;
+        }
+        thr = lo;
+        float drop = 0.0f;
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr)
+            if (key[rr] != 0ull && key[rr] < thr) drop += 1.0f / (1.0f + __expf(-zz[rr]));
+        for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+        fb = drop > p.fb_thr;
+    } else {
+        thr = 1;  // every valid candidate
+    }
+    // kept candidates in slot order
+    int base = 0;
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+    for (int rr = 0; rr < RPL; ++rr) {
+        const bool k = key[rr] != 0ull && key[rr] >= thr;
+        const uint64_t m = __ballot(k);
+        if (k) p.kept[col * keep + base + __popcll(m & below)] = id[rr];
+        base += __popcll(m);
+    }
+    for (int q = base + lane; q < keep; q += 64) p.kept[col * keep + q] = -1;
+    if (lane == 0) {
+        p.kept_len[col] = base;
+        p.fallback[col] = fb ? 1 : 0;
+        if (fb && p.fb_list) {
+            const int pos = atomicAdd(p.fb_count, 1);
+            p.fb_list[pos] = (int32_t)col;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// training: forward + weighted BCE + backward for rows of features
+// ---------------------------------------------------------------------------
+// One wave per block of rows; tiles of 16 rows.  Weight gradients are
+// reduced over rows with MFMAs whose operands are re-laid out through LDS,
+// accumulated in registers over the wave's rows and written as one partial
+// per wave; a second kernel sums the partials in a fixed order.
+constexpr int kTrainTilesPerWave = 16;  // 256 rows per wave
+
+__global__ __launch_bounds__(64) void mlp_grad_kernel(MlpTrainArgs p) {
+    __shared__ __align__(16) uint16_t sh_h1[16][kH];   // H1q of the tile, [row][hid]
+    __shared__ __align__(16) uint16_t sh_d2[16][kH];   // dH2 (bf16), [row][hid]
+    __shared__ __align__(16) uint16_t sh_d1[16][kH];   // dH1 (bf16), [row][hid]
+    __shared__ __align__(16) uint16_t sh_x[16][kF];    // X (bf16), [row][feat]
+    const int lane = lane_id();
+    const int cl = lane & 15, g = lane >> 4;
+    MlpRegs R;
+    load_mlp(R, p.params, p.params_bf16, lane);
+    // W2 as the A operand of dH1^T = W2 dH2^T: lane (in 16h + l%16, out 16h2 + 4g + i)
+    short4_t aw2[4][4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)
+                aw2[h][h2][i] = (short)p.params_bf16[kOffW2 + (16 * h + cl) * kH + 16 * h2 + 4 * g + i];
+    float4_t gW2[4][4], gW1[4];  // dW2^T tiles (out 16h2.., in 16h..), dW1^T tiles (hid 16h.., feat)
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        gW1[a] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int b = 0; b < 4; ++b) gW2[a][b] = float4_t{0.f, 0.f, 0.f, 0.f};
+    }
+    float gw3[4][4] = {}, gb1[4][4] = {}, gb2[4][4] = {};
+    float gb3 = 0.0f, loss = 0.0f;
+    const int64_t row0 = (int64_t)blockIdx.x * kTrainTilesPerWave * 16;
+    for (int tile = 0; tile < kTrainTilesPerWave; ++tile) {
+        const int64_t row = row0 + tile * 16 + cl;
+        const bool valid = row < p.n_rows;
+        // inputs
+        short4_t xb;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float v = valid ? p.x[row * kF + 4 * g + i] : 0.0f;
+            xb[i] = (short)bf16_bits(v);
+            sh_x[cl][4 * g + i] = (uint16_t)xb[i];
+        }
+        short4_t h1q[4];
+        float4_t act2[4];
+        const float z = mlp_tile(R, xb, h1q, act2);
+        const float y = valid ? (float)p.y[row] : 0.0f;
+        const float wgt = valid ? (y > 0.5f ? p.pos_weight : 1.0f) : 0.0f;
+        const float sig = 1.0f / (1.0f + __expf(-z));
+        const float dz = wgt * (sig - y) * p.inv_n;
+        if (g == 0 && valid) loss += wgt * (fmaxf(z, 0.0f) - z * y + log1pf(__expf(-fabsf(z))));
+        if (g == 0) gb3 += dz;
+        // layer 3 and dH2 (D layout: hid 16h2 + 4g + i, row l%16)
+        float4_t d2[4];
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                gw3[h2][i] += dz * act2[h2][i];
+                d2[h2][i] = act2[h2][i] > 0.0f ? dz * R.w3[h2][i] : 0.0f;
+                gb2[h2][i] += d2[h2][i];
+            }
+        // dH1^T = W2 dH2^T (B operand = dH2^T in D layout, rounded to bf16)
+        short4_t d2q[4];
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) d2q[h2][i] = (short)bf16_bits(d2[h2][i]);
+        short4_t d1q[4];
+#pragma unroll
+        for (int h = 0; h < 4; ++h) {
+            float4_t acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+            for (int h2 = 0; h2 < 4; ++h2) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(aw2[h][h2], d2q[h2], acc, 0, 0, 0);
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                // relu' of layer 1: the pre-rounding activation is > 0 exactly when its bf16 is
+                const float dv = bf16_to_f32((uint16_t)h1q[h][i]) > 0.0f ? acc[i] : 0.0f;
+                gb1[h][i] += dv;
+                d1q[h][i] = (short)bf16_bits(dv);
+            }
+        }
+        // re-lay H1q, dH2, dH1 as [row][hid] through LDS
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                sh_h1[cl][16 * h + 4 * g + i] = (uint16_t)h1q[h][i];
+                sh_d2[cl][16 * h + 4 * g + i] = (uint16_t)d2q[h][i];
+                sh_d1[cl][16 * h + 4 * g + i] = (uint16_t)d1q[h][i];
+            }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        // dW2^T (out x in) += dH2^T (out x rows) * H1 (rows x in): A lane (out 16h2 + l%16, row 4g+i),
+        // B lane (in 16h + l%16, row 4g+i)
+#pragma unroll
+        for (int h2 = 0; h2 < 4; ++h2) {
+            short4_t a;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) a[i] = (short)sh_d2[4 * g + i][16 * h2 + cl];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                short4_t b;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) b[i] = (short)sh_h1[4 * g + i][16 * h + cl];
+                gW2[h2][h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, gW2[h2][h], 0, 0, 0);
+            }
+        }
+        // dW1^T (hid x feat) += dH1^T (hid x rows) * X (rows x feat)
+        {
+            short4_t b;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) b[i] = (short)sh_x[4 * g + i][cl];
+#pragma unroll
+            for (int h = 0; h < 4; ++h) {
+                short4_t a;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) a[i] = (short)sh_d1[4 * g + i][16 * h + cl];
+                gW1[h] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, gW1[h], 0, 0, 0);
+            }
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+    // reduce the per-lane bias / w3 partials over the 16 rows of a lane group
+    auto row_sum = [](float v) {
+        v += __shfl_xor(v, 1, 64);
+        v += __shfl_xor(v, 2, 64);
+        v += __shfl_xor(v, 4, 64);
+        v += __shfl_xor(v, 8, 64);
+        return v;
+    };
+    float* out = p.partials + (int64_t)blockIdx.x * (kNParams + 1);
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float a = row_sum(gw3[h][i]), b1 = row_sum(gb1[h][i]), b2 = row_sum(gb2[h][i]);
+            if (cl == 0) {
+                out[kOffW3 + 16 * h + 4 * g + i] = a;
+                out[kOffB1 + 16 * h + 4 * g + i] = b1;
+                out[kOffB2 + 16 * h + 4 * g + i] = b2;
+            }
+        }
+    // D layout of the gradient tiles: lane (row 4g+i of the tile, col l%16)
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2)
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+#pragma unroll
+            for (int i = 0; i < 4; ++i)  // dW2[in][out] with out = 16h2 + 4g + i, in = 16h + l%16
+                out[kOffW2 + (16 * h + cl) * kH + 16 * h2 + 4 * g + i] = gW2[h2][h][i];
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i)  // dW1[feat][hid] with hid = 16h + 4g + i, feat = l%16
+            out[kOffW1 + cl * kH + 16 * h + 4 * g + i] = gW1[h][i];
+    float lsum = row_sum(loss);
+    lsum += __shfl_xor(lsum, 16, 64);
+    lsum += __shfl_xor(lsum, 32, 64);
+    float g3 = row_sum(gb3);
+    if (lane == 0) {
+        out[kOffB3] = g3;
+        out[kNParams] = lsum;
+    }
+}
+
+// grad[j] = sum over waves of partial[w][j] in a fixed order; slot kNParams = loss sum
+__global__ __launch_bounds__(256) void reduce_partials_kernel(const float* __restrict__ partials, int nparts,
+                                                              float* __restrict__ grad) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j > kNParams) return;
+    float s = 0.0f;
+    for (int w = 0; w < nparts; ++w) s += partials[(int64_t)w * (kNParams + 1) + j];
+    grad[j] = s;
+}
+
+// Adam (Kingma & Ba) on the FP32 master parameters; refreshes the BF16 copy.
+__global__ __launch_bounds__(256) void adam_kernel(float* __restrict__ p, uint16_t* __restrict__ pb,
+                                                   const float* __restrict__ g, float* __restrict__ m,
+                                                   float* __restrict__ v, int n, float lr, float b1, float b2,
+                                                   float eps, float c1, float c2) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j >= n) return;
+    const float gj = g[j];
+    const float mj = b1 * m[j] + (1.0f - b1) * gj;
+    const float vj = b2 * v[j] + (1.0f - b2) * gj * gj;
+    m[j] = mj;
+    v[j] = vj;
+    const float pj = p[j] - lr * (mj / c1) / (sqrtf(vj / c2) + eps);
+    p[j] = pj;
+    pb[j] = bf16_bits(pj);
+}
+
+__global__ __launch_bounds__(256) void to_bf16_kernel(const float* __restrict__ p, uint16_t* __restrict__ pb, int n) {
+    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    if (j < n) pb[j] = bf16_bits(p[j]);
+}
+
+// forward only: logits of feature rows (for tests and evaluation)
+__global__ __launch_bounds__(64) void mlp_forward_kernel(MlpTrainArgs p, float* __restrict__ z_out) {
+    const int lane = lane_id();
+    const int cl = lane & 15, g = lane >> 4;
+    MlpRegs R;
+    load_mlp(R, p.params, p.params_bf16, lane);
+    const int64_t row0 = (int64_t)blockIdx.x * kTrainTilesPerWave * 16;
+    for (int tile = 0; tile < kTrainTilesPerWave; ++tile) {
+        const int64_t row = row0 + tile * 16 + cl;
+        const bool valid = row < p.n_rows;
+        short4_t xb;
+#pragma unroll
+        for (int i = 0; i < 4; ++i) xb[i] = (short)bf16_bits(valid ? p.x[row * kF + 4 * g + i] : 0.0f);
+        const float z = mlp_tile(R, xb, nullptr, nullptr);
+        if (g == 0 && valid) z_out[row] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
+    if (a.n_targets == 0) return hipSuccess;
+    const unsigned grid = (unsigned)((a.n_targets + kScrWaves - 1) / kScrWaves);
+    switch (rpl) {
+        case 1: hipLaunchKernelGGL(screen_kernel<1>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL(screen_kernel<2>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 4: hipLaunchKernelGGL(screen_kernel<4>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 8: hipLaunchKernelGGL(screen_kernel<8>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+int mlp_nparams() { return kNParams; }
+int64_t mlp_grad_nparts(int64_t n_rows) { return (n_rows + kTrainTilesPerWave * 16 - 1) / (kTrainTilesPerWave * 16); }
+
+hipError_t launch_mlp_grad(const MlpTrainArgs& a, float* grad, hipStream_t s) {
+    const int64_t parts = mlp_grad_nparts(a.n_rows);
+    if (parts > 0) hipLaunchKernelGGL(mlp_grad_kernel, dim3((unsigned)parts), dim3(64), 0, s, a);
+    hipLaunchKernelGGL(reduce_partials_kernel, dim3((kNParams + 1 + 255) / 256), dim3(256), 0, s, a.partials,
+                       (int)parts, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_mlp_forward(const MlpTrainArgs& a, float* z, hipStream_t s) {
+    const int64_t parts = mlp_grad_nparts(a.n_rows);
+    if (parts > 0) hipLaunchKernelGGL(mlp_forward_kernel, dim3((unsigned)parts), dim3(64), 0, s, a, z);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float* p, uint16_t* pb, const float* g, float* m, float* v, int n, float lr, float b1,
+                       float b2, float eps, int step, hipStream_t s) {
+    const float c1 = 1.0f - powf(b1, (float)step), c2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, pb, g, m, v, n, lr, b1, b2, eps, c1,
+                       c2);
+    return hipGetLastError();
+}
+
+hipError_t launch_to_bf16(const float* p, uint16_t* pb, int n, hipStream_t s) {
+    hipLaunchKernelGGL(to_bf16_kernel, dim3((n + 255) / 256), dim3(256), 0, s, p, pb, n);
+    return hipGetLastError();
+}
+
+}  // namespace csel

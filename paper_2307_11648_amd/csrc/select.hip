@@ -14,7 +14,7 @@ hipError_t launch_select_double_3(const SelectArgs&, int, int, hipStream_t);
 hipError_t launch_select_double_5(const SelectArgs&, int, int, hipStream_t);
 
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s) {
-    if (a.n_targets == 0) return hipSuccess;
+    if (a.n_targets == 0 || a.n_waves == 0) return hipSuccess;
     if (precision == 0) {
         switch (a.two_nu) {
             case 1: return launch_select_double_1(a, rpl, kmax, s);

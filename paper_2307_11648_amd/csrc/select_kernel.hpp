@@ -44,8 +44,13 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
-    const int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
-    if (col >= p.n_targets) return;
+    const int64_t w_index = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
+    int64_t col = w_index;
+    if (p.col_list) {
+        if (w_index >= (int64_t)*p.col_count) return;
+        col = p.col_list[w_index];
+    }
+    if (col < 0 || col >= p.n_targets) return;
 
     const int kout = p.k;
     int32_t* sel_out = p.sel + col * kout;
@@ -266,7 +271,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 
 template <typename T, int TWO_NU, int RPL, int KMAX>
 static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
-    const int64_t blocks = (a.n_targets + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
+    const int64_t blocks = (a.n_waves + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
     hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

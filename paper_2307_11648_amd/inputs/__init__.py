@@ -36,6 +36,9 @@ def _load():
     lib.csel_geo_reverse_maximin.restype = ctypes.c_int
     lib.csel_geo_later_knn.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, _i32p, _i32p]
     lib.csel_geo_later_knn.restype = ctypes.c_int
+    lib.csel_geo_later_knn_subset.argtypes = [_f64p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, _i32p, _i32p, _i32p]
+    lib.csel_geo_later_knn_subset.restype = ctypes.c_int
     lib.csel_geo_make_groups.argtypes = [_f64p, _f64p, ctypes.c_int32, ctypes.c_int32, _i32p, ctypes.c_int32,
                                          ctypes.c_double, _i32p, _i32p]
     lib.csel_geo_make_groups.restype = ctypes.c_int32
@@ -108,6 +111,21 @@ def later_knn_pools(x_ordered: np.ndarray, C: int):
     rc = _load().csel_geo_later_knn(_p(x, _f64p), n, d, C, _p(pool, _i32p), _p(plen, _i32p))
     if rc != 0:
         raise ValueError("later_knn_pools: bad arguments")
+    return pool, plen
+
+
+def later_knn_pools_subset(x_ordered: np.ndarray, C: int, positions):
+    """later_knn_pools for the given ordering positions only (rows follow
+    `positions`)."""
+    x = np.ascontiguousarray(x_ordered, dtype=np.float64)
+    n, d = x.shape
+    q = np.ascontiguousarray(positions, dtype=np.int32)
+    pool = np.empty((len(q), C), np.int32)
+    plen = np.empty(len(q), np.int32)
+    rc = _load().csel_geo_later_knn_subset(_p(x, _f64p), n, d, C, len(q), _p(q, _i32p), _p(pool, _i32p),
+                                           _p(plen, _i32p))
+    if rc != 0:
+        raise ValueError("later_knn_pools_subset: bad arguments")
     return pool, plen
 
 
@@ -238,6 +256,18 @@ def workload_clustered(n: int = 1_000_000, seed: int = 4, C: int = 512, k: int =
     in [0,1]^3, Matern 3/2, l = 0.05; pools of 512, k = 32."""
     return single_target(f"clustered n={n} d=3 nu=3/2 C={C} k={k}", cluster_points(n, 3, seed),
                          Kernel(3, 0.05), C, k)
+
+
+def workload_clustered_training(n: int = 1_000_000, seed: int = 40, C: int = 512, k: int = 32,
+                                n_columns: int = 50_000):
+    """Training cloud for the learned screen: the clustered distribution with
+    its own seed; n_columns seeded columns with full pools of C."""
+    xo, ell = ordered_cloud(cluster_points(n, 3, seed))
+    rng = np.random.default_rng(seed + 1)
+    t = np.sort(rng.choice(n, size=min(n_columns, n), replace=False)).astype(np.int32)
+    pool, plen = later_knn_pools_subset(xo, C, t)
+    return SingleTargetWorkload(f"clustered-training n={n} d=3 nu=3/2 C={C} k={k}", xo, ell, Kernel(3, 0.05), t,
+                                pool, plen, k)
 
 
 def workload_aggregated(n: int = 1_000_000, seed: int = 3, C: int = 512, k: int = 64,

@@ -318,6 +318,40 @@ int csel_geo_later_knn(const double *x, int32_t n, int32_t d, int32_t C, int32_t
     return 0;
 }
 
+/* As csel_geo_later_knn, for the query positions q[0..nq) only: row r of
+ * pool/len belongs to position q[r]. */
+int csel_geo_later_knn_subset(const double *x, int32_t n, int32_t d, int32_t C, int32_t nq, const int32_t *q,
+                              int32_t *pool, int32_t *len) {
+    if (n <= 0 || d < 1 || d > MAXD || C < 0 || nq < 0) return -1;
+    laterforest F; forest_build(&F, x, n, d);
+    int32_t maxnodes = 0;
+    for (int32_t c = 0; c < F.nchunks; ++c) if (F.trees[c].nnodes > maxnodes) maxnodes = F.trees[c].nnodes;
+#pragma omp parallel
+    {
+        nbr *h = (nbr *)malloc(sizeof(nbr) * (C > 0 ? C : 1));
+        int32_t *stack = (int32_t *)malloc(sizeof(int32_t) * (maxnodes + 8));
+#pragma omp for schedule(dynamic, 64)
+        for (int32_t r = 0; r < nq; ++r) {
+            int32_t i = q[r];
+            int32_t *row = pool + (int64_t)r * C;
+            if (i < 0 || i >= n) {
+                for (int32_t j = 0; j < C; ++j) row[j] = -1;
+                len[r] = 0;
+                continue;
+            }
+            int32_t want = n - 1 - i; if (want > C) want = C;
+            kfilter f = {i, NULL, 0.0, NULL};
+            int32_t got = kd_knn(forest_pick(&F, i), x + (int64_t)i * d, want, &f, h, stack);
+            qsort(h, got, sizeof(nbr), nbr_cmp);
+            for (int32_t j = 0; j < C; ++j) row[j] = j < got ? h[j].id : -1;
+            len[r] = got;
+        }
+        free(h); free(stack);
+    }
+    forest_free(&F);
+    return 0;
+}
+
 /* Groups of nearby columns (supernodes).  Repeatedly take the earliest
  * unassigned id p and join to it up to m_g - 1 of its nearest unassigned later
  * ids j with ell[j] <= lambda * ell[p].  members are listed in increasing id.

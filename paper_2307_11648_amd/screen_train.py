@@ -1,0 +1,97 @@
+"""Training of the learned candidate screen, on the GPU, with the library's
+own kernels.
+
+Labels come from the exact method: a candidate is positive when the greedy
+selection (csel_select_and_factor on the full pool) selects it.  Features
+come from csel_screen_features.  Training is weighted BCE with logits by Adam
+(csel_mlp_grad + csel_mlp_adam, FP32 master weights, BF16 copy for the
+MFMA forward).  torch supplies memory, the random row sampling of each
+minibatch and the bookkeeping; every forward, backward and update step runs
+in libcsel.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import csel
+
+
+def init_params(seed: int, device) -> torch.Tensor:
+    """He-uniform weights, zero biases (FP32 vector, csel layout)."""
+    F, H = 16, 64
+    g = np.random.default_rng(seed)
+    p = np.zeros(csel.mlp_num_params(), np.float32)
+    o = 0
+    p[o:o + F * H] = g.uniform(-1, 1, F * H) * math.sqrt(6.0 / F)
+    o += F * H + H
+    p[o:o + H * H] = g.uniform(-1, 1, H * H) * math.sqrt(6.0 / H)
+    o += H * H + H
+    p[o:o + H] = g.uniform(-1, 1, H) * math.sqrt(6.0 / H)
+    return torch.from_numpy(p).to(device)
+
+
+def training_set(points, kernel, targets, pool, pool_len, k: int, precision: str = "mixed"):
+    """(X [rows, 16] float32, y [rows] uint8) for every valid pool slot of the
+    given columns; y = 1 where the exact greedy selection picks the slot."""
+    sel = csel.select_and_factor(points, kernel, targets, pool, pool_len, k, precision)["sel"]
+    feats = csel.screen_features(points, kernel, targets, pool, pool_len)
+    T, C = pool.shape
+    valid = torch.arange(C, device=pool.device)[None, :] < pool_len[:, None]
+    chosen = torch.zeros((T, C), dtype=torch.bool, device=pool.device)
+    for t0 in range(0, T, 4096):
+        t1 = min(T, t0 + 4096)
+        chosen[t0:t1] = (pool[t0:t1, :, None] == sel[t0:t1, None, :]).any(-1)
+    chosen &= valid
+    X = feats[valid].contiguous()
+    y = chosen[valid].to(torch.uint8).contiguous()
+    return X, y
+
+
+def train(X, y, steps: int = 3000, batch: int = 8192, lr: float = 2e-3, seed: int = 0, pos_weight: float = 1.0,
+          log_every: int = 0):
+    """Adam on minibatches of rows; returns (params FP32, params BF16, losses)."""
+    dev = X.device
+    p = init_params(seed, dev)
+    pb = csel.mlp_to_bf16(p)
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    gen = torch.Generator(device=dev)
+    gen.manual_seed(seed)
+    n = X.shape[0]
+    grad = None
+    ws = None
+    losses = []
+    for step in range(1, steps + 1):
+        idx = torch.randint(0, n, (batch,), device=dev, generator=gen)
+        xb = X[idx].contiguous()
+        yb = y[idx].contiguous()
+        grad, ws = csel.mlp_grad(p, pb, xb, yb, pos_weight, grad=grad, workspace=ws)
+        csel.mlp_adam(p, pb, grad[:-1], m, v, lr, step)
+        if log_every and step % log_every == 0:
+            losses.append(float(grad[-1].item()) / batch)
+    return p, pb, losses
+
+
+def mean_loss(p, pb, X, y, chunk: int = 1 << 20) -> float:
+    tot = 0.0
+    ws = None
+    grad = None
+    for a in range(0, X.shape[0], chunk):
+        b = min(X.shape[0], a + chunk)
+        grad, ws = csel.mlp_grad(p, pb, X[a:b].contiguous(), y[a:b].contiguous(), 1.0, grad=grad, workspace=ws)
+        tot += float(grad[-1].item())
+    return tot / X.shape[0]
+
+
+def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep: int, precision: str = "mixed",
+                    fallback_threshold: float = 0.5, out=None, scr=None):
+    """The screened hot path: screen, exact selection on the kept candidates,
+    exact selection on the full pool for the fallback columns (no host sync)."""
+    scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr)
+    out = csel.select_and_factor(points, kernel, targets, scr["kept"], scr["kept_len"], k, precision, out=out)
+    csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, scr["fallback_list"],
+                                scr["fallback_count"], targets.shape[0], out)
+    return out, scr

@@ -1,0 +1,222 @@
+"""GPU parity of the learned screen (features, MLP forward/backward, Adam,
+top-keep, fallback) against the screen oracle, and the screen's gain."""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from oracle import screen as so
+from paper_2307_11648_amd import csel, inputs, screen_train
+from parity import compare_single
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    csel.load()
+
+
+def _t(a, dtype):
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device="cuda", dtype=dtype)
+
+
+@pytest.fixture(scope="module")
+def clustered():
+    w = inputs.workload_clustered(n=8000, seed=14, C=512, k=32)
+    dev = {"pts": _t(w.points, torch.float64), "tg": _t(w.targets, torch.int32), "pl": _t(w.pool, torch.int32),
+           "ln": _t(w.pool_len, torch.int32)}
+    return w, dev
+
+
+def _rand_params(seed):
+    p = torch.from_numpy((np.random.default_rng(seed).standard_normal(so.N_PARAMS) * 0.25).astype(np.float32))
+    p = p.cuda()
+    return p, csel.mlp_to_bf16(p)
+
+
+def test_features_match_oracle(clustered):
+    print("case: screen features n=8000 C=512", flush=True)
+    w, d = clustered
+    f = csel.screen_features(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"]).cpu().numpy()
+    worst = 0.0
+    for t in list(range(0, 7800, 131)) + [7990, 7999]:
+        C = int(w.pool_len[t])
+        ref = so.features(w.points, w.kernel, int(w.targets[t]), w.pool[t, :C])
+        err = np.abs(f[t, :C] - ref)
+        worst = max(worst, float(err.max()) if C else 0.0)
+        np.testing.assert_allclose(f[t, :C], ref, rtol=2e-4, atol=2e-5)
+        assert np.all(f[t, C:] == 0)
+    print("worst feature error", worst)
+
+
+def test_bf16_conversion_matches_oracle():
+    p, pb = _rand_params(5)
+    ref = so.bf16_round(p.cpu().numpy())
+    got = (pb.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16
+    np.testing.assert_array_equal(got.view(np.float32).astype(np.float64), ref)
+
+
+def test_mlp_forward_and_gradient_match_oracle(clustered):
+    print("case: mlp forward/backward", flush=True)
+    w, d = clustered
+    f = csel.screen_features(d["pts"], w.kernel, d["tg"][:200], d["pl"][:200], d["ln"][:200])
+    X = f.view(-1, 16)[: 200 * 512 - 77].contiguous()  # a ragged number of rows
+    y = (torch.rand(X.shape[0], generator=torch.Generator().manual_seed(3)) < 0.07).to(torch.uint8).cuda()
+    p, pb = _rand_params(7)
+    z = csel.mlp_forward(p, pb, X).cpu().numpy()
+    Xn, yn, pn = X.cpu().numpy().astype(np.float64), y.cpu().numpy(), p.cpu().numpy().astype(np.float64)
+    zr, _ = so.mlp_forward(Xn, pn, bf16=True)
+    rel = np.linalg.norm(z - zr) / np.linalg.norm(zr)
+    print("logit normwise rel err", rel, "max abs", np.max(np.abs(z - zr)))
+    assert rel <= 1e-3
+    g, _ = csel.mlp_grad(p, pb, X, y, 4.0)
+    g = g.cpu().numpy()
+    loss, gr = so.bce_loss_and_grad(Xn, yn, pn, pos_weight=4.0, bf16=True)
+    assert g[-1] / X.shape[0] == pytest.approx(loss, rel=1e-3)
+    relg = np.linalg.norm(g[:-1] - gr) / np.linalg.norm(gr)
+    print("gradient normwise rel err", relg)
+    assert relg <= 2e-2
+    # per block of parameters too (each block is a separate backward product)
+    for a, b in ((so.OFF_W1, so.OFF_B1), (so.OFF_B1, so.OFF_W2), (so.OFF_W2, so.OFF_B2), (so.OFF_B2, so.OFF_W3),
+                 (so.OFF_W3, so.OFF_B3), (so.OFF_B3, so.N_PARAMS)):
+        assert np.linalg.norm(g[a:b] - gr[a:b]) <= 3e-2 * np.linalg.norm(gr[a:b]) + 1e-7
+    # deterministic reduction
+    g2, _ = csel.mlp_grad(p, pb, X, y, 4.0)
+    assert np.array_equal(g2.cpu().numpy(), g)
+
+
+def test_adam_matches_oracle():
+    p, pb = _rand_params(11)
+    g = torch.from_numpy(np.random.default_rng(12).standard_normal(so.N_PARAMS).astype(np.float32)).cuda()
+    m = torch.zeros_like(p)
+    v = torch.zeros_like(p)
+    pn, mn, vn = p.cpu().numpy().astype(np.float64), np.zeros(so.N_PARAMS), np.zeros(so.N_PARAMS)
+    for step in (1, 2, 3):
+        csel.mlp_adam(p, pb, g, m, v, 1e-2, step)
+        pn, mn, vn = so.adam_step(pn, g.cpu().numpy().astype(np.float64), mn, vn, step, 1e-2)
+    np.testing.assert_allclose(p.cpu().numpy(), pn, rtol=1e-5, atol=1e-6)
+    ref = so.bf16_round(p.cpu().numpy())
+    got = ((pb.cpu().numpy().astype(np.int32) & 0xFFFF).astype(np.uint32) << 16).view(np.float32)
+    np.testing.assert_array_equal(got.astype(np.float64), ref)
+
+
+def test_screen_keep_and_fallback_match_oracle(clustered):
+    print("case: screen top-keep", flush=True)
+    w, d = clustered
+    p, pb = _rand_params(21)
+    keep = 128
+    out = csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, keep, 0.5, want_logits=True)
+    torch.cuda.synchronize()
+    z = out["logits"].cpu().numpy()
+    kept = out["kept"].cpu().numpy()
+    kl = out["kept_len"].cpu().numpy()
+    fb = out["fallback"].cpu().numpy()
+    nfb = int(out["fallback_count"].item())
+    assert nfb == int(np.sum(fb == 1))
+    assert set(out["fallback_list"].cpu().numpy()[:nfb].tolist()) == set(np.where(fb == 1)[0].tolist())
+    for t in range(len(w.targets)):
+        C = int(w.pool_len[t])
+        ks, f = so.screen_keep(z[t], C, keep, 0.5)
+        # integer work on the GPU's own logits: bit-exact
+        assert kl[t] == len(ks)
+        assert np.array_equal(kept[t, : kl[t]], w.pool[t, ks])
+        assert np.all(kept[t, kl[t]:] == -1)
+        if C > keep:
+            drop = np.sort(np.setdiff1d(np.arange(C), ks))
+            s = float(np.sum(1.0 / (1.0 + np.exp(-z[t, drop].astype(np.float64)))))
+            if abs(s - 0.5) > 1e-4:
+                assert bool(fb[t]) == f
+    # GPU logits against the oracle's end-to-end logits (oracle features, FP64 MLP)
+    for t in range(0, len(w.targets), 397):
+        C = int(w.pool_len[t])
+        fr = so.features(w.points, w.kernel, int(w.targets[t]), w.pool[t, :C])
+        zr, _ = so.mlp_forward(fr, p.cpu().numpy().astype(np.float64), bf16=True)
+        assert np.linalg.norm(z[t, :C] - zr) <= 5e-3 * np.linalg.norm(zr) + 1e-5
+
+
+def test_screened_selection_parity(clustered):
+    """Exact selection on the kept pools plus full-pool selection for the
+    fallback columns equals the oracle run on the same per-column pools."""
+    print("case: screened selection parity", flush=True)
+    w, d = clustered
+    p, pb = _rand_params(33)
+    # a threshold at the median dropped mass sends about half the columns to the full pool
+    z = csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, 128, 0.5, want_logits=True)["logits"]
+    zs = torch.sort(z.cpu(), dim=1, descending=True).values.double()
+    drop = [float(torch.sigmoid(zs[t, 128:int(w.pool_len[t])]).sum()) for t in range(len(w.targets))]
+    thr = float(np.median([v for v, L in zip(drop, w.pool_len) if L > 128]))
+    out, scr = screen_train.screened_select(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], 32, p, pb, 128,
+                                            precision="fp64", fallback_threshold=thr)
+    torch.cuda.synchronize()
+    fb = scr["fallback"].cpu().numpy()
+    kept = scr["kept"].cpu().numpy()
+    kl = scr["kept_len"].cpu().numpy()
+    assert 0 < fb.sum() < len(fb)  # both paths exercised
+    pool = np.full((len(w.targets), 512), -1, np.int32)
+    plen = np.zeros(len(w.targets), np.int32)
+    for t in range(len(w.targets)):
+        if fb[t]:
+            pool[t] = w.pool[t]
+            plen[t] = w.pool_len[t]
+        else:
+            pool[t, : kl[t]] = kept[t, : kl[t]]
+            plen[t] = kl[t]
+    o = oracle.select_and_factor(w.points, w.kernel, w.targets, pool, plen, 32)
+    g = {key: v.cpu().numpy() for key, v in out.items()}
+    g["gap"] = o["gap"]  # not requested from the GPU
+    rep = compare_single(g, o, 1e-6, factor_rtol=1e-5, logcv_atol=1e-8)
+    print(rep["identical"], "of", rep["columns"], "identical")
+    assert rep["identical"] >= 0.97 * rep["columns"]
+
+
+def test_trained_screen_gains(tmp_path):
+    """Train on a separate cloud of the same distribution (labels from exact
+    greedy selections), then screen 512-candidate pools to 128 on a test cloud:
+    the trained screen keeps the KL within 1% of full-pool selection, beats the
+    untrained network and random screening, and is reported against the
+    128-nearest screen.  KL is exact (dense log det on the GPU, FP64)."""
+    print("case: trained screen gain, n=12000", flush=True)
+    n = 12000
+    tr = inputs.workload_clustered(n=n, seed=40, C=512, k=32)
+    te = inputs.workload_clustered(n=n, seed=41, C=512, k=32)
+    dt = lambda w: (_t(w.points, torch.float64), _t(w.targets, torch.int32), _t(w.pool, torch.int32),  # noqa: E731
+                    _t(w.pool_len, torch.int32))
+    P, Tg, Pl, Ln = dt(tr)
+    X, y = screen_train.training_set(P, tr.kernel, Tg, Pl, Ln, 32, "fp64")
+    print("training rows", X.shape[0], "positives", float(y.float().mean()))
+    p, pb, losses = screen_train.train(X, y, steps=1500, batch=8192, lr=3e-3, seed=1, log_every=500)
+    print("training losses", losses)
+    p0, pb0 = _rand_params(99)
+    P, Tg, Pl, Ln = dt(te)
+    full = csel.select_and_factor(P, te.kernel, Tg, Pl, Ln, 32, "fp64")
+    # exact log det of Theta on the GPU (evaluation only)
+    th = torch.from_numpy(oracle.covariance(te.points, te.kernel)).cuda()
+    ld = float(2.0 * torch.log(torch.diagonal(torch.linalg.cholesky(th))).sum().item())
+    del th
+    S_full = float(full["log_condvar"].sum().item())
+    kl_full = 0.5 * (S_full - ld)
+
+    def kl_of(pool_t, len_t):
+        o = csel.select_and_factor(P, te.kernel, Tg, pool_t, len_t, 32, "fp64")
+        return 0.5 * (float(o["log_condvar"].sum().item()) - ld)
+
+    res = {}
+    for name, (pp, ppb) in {"trained": (p, pb), "untrained": (p0, pb0)}.items():
+        out, scr = screen_train.screened_select(P, te.kernel, Tg, Pl, Ln, 32, pp, ppb, 128, precision="fp64",
+                                                fallback_threshold=1e9)  # no fallback: the screen alone
+        res[name] = 0.5 * (float(out["log_condvar"].sum().item()) - ld)
+    res["nearest128"] = kl_of(Pl[:, :128].contiguous(), torch.clamp(Ln, max=128))
+    rng = np.random.default_rng(0)
+    pr = te.pool.copy()
+    for t in range(n):
+        L = te.pool_len[t]
+        if L > 128:
+            pr[t, :128] = te.pool[t, np.sort(rng.choice(L, 128, replace=False))]
+    res["random128"] = kl_of(_t(pr[:, :128], torch.int32), torch.clamp(Ln, max=128))
+    gaps = {k: (v - kl_full) / kl_full for k, v in res.items()}
+    print("KL full", kl_full, "relative gaps", gaps)
+    assert gaps["trained"] <= 0.01
+    assert gaps["trained"] < gaps["untrained"]
+    assert gaps["trained"] < gaps["random128"]
