@@ -16,6 +16,7 @@ Prints ONE JSON line (rank 0, N = 1 GPU).
 """
 import argparse
 import json
+import math
 import os
 import sys
 import time
@@ -199,12 +200,150 @@ def bench_groups(args):
     print(json.dumps(res), flush=True)
 
 
+def _matern_torch(two_nu, a):
+    import torch
+    e = torch.exp(-a)
+    if two_nu == 1:
+        return e
+    if two_nu == 3:
+        return (1 + a) * e
+    return (1 + a + a * a / 3.0) * e
+
+
+def kl_gap_estimate(w, targets_sample, lcv_plain, lcv_screen, dS, n_ref=2048):
+    """Relative KL gap of the screened factor, (S_screen - S_plain) / (2 KL_plain).
+
+    2 KL_plain = sum_i [log Theta_ii|s_i - log Theta_ii|i+1:] (eq. obj_chol);
+    the second term is estimated on a seeded sample of columns by conditioning
+    on the n_ref nearest later points (dense FP64 Cholesky on the GPU; the
+    screening effect makes the rest negligible) and scaled to all columns."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import inputs
+
+    pool, plen = inputs.later_knn_pools_subset(w.points, n_ref, targets_sample)
+    X = torch.from_numpy(w.points).cuda()
+    c = math.sqrt(w.kernel.two_nu) / w.kernel.length_scale
+    terms = []
+    for r, i in enumerate(targets_sample):
+        S = torch.from_numpy(pool[r, : plen[r]].astype(np.int64)).cuda()
+        if len(S) == 0:
+            ref = w.kernel.variance + w.kernel.nugget
+        else:
+            xs = X[S]
+            K = w.kernel.variance * _matern_torch(w.kernel.two_nu, c * torch.cdist(xs, xs))
+            K += w.kernel.nugget * torch.eye(len(S), dtype=K.dtype, device=K.device)
+            k = w.kernel.variance * _matern_torch(w.kernel.two_nu, c * torch.linalg.norm(xs - X[int(i)], dim=1))
+            Lc = torch.linalg.cholesky(K)
+            z = torch.linalg.solve_triangular(Lc, k[:, None], upper=False)
+            ref = float(w.kernel.variance + w.kernel.nugget - (z * z).sum())
+        terms.append(float(lcv_plain[r]) - math.log(ref))
+    kl2_plain = np.mean(terms) * len(w.targets)
+    return dS / kl2_plain, kl2_plain / 2.0, len(targets_sample)
+
+
+def bench_screened(args):
+    """Plain full-pool selection vs learned-screened selection on the clustered
+    1e6-point workload (pools of 512, keep 128, k = 32)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs, screen_train
+
+    n = args.n or 1_000_000
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    print("bench: training cloud", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    tr = inputs.workload_clustered_training(n=n, n_columns=min(50_000, n))
+    P, Tg, Pl, Ln = t(tr.points, torch.float64), t(tr.targets, torch.int32), t(tr.pool, torch.int32), \
+        t(tr.pool_len, torch.int32)
+    X, y = screen_train.training_set(P, tr.kernel, Tg, Pl, Ln, 32, "fp64")
+    del P, Tg, Pl, Ln
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    p, pb, losses = screen_train.train(X, y, steps=args.train_steps, batch=8192, lr=3e-3, seed=1, log_every=500)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t1
+    rows = int(X.shape[0])
+    del X, y
+    print(f"bench: trained on {rows} rows in {t_train:.1f} s (set-up {t1 - t0:.1f} s); losses {losses}",
+          file=sys.stderr, flush=True)
+    print("bench: building inputs", file=sys.stderr, flush=True)
+    w = inputs.workload_clustered(n=n)
+    k, keep = 32, 128
+    pts, tg, pl, ln = t(w.points, torch.float64), t(w.targets, torch.int32), t(w.pool, torch.int32), \
+        t(w.pool_len, torch.int32)
+    T = len(w.targets)
+    prec = args.precision
+    plain = csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec)
+    fbt = args.fallback_threshold
+    scr_out, scr = screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
+                                                fallback_threshold=fbt)
+    torch.cuda.synchronize()
+
+    def time_it(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+               for _ in range(args.steps)]
+        for a, b_ in evs:
+            a.record()
+            fn()
+            b_.record()
+        torch.cuda.synchronize()
+        return float(np.mean([a.elapsed_time(b_) for a, b_ in evs]))
+
+    ms_plain = time_it(lambda: csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, out=plain))
+    ms_screen = time_it(lambda: screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
+                                                             fallback_threshold=fbt, out=scr_out, scr=scr))
+    # component times of the screened step
+    ms_scr_only = time_it(lambda: csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr))
+    ms_kept = time_it(lambda: csel.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec,
+                                                     out=scr_out))
+    screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec, fallback_threshold=fbt,
+                                 out=scr_out, scr=scr)
+    nfb = int(scr["fallback_count"].item())
+    S_plain = float(plain["log_condvar"].sum().item())
+    S_screen = float(scr_out["log_condvar"].sum().item())
+    rng = np.random.default_rng(77)
+    samp = np.sort(rng.choice(T, size=96, replace=False)).astype(np.int32)
+    lcv_p = plain["log_condvar"].cpu().numpy()[samp]
+    gap, kl_plain, ns = kl_gap_estimate(w, samp, lcv_p, None, S_screen - S_plain)
+    flops, _ = column_work(np.minimum(w.pool_len, keep), k, 3, 3)
+    res = {
+        "metric": METRIC, "value": T / (ms_screen * 1e-3), "unit": "columns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_screen, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "bf16+f32+f64" if prec == "mixed" else "bf16+f64", "data": "synthetic",
+        "config": {"workload": f"learned-screened selection, N={n} in [0,1]^3 (20 Gaussian clusters sigma 0.03 + 20% "
+                               f"uniform), Matern 3/2, l=0.05, pools of 512 -> keep {keep}, k={k}, {prec}; MLP "
+                               f"16-64-64-1 trained on the GPU on {rows} rows from {len(tr.targets)} exact selections",
+                   "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain, "screened_ms": ms_screen,
+                   "screen_kernel_ms": ms_scr_only, "kept_select_ms": ms_kept,
+                   "fallback_threshold": fbt, "speedup_vs_plain": ms_plain / ms_screen,
+                   "fallback_columns": nfb, "delta_S": S_screen - S_plain,
+                   "kl_gap_relative_estimate": gap, "kl_plain_estimate": kl_plain,
+                   "kl_estimate_sample_columns": ns, "train_seconds": t_train},
+        "roofline": {"bound": "alu", "kernel": "select_factor_kernel on kept pools",
+                     "achieved": float(np.sum(flops)) / (ms_kept * 1e-3) / 1e12, "kernel_ms": ms_kept,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "traffic": None},
+    }
+    res["roofline"]["frac"] = res["roofline"]["achieved"] / PEAK_ALU_TFLOPS
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain", choices=["plain", "aggregated", "gp"])
+    ap.add_argument("--workload", default="plain", choices=["plain", "aggregated", "gp", "screened"])
+    ap.add_argument("--train-steps", type=int, default=3000, help="screened workload: Adam steps")
+    ap.add_argument("--fallback-threshold", type=float, default=2.0,
+                    help="screened workload: fall back to the full pool when the dropped candidates' summed "
+                         "selection probability exceeds this")
     ap.add_argument("--n", type=int, default=0, help="number of points (0 = the workload's full size)")
     ap.add_argument("--precision", default="", choices=["", "mixed", "fp64"],
                     help="default: mixed, except fp64 for the GP workload (its conditional variances fall "
@@ -230,6 +369,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if not args.precision:
         args.precision = "fp64" if args.workload == "gp" else "mixed"
+    if args.workload == "screened":
+        return bench_screened(args)
     if args.workload != "plain":
         return bench_groups(args)
     args.n = args.n or 100_000
