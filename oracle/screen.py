@@ -168,16 +168,24 @@ def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
+def rank_key(z, s):
+    """Ranking key of a candidate: the float32 logit compared at 2^-14
+    relative resolution (its order-preserving 32-bit image with the low 9 bits
+    cleared), ties to the smaller slot."""
+    b = int(np.float32(z).view(np.uint32))
+    mono = (~b & 0xFFFFFFFF) if b & 0x80000000 else (b | 0x80000000)
+    return ((mono & ~0x1FF) & 0xFFFFFFFF, -s)
+
+
 def screen_keep(logits, pool_len, keep, fallback_threshold=0.5):
-    """Kept slots (ascending) of one column: the `keep` largest logits, ties to
-    the smaller slot; and the fallback flag: the expected number of true
-    selections among the dropped candidates, sum sigmoid(logit), exceeds the
-    threshold."""
+    """Kept slots (ascending) of one column: the `keep` largest logits by
+    rank_key; and the fallback flag: the expected number of true selections
+    among the dropped candidates, sum sigmoid(logit), exceeds the threshold."""
     z = np.asarray(logits[:pool_len], np.float64)
     C = len(z)
     if C <= keep:
         return np.arange(C), False
-    order = sorted(range(C), key=lambda s: (-z[s], s))
+    order = sorted(range(C), key=lambda s: rank_key(z[s], s), reverse=True)
     kept = np.sort(np.array(order[:keep]))
     dropped = np.array(order[keep:])
     fb = float(np.sum(1.0 / (1.0 + np.exp(-z[dropped])))) > fallback_threshold

@@ -23,9 +23,13 @@ GEO_LIB = os.path.join(PKG, "inputs", "libcsel_geometry.so")
 # (source, extra defines): the single-target kernel families compile as
 # separate objects so the build runs in parallel.
 HIP_UNITS = [("abi.cpp", []), ("select.hip", [])] + [
-    ("select_inst.hip", [f"-DCSEL_SEL_T={t}", f"-DCSEL_SEL_NU={nu}"])
-    for t in ("float", "double") for nu in (1, 3, 5)
-] + [(s, []) for s in ("aggregate.hip", "apply.hip", "screen.hip")]
+    ("select_inst.hip", [f"-DCSEL_SEL_T={t}", f"-DCSEL_SEL_NU={nu}", f"-DCSEL_SEL_GAP={g}"])
+    for t in ("float", "double") for nu in (1, 3, 5) for g in (0, 1)
+] + [(s, []) for s in ("aggregate.hip", "apply.hip")] + [
+    # the screen's ReLU/min/max need no NaN handling: plain v_max/v_min without
+    # the IEEE-mode quieting of their inputs
+    ("screen.hip", ["-mno-amdgpu-ieee", "-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
+]
 
 HIPCC_FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",

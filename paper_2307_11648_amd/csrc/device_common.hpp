@@ -20,6 +20,8 @@ __device__ __forceinline__ float bcast(float v, int lane) {
     return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
 }
 __device__ __forceinline__ int32_t bcast(int32_t v, int lane) { return __builtin_amdgcn_readlane(v, lane); }
+// broadcast from a lane that differs between lanes (ds_bpermute)
+__device__ __forceinline__ int32_t bcast_dyn(int32_t v, int src_lane) { return __shfl(v, src_lane, 64); }
 __device__ __forceinline__ double bcast(double v, int lane) {
     int64_t b = __double_as_longlong(v);
     int32_t lo = __builtin_amdgcn_readlane((int32_t)(b & 0xffffffff), lane);

@@ -78,28 +78,44 @@ __device__ __forceinline__ void load_mlp(MlpRegs& R, const float* __restrict__ p
     R.b3 = p[kOffB3];
 }
 
+typedef float float2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+
+// two floats -> two bf16 (round to nearest even, v_cvt_pk_bf16_f32), as the
+// low and high halves of a 32-bit word
+__device__ __forceinline__ uint32_t pack_bf16x2(float a, float b) {
+    const bf16x2_t v = __builtin_convertvector(float2_t{a, b}, bf16x2_t);
+    return __builtin_bit_cast(uint32_t, v);
+}
+
+__device__ __forceinline__ short4_t pack_bf16x4(float a, float b, float c, float d) {
+    const uint2 v = {pack_bf16x2(a, b), pack_bf16x2(c, d)};
+    return __builtin_bit_cast(short4_t, v);
+}
+
 // Forward for one tile of 16 candidates; xb = B operand (feat 4g+i of candidate l%16).
-// Returns the logit of candidate l%16 (identical in the four lanes that share it);
-// optionally exposes H1 (bf16 operand form) and H2 (fp32) for the backward pass.
+// The biases seed the MFMA accumulators.  Returns the logit of candidate l%16
+// (identical in the four lanes that share it); optionally exposes H1 (bf16
+// operand form) and H2 (fp32) for the backward pass.
 __device__ __forceinline__ float mlp_tile(const MlpRegs& R, short4_t xb, short4_t* h1q_out, float4_t* h2_out) {
     short4_t h1q[4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
-        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[h], xb, acc, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) h1q[h][i] = (short)bf16_bits(fmaxf(acc[i] + R.b1[h][i], 0.0f));
+        h1q[h] = pack_bf16x4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
     }
     float part = 0.0f;
 #pragma unroll
     for (int h2 = 0; h2 < 4; ++h2) {
-        float4_t acc = {0.f, 0.f, 0.f, 0.f};
+        float4_t acc = {R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
 #pragma unroll
         for (int h = 0; h < 4; ++h) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[h2][h], h1q[h], acc, 0, 0, 0);
         float4_t hv;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            hv[i] = fmaxf(acc[i] + R.b2[h2][i], 0.0f);
+            hv[i] = fmaxf(acc[i], 0.0f);
             part += hv[i] * R.w3[h2][i];
         }
         if (h2_out) h2_out[h2] = hv;
@@ -113,207 +129,316 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs& R, short4_t xb, short4_
     return part + R.b3;
 }
 
+// Weight operands of the MFMAs staged in LDS (shared by the waves of a block)
+// in per-lane operand order: A fragment f of lane l at [f][l].
+struct MlpLds {
+    uint2 a1[4][64];
+    uint2 a2[16][64];  // fragment 4*h2 + h
+};
+
+__device__ __forceinline__ void stage_mlp(MlpLds& L, const uint16_t* __restrict__ pb) {
+    for (int e = threadIdx.x; e < 20 * 64; e += blockDim.x) {
+        const int f = e >> 6, l = e & 63, c = l & 15, g = l >> 4;
+        short4_t v;
+        if (f < 4) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = (short)pb[kOffW1 + (4 * g + i) * kH + 16 * f + c];
+            L.a1[f][l] = __builtin_bit_cast(uint2, v);
+        } else {
+            const int h2 = (f - 4) >> 2, h = (f - 4) & 3;
+#pragma unroll
+            for (int i = 0; i < 4; ++i) v[i] = (short)pb[kOffW2 + (16 * h + 4 * g + i) * kH + 16 * h2 + c];
+            L.a2[f - 4][l] = __builtin_bit_cast(uint2, v);
+        }
+    }
+}
+
+// As mlp_tile, with the MFMA weight operands read from LDS.
+__device__ __forceinline__ float mlp_tile_lds(const MlpRegs& R, const MlpLds& L, short4_t xb, int lane) {
+    short4_t h1q[4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
+        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, L.a1[h][lane]), xb, acc, 0, 0, 0);
+        h1q[h] = pack_bf16x4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
+    }
+    float part = 0.0f;
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2) {
+        float4_t acc = {R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
+#pragma unroll
+        for (int h = 0; h < 4; ++h)
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, L.a2[4 * h2 + h][lane]),
+                                                             h1q[h], acc, 0, 0, 0);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) part += fmaxf(acc[i], 0.0f) * R.w3[h2][i];
+    }
+    part += __shfl_xor(part, 16, 64);
+    part += __shfl_xor(part, 32, 64);
+    return part + R.b3;
+}
+
+// biases and w3 only (the screen keeps the MFMA operands in LDS)
+__device__ __forceinline__ void load_mlp_vec(MlpRegs& R, const float* __restrict__ p, const uint16_t* __restrict__ pb,
+                                             int lane) {
+    const int g = lane >> 4;
+#pragma unroll
+    for (int h = 0; h < 4; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            R.b1[h][i] = p[kOffB1 + 16 * h + 4 * g + i];
+            R.b2[h][i] = p[kOffB2 + 16 * h + 4 * g + i];
+            R.w3[h][i] = bf16_to_f32(pb[kOffW3 + 16 * h + 4 * g + i]);
+        }
+    R.b3 = p[kOffB3];
+}
+
 // ---------------------------------------------------------------------------
 // features of one candidate (FP32); see the feature list in the header
 // ---------------------------------------------------------------------------
-struct NearInfo {
-    float d0[3], r0, dl[8][3], rl[8];
-    int nnear;
+// Features of one candidate except the nearest-eight terms f6, f7 (which the
+// caller accumulates with the neighbour loop outermost).  FP32; divisions use
+// hardware reciprocals (the features feed BF16 MFMA operands).
+struct ColumnConsts {
+    float inv_ell, cnu, tiny, adiag, inv_adiag, r0, inv_r0g, log_r0g, rho_i0, inv_c, inv_log1p_c;
 };
 
-__device__ __forceinline__ void candidate_features(const ScreenArgs& p, int C, int s, const float d[3], float r,
-                                                   const float xj_rel0[3], const NearInfo& nb, float f[kF]) {
-    const float ell = (float)p.ell;
-    const float cnu = (float)p.c_nu;
-    const float tiny = 1e-9f * ell;
-    const float adiag = 1.0f + (float)(p.nugget / p.s2);
-    const float r0 = fmaxf(nb.r0, tiny);
-    const float rs = fmaxf(r, tiny);
-    f[0] = __logf(rs / r0);
-    f[1] = (float)s / (float)C;
-    const float rho_i = corr(p.two_nu, cnu * r);
+__device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
+__device__ __forceinline__ void candidate_features(const ScreenArgs& p, const ColumnConsts& k, int s, const float d[3],
+                                                   float r, const float d0[3], float f[kF]) {
+    const float rs = fmaxf(r, k.tiny);
+    f[0] = __logf(rs) - k.log_r0g;
+    f[1] = (float)s * k.inv_c;
+    const float rho_i = corr(p.two_nu, k.cnu * r);
     f[2] = rho_i;
-    f[3] = r / ell;
-    f[4] = nb.r0 / ell;
-    const float dot0 = d[0] * nb.d0[0] + d[1] * nb.d0[1] + d[2] * nb.d0[2];
-    f[5] = r > 0.0f ? dot0 / (rs * r0) : 1.0f;
-    float best = INFINITY, cnt = 0.0f;
-#pragma unroll
-    for (int l = 0; l < 8; ++l) {
-        if (l < nb.nnear && l != s) {
-            const float e0 = d[0] - nb.dl[l][0], e1 = d[1] - nb.dl[l][1], e2 = d[2] - nb.dl[l][2];
-            best = fminf(best, sqrtf(e0 * e0 + e1 * e1 + e2 * e2) / rs);
-            const float dl = d[0] * nb.dl[l][0] + d[1] * nb.dl[l][1] + d[2] * nb.dl[l][2];
-            if (nb.rl[l] < r && dl / (rs * fmaxf(nb.rl[l], tiny)) > 0.7f) cnt += 1.0f;
-        }
-    }
-    f[6] = best < INFINITY ? best : 0.0f;
-    f[7] = cnt * 0.125f;
-    const float dj0 = sqrtf(xj_rel0[0] * xj_rel0[0] + xj_rel0[1] * xj_rel0[1] + xj_rel0[2] * xj_rel0[2]);
-    const float rho_j0c = corr(p.two_nu, cnu * dj0);
+    f[3] = r * k.inv_ell;
+    f[4] = k.r0 * k.inv_ell;
+    const float dot0 = d[0] * d0[0] + d[1] * d0[1] + d[2] * d0[2];
+    f[5] = r > 0.0f ? dot0 * frcp(rs) * k.inv_r0g : 1.0f;
+    const float e0 = d[0] - d0[0], e1 = d[1] - d0[1], e2 = d[2] - d0[2];
+    const float dj0 = __builtin_amdgcn_sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+    const float rho_j0c = corr(p.two_nu, k.cnu * dj0);
     f[8] = rho_j0c;
-    const float rho_j0 = s == 0 ? adiag : rho_j0c;
-    const float rho_i0 = corr(p.two_nu, cnu * nb.r0);
-    const float cov1 = rho_i - rho_i0 * rho_j0 / adiag;
-    const float var1 = adiag - rho_j0 * rho_j0 / adiag;
-    f[9] = s == 0 ? 1.0f : (var1 > 1e-12f * adiag ? cov1 * cov1 / var1 / adiag : 0.0f);
+    const float cov1 = rho_i - k.rho_i0 * rho_j0c * k.inv_adiag;
+    const float var1 = k.adiag - rho_j0c * rho_j0c * k.inv_adiag;
+    f[9] = s == 0 ? 1.0f : (var1 > 1e-12f * k.adiag ? cov1 * cov1 * frcp(var1) * k.inv_adiag : 0.0f);
     f[10] = s == 0 ? 1.0f : 0.0f;
-    f[11] = __logf(1.0f + (float)s) / __logf(1.0f + (float)C);
+    f[11] = __logf(1.0f + (float)s) * k.inv_log1p_c;
 #pragma unroll
     for (int q = 12; q < kF; ++q) f[q] = 0.0f;
 }
 
 constexpr int kScrWaves = 2;
 
-// One wave per column.  RPL = candidates per lane (pool <= 64*RPL).
-template <int RPL>
+// One wave per column, grid-stride over the columns (each wave loads the MLP
+// weights once).  The pool (<= 64*RPL*NCH candidates) is processed in NCH
+// chunks of 64*RPL (RPL per lane) for features and the MLP, so only one
+// chunk's candidate state is live; the logits of the whole pool then go
+// through the top-keep selection.
+template <int RPL, int NCH>
 __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
-    constexpr int MAXC = 64 * RPL;
-    __shared__ __align__(16) uint16_t sh_x[kScrWaves][MAXC][kF];
+    constexpr int CH = 64 * RPL;
+    constexpr int MAXC = CH * NCH;
+    constexpr int KPL = RPL * NCH;  // keys per lane
+    __shared__ __align__(16) uint16_t sh_x[kScrWaves][CH][kF];
     __shared__ float sh_z[kScrWaves][MAXC];
+    __shared__ float4 sh_nb[kScrWaves][8];  // nearest eight: offset from the target, distance
+    __shared__ MlpLds sh_w;
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
-    const int64_t col = (int64_t)blockIdx.x * kScrWaves + wib;
-    if (col >= p.n_targets) return;
-    const int32_t tgt = __builtin_amdgcn_readfirstlane(p.targets[col]);
-    int32_t C = __builtin_amdgcn_readfirstlane(p.pool_len[col]);
-    const bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > p.stride || C > MAXC;
-    if (bad) C = 0;
-    const int dim = p.dim;
-    double xi[3] = {0.0, 0.0, 0.0};
-    if (!bad)
-        for (int q = 0; q < dim; ++q) xi[q] = p.pts[(int64_t)tgt * dim + q];
-    // my candidates: offsets from the target
-    float d[RPL][3], r[RPL];
-    int32_t id[RPL];
-    bool my_bad = false;
-#pragma unroll
-    for (int rr = 0; rr < RPL; ++rr) {
-        const int s = rr * 64 + lane;
-        d[rr][0] = d[rr][1] = d[rr][2] = 0.0f;
-        r[rr] = 0.0f;
-        id[rr] = -1;
-        if (s < C) {
-            const int32_t q = p.pool[col * p.stride + s];
-            if (q < 0 || (int64_t)q >= p.n) {
-                my_bad = true;
-            } else {
-                id[rr] = q;
-                for (int c = 0; c < dim; ++c) d[rr][c] = (float)(p.pts[(int64_t)q * dim + c] - xi[c]);
-                r[rr] = sqrtf(d[rr][0] * d[rr][0] + d[rr][1] * d[rr][1] + d[rr][2] * d[rr][2]);
-            }
-        }
-    }
-    if (__any(my_bad) || bad) {
-        if (lane == 0 && p.mode == 0) {
-            p.kept_len[col] = 0;
-            p.fallback[col] = 3;
-        }
-        return;
-    }
-    // the nearest eight candidates (slots 0..7 live in lanes 0..7, rr = 0)
-    NearInfo nb;
-    nb.nnear = min(8, C);
-    nb.d0[0] = bcast(d[0][0], 0);
-    nb.d0[1] = bcast(d[0][1], 0);
-    nb.d0[2] = bcast(d[0][2], 0);
-    nb.r0 = bcast(r[0], 0);
-#pragma unroll
-    for (int l = 0; l < 8; ++l) {
-        nb.dl[l][0] = bcast(d[0][0], l);
-        nb.dl[l][1] = bcast(d[0][1], l);
-        nb.dl[l][2] = bcast(d[0][2], l);
-        nb.rl[l] = bcast(r[0], l);
-    }
-    // features -> LDS (bf16), optionally -> global (fp32)
-#pragma unroll
-    for (int rr = 0; rr < RPL; ++rr) {
-        const int s = rr * 64 + lane;
-        float f[kF];
-        if (s < C) {
-            const float rel0[3] = {d[rr][0] - nb.d0[0], d[rr][1] - nb.d0[1], d[rr][2] - nb.d0[2]};
-            candidate_features(p, C, s, d[rr], r[rr], rel0, nb, f);
-        } else {
-#pragma unroll
-            for (int q = 0; q < kF; ++q) f[q] = 0.0f;
-        }
-#pragma unroll
-        for (int q = 0; q < kF; ++q) sh_x[wib][s][q] = bf16_bits(f[q]);
-        if (p.feats && s < C)
-#pragma unroll
-            for (int q = 0; q < kF; ++q) p.feats[(col * p.stride + s) * kF + q] = f[q];
-    }
-    if (p.mode == 1) return;  // features only
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // MLP over tiles of 16 candidates
-    MlpRegs R;
-    load_mlp(R, p.params, p.params_bf16, lane);
-    const int ntiles = (C + 15) >> 4;
     const int cl = lane & 15, g = lane >> 4;
-    for (int tile = 0; tile < ntiles; ++tile) {
-        const int s = tile * 16 + cl;
-        short4_t xb;
-#pragma unroll
-        for (int i = 0; i < 4; ++i) xb[i] = (short)sh_x[wib][s][4 * g + i];
-        const float z = mlp_tile(R, xb, nullptr, nullptr);
-        if (g == 0) sh_z[wib][s] = z;
+    MlpRegs R;
+    if (p.mode == 0) {
+        stage_mlp(sh_w, p.params_bf16);
+        load_mlp_vec(R, p.params, p.params_bf16, lane);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // keys: monotone logit bits, then the smaller slot
-    uint64_t key[RPL];
-    float zz[RPL];
-#pragma unroll
-    for (int rr = 0; rr < RPL; ++rr) {
-        const int s = rr * 64 + lane;
-        zz[rr] = s < C ? sh_z[wib][s] : 0.0f;
-        const uint32_t b = __float_as_uint(zz[rr]);
-        const uint32_t mono = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-        key[rr] = s < C ? (((uint64_t)mono << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)s)) : 0ull;
-        if (p.logits && s < C) p.logits[col * p.stride + s] = zz[rr];
-    }
-    const int keep = p.keep;
-    uint64_t thr = 0;  // kept = key >= thr
-    bool fb = false;
-    if (C > keep) {
-        // bisection for the keep-th largest key
-        uint64_t lo = 0, hi = ~0ull;
-        while (lo < hi) {
-            const uint64_t mid = lo + (hi - lo) / 2 + 1;
-            int cnt = 0;
-#pragma unroll
-            for (int rr = 0; rr < RPL; ++rr) cnt += __popcll(__ballot(key[rr] >= mid));
-            if (cnt >= keep) lo = mid;
-            else hi = mid - 1;
+    __syncthreads();
+    const int dim = p.dim;
+    for (int64_t col = (int64_t)blockIdx.x * kScrWaves + wib; col < p.n_targets;
+         col += (int64_t)gridDim.x * kScrWaves) {
+        const int32_t tgt = __builtin_amdgcn_readfirstlane(p.targets[col]);
+        int32_t C = __builtin_amdgcn_readfirstlane(p.pool_len[col]);
+        bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > p.stride || C > MAXC;
+        if (bad) C = 0;
+        double xi[3] = {0.0, 0.0, 0.0};
+        if (!bad)
+            for (int q = 0; q < dim; ++q) xi[q] = p.pts[(int64_t)tgt * dim + q];
+        // every pool index in range?
+        bool my_bad = false;
+        for (int s = lane; s < C; s += 64) {
+            const int32_t q = p.pool[col * p.stride + s];
+            my_bad |= q < 0 || (int64_t)q >= p.n;
         }
-        thr = lo;
-        float drop = 0.0f;
+        if (__any(my_bad) || bad) {
+            if (lane == 0 && p.mode == 0) {
+                p.kept_len[col] = 0;
+                p.fallback[col] = 3;
+            }
+            continue;
+        }
+        // the nearest eight candidates -> LDS (read back as broadcasts)
+        if (lane < 8) {
+            float4 v = {0.f, 0.f, 0.f, 0.f};
+            if (lane < C) {
+                const int32_t q = p.pool[col * p.stride + lane];
+                v.x = (float)(p.pts[(int64_t)q * dim] - xi[0]);
+                if (dim > 1) v.y = (float)(p.pts[(int64_t)q * dim + 1] - xi[1]);
+                if (dim > 2) v.z = (float)(p.pts[(int64_t)q * dim + 2] - xi[2]);
+                v.w = __builtin_amdgcn_sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
+            }
+            sh_nb[wib][lane] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        const float4 nb0 = sh_nb[wib][0];
+        const float d0[3] = {nb0.x, nb0.y, nb0.z};
+        ColumnConsts kc;
+        kc.inv_ell = (float)(1.0 / p.ell);
+        kc.cnu = (float)p.c_nu;
+        kc.tiny = 1e-9f * (float)p.ell;
+        kc.adiag = 1.0f + (float)(p.nugget / p.s2);
+        kc.inv_adiag = 1.0f / kc.adiag;
+        kc.r0 = nb0.w;
+        const float r0g = fmaxf(kc.r0, kc.tiny);
+        kc.inv_r0g = 1.0f / r0g;
+        kc.log_r0g = __logf(r0g);
+        kc.rho_i0 = corr(p.two_nu, kc.cnu * kc.r0);
+        kc.inv_c = 1.0f / (float)max(C, 1);
+        kc.inv_log1p_c = 1.0f / __logf(1.0f + (float)max(C, 1));
+        const int nnear = min(8, C);
+        for (int ch = 0; ch < NCH; ++ch) {
+            if (ch * CH >= C) break;
+            // this chunk's candidates: offsets from the target
+            float d[RPL][3], r[RPL];
 #pragma unroll
-        for (int rr = 0; rr < RPL; ++rr)
-            if (key[rr] != 0ull && key[rr] < thr) drop += 1.0f / (1.0f + __expf(-zz[rr]));
-        for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
-        fb = drop > p.fb_thr;
-    } else {
-        thr = 1;  // every valid candidate
-    }
-    // kept candidates in slot order
-    int base = 0;
-    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+            for (int rr = 0; rr < RPL; ++rr) {
+                const int s = ch * CH + rr * 64 + lane;
+                d[rr][0] = d[rr][1] = d[rr][2] = 0.0f;
+                if (s < C) {
+                    const int32_t q = p.pool[col * p.stride + s];
+                    for (int c = 0; c < dim; ++c) d[rr][c] = (float)(p.pts[(int64_t)q * dim + c] - xi[c]);
+                }
+                r[rr] = __builtin_amdgcn_sqrtf(d[rr][0] * d[rr][0] + d[rr][1] * d[rr][1] + d[rr][2] * d[rr][2]);
+            }
+            // nearest-eight terms, neighbour outermost: squared distance to the
+            // nearest other of slots 0..7 (f6) and the count of closer ones inside
+            // the cos > 0.7 cone (f7, tested as d.d_l > 0.7 r_s max(r_l, tiny))
+            float best2[RPL], cnt[RPL];
 #pragma unroll
-    for (int rr = 0; rr < RPL; ++rr) {
-        const bool k = key[rr] != 0ull && key[rr] >= thr;
-        const uint64_t m = __ballot(k);
-        if (k) p.kept[col * keep + base + __popcll(m & below)] = id[rr];
-        base += __popcll(m);
-    }
-    for (int q = base + lane; q < keep; q += 64) p.kept[col * keep + q] = -1;
-    if (lane == 0) {
-        p.kept_len[col] = base;
-        p.fallback[col] = fb ? 1 : 0;
-        if (fb && p.fb_list) {
-            const int pos = atomicAdd(p.fb_count, 1);
-            p.fb_list[pos] = (int32_t)col;
+            for (int rr = 0; rr < RPL; ++rr) {
+                best2[rr] = INFINITY;
+                cnt[rr] = 0.0f;
+            }
+            for (int l = 0; l < nnear; ++l) {
+                const float4 nl = sh_nb[wib][l];
+                const float cone = 0.7f * fmaxf(nl.w, kc.tiny);
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    const int s = ch * CH + rr * 64 + lane;
+                    const float e0 = d[rr][0] - nl.x, e1 = d[rr][1] - nl.y, e2 = d[rr][2] - nl.z;
+                    const float e2s = e0 * e0 + e1 * e1 + e2 * e2;
+                    const float dl = d[rr][0] * nl.x + d[rr][1] * nl.y + d[rr][2] * nl.z;
+                    const bool other = s != l;
+                    best2[rr] = other ? fminf(best2[rr], e2s) : best2[rr];
+                    const float rsv = fmaxf(r[rr], kc.tiny);
+                    cnt[rr] += (other && nl.w < r[rr] && dl > rsv * cone) ? 1.0f : 0.0f;
+                }
+            }
+            // features -> LDS (bf16), optionally -> global (fp32)
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) {
+                const int sl = rr * 64 + lane;
+                const int s = ch * CH + sl;
+                float f[kF];
+                candidate_features(p, kc, s, d[rr], r[rr], d0, f);
+                const float rsv = fmaxf(r[rr], kc.tiny);
+                f[6] = best2[rr] < INFINITY ? __builtin_amdgcn_sqrtf(best2[rr]) * frcp(rsv) : 0.0f;
+                f[7] = cnt[rr] * 0.125f;
+                if (s >= C) {
+#pragma unroll
+                    for (int q = 0; q < kF; ++q) f[q] = 0.0f;
+                }
+                uint4* row = reinterpret_cast<uint4*>(&sh_x[wib][sl][0]);
+                row[0] = uint4{pack_bf16x2(f[0], f[1]), pack_bf16x2(f[2], f[3]), pack_bf16x2(f[4], f[5]),
+                               pack_bf16x2(f[6], f[7])};
+                row[1] = uint4{pack_bf16x2(f[8], f[9]), pack_bf16x2(f[10], f[11]), pack_bf16x2(f[12], f[13]),
+                               pack_bf16x2(f[14], f[15])};
+                if (p.feats && s < C)
+#pragma unroll
+                    for (int q = 0; q < kF; ++q) p.feats[(col * p.stride + s) * kF + q] = f[q];
+            }
+            if (p.mode == 1) continue;  // features only
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            // MLP over this chunk's tiles of 16 candidates
+            const int ntiles = (min(C - ch * CH, CH) + 15) >> 4;
+            for (int tile = 0; tile < ntiles; ++tile) {
+                const int sl = tile * 16 + cl;
+                const short4_t xb =
+                    __builtin_bit_cast(short4_t, *reinterpret_cast<const uint2*>(&sh_x[wib][sl][4 * g]));
+                const float z = mlp_tile_lds(R, sh_w, xb, lane);
+                if (g == 0) sh_z[wib][ch * CH + sl] = z;
+            }
+            __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (p.mode == 1) continue;
+        // 32-bit keys: the monotone image of the logit with its low 9 bits replaced
+        // by (511 - slot): larger logit first (at 2^-14 relative resolution), then
+        // the smaller slot; 0 marks an empty slot.  Slot s = kk*64 + lane.
+        uint32_t key[KPL];
+        float zz[KPL];
+#pragma unroll
+        for (int kk = 0; kk < KPL; ++kk) {
+            const int s = kk * 64 + lane;
+            zz[kk] = s < C ? sh_z[wib][s] : 0.0f;
+            const uint32_t b = __float_as_uint(zz[kk]);
+            const uint32_t mono = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+            key[kk] = s < C ? ((mono & ~0x1FFu) | (uint32_t)(511 - s)) : 0u;
+            if (p.logits && s < C) p.logits[col * p.stride + s] = zz[kk];
+        }
+        const int keep = p.keep;
+        uint32_t thr = 1u;  // kept = key >= thr
+        bool fb = false;
+        if (C > keep) {
+            // bisection for the keep-th largest key (keys are distinct)
+            uint32_t lo = 0u, hi = 0xFFFFFFFFu;
+            while (lo < hi) {
+                const uint32_t mid = lo + (hi - lo) / 2u + 1u;
+                int cntk = 0;
+#pragma unroll
+                for (int kk = 0; kk < KPL; ++kk) cntk += __popcll(__ballot(key[kk] >= mid));
+                if (cntk >= keep) lo = mid;
+                else hi = mid - 1u;
+            }
+            thr = lo;
+            float drop = 0.0f;
+#pragma unroll
+            for (int kk = 0; kk < KPL; ++kk)
+                if (key[kk] != 0u && key[kk] < thr) drop += 1.0f / (1.0f + __expf(-zz[kk]));
+            for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+            fb = drop > p.fb_thr;
+        }
+        // kept candidates in slot order
+        int base = 0;
+        const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+#pragma unroll
+        for (int kk = 0; kk < KPL; ++kk) {
+            const int s = kk * 64 + lane;
+            const bool k = key[kk] != 0u && key[kk] >= thr;
+            const uint64_t m = __ballot(k);
+            if (k) p.kept[col * keep + base + __popcll(m & below)] = p.pool[col * p.stride + s];
+            base += __popcll(m);
+        }
+        for (int q = base + lane; q < keep; q += 64) p.kept[col * keep + q] = -1;
+        if (lane == 0) {
+            p.kept_len[col] = base;
+            p.fallback[col] = fb ? 1 : 0;
+            if (fb && p.fb_list) {
+                const int pos = atomicAdd(p.fb_count, 1);
+                p.fb_list[pos] = (int32_t)col;
+            }
         }
     }
 }
@@ -545,12 +670,13 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(MlpTrainArgs p, float* 
 // ---------------------------------------------------------------------------
 hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
     if (a.n_targets == 0) return hipSuccess;
-    const unsigned grid = (unsigned)((a.n_targets + kScrWaves - 1) / kScrWaves);
+    // enough waves to fill the chip several times over; each loops over columns
+    const unsigned grid = (unsigned)std::min<int64_t>((a.n_targets + kScrWaves - 1) / kScrWaves, 8192);
     switch (rpl) {
-        case 1: hipLaunchKernelGGL(screen_kernel<1>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL(screen_kernel<2>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
-        case 4: hipLaunchKernelGGL(screen_kernel<4>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
-        case 8: hipLaunchKernelGGL(screen_kernel<8>, dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 1: hipLaunchKernelGGL((screen_kernel<1, 1>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 2: hipLaunchKernelGGL((screen_kernel<2, 1>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 4: hipLaunchKernelGGL((screen_kernel<4, 1>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 8: hipLaunchKernelGGL((screen_kernel<4, 2>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();

@@ -6,28 +6,36 @@
 
 namespace csel {
 
-hipError_t launch_select_float_1(const SelectArgs&, int, int, hipStream_t);
-hipError_t launch_select_float_3(const SelectArgs&, int, int, hipStream_t);
-hipError_t launch_select_float_5(const SelectArgs&, int, int, hipStream_t);
-hipError_t launch_select_double_1(const SelectArgs&, int, int, hipStream_t);
-hipError_t launch_select_double_3(const SelectArgs&, int, int, hipStream_t);
-hipError_t launch_select_double_5(const SelectArgs&, int, int, hipStream_t);
+#define CSEL_DECL(T, NU)                                                              \
+    hipError_t launch_select_##T##_##NU##_0(const SelectArgs&, int, int, hipStream_t); \
+    hipError_t launch_select_##T##_##NU##_1(const SelectArgs&, int, int, hipStream_t);
+CSEL_DECL(float, 1)
+CSEL_DECL(float, 3)
+CSEL_DECL(float, 5)
+CSEL_DECL(double, 1)
+CSEL_DECL(double, 3)
+CSEL_DECL(double, 5)
+#undef CSEL_DECL
 
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s) {
     if (a.n_targets == 0 || a.n_waves == 0) return hipSuccess;
+    const bool gap = a.gap != nullptr;
+#define CSEL_CASE(T, NU) \
+    return gap ? launch_select_##T##_##NU##_1(a, rpl, kmax, s) : launch_select_##T##_##NU##_0(a, rpl, kmax, s);
     if (precision == 0) {
         switch (a.two_nu) {
-            case 1: return launch_select_double_1(a, rpl, kmax, s);
-            case 3: return launch_select_double_3(a, rpl, kmax, s);
-            case 5: return launch_select_double_5(a, rpl, kmax, s);
+            case 1: CSEL_CASE(double, 1)
+            case 3: CSEL_CASE(double, 3)
+            case 5: CSEL_CASE(double, 5)
         }
     } else {
         switch (a.two_nu) {
-            case 1: return launch_select_float_1(a, rpl, kmax, s);
-            case 3: return launch_select_float_3(a, rpl, kmax, s);
-            case 5: return launch_select_float_5(a, rpl, kmax, s);
+            case 1: CSEL_CASE(float, 1)
+            case 3: CSEL_CASE(float, 3)
+            case 5: CSEL_CASE(float, 5)
         }
     }
+#undef CSEL_CASE
     return hipErrorInvalidValue;
 }
 

@@ -29,6 +29,20 @@
 
 namespace csel {
 
+// distance square root: the hardware v_sqrt_f32 (1 ulp) in FP32, the
+// correctly rounded one in FP64
+template <typename T>
+__device__ __forceinline__ T tsqrt(T x) {
+    if constexpr (sizeof(T) == 4) return __builtin_amdgcn_sqrtf(x);
+    else return sqrt(x);
+}
+
+// 1/v in FP64: hardware reciprocal refined by one Newton step (about 1 ulp)
+__device__ __forceinline__ double rcp64(double v) {
+    const double r = __builtin_amdgcn_rcp(v);
+    return r * fma(-v, r, 2.0);
+}
+
 template <typename T, int TWO_NU>
 __device__ __forceinline__ T matern(T r, T c, T s2) {
     if constexpr (sizeof(T) == 4) return matern_f32<TWO_NU>(r, c, s2);
@@ -37,7 +51,9 @@ __device__ __forceinline__ T matern(T r, T c, T s2) {
 
 constexpr int kSelWavesPerBlock = 4;
 
-template <typename T, int TWO_NU, int RPL, int KMAX>
+// GAP: also track the second-best score of every step (top-two reduction) for
+// the top2_gap output; without it the reduction is a plain maximum.
+template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
 __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
     __shared__ double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
@@ -91,7 +107,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 live |= 1u << rr;
             }
         }
-        const T r = sqrt(dx[rr][0] * dx[rr][0] + dx[rr][1] * dx[rr][1] + dx[rr][2] * dx[rr][2]);
+        const T r = tsqrt(dx[rr][0] * dx[rr][0] + dx[rr][1] * dx[rr][1] + dx[rr][2] * dx[rr][2]);
         cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
         var[rr] = prior;
     }
@@ -122,15 +138,28 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 #pragma unroll
     for (int t = 0; t < KMAX; ++t) {
         if (t < kk && !stopped) {
-            Top2 loc = {0ull, 0ull};
+            Top2 w;
+            if constexpr (GAP) {
+                Top2 loc = {0ull, 0ull};
 #pragma unroll
-            for (int rr = 0; rr < RPL; ++rr) {
-                if (((live >> rr) & 1u) && var[rr] > thr) {
-                    const double sc = cov[rr] * cov[rr] / var[rr];
-                    insert(loc, make_key(sc, rr * kWave + lane));
+                for (int rr = 0; rr < RPL; ++rr) {
+                    if (((live >> rr) & 1u) && var[rr] > thr) {
+                        const double sc = cov[rr] * cov[rr] * rcp64(var[rr]);
+                        insert(loc, make_key(sc, rr * kWave + lane));
+                    }
                 }
+                w = wave_top2(loc);
+            } else {
+                uint64_t best = 0ull;
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    const double sc = cov[rr] * cov[rr] * rcp64(var[rr]);
+                    const uint64_t key = (((live >> rr) & 1u) && var[rr] > thr) ? make_key(sc, rr * kWave + lane) : 0ull;
+                    best = key > best ? key : best;
+                }
+                w.k1 = wave_max64(best);
+                w.k2 = 0ull;
             }
-            const Top2 w = wave_top2(loc);
             if (w.k1 == 0ull) {
                 st = 1;
                 stopped = true;
@@ -165,7 +194,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
                     const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
-                    const T r = sqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    const T r = tsqrt(e0 * e0 + e1 * e1 + e2 * e2);
                     T acc = matern<T, TWO_NU>(r, cnu, s2);
                     if (pid[rr] == idk) acc += nug;
 #pragma unroll
@@ -198,15 +227,37 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         if (dim > 2) xr2 = p.pts[(int64_t)my_id * dim + 2];
     }
     const double cnu64 = p.c_nu, s264 = p.s2, nug64 = p.nugget;
+    // Theta' lower triangle, its tri(M) entries spread over the 64 lanes, staged
+    // in LDS; then lane r loads its row
+    double(*TH)[KMAX + 2] = sh_r[wib];
+    {
+        const int ne = M * (M + 1) / 2;
+        // uniform trip count: every lane takes part in the cross-lane reads
+        for (int e0 = 0; e0 < ne; e0 += kWave) {
+            const int e = min(e0 + lane, ne - 1);
+            int r = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+            while ((r + 1) * (r + 2) / 2 <= e) ++r;
+            while (r * (r + 1) / 2 > e) --r;
+            const int c = e - r * (r + 1) / 2;
+            const int32_t sr = bcast_dyn(my_sel, r), sc_ = bcast_dyn(my_sel, c);
+            const int32_t ir = r < nsel ? sr : tgt;
+            const int32_t ic = c < nsel ? sc_ : tgt;
+            if (e0 + lane >= ne) continue;
+            double s = 0.0;
+            for (int q = 0; q < dim; ++q) {
+                const double df = p.pts[(int64_t)ir * dim + q] - p.pts[(int64_t)ic * dim + q];
+                s += df * df;
+            }
+            TH[r][c] = matern_f64<TWO_NU>(sqrt(s), cnu64, s264) + (ir == ic ? nug64 : 0.0);
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     double a[KMAX + 1];
 #pragma unroll
-    for (int c = 0; c <= KMAX; ++c) {
-        if (c >= M) continue;
-        const double y0 = bcast(xr0, c), y1 = bcast(xr1, c), y2 = bcast(xr2, c);
-        const int32_t idc = bcast(my_id, c);
-        const double e0 = xr0 - y0, e1 = xr1 - y1, e2 = xr2 - y2;
-        a[c] = matern_f64<TWO_NU>(sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnu64, s264) + (my_id == idc ? nug64 : 0.0);
-    }
+    for (int c = 0; c <= KMAX; ++c) a[c] = (c <= lane && lane < M) ? TH[lane][c] : 0.0;
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     bool pd = true;
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
@@ -269,28 +320,28 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     if (lane == 0) p.status[col] = (uint8_t)st;
 }
 
-template <typename T, int TWO_NU, int RPL, int KMAX>
+template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
 static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
     const int64_t blocks = (a.n_waves + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
-    hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX>), dim3((unsigned)blocks), dim3(256), 0, s, a);
+    hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX, GAP>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
-template <typename T, int TWO_NU>
+template <typename T, int TWO_NU, bool GAP>
 static hipError_t launch_nu_impl(const SelectArgs& a, int rpl, int kmax, hipStream_t s) {
     if (kmax == 16) {
         switch (rpl) {
-            case 1: return launch_one<T, TWO_NU, 1, 16>(a, s);
-            case 2: return launch_one<T, TWO_NU, 2, 16>(a, s);
-            case 4: return launch_one<T, TWO_NU, 4, 16>(a, s);
-            case 8: return launch_one<T, TWO_NU, 8, 16>(a, s);
+            case 1: return launch_one<T, TWO_NU, 1, 16, GAP>(a, s);
+            case 2: return launch_one<T, TWO_NU, 2, 16, GAP>(a, s);
+            case 4: return launch_one<T, TWO_NU, 4, 16, GAP>(a, s);
+            case 8: return launch_one<T, TWO_NU, 8, 16, GAP>(a, s);
         }
     } else if (kmax == 32) {
         switch (rpl) {
-            case 1: return launch_one<T, TWO_NU, 1, 32>(a, s);
-            case 2: return launch_one<T, TWO_NU, 2, 32>(a, s);
-            case 4: return launch_one<T, TWO_NU, 4, 32>(a, s);
-            case 8: return launch_one<T, TWO_NU, 8, 32>(a, s);
+            case 1: return launch_one<T, TWO_NU, 1, 32, GAP>(a, s);
+            case 2: return launch_one<T, TWO_NU, 2, 32, GAP>(a, s);
+            case 4: return launch_one<T, TWO_NU, 4, 32, GAP>(a, s);
+            case 8: return launch_one<T, TWO_NU, 8, 32, GAP>(a, s);
         }
     }
     return hipErrorInvalidValue;

@@ -209,3 +209,18 @@ def test_host_validation_errors():
         csel.select_and_factor(x, inputs.Kernel(3, 0.1), t, p, t, 40)
     with pytest.raises(ValueError):
         csel.select_and_factor(x.cpu(), inputs.Kernel(3, 0.1), t, p, t, 2)
+
+
+def test_gap_and_no_gap_variants_agree():
+    """The kernel without top2_gap (a plain maximum instead of the top-two
+    reduction) takes the same decisions bit for bit."""
+    print("case: gap vs no-gap variants", flush=True)
+    w = inputs.workload_plain_batched(n=6000, seed=9)
+    pts = _dev(w.points, torch.float64)
+    args = (_dev(w.targets, torch.int32), _dev(w.pool, torch.int32), _dev(w.pool_len, torch.int32))
+    for prec in ("fp64", "mixed"):
+        a = csel.select_and_factor(pts, w.kernel, *args, 32, prec, want_gap=True)
+        b = csel.select_and_factor(pts, w.kernel, *args, 32, prec, want_gap=False)
+        torch.cuda.synchronize()
+        for key in ("sel", "factor", "log_condvar", "status"):
+            assert torch.equal(a[key], b[key]), (prec, key)
