@@ -19,9 +19,10 @@ candidate j of target i (pool sorted by distance, slot s, nearest slot 0):
 with d_s = x_{p_s} - x_i, r_s = |d_s|, guarded against zero distances.
 
 MLP: 16 -> 64 -> 64 -> 1 with ReLU.  The GPU computes it with BF16 inputs,
-BF16 weights and BF16 first-layer activations (MFMA operands) and FP32
-accumulation; `mlp_forward(..., bf16=True)` evaluates the same rounded
-quantities in FP64 so the two sides differ only by accumulation order.
+BF16 weights and BF16 activations of both hidden layers (matrix-core
+operands) and FP32 accumulation; `mlp_forward(..., bf16=True)` evaluates the
+same rounded quantities in FP64 so the two sides differ only by accumulation
+order.  The backward pass takes the rounding as the identity.
 Parameters are one FP32 vector: W1[16][64], b1[64], W2[64][64], b2[64],
 w3[64], b3 (5313 values).
 """
@@ -130,8 +131,9 @@ def mlp_forward(X, p, bf16=True):
     H1q = bf16_round(H1) if bf16 else H1
     Z2 = H1q @ W2 + b2
     H2 = np.maximum(Z2, 0.0)
-    z = H2 @ w3 + b3
-    return z, {"X": X, "W1": W1, "W2": W2, "w3": w3, "H1": H1, "H1q": H1q, "H2": H2}
+    H2q = bf16_round(H2) if bf16 else H2
+    z = H2q @ w3 + b3
+    return z, {"X": X, "W1": W1, "W2": W2, "w3": w3, "H1": H1, "H1q": H1q, "H2": H2, "H2q": H2q}
 
 
 def bce_loss_and_grad(X, y, p, pos_weight=1.0, bf16=True):
@@ -148,7 +150,7 @@ def bce_loss_and_grad(X, y, p, pos_weight=1.0, bf16=True):
     dz = wgt * (sig - y) / N
     g = np.zeros(N_PARAMS)
     H2, H1q, H1 = a["H2"], a["H1q"], a["H1"]
-    g[OFF_W3:OFF_B3] = H2.T @ dz
+    g[OFF_W3:OFF_B3] = a["H2q"].T @ dz
     g[OFF_B3] = dz.sum()
     dH2 = np.outer(dz, a["w3"]) * (H2 > 0)
     g[OFF_W2:OFF_B2] = (H1q.T @ dH2).ravel()

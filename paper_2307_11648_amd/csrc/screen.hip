@@ -13,7 +13,10 @@
 // v_mfma_f32_16x16x16_bf16 tiles (A: weights, 16 hidden x 16 k; B: 16 k x 16
 // candidates; D: 16 hidden x 16 candidates).  Lane l of a 16x16x16 MFMA holds
 // A[l%16][4(l/16)+i], B[4(l/16)+i][l%16] and D[4(l/16)+i][l%16], i = 0..3.
-// The last layer (64 -> 1) is a VALU dot product plus a cross-row sum.
+// The second hidden layer's activations are rounded to BF16 as well; the
+// screen evaluates the last layer (64 -> 1) as an MFMA with w3 in the first
+// row of A, the training kernels as a VALU dot product of the same rounded
+// values.
 //
 // Parameters: one FP32 vector W1[16][64], b1[64], W2[64][64], b2[64],
 // w3[64], b3 and its BF16 copy (same indexing); weights enter the MFMAs in
@@ -22,6 +25,10 @@
 
 #include "device_common.hpp"
 #include "launch.hpp"
+
+#ifndef KNT
+#define KNT 4
+#endif
 
 namespace csel {
 
@@ -94,6 +101,13 @@ __device__ __forceinline__ short4_t pack_bf16x4(float a, float b, float c, float
     return __builtin_bit_cast(short4_t, v);
 }
 
+// ReLU of packed bf16 values: rounding to bf16 keeps the sign, and a bf16
+// with its sign bit set reads as a negative int16, so max(., 0) per 16-bit
+// half (v_pk_max_i16) equals rounding max(x, 0).
+__device__ __forceinline__ short4_t relu_bf16x4(short4_t v) {
+    return __builtin_elementwise_max(v, short4_t{0, 0, 0, 0});
+}
+
 // Forward for one tile of 16 candidates; xb = B operand (feat 4g+i of candidate l%16).
 // The biases seed the MFMA accumulators.  Returns the logit of candidate l%16
 // (identical in the four lanes that share it); optionally exposes H1 (bf16
@@ -104,7 +118,7 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs& R, short4_t xb, short4_
     for (int h = 0; h < 4; ++h) {
         float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a1[h], xb, acc, 0, 0, 0);
-        h1q[h] = pack_bf16x4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
+        h1q[h] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
     }
     float part = 0.0f;
 #pragma unroll
@@ -112,10 +126,11 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs& R, short4_t xb, short4_
         float4_t acc = {R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
 #pragma unroll
         for (int h = 0; h < 4; ++h) acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(R.a2[h2][h], h1q[h], acc, 0, 0, 0);
+        const short4_t h2q = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
         float4_t hv;
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
-            hv[i] = fmaxf(acc[i], 0.0f);
+            hv[i] = bf16_to_f32((uint16_t)h2q[i]);
             part += hv[i] * R.w3[h2][i];
         }
         if (h2_out) h2_out[h2] = hv;
@@ -131,24 +146,48 @@ __device__ __forceinline__ float mlp_tile(const MlpRegs& R, short4_t xb, short4_
 
 // Weight operands of the MFMAs staged in LDS (shared by the waves of a block)
 // in per-lane operand order: A fragment f of lane l at [f][l].
+// Layer 2 uses v_mfma_f32_16x16x32_bf16 (lane l: A[l%16][8(l/16)+j], B[8(l/16)+j][l%16],
+// j = 0..7).  Its K = 32 block q covers hidden units 32q + 4g + (0..3) and
+// 32q + 16 + 4g + (0..3) for lane group g, the order in which the layer-1
+// output fragments of tiles 2q and 2q+1 sit in a lane, so B is their plain
+// concatenation; W2 is staged in the same order.
+// The last layer uses the same K = 32 blocks with A = w3 in row 0 (lanes
+// l % 16 == 0), zeros elsewhere.
 struct MlpLds {
     uint2 a1[4][64];
-    uint2 a2[16][64];  // fragment 4*h2 + h
+    uint4 a2[4][2][64];  // [h2][q][lane]
+    uint4 a3[2][64];     // [q][lane]
 };
 
 __device__ __forceinline__ void stage_mlp(MlpLds& L, const uint16_t* __restrict__ pb) {
-    for (int e = threadIdx.x; e < 20 * 64; e += blockDim.x) {
+    for (int e = threadIdx.x; e < 14 * 64; e += blockDim.x) {
         const int f = e >> 6, l = e & 63, c = l & 15, g = l >> 4;
-        short4_t v;
-        if (f < 4) {
+        if (f >= 12) {
+            const int q = f - 12;
+            uint32_t w[4];
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int u0 = 32 * q + (2 * j < 4 ? 4 * g + 2 * j : 16 + 4 * g + (2 * j - 4));
+                w[j] = c == 0 ? (uint32_t)pb[kOffW3 + u0] | ((uint32_t)pb[kOffW3 + u0 + 1] << 16) : 0u;
+            }
+            L.a3[q][l] = uint4{w[0], w[1], w[2], w[3]};
+        } else if (f < 4) {
+            short4_t v;
 #pragma unroll
             for (int i = 0; i < 4; ++i) v[i] = (short)pb[kOffW1 + (4 * g + i) * kH + 16 * f + c];
             L.a1[f][l] = __builtin_bit_cast(uint2, v);
         } else {
-            const int h2 = (f - 4) >> 2, h = (f - 4) & 3;
+            const int h2 = (f - 4) >> 1, q = (f - 4) & 1;
+            short v[8];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) v[i] = (short)pb[kOffW2 + (16 * h + 4 * g + i) * kH + 16 * h2 + c];
-            L.a2[f - 4][l] = __builtin_bit_cast(uint2, v);
+            for (int j = 0; j < 8; ++j) {
+                const int unit = 32 * q + (j < 4 ? 4 * g + j : 16 + 4 * g + (j - 4));
+                v[j] = (short)pb[kOffW2 + unit * kH + 16 * h2 + c];
+            }
+            L.a2[h2][q][l] = uint4{(uint32_t)(uint16_t)v[0] | ((uint32_t)(uint16_t)v[1] << 16),
+                                   (uint32_t)(uint16_t)v[2] | ((uint32_t)(uint16_t)v[3] << 16),
+                                   (uint32_t)(uint16_t)v[4] | ((uint32_t)(uint16_t)v[5] << 16),
+                                   (uint32_t)(uint16_t)v[6] | ((uint32_t)(uint16_t)v[7] << 16)};
         }
     }
 }
@@ -160,22 +199,87 @@ __device__ __forceinline__ float mlp_tile_lds(const MlpRegs& R, const MlpLds& L,
     for (int h = 0; h < 4; ++h) {
         float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
         acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, L.a1[h][lane]), xb, acc, 0, 0, 0);
-        h1q[h] = pack_bf16x4(fmaxf(acc[0], 0.0f), fmaxf(acc[1], 0.0f), fmaxf(acc[2], 0.0f), fmaxf(acc[3], 0.0f));
+        h1q[h] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
     }
-    float part = 0.0f;
+    bf16x8_t b2op[2];
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint2 lo = __builtin_bit_cast(uint2, h1q[2 * q]), hi = __builtin_bit_cast(uint2, h1q[2 * q + 1]);
+        b2op[q] = __builtin_bit_cast(bf16x8_t, uint4{lo.x, lo.y, hi.x, hi.y});
+    }
+    short4_t h2q[4];
 #pragma unroll
     for (int h2 = 0; h2 < 4; ++h2) {
         float4_t acc = {R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
 #pragma unroll
-        for (int h = 0; h < 4; ++h)
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, L.a2[4 * h2 + h][lane]),
-                                                             h1q[h], acc, 0, 0, 0);
-#pragma unroll
-        for (int i = 0; i < 4; ++i) part += fmaxf(acc[i], 0.0f) * R.w3[h2][i];
+        for (int q = 0; q < 2; ++q)
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, L.a2[h2][q][lane]), b2op[q],
+                                                          acc, 0, 0, 0);
+        h2q[h2] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
     }
-    part += __shfl_xor(part, 16, 64);
-    part += __shfl_xor(part, 32, 64);
-    return part + R.b3;
+    float4_t acc = {R.b3, R.b3, R.b3, R.b3};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const uint2 lo = __builtin_bit_cast(uint2, h2q[2 * q]), hi = __builtin_bit_cast(uint2, h2q[2 * q + 1]);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, L.a3[q][lane]),
+                                                      __builtin_bit_cast(bf16x8_t, uint4{lo.x, lo.y, hi.x, hi.y}),
+                                                      acc, 0, 0, 0);
+    }
+    return acc[0];  // row 0 of D: the logit of candidate l % 16 in lanes 0..15
+}
+
+// As mlp_tile_lds for NT independent tiles at once: each weight operand is
+// read from LDS once and applied to every tile, and the tiles' MFMA chains
+// interleave.
+template <int NT>
+__device__ __forceinline__ void mlp_tiles_lds(const MlpRegs& R, const MlpLds& L, const short4_t (&xb)[NT],
+                                              float (&z)[NT], int lane) {
+    short4_t h1q[NT][4];
+#pragma unroll
+    for (int h = 0; h < 4; ++h) {
+        const short4_t a = __builtin_bit_cast(short4_t, L.a1[h][lane]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
+            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb[t], acc, 0, 0, 0);
+            h1q[t][h] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
+        }
+    }
+    short4_t h2q[NT][4];
+#pragma unroll
+    for (int h2 = 0; h2 < 4; ++h2) {
+        float4_t acc[NT];
+#pragma unroll
+        for (int t = 0; t < NT; ++t) acc[t] = float4_t{R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            const bf16x8_t a = __builtin_bit_cast(bf16x8_t, L.a2[h2][q][lane]);
+#pragma unroll
+            for (int t = 0; t < NT; ++t) {
+                const uint2 lo = __builtin_bit_cast(uint2, h1q[t][2 * q]);
+                const uint2 hi = __builtin_bit_cast(uint2, h1q[t][2 * q + 1]);
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(
+                    a, __builtin_bit_cast(bf16x8_t, uint4{lo.x, lo.y, hi.x, hi.y}), acc[t], 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < NT; ++t) h2q[t][h2] = relu_bf16x4(pack_bf16x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
+    }
+    float4_t acc[NT];
+#pragma unroll
+    for (int t = 0; t < NT; ++t) acc[t] = float4_t{R.b3, R.b3, R.b3, R.b3};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const bf16x8_t a = __builtin_bit_cast(bf16x8_t, L.a3[q][lane]);
+#pragma unroll
+        for (int t = 0; t < NT; ++t) {
+            const uint2 lo = __builtin_bit_cast(uint2, h2q[t][2 * q]), hi = __builtin_bit_cast(uint2, h2q[t][2 * q + 1]);
+            acc[t] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, __builtin_bit_cast(bf16x8_t, uint4{lo.x, lo.y, hi.x, hi.y}),
+                                                             acc[t], 0, 0, 0);
+        }
+    }
+#pragma unroll
+    for (int t = 0; t < NT; ++t) z[t] = acc[t][0];
 }
 
 // biases and w3 only (the screen keeps the MFMA operands in LDS)
@@ -241,6 +345,8 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
     constexpr int CH = 64 * RPL;
     constexpr int MAXC = CH * NCH;
     constexpr int KPL = RPL * NCH;  // keys per lane
+    constexpr int kNT = KNT;
+    static_assert((CH / 16) % kNT == 0, "tile groups must divide a chunk");
     __shared__ __align__(16) uint16_t sh_x[kScrWaves][CH][kF];
     __shared__ float sh_z[kScrWaves][MAXC];
     __shared__ float4 sh_nb[kScrWaves][8];  // nearest eight: offset from the target, distance
@@ -255,71 +361,110 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
     }
     __syncthreads();
     const int dim = p.dim;
-    for (int64_t col = (int64_t)blockIdx.x * kScrWaves + wib; col < p.n_targets;
-         col += (int64_t)gridDim.x * kScrWaves) {
-        const int32_t tgt = __builtin_amdgcn_readfirstlane(p.targets[col]);
-        int32_t C = __builtin_amdgcn_readfirstlane(p.pool_len[col]);
-        bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > p.stride || C > MAXC;
-        if (bad) C = 0;
-        double xi[3] = {0.0, 0.0, 0.0};
-        if (!bad)
-            for (int q = 0; q < dim; ++q) xi[q] = p.pts[(int64_t)tgt * dim + q];
-        // every pool index in range?
-        bool my_bad = false;
-        for (int s = lane; s < C; s += 64) {
-            const int32_t q = p.pool[col * p.stride + s];
-            my_bad |= q < 0 || (int64_t)q >= p.n;
+    ColumnConsts kc0;
+    kc0.inv_ell = (float)(1.0 / p.ell);
+    kc0.cnu = (float)p.c_nu;
+    kc0.tiny = 1e-9f * (float)p.ell;
+    kc0.adiag = 1.0f + (float)(p.nugget / p.s2);
+    kc0.inv_adiag = 1.0f / kc0.adiag;
+    const int64_t cstep = (int64_t)gridDim.x * kScrWaves;
+    const int lim = min(p.stride, MAXC);  // pool entries a column may use
+    // The next column's target, pool length, pool indices (slot kk*64 + lane)
+    // and target coordinates (lane c < dim) are loaded while this column is
+    // processed; the pool indices stay in registers for the whole column.
+    int32_t nx_pid[KPL];
+    int32_t nx_tgt = -1, nx_len = 0;
+    double nx_xc = 0.0;
+    auto fetch_ids = [&](int64_t c) {
+        nx_tgt = -1;
+        nx_len = 0;
+#pragma unroll
+        for (int kk = 0; kk < KPL; ++kk) nx_pid[kk] = -1;
+        if (c < p.n_targets) {
+            if (lane == 0) {  // vector loads, so they complete in order with the gathers
+                nx_tgt = p.targets[c];
+                nx_len = p.pool_len[c];
+            }
+#pragma unroll
+            for (int kk = 0; kk < KPL; ++kk)
+                if (kk * 64 + lane < lim) nx_pid[kk] = p.pool[c * p.stride + kk * 64 + lane];
         }
+    };
+    auto fetch_xi = [&]() {
+        const int32_t t = __builtin_amdgcn_readfirstlane(nx_tgt);
+        nx_xc = 0.0;
+        if (t >= 0 && (int64_t)t < p.n && lane < dim) nx_xc = p.pts[(int64_t)t * dim + lane];
+    };
+    int64_t col = (int64_t)blockIdx.x * kScrWaves + wib;
+    fetch_ids(col);
+    fetch_xi();
+    for (; col < p.n_targets; col += cstep) {
+        const int32_t tgt = __builtin_amdgcn_readfirstlane(nx_tgt);
+        int32_t C = __builtin_amdgcn_readfirstlane(nx_len);
+        int32_t pid[KPL];
+#pragma unroll
+        for (int kk = 0; kk < KPL; ++kk) pid[kk] = nx_pid[kk];
+        const double xi[3] = {bcast(nx_xc, 0), bcast(nx_xc, 1), bcast(nx_xc, 2)};  // zero past dim
+        fetch_ids(col + cstep);
+        const bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > lim;
+        bool my_bad = false;
+#pragma unroll
+        for (int kk = 0; kk < KPL; ++kk)
+            if (kk * 64 + lane < C) my_bad |= pid[kk] < 0 || (int64_t)pid[kk] >= p.n;
         if (__any(my_bad) || bad) {
             if (lane == 0 && p.mode == 0) {
                 p.kept_len[col] = 0;
                 p.fallback[col] = 3;
             }
+            fetch_xi();
             continue;
         }
-        // the nearest eight candidates -> LDS (read back as broadcasts)
-        if (lane < 8) {
-            float4 v = {0.f, 0.f, 0.f, 0.f};
-            if (lane < C) {
-                const int32_t q = p.pool[col * p.stride + lane];
-                v.x = (float)(p.pts[(int64_t)q * dim] - xi[0]);
-                if (dim > 1) v.y = (float)(p.pts[(int64_t)q * dim + 1] - xi[1]);
-                if (dim > 2) v.z = (float)(p.pts[(int64_t)q * dim + 2] - xi[2]);
-                v.w = __builtin_amdgcn_sqrtf(v.x * v.x + v.y * v.y + v.z * v.z);
-            }
-            sh_nb[wib][lane] = v;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-        const float4 nb0 = sh_nb[wib][0];
-        const float d0[3] = {nb0.x, nb0.y, nb0.z};
-        ColumnConsts kc;
-        kc.inv_ell = (float)(1.0 / p.ell);
-        kc.cnu = (float)p.c_nu;
-        kc.tiny = 1e-9f * (float)p.ell;
-        kc.adiag = 1.0f + (float)(p.nugget / p.s2);
-        kc.inv_adiag = 1.0f / kc.adiag;
-        kc.r0 = nb0.w;
-        const float r0g = fmaxf(kc.r0, kc.tiny);
-        kc.inv_r0g = 1.0f / r0g;
-        kc.log_r0g = __logf(r0g);
-        kc.rho_i0 = corr(p.two_nu, kc.cnu * kc.r0);
-        kc.inv_c = 1.0f / (float)max(C, 1);
-        kc.inv_log1p_c = 1.0f / __logf(1.0f + (float)max(C, 1));
+        if (C == 0) fetch_xi();
+        ColumnConsts kc = kc0;
+        float d0[3] = {0.0f, 0.0f, 0.0f};
         const int nnear = min(8, C);
         for (int ch = 0; ch < NCH; ++ch) {
             if (ch * CH >= C) break;
-            // this chunk's candidates: offsets from the target
+            // this chunk's candidates: offsets from the target (one gather per coordinate)
+            double xq[RPL][3];
+#pragma unroll
+            for (int rr = 0; rr < RPL; ++rr) {
+                const int kk = ch * RPL + rr;
+                const bool ok = kk * 64 + lane < C;
+                const int64_t base = (int64_t)(ok ? pid[kk] : tgt) * dim;
+                // branch-free (a clamped coordinate, zeroed past dim) so the
+                // loads stay in flight together
+#pragma unroll
+                for (int c = 0; c < 3; ++c) {
+                    const double v = p.pts[base + min(c, dim - 1)];
+                    xq[rr][c] = c < dim ? v : 0.0;
+                }
+            }
+            if (ch == 0) fetch_xi();  // the next target index was loaded before these gathers
             float d[RPL][3], r[RPL];
 #pragma unroll
             for (int rr = 0; rr < RPL; ++rr) {
-                const int s = ch * CH + rr * 64 + lane;
-                d[rr][0] = d[rr][1] = d[rr][2] = 0.0f;
-                if (s < C) {
-                    const int32_t q = p.pool[col * p.stride + s];
-                    for (int c = 0; c < dim; ++c) d[rr][c] = (float)(p.pts[(int64_t)q * dim + c] - xi[c]);
-                }
+#pragma unroll
+                for (int c = 0; c < 3; ++c) d[rr][c] = (float)(xq[rr][c] - xi[c]);
                 r[rr] = __builtin_amdgcn_sqrtf(d[rr][0] * d[rr][0] + d[rr][1] * d[rr][1] + d[rr][2] * d[rr][2]);
+            }
+            if (ch == 0) {
+                // the nearest eight (slots 0..7: lanes 0..7 of the first row) -> LDS
+                if (lane < 8)
+                    sh_nb[wib][lane] = lane < C ? float4{d[0][0], d[0][1], d[0][2], r[0]} : float4{0.f, 0.f, 0.f, 0.f};
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const float4 nb0 = sh_nb[wib][0];
+                d0[0] = nb0.x;
+                d0[1] = nb0.y;
+                d0[2] = nb0.z;
+                kc.r0 = nb0.w;
+                const float r0g = fmaxf(kc.r0, kc.tiny);
+                kc.inv_r0g = frcp(r0g);
+                kc.log_r0g = __logf(r0g);
+                kc.rho_i0 = corr(p.two_nu, kc.cnu * kc.r0);
+                kc.inv_c = frcp((float)max(C, 1));
+                kc.inv_log1p_c = frcp(__logf(1.0f + (float)max(C, 1)));
             }
             // nearest-eight terms, neighbour outermost: squared distance to the
             // nearest other of slots 0..7 (f6) and the count of closer ones inside
@@ -355,10 +500,9 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
                 const float rsv = fmaxf(r[rr], kc.tiny);
                 f[6] = best2[rr] < INFINITY ? __builtin_amdgcn_sqrtf(best2[rr]) * frcp(rsv) : 0.0f;
                 f[7] = cnt[rr] * 0.125f;
-                if (s >= C) {
-#pragma unroll
-                    for (int q = 0; q < kF; ++q) f[q] = 0.0f;
-                }
+                // rows of slots >= C hold finite values (of the target's own
+                // offset); the MLP keeps candidates apart (one B column each)
+                // and their logits are never read
                 uint4* row = reinterpret_cast<uint4*>(&sh_x[wib][sl][0]);
                 row[0] = uint4{pack_bf16x2(f[0], f[1]), pack_bf16x2(f[2], f[3]), pack_bf16x2(f[4], f[5]),
                                pack_bf16x2(f[6], f[7])};
@@ -371,14 +515,22 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
             if (p.mode == 1) continue;  // features only
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            // MLP over this chunk's tiles of 16 candidates
+            // MLP over this chunk's tiles of 16 candidates, kNT tiles at a time
+            // (CH / 16 is a multiple of kNT, so the rows a group reads past
+            // ntiles are this chunk's; their logits are unused)
             const int ntiles = (min(C - ch * CH, CH) + 15) >> 4;
-            for (int tile = 0; tile < ntiles; ++tile) {
-                const int sl = tile * 16 + cl;
-                const short4_t xb =
-                    __builtin_bit_cast(short4_t, *reinterpret_cast<const uint2*>(&sh_x[wib][sl][4 * g]));
-                const float z = mlp_tile_lds(R, sh_w, xb, lane);
-                if (g == 0) sh_z[wib][ch * CH + sl] = z;
+            for (int tile = 0; tile < ntiles; tile += kNT) {
+                asm volatile("" ::: "memory");  // keep the weight operands in LDS (not hoisted to VGPRs)
+                short4_t xb[kNT];
+                float z[kNT];
+#pragma unroll
+                for (int t = 0; t < kNT; ++t)
+                    xb[t] = __builtin_bit_cast(short4_t,
+                                               *reinterpret_cast<const uint2*>(&sh_x[wib][(tile + t) * 16 + cl][4 * g]));
+                mlp_tiles_lds<kNT>(R, sh_w, xb, z, lane);
+#pragma unroll
+                for (int t = 0; t < kNT; ++t)
+                    if (g == 0) sh_z[wib][ch * CH + (tile + t) * 16 + cl] = z[t];
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -416,7 +568,7 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
             float drop = 0.0f;
 #pragma unroll
             for (int kk = 0; kk < KPL; ++kk)
-                if (key[kk] != 0u && key[kk] < thr) drop += 1.0f / (1.0f + __expf(-zz[kk]));
+                if (key[kk] != 0u && key[kk] < thr) drop += frcp(1.0f + __expf(-zz[kk]));
             for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
             fb = drop > p.fb_thr;
         }
@@ -425,10 +577,9 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
         for (int kk = 0; kk < KPL; ++kk) {
-            const int s = kk * 64 + lane;
             const bool k = key[kk] != 0u && key[kk] >= thr;
             const uint64_t m = __ballot(k);
-            if (k) p.kept[col * keep + base + __popcll(m & below)] = p.pool[col * p.stride + s];
+            if (k) p.kept[col * keep + base + __popcll(m & below)] = pid[kk];
             base += __popcll(m);
         }
         for (int q = base + lane; q < keep; q += 64) p.kept[col * keep + q] = -1;

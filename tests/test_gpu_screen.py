@@ -220,3 +220,56 @@ def test_trained_screen_gains(tmp_path):
     assert gaps["trained"] <= 0.01
     assert gaps["trained"] < gaps["untrained"]
     assert gaps["trained"] < gaps["random128"]
+
+
+@pytest.mark.parametrize("d,C,keep", [(1, 64, 16), (2, 128, 40), (3, 256, 128), (2, 512, 128)])
+def test_screen_ragged_dims_and_bad_rows(d, C, keep):
+    """Every pool width (one to eight candidates per lane), dimensions 1-3,
+    ragged pool lengths (the ordering's tail, an empty pool), and rows the
+    screen must reject (target or pool index out of range, pool length past
+    the stride): kept lists and flags bit-exact on the GPU's own logits,
+    logits against the oracle's features and MLP."""
+    print(f"case: screen edge cases d={d} C={C} keep={keep}", flush=True)
+    n = 1500
+    w = inputs.single_target(f"edge d={d}", inputs.uniform_points(n, d, 50 + d + C), inputs.Kernel(3, 0.08), C, 8)
+    pool = w.pool.copy()
+    plen = w.pool_len.copy()
+    tg = w.targets.copy()
+    T = len(tg)
+    bad = {3: "target", 10: "index", 17: "length"}
+    tg[3] = -1
+    pool[10, min(5, plen[10] - 1)] = n
+    plen[17] = C + 1
+    plen[25] = 0
+    p, pb = _rand_params(60 + C)
+    out = csel.screen(_t(w.points, torch.float64), w.kernel, _t(tg, torch.int32), _t(pool, torch.int32),
+                      _t(plen, torch.int32), p, pb, keep, 0.7, want_logits=True)
+    torch.cuda.synchronize()
+    z = out["logits"].cpu().numpy()
+    kept, kl = out["kept"].cpu().numpy(), out["kept_len"].cpu().numpy()
+    fb = out["fallback"].cpu().numpy()
+    nfb = int(out["fallback_count"].item())
+    assert set(out["fallback_list"].cpu().numpy()[:nfb].tolist()) == set(np.where(fb == 1)[0].tolist())
+    for t in range(T):
+        if t in bad:
+            assert kl[t] == 0 and fb[t] == 3, (t, bad[t])
+            continue
+        L = int(plen[t])
+        ks, f = so.screen_keep(z[t], L, keep, 0.7)
+        assert kl[t] == len(ks) and np.array_equal(kept[t, : kl[t]], pool[t, ks]), t
+        assert np.all(kept[t, kl[t]:] == -1)
+        if L > keep:
+            drop = np.sort(np.setdiff1d(np.arange(L), ks))
+            s = float(np.sum(1.0 / (1.0 + np.exp(-z[t, drop].astype(np.float64)))))
+            if abs(s - 0.7) > 1e-4:
+                assert bool(fb[t]) == f, t
+        else:
+            assert fb[t] == 0
+    pn = p.cpu().numpy().astype(np.float64)
+    for t in list(range(0, T, 97)) + [T - 2, T - 5, T - 9, T - 70]:
+        L = int(plen[t])
+        if t in bad or L == 0:
+            continue
+        fr = so.features(w.points, w.kernel, int(tg[t]), pool[t, :L])
+        zr, _ = so.mlp_forward(fr, pn, bf16=True)
+        assert np.linalg.norm(z[t, :L] - zr) <= 5e-3 * np.linalg.norm(zr) + 1e-5, t

@@ -109,3 +109,36 @@ def test_screen_keep_picks_largest_logits_in_slot_order():
     assert fb  # dropped sigmoids sum to 0.525 + 0.269 + 0.047
     kept, fb = so.screen_keep(z, 2, 3)
     assert list(kept) == [0, 1] and not fb
+
+
+def _torch_st_bf16(t):
+    """Round to bfloat16 in the forward pass, identity in the backward pass."""
+    return t + (t.to(torch.bfloat16).to(t.dtype) - t).detach()
+
+
+def test_bf16_forward_and_backward_match_torch_straight_through():
+    """The rounded forward (inputs, weights and both hidden activations in
+    BF16) and its gradient with the rounding taken as the identity, against
+    torch's own bfloat16 casts and autograd."""
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((48, so.F))
+    y = (rng.random(48) < 0.25).astype(np.float64)
+    p = _params(9)
+    loss, g = so.bce_loss_and_grad(X, y, p, pos_weight=2.5, bf16=True)
+    z, _ = so.mlp_forward(X, p, bf16=True)
+    pt = torch.tensor(p, dtype=torch.float64, requires_grad=True)
+    W1 = _torch_st_bf16(pt[so.OFF_W1:so.OFF_B1].view(so.F, so.H))
+    b1 = pt[so.OFF_B1:so.OFF_W2]
+    W2 = _torch_st_bf16(pt[so.OFF_W2:so.OFF_B2].view(so.H, so.H))
+    b2 = pt[so.OFF_B2:so.OFF_W3]
+    w3 = _torch_st_bf16(pt[so.OFF_W3:so.OFF_B3])
+    b3 = pt[so.OFF_B3]
+    Xt = torch.tensor(X).to(torch.bfloat16).to(torch.float64)
+    h1 = _torch_st_bf16(torch.relu(Xt @ W1 + b1))
+    h2 = _torch_st_bf16(torch.relu(h1 @ W2 + b2))
+    zt = h2 @ w3 + b3
+    lt = torch.nn.functional.binary_cross_entropy_with_logits(zt, torch.tensor(y), pos_weight=torch.tensor(2.5))
+    lt.backward()
+    np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-12, atol=1e-12)
+    assert loss == pytest.approx(lt.item(), rel=1e-12)
+    np.testing.assert_allclose(g, pt.grad.numpy(), rtol=1e-10, atol=1e-14)
