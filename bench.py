@@ -1,16 +1,20 @@
 #!/usr/bin/env python3
-"""Benchmark of the selection hot path: selected factor columns per second.
+"""Benchmark of the selection hot path: selected factor columns per second,
+plain full-pool selection against learned-screened selection.
 
-One step = one pass of the whole hot path over the workload: greedy
-conditional selection for every column (FP32 covariance evaluation and GEMV,
-FP64 downdates), the FP64 Theta_ss Cholesky and eq. L_col column, and the
-deterministic sum of log conditional variances (the KL data term of
-eq. obj_chol).  Inputs are resident in HBM before timing starts; ordering and
-pools are untimed set-up.
+Default workload (--workload screened): N = 1,000,000 points in [0,1]^3 (20
+Gaussian clusters with sigma 0.03 plus 20% uniform background), Matern 3/2,
+l = 0.05, pools of the 512 nearest later-ordered points, k = 32, mixed
+precision.  The screen's MLP is first trained on the GPU (untimed set-up) on
+exact selections of a separate cloud.  One timed step = screen every column
+(features, BF16 MLP, top-128 and the fallback flag), exact greedy selection
+with the factor column (Sec. 3.1, eq. L_col) on the kept pools, and full-pool
+selection of the fallback columns; plain full-pool selection is timed the
+same way.  Inputs are resident in HBM before timing; ordering, pools and
+training are set-up.
 
-Default workload: N = 100,000 points uniform in [0,1]^3, Matern 5/2,
-l = 0.05, nugget 1e-6, pools of the 256 nearest later-ordered points (uneven
-at the tail), k = 32, mixed precision.
+Other workloads: plain (N = 100,000 uniform in [0,1]^3, Matern 5/2, pools of
+256, k = 32, replayed as a HIP graph), aggregated and gp.
 
 Prints ONE JSON line (rank 0, N = 1 GPU).
 """
@@ -27,6 +31,7 @@ sys.path.insert(0, ROOT)
 METRIC = "selected factor columns/s at fixed KL gap; plain vs learned-screened"
 PEAK_ALU_TFLOPS = 78.6  # 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz, unpacked FP32 = FP64 vector rate
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0  # dense BF16 MFMA
 
 
 def eval_flops(dim: int, two_nu: int) -> int:
@@ -243,6 +248,66 @@ def kl_gap_estimate(w, targets_sample, lcv_plain, lcv_screen, dS, n_ref=2048):
     return dS / kl2_plain, kl2_plain / 2.0, len(targets_sample)
 
 
+def cpu_baseline_screened(w, k, keep, fbt, p_np, seconds):
+    """Time the oracle's screened pipeline (features, BF16-rounded MLP, top-keep
+    with the fallback rule, exact FP64 selection on the kept or full pool) on a
+    bounded seeded sample of the same columns, one host thread."""
+    import numpy as np
+
+    import oracle
+    from oracle import screen as so
+
+    rng = np.random.default_rng(4321)
+    T = len(w.targets)
+
+    def run(idx):
+        t0 = time.perf_counter()
+        pools = np.full((len(idx), w.pool.shape[1]), -1, np.int32)
+        lens = np.zeros(len(idx), np.int32)
+        for r, t in enumerate(idx):
+            L = int(w.pool_len[t])
+            f = so.features(w.points, w.kernel, int(w.targets[t]), w.pool[t, :L])
+            z, _ = so.mlp_forward(f, p_np, bf16=True)
+            kept, fb = so.screen_keep(z, L, keep, fbt)
+            if fb:
+                pools[r, :L] = w.pool[t, :L]
+                lens[r] = L
+            else:
+                pools[r, : len(kept)] = w.pool[t, kept]
+                lens[r] = len(kept)
+        oracle.select_and_factor(w.points, w.kernel, w.targets[idx], pools, lens, k, nthreads=1)
+        return time.perf_counter() - t0
+
+    probe = np.sort(rng.choice(T, size=min(T, 64), replace=False))
+    dt = run(probe)
+    m = int(min(T, max(len(probe), len(probe) * seconds / max(dt, 1e-6))))
+    idx = np.sort(rng.choice(T, size=m, replace=False))
+    dt = run(idx)
+    return {"value": m / dt, "unit": "columns/s", "cores": 1, "kind": "oracle",
+            "sample": f"{m} of {T} columns (seeded uniform sample): numpy FP64 features and MLP on BF16-rounded "
+                      f"weights, top-{keep} with the fallback rule, FP64 C oracle selection, one thread, {dt:.1f} s"}
+
+
+def _source_digest(*names):
+    import hashlib
+
+    h = hashlib.sha256()
+    for n in names:
+        with open(os.path.join(ROOT, "paper_2307_11648_amd", "csrc", n), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+# HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
+# this script (copy-probe calibrated), keyed by the digest of the kernel's
+# sources at measurement time; a changed kernel reports null.
+MEASURED_TRAFFIC = {
+    # FETCH_SIZE x 2.000 (a 1 GiB device copy reads as 524,316 KiB) + WRITE_SIZE x 1.000
+    ("select_factor_kernel (kept pools)", "cf0f57f73c4d7ace"): 5511585 * 1.99989 * 1024 + 398456 * 1024,
+    ("screen_kernel", "815a311744bccb92"): 24388585 * 1.99989 * 1024 + 549197 * 1024,
+}
+
+
 def bench_screened(args):
     """Plain full-pool selection vs learned-screened selection on the clustered
     1e6-point workload (pools of 512, keep 128, k = 32)."""
@@ -254,6 +319,14 @@ def bench_screened(args):
     n = args.n or 1_000_000
     dev = torch.device("cuda:0")
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    if args.copy_probe:
+        # a plain copy of known size (1 GiB read + 1 GiB written) for calibrating
+        # the HBM byte counters of a profiler run
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     print("bench: training cloud", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     tr = inputs.workload_clustered_training(n=n, n_columns=min(50_000, n))
@@ -277,42 +350,83 @@ def bench_screened(args):
         t(w.pool_len, torch.int32)
     T = len(w.targets)
     prec = args.precision
-    plain = csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec)
     fbt = args.fallback_threshold
+    plain = csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec)
     scr_out, scr = screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
                                                 fallback_threshold=fbt)
     torch.cuda.synchronize()
 
-    def time_it(fn):
+    def screened_step(ev=None):
+        # screen, exact selection on the kept pools, full-pool selection of the
+        # fallback columns (device-side list, no host synchronisation)
+        if ev is not None:
+            ev[0].record()
+        csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr)
+        if ev is not None:
+            ev[1].record()
+        csel.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, out=scr_out)
+        if ev is not None:
+            ev[2].record()
+        csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, scr["fallback_list"],
+                                    scr["fallback_count"], T, scr_out)
+        if ev is not None:
+            ev[3].record()
+
+    def plain_step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, out=plain)
+        if ev is not None:
+            ev[1].record()
+
+    def timed(fn, nev):
         for _ in range(args.warmup):
             fn()
+        evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
         torch.cuda.synchronize()
-        evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-               for _ in range(args.steps)]
-        for a, b_ in evs:
-            a.record()
-            fn()
-            b_.record()
+        t_a = time.perf_counter()
+        for e in evs:
+            fn(e)
         torch.cuda.synchronize()
-        return float(np.mean([a.elapsed_time(b_) for a, b_ in evs]))
+        wall = (time.perf_counter() - t_a) * 1e3
+        parts = [float(np.mean([e[j].elapsed_time(e[j + 1]) for e in evs])) for j in range(nev - 1)]
+        total = float(np.mean([e[0].elapsed_time(e[-1]) for e in evs]))
+        return total, parts, wall / args.steps
 
-    ms_plain = time_it(lambda: csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, out=plain))
-    ms_screen = time_it(lambda: screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
-                                                             fallback_threshold=fbt, out=scr_out, scr=scr))
-    # component times of the screened step
-    ms_scr_only = time_it(lambda: csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr))
-    ms_kept = time_it(lambda: csel.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec,
-                                                     out=scr_out))
-    screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec, fallback_threshold=fbt,
-                                 out=scr_out, scr=scr)
+    print("bench: timing plain", file=sys.stderr, flush=True)
+    ms_plain, _, _ = timed(plain_step, 2)
+    print("bench: timing screened", file=sys.stderr, flush=True)
+    ms_screen, (ms_scr, ms_kept, ms_fb), wall_screen = timed(screened_step, 4)
     nfb = int(scr["fallback_count"].item())
     S_plain = float(plain["log_condvar"].sum().item())
     S_screen = float(scr_out["log_condvar"].sum().item())
+    st = scr_out["status"].cpu().numpy()
     rng = np.random.default_rng(77)
     samp = np.sort(rng.choice(T, size=96, replace=False)).astype(np.int32)
     lcv_p = plain["log_condvar"].cpu().numpy()[samp]
+    print("bench: KL gap estimate", file=sys.stderr, flush=True)
     gap, kl_plain, ns = kl_gap_estimate(w, samp, lcv_p, None, S_screen - S_plain)
-    flops, _ = column_work(np.minimum(w.pool_len, keep), k, 3, 3)
+    kl_len = scr["kept_len"].cpu().numpy()
+    flops_kept, _ = column_work(kl_len, k, 3, 3)
+    flops_plain, _ = column_work(w.pool_len, k, 3, 3)
+    mlp_flops = 2.0 * (16 * 64 + 64 * 64 + 64) * float(np.sum(w.pool_len))
+    kernels = {
+        "select_factor_kernel (kept pools)": {"bound": "alu", "ms": ms_kept, "work": float(np.sum(flops_kept)),
+                                              "peak": PEAK_ALU_TFLOPS, "src": ("select_kernel.hpp", "device_common.hpp")},
+        "screen_kernel": {"bound": "mfma", "ms": ms_scr, "work": mlp_flops, "peak": PEAK_BF16_TFLOPS,
+                          "src": ("screen.hip", "device_common.hpp")},
+    }
+    dom = max(kernels, key=lambda kname: kernels[kname]["ms"])
+
+    def roof(kname):
+        kd = kernels[kname]
+        ach = kd["work"] / (kd["ms"] * 1e-3) / 1e12
+        tr = MEASURED_TRAFFIC.get((kname, _source_digest(*kd["src"])))
+        return {"bound": kd["bound"], "kernel": kname, "achieved": ach, "peak": kd["peak"], "unit": "TFLOP/s",
+                "frac": ach / kd["peak"], "traffic": tr, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE "
+                "+ WRITE_SIZE, copy-calibrated)", "kernel_ms": kd["ms"],
+                "algorithmic_tflop_per_launch": kd["work"] / 1e12}
+
     res = {
         "metric": METRIC, "value": T / (ms_screen * 1e-3), "unit": "columns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_screen, "higher_is_better": True, "scaling": "weak",
@@ -320,17 +434,24 @@ def bench_screened(args):
         "config": {"workload": f"learned-screened selection, N={n} in [0,1]^3 (20 Gaussian clusters sigma 0.03 + 20% "
                                f"uniform), Matern 3/2, l=0.05, pools of 512 -> keep {keep}, k={k}, {prec}; MLP "
                                f"16-64-64-1 trained on the GPU on {rows} rows from {len(tr.targets)} exact selections",
-                   "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain, "screened_ms": ms_screen,
-                   "screen_kernel_ms": ms_scr_only, "kept_select_ms": ms_kept,
-                   "fallback_threshold": fbt, "speedup_vs_plain": ms_plain / ms_screen,
-                   "fallback_columns": nfb, "delta_S": S_screen - S_plain,
+                   "columns": T, "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain,
+                   "screened_ms": ms_screen, "screened_wall_ms_per_step": wall_screen,
+                   "screen_kernel_ms": ms_scr, "kept_select_ms": ms_kept, "fallback_select_ms": ms_fb,
+                   "speedup_vs_plain": ms_plain / ms_screen, "fallback_threshold": fbt, "fallback_columns": nfb,
+                   "status_nonzero": int(np.count_nonzero(st)), "delta_S": S_screen - S_plain,
                    "kl_gap_relative_estimate": gap, "kl_plain_estimate": kl_plain,
-                   "kl_estimate_sample_columns": ns, "train_seconds": t_train},
-        "roofline": {"bound": "alu", "kernel": "select_factor_kernel on kept pools",
-                     "achieved": float(np.sum(flops)) / (ms_kept * 1e-3) / 1e12, "kernel_ms": ms_kept,
-                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "traffic": None},
+                   "kl_estimate_sample_columns": ns, "train_seconds": t_train,
+                   "plain_roofline_frac": float(np.sum(flops_plain)) / (ms_plain * 1e-3) / 1e12 / PEAK_ALU_TFLOPS},
+        "roofline": roof(dom),
+        "roofline_other": [roof(kname) for kname in kernels if kname != dom],
     }
-    res["roofline"]["frac"] = res["roofline"]["achieved"] / PEAK_ALU_TFLOPS
+    if args.cpu_seconds > 0:
+        print("bench: cpu baseline (screened oracle)", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline_screened(w, k, keep, fbt, p.cpu().numpy().astype(np.float64),
+                                                    args.cpu_seconds)
+        print("bench: cpu baseline (plain oracle)", file=sys.stderr, flush=True)
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        res["cpu_baseline_plain"] = cpu_baseline(w, k, args.cpu_seconds, threads)
     print(json.dumps(res), flush=True)
 
 
@@ -339,7 +460,7 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="plain", choices=["plain", "aggregated", "gp", "screened"])
+    ap.add_argument("--workload", default="screened", choices=["screened", "plain", "aggregated", "gp"])
     ap.add_argument("--train-steps", type=int, default=3000, help="screened workload: Adam steps")
     ap.add_argument("--fallback-threshold", type=float, default=2.0,
                     help="screened workload: fall back to the full pool when the dropped candidates' summed "
@@ -349,7 +470,9 @@ def main():
                     help="default: mixed, except fp64 for the GP workload (its conditional variances fall "
                          "below the FP32 error floor)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
-    ap.add_argument("--graph", type=int, default=1, help="replay the step as a captured HIP graph")
+    ap.add_argument("--graph", type=int, default=1, help="plain workload: replay the step as a captured HIP graph")
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="screened workload: run one 1 GiB device copy first (profiler byte-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
