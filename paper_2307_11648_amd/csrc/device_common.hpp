@@ -88,6 +88,22 @@ __device__ __forceinline__ Top2 wave_top2(Top2 v) {
     return merge(merge(r0, r1), merge(r2, r3));
 }
 
+// Wave-wide max of a 32-bit key (uniform result): DPP inside each row of 16
+// lanes, readlane across the rows.
+template <int CTRL>
+__device__ __forceinline__ uint32_t dpp32(uint32_t v) {
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
+}
+__device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
+    v = max(v, dpp32<kDppQuadXor1>(v));
+    v = max(v, dpp32<kDppQuadXor2>(v));
+    v = max(v, dpp32<kDppRowRor4>(v));
+    v = max(v, dpp32<kDppRowRor8>(v));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return max(max(a, b), max(c, d));
+}
+
 // Wave-wide max of a 64-bit key (uniform result).
 __device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
     uint64_t o;

@@ -10,7 +10,7 @@
 //
 // One pick (Sec. 3.1, eq. cond_select / eq. obj_gp; App. C.1):
 //   score = cov^2 / var (FP64) -> wave top-two via DPP -> the winner's factor
-//   row, offset, var and cov are broadcast with readlane -> every lane
+//   row, offset, var and cov are broadcast through LDS -> every lane
 //   evaluates Theta(row, winner), subtracts the GEMV L[row] . L[winner] and
 //   scales by 1/sqrt(var_winner) -> FP64 rank-one downdate of var and cov.
 // The target's own factor row is never formed: its entry for pick t is
@@ -18,9 +18,16 @@
 //
 // Factor column (eq. L_col): lanes 0..s-1 hold the selected points and lane s
 // the target.  Theta' = Theta over [selected..., target] is built in FP64
-// (lane r owns row r), factored by a right-looking Cholesky with readlane
-// broadcasts, and L_{s,i} follows from one back-substitution with the last
-// unit vector: with Theta' = R R^T, Theta'^{-1} e_last = R^{-T} e_last / R_ll.
+// (its lower triangle spread over the lanes, staged in LDS; lane r then owns
+// row r), factored by a left-looking Cholesky that reads the finished rows of
+// R back from LDS as broadcasts, and L_{s,i} follows from one
+// back-substitution with the last unit vector: with Theta' = R R^T,
+// Theta'^{-1} e_last = R^{-T} e_last / R_ll.
+//
+// Argmax keys: 64-bit (the FP64 score with the slot in its low mantissa bits)
+// for FP64 and for the top-two variant; the mixed-precision kernel without
+// the gap output takes the maximum of the FP32 score's bits and resolves
+// equal maxima to the smallest slot with ballots.
 
 #pragma once
 
@@ -149,7 +156,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                     }
                 }
                 w = wave_top2(loc);
-            } else {
+            } else if constexpr (sizeof(T) == 8) {
                 uint64_t best = 0ull;
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
@@ -158,6 +165,27 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                     best = key > best ? key : best;
                 }
                 w.k1 = wave_max64(best);
+                w.k2 = 0ull;
+            } else {
+                // FP32 score of the FP64 state; key = its bits with the top bit
+                // marking a valid candidate (scores are >= 0), 0 = none
+                uint32_t key[RPL], best = 0u;
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    const float cf = (float)cov[rr];
+                    const float sc = cf * cf * __builtin_amdgcn_rcpf((float)var[rr]);
+                    key[rr] = (((live >> rr) & 1u) && var[rr] > thr) ? (__float_as_uint(sc) | 0x80000000u) : 0u;
+                    best = max(best, key[rr]);
+                }
+                best = wave_max32(best);
+                // the smallest slot holding the maximum
+                int slot = -1;
+#pragma unroll
+                for (int rr = RPL - 1; rr >= 0; --rr) {
+                    const uint64_t m = __ballot(key[rr] == best);
+                    if (m) slot = rr * kWave + (int)__builtin_ctzll(m);
+                }
+                w.k1 = best == 0u ? 0ull : make_key(0.0, slot);
                 w.k2 = 0ull;
             }
             if (w.k1 == 0ull) {
@@ -170,36 +198,55 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 const double sa = key_score(w.k1), sb = key_score(w.k2);
                 const float g = (w.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
 
-                // broadcast the winner's row
-                T Lk[KMAX];
-                T dk0 = (T)0, dk1 = (T)0, dk2 = (T)0;
-                double vk = 1.0, ck = 0.0;
-                int32_t idk = -1;
+                // broadcast the winner's row through LDS (the factor-phase
+                // buffer is free during the picks): the winning lane stores
+                // its factor row, offset, var, cov and index; every lane reads
+                // them back as broadcasts
+                T* bc = reinterpret_cast<T*>(&sh_r[wib][0][0]);
+                double* bcd = &sh_r[wib][KMAX][0];
+                if (lane == ls) {
 #pragma unroll
-                for (int rr = 0; rr < RPL; ++rr) {
-                    if (rr == rs) {
+                    for (int rr = 0; rr < RPL; ++rr) {
+                        if (rr == rs) {
 #pragma unroll
-                        for (int q = 0; q < t; ++q) Lk[q] = bcast(L[rr][q], ls);
-                        dk0 = bcast(dx[rr][0], ls);
-                        dk1 = bcast(dx[rr][1], ls);
-                        dk2 = bcast(dx[rr][2], ls);
-                        vk = bcast(var[rr], ls);
-                        ck = bcast(cov[rr], ls);
-                        idk = bcast(pid[rr], ls);
+                            for (int q = 0; q < t; ++q) bc[q] = L[rr][q];
+                            bc[KMAX] = dx[rr][0];
+                            bc[KMAX + 1] = dx[rr][1];
+                            bc[KMAX + 2] = dx[rr][2];
+                            bcd[0] = var[rr];
+                            bcd[1] = cov[rr];
+                            bcd[2] = (double)pid[rr];
+                        }
                     }
                 }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const T dk0 = bc[KMAX], dk1 = bc[KMAX + 1], dk2 = bc[KMAX + 2];
+                const double vk = bcd[0], ck = bcd[1];
+                const int32_t idk = (int32_t)bcd[2];
                 const double inv_sd = 1.0 / sqrt(vk);
                 const double ui = ck * inv_sd;
                 const T inv_sd_t = (T)inv_sd;
+                T acc[RPL];
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
                     const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
                     const T r = tsqrt(e0 * e0 + e1 * e1 + e2 * e2);
-                    T acc = matern<T, TWO_NU>(r, cnu, s2);
-                    if (pid[rr] == idk) acc += nug;
+                    acc[rr] = matern<T, TWO_NU>(r, cnu, s2);
+                    if (pid[rr] == idk) acc[rr] += nug;
+                }
+                // GEMV with the broadcast row, one LDS element at a time for all rows
 #pragma unroll
-                    for (int q = 0; q < t; ++q) acc -= L[rr][q] * Lk[q];
-                    const T u = acc * inv_sd_t;
+                for (int q = 0; q < t; ++q) {
+                    const T lk = bc[q];
+#pragma unroll
+                    for (int rr = 0; rr < RPL; ++rr) acc[rr] -= L[rr][q] * lk;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int rr = 0; rr < RPL; ++rr) {
+                    const T u = acc[rr] * inv_sd_t;
                     L[rr][t] = u;
                     const double ud = (double)u;
                     var[rr] -= ud * ud;
@@ -258,38 +305,34 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     for (int c = 0; c <= KMAX; ++c) a[c] = (c <= lane && lane < M) ? TH[lane][c] : 0.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
+    // Left-looking Cholesky Theta' = R R^T by columns: lane r finishes R[r][j]
+    // from its own row (registers) and row j of R, read from LDS as a
+    // broadcast; every lane then stores its column-j entry into row r of the
+    // LDS copy, which rows > j read in later steps.  Entries a lane computes
+    // above its diagonal are never read.
     bool pd = true;
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j >= M || !pd) continue;
-        const double piv = bcast(a[j], j);
+        double sj = a[j];
+#pragma unroll
+        for (int c = 0; c < j; ++c) sj -= a[c] * TH[j][c];
+        const double piv = bcast(sj, j);
         if (!(piv > 0.0)) {
             pd = false;
             continue;
         }
         const double dj = sqrt(piv);
-        const double inv = 1.0 / dj;
-        if (lane > j) a[j] *= inv;
-        else if (lane == j) a[j] = dj;
-#pragma unroll
-        for (int c = j + 1; c <= KMAX; ++c) {
-            if (c >= M) continue;
-            const double lc = bcast(a[j], c);
-            if (lane >= c) a[c] -= a[j] * lc;
-        }
+        a[j] = lane == j ? dj : sj * rcp64(dj);
+        if (lane < M) TH[lane][j] = a[j];
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
     }
 
     double y = 0.0;
     if (pd) {
-        // rows of R to LDS (lane r writes row r), then back-substitution
+        // back-substitution with the rows of R left in LDS by the factorisation
         double(*R)[KMAX + 2] = sh_r[wib];
-        if (lane < M) {
-#pragma unroll
-            for (int c = 0; c <= KMAX; ++c)
-                if (c <= lane) R[lane][c] = a[c];
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
         const int l = nsel;
         double acc = 0.0;
 #pragma unroll

@@ -212,8 +212,12 @@ def test_host_validation_errors():
 
 
 def test_gap_and_no_gap_variants_agree():
-    """The kernel without top2_gap (a plain maximum instead of the top-two
-    reduction) takes the same decisions bit for bit."""
+    """FP64: the kernel without top2_gap (a plain maximum instead of the
+    top-two reduction) takes the same decisions bit for bit.  Mixed: the
+    variant without the gap ranks by the FP32 score of the FP64 state (the
+    gap variant by the FP64 score), so near-ties may resolve differently:
+    both pass the FP64 replay, and columns with the same picks agree bit for
+    bit."""
     print("case: gap vs no-gap variants", flush=True)
     w = inputs.workload_plain_batched(n=6000, seed=9)
     pts = _dev(w.points, torch.float64)
@@ -222,5 +226,18 @@ def test_gap_and_no_gap_variants_agree():
         a = csel.select_and_factor(pts, w.kernel, *args, 32, prec, want_gap=True)
         b = csel.select_and_factor(pts, w.kernel, *args, 32, prec, want_gap=False)
         torch.cuda.synchronize()
-        for key in ("sel", "factor", "log_condvar", "status"):
-            assert torch.equal(a[key], b[key]), (prec, key)
+        if prec == "fp64":
+            for key in ("sel", "factor", "log_condvar", "status"):
+                assert torch.equal(a[key], b[key]), (prec, key)
+            continue
+        ga = {key: v.cpu().numpy() for key, v in a.items()}
+        gb = {key: v.cpu().numpy() for key, v in b.items()}
+        same = np.all(ga["sel"] == gb["sel"], axis=1)
+        print("mixed gap / no-gap identical columns", int(same.sum()), "of", len(same))
+        assert same.mean() >= 0.99
+        for key in ("factor", "log_condvar", "status"):
+            assert np.array_equal(ga[key][same], gb[key][same]), key
+        cols = np.arange(len(w.targets))
+        for g in (ga, gb):
+            short, fac = replay_check(g, w.points, w.kernel, w.targets, w.pool, w.pool_len, 32, cols, TAU_MIXED, 1e-3)
+            print("mixed replay worst shortfall", short, "factor", fac)
