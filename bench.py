@@ -352,8 +352,18 @@ def bench_screened(args):
     prec = args.precision
     fbt = args.fallback_threshold
     plain = csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec)
+    # the screen's column processing order (Morton order of the targets): set-up,
+    # like the pools; its own time is reported
+    order, order_ws = csel.spatial_order(pts, tg)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    csel.spatial_order(pts, tg, out=order, workspace=order_ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_order = e0.elapsed_time(e1)
     scr_out, scr = screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
-                                                fallback_threshold=fbt)
+                                                fallback_threshold=fbt, order=order)
     torch.cuda.synchronize()
 
     def screened_step(ev=None):
@@ -361,7 +371,7 @@ def bench_screened(args):
         # fallback columns (device-side list, no host synchronisation)
         if ev is not None:
             ev[0].record()
-        csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr)
+        csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr, order=order)
         if ev is not None:
             ev[1].record()
         csel.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, out=scr_out)
@@ -437,6 +447,7 @@ def bench_screened(args):
                    "columns": T, "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain,
                    "screened_ms": ms_screen, "screened_wall_ms_per_step": wall_screen,
                    "screen_kernel_ms": ms_scr, "kept_select_ms": ms_kept, "fallback_select_ms": ms_fb,
+                   "spatial_order_setup_ms": ms_order,
                    "speedup_vs_plain": ms_plain / ms_screen, "fallback_threshold": fbt, "fallback_columns": nfb,
                    "status_nonzero": int(np.count_nonzero(st)), "delta_S": S_screen - S_plain,
                    "kl_gap_relative_estimate": gap, "kl_plain_estimate": kl_plain,

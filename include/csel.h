@@ -231,7 +231,7 @@ int csel_select_and_factor_list(const double *pts, int64_t n, int32_t dim, const
  * candidate of a column from 16 geometric features; the `keep` best are
  * kept, and the exact greedy selection of csel_select_and_factor runs on the
  * kept candidates.  The MLP is 16 -> 64 -> 64 -> 1 with ReLU, evaluated with
- * BF16 inputs, weights and first-layer activations on MFMA, FP32
+ * BF16 inputs, weights and hidden-layer activations on MFMA, FP32
  * accumulation and FP32 biases.  Parameters are one FP32 vector of
  * csel_mlp_num_params() values, W1[16][64], b1[64], W2[64][64], b2[64],
  * w3[64], b3, plus its BF16 copy (uint16 bit patterns, same indexing).
@@ -262,12 +262,36 @@ int csel_screen_features(const double *pts, int64_t n, int32_t dim, const csel_k
  * indices are appended there (count reset by this call; list order is not
  * deterministic).  fallback = 3 marks bad input.  logits [n_targets]
  * [pool_stride] is optional.  pool_stride <= 512.
+ *
+ * order (optional, device int32 [n_targets]): the order in which the columns
+ * are processed, e.g. from csel_spatial_order; results do not depend on it.
+ * A column absent from it is not processed (its outputs are left as they
+ * were); entries outside [0, n_targets) are skipped; a column listed twice
+ * is processed twice (its fallback index is then appended twice).  NULL
+ * processes 0, 1, ..., n_targets - 1.
  */
 int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_targets,
                 const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride,
                 const float *params, const uint16_t *params_bf16, int32_t keep, float fallback_threshold,
                 int32_t *kept_idx, int32_t *kept_len, uint8_t *fallback, float *logits, int32_t *fallback_list,
-                int32_t *fallback_count, hipStream_t stream);
+                int32_t *fallback_count, const int32_t *order, hipStream_t stream);
+
+/*
+ * csel_spatial_order -- a processing order of the columns by the Morton
+ * (Z-order) code of their target points: coordinates quantised over the
+ * targets' bounding box (10 bits per coordinate in 3-D, 15 in 2-D, 30 in
+ * 1-D), sorted stably, so equal codes keep increasing column order.
+ * order[k] (device int32 [n_targets]) is the k-th column to process.  Not
+ * part of the paper: a schedule under which the columns in flight together
+ * have nearby targets, so their candidate pools overlap in cache.  Targets
+ * out of [0, n) are placed as if at the origin of the box.
+ *
+ *   workspace  device memory of csel_spatial_order_workspace_size(n_targets)
+ *              bytes, caller-owned, not kept after the call's work ends
+ */
+int64_t csel_spatial_order_workspace_size(int64_t n_targets);
+int csel_spatial_order(const double *pts, int64_t n, int32_t dim, int64_t n_targets, const int32_t *targets,
+                       void *workspace, int64_t workspace_bytes, int32_t *order, hipStream_t stream);
 
 /* MLP logits [n_rows] of feature rows x [n_rows][16]. */
 int csel_mlp_forward(const float *params, const uint16_t *params_bf16, const float *x, int64_t n_rows,

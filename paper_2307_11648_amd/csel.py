@@ -80,8 +80,12 @@ def load():
     lib.csel_screen_features.restype = ctypes.c_int
     lib.csel_screen.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64, _vp, _vp,
                                 _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_float, _vp, _vp, _vp, _vp, _vp, _vp,
-                                _vp]
+                                _vp, _vp]
     lib.csel_screen.restype = ctypes.c_int
+    lib.csel_spatial_order_workspace_size.argtypes = [_c.c_int64]
+    lib.csel_spatial_order_workspace_size.restype = ctypes.c_int64
+    lib.csel_spatial_order.argtypes = [_vp, _c.c_int64, _c.c_int32, _c.c_int64, _vp, _vp, _c.c_int64, _vp, _vp]
+    lib.csel_spatial_order.restype = ctypes.c_int
     lib.csel_mlp_forward.argtypes = [_vp, _vp, _vp, _c.c_int64, _vp, _vp]
     lib.csel_mlp_forward.restype = ctypes.c_int
     lib.csel_mlp_grad_workspace_size.argtypes = [_c.c_int64]
@@ -210,10 +214,29 @@ def screen_features(points, kernel, targets, pool, pool_len, stream=None):
     return feats
 
 
+def spatial_order(points, targets, out=None, workspace=None, stream=None):
+    """csel_spatial_order: int32 [T] processing order of the columns by the
+    Morton code of their targets.  Returns (order, workspace)."""
+    lib = load()
+    T = targets.shape[0]
+    dev = points.device
+    if out is None:
+        out = torch.empty(max(T, 1), dtype=torch.int32, device=dev)
+    need = int(lib.csel_spatial_order_workspace_size(T))
+    if need < 0:
+        raise CselError(lib.csel_last_error().decode())
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib.csel_spatial_order(points.data_ptr(), points.shape[0], points.shape[1], T, targets.data_ptr(),
+                                  workspace.data_ptr(), workspace.numel(), out.data_ptr(), _stream(stream)))
+    return out[:T], workspace
+
+
 def screen(points, kernel, targets, pool, pool_len, params, params_bf16, keep: int, fallback_threshold=0.5,
-           want_logits=False, out=None, stream=None) -> dict:
+           want_logits=False, out=None, order=None, stream=None) -> dict:
     """csel_screen: kept [T, keep] ids in distance order, kept_len [T],
-    fallback [T] u8, fallback_list [T] int32 with fallback_count [1]."""
+    fallback [T] u8, fallback_list [T] int32 with fallback_count [1].
+    `order` (int32 [T], optional) is the processing order of the columns."""
     lib = load()
     _dev(params, torch.float32, "params")
     T = targets.shape[0]
@@ -232,7 +255,8 @@ def screen(points, kernel, targets, pool, pool_len, params, params_bf16, keep: i
                            targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride, params.data_ptr(),
                            params_bf16.data_ptr(), int(keep), float(fallback_threshold), out["kept"].data_ptr(),
                            out["kept_len"].data_ptr(), out["fallback"].data_ptr(), _ptr(out.get("logits")),
-                           out["fallback_list"].data_ptr(), out["fallback_count"].data_ptr(), _stream(stream)))
+                           out["fallback_list"].data_ptr(), out["fallback_count"].data_ptr(), _ptr(order),
+                           _stream(stream)))
     return out
 
 

@@ -279,7 +279,8 @@ static int screen_common(const double* pts, int64_t n, int32_t dim, const csel_k
     if (rc) return rc;
     if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
     if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
-    if (n_targets < 0) return fail(CSEL_EINVAL, "n_targets must be >= 0");
+    if (n_targets < 0 || n_targets > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_targets must be in [0, 2^31) (got %lld)", (long long)n_targets);
     if (pool_stride < 1 || pool_stride > kScreenMaxPool)
         return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [1, %d] (got %d)", kScreenMaxPool, pool_stride);
     if (n_targets > 0 && (!pts || !targets || !pool_idx || !pool_len))
@@ -330,7 +331,8 @@ CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_k
                          const int32_t* targets, const int32_t* pool_idx, const int32_t* pool_len,
                          int32_t pool_stride, const float* params, const uint16_t* params_bf16, int32_t keep,
                          float fallback_threshold, int32_t* kept_idx, int32_t* kept_len, uint8_t* fallback,
-                         float* logits, int32_t* fallback_list, int32_t* fallback_count, hipStream_t stream) {
+                         float* logits, int32_t* fallback_list, int32_t* fallback_count, const int32_t* order,
+                         hipStream_t stream) {
     g_err[0] = 0;
     csel::ScreenArgs a;
     int rc = screen_common(pts, n, dim, kernel, n_targets, targets, pool_idx, pool_len, pool_stride, a);
@@ -359,12 +361,41 @@ CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_k
     a.fallback = fallback;
     a.fb_list = fallback_list;
     a.fb_count = fallback_count;
+    a.order = order;
     if (fallback_count) {
         hipError_t e = csel::launch_fill_i32(fallback_count, 1, 0, stream);
         if (e != hipSuccess) return hip_fail(e, "fill launch");
     }
     hipError_t e = csel::launch_screen(a, screen_rpl(pool_stride), stream);
     if (e != hipSuccess) return hip_fail(e, "screen launch");
+    return CSEL_OK;
+}
+
+CSEL_API int64_t csel_spatial_order_workspace_size(int64_t n_targets) {
+    g_err[0] = 0;
+    if (n_targets < 0 || n_targets > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_targets must be in [0, 2^31) (got %lld)", (long long)n_targets);
+    const int64_t w = csel::spatial_order_workspace(n_targets);
+    if (w < 0) return fail(CSEL_EHIP, "radix sort could not size its temporary storage");
+    return w;
+}
+
+CSEL_API int csel_spatial_order(const double* pts, int64_t n, int32_t dim, int64_t n_targets,
+                                const int32_t* targets, void* workspace, int64_t workspace_bytes, int32_t* order,
+                                hipStream_t stream) {
+    g_err[0] = 0;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_targets < 0 || n_targets > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_targets must be in [0, 2^31) (got %lld)", (long long)n_targets);
+    if (n_targets == 0) return CSEL_OK;
+    if (!pts || !targets || !order) return fail(CSEL_EINVAL, "a required array is NULL");
+    const int64_t need = csel::spatial_order_workspace(n_targets);
+    if (need < 0) return fail(CSEL_EHIP, "radix sort could not size its temporary storage");
+    if (!workspace || workspace_bytes < need)
+        return fail(CSEL_EINVAL, "workspace too small: %lld bytes needed", (long long)need);
+    hipError_t e = csel::launch_spatial_order(pts, n, dim, n_targets, targets, workspace, order, stream);
+    if (e != hipSuccess) return hip_fail(e, "spatial order launch");
     return CSEL_OK;
 }
 

@@ -58,6 +58,7 @@ struct ScreenArgs {
     uint8_t* fallback;
     int32_t* fb_list;
     int32_t* fb_count;
+    const int32_t* order;  // processing order of the columns (nullptr: 0, 1, ...)
 };
 
 struct MlpTrainArgs {
@@ -80,6 +81,11 @@ hipError_t launch_adam(float* p, uint16_t* pb, const float* g, float* m, float* 
                        float b2, float eps, int step, hipStream_t s);
 hipError_t launch_to_bf16(const float* p, uint16_t* pb, int n, hipStream_t s);
 hipError_t launch_fill_i32(int32_t* x, int64_t n, int32_t v, hipStream_t s);
+
+// spatial (Morton) processing order of the target columns
+int64_t spatial_order_workspace(int64_t n_targets);
+hipError_t launch_spatial_order(const double* pts, int64_t n, int dim, int64_t n_targets, const int32_t* targets,
+                                void* workspace, int32_t* order, hipStream_t s);
 
 struct AggArgs {
     const double* pts;

@@ -335,8 +335,8 @@ __device__ __forceinline__ void candidate_features(const ScreenArgs& p, const Co
 
 constexpr int kScrWaves = 2;
 
-// One wave per column, grid-stride over the columns (each wave loads the MLP
-// weights once).  The pool (<= 64*RPL*NCH candidates) is processed in NCH
+// One wave per column; persistent waves walk through the processing order
+// (each wave stages the MLP weights once).  The pool (<= 64*RPL*NCH candidates) is processed in NCH
 // chunks of 64*RPL (RPL per lane) for features and the MLP, so only one
 // chunk's candidate state is live; the logits of the whole pool then go
 // through the top-keep selection.
@@ -367,11 +367,27 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
     kc0.tiny = 1e-9f * (float)p.ell;
     kc0.adiag = 1.0f + (float)(p.nugget / p.s2);
     kc0.inv_adiag = 1.0f / kc0.adiag;
-    const int64_t cstep = (int64_t)gridDim.x * kScrWaves;
     const int lim = min(p.stride, MAXC);  // pool entries a column may use
+    // Positions in the processing order are split into eight contiguous
+    // segments, one per XCD (workgroups go to the XCDs round-robin, so block
+    // b runs on XCD b % 8): the waves of one XCD walk through their segment
+    // side by side and share that XCD's L2.  The grid is a multiple of 8.
+    const int64_t T = p.n_targets;
+    const int64_t seg = (T + 7) / 8;
+    const int64_t seg0 = (int64_t)(blockIdx.x & 7u) * seg;
+    const int64_t seg1 = min(seg0 + seg, T);
+    const int64_t pstep = (int64_t)(gridDim.x >> 3) * kScrWaves;
+    int64_t pos = seg0 + (int64_t)(blockIdx.x >> 3) * kScrWaves + wib;
+    // the column at a position (-1 past the segment), loaded by lane 0
+    auto col_load = [&](int64_t ps) -> int32_t {
+        int32_t c = -1;
+        if (ps < seg1 && lane == 0) c = p.order ? p.order[ps] : (int32_t)ps;
+        return c;
+    };
     // The next column's target, pool length, pool indices (slot kk*64 + lane)
     // and target coordinates (lane c < dim) are loaded while this column is
-    // processed; the pool indices stay in registers for the whole column.
+    // processed, and the column after it is looked up; the pool indices stay
+    // in registers for the whole column.
     int32_t nx_pid[KPL];
     int32_t nx_tgt = -1, nx_len = 0;
     double nx_xc = 0.0;
@@ -380,7 +396,7 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
         nx_len = 0;
 #pragma unroll
         for (int kk = 0; kk < KPL; ++kk) nx_pid[kk] = -1;
-        if (c < p.n_targets) {
+        if (c >= 0 && c < T) {
             if (lane == 0) {  // vector loads, so they complete in order with the gathers
                 nx_tgt = p.targets[c];
                 nx_len = p.pool_len[c];
@@ -395,17 +411,25 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
         nx_xc = 0.0;
         if (t >= 0 && (int64_t)t < p.n && lane < dim) nx_xc = p.pts[(int64_t)t * dim + lane];
     };
-    int64_t col = (int64_t)blockIdx.x * kScrWaves + wib;
-    fetch_ids(col);
+    int32_t c_cur = __builtin_amdgcn_readfirstlane(col_load(pos));
+    fetch_ids(c_cur);
     fetch_xi();
-    for (; col < p.n_targets; col += cstep) {
+    int32_t c_nx = col_load(pos + pstep);
+    for (; pos < seg1; pos += pstep) {
+        const int64_t col = c_cur;
         const int32_t tgt = __builtin_amdgcn_readfirstlane(nx_tgt);
         int32_t C = __builtin_amdgcn_readfirstlane(nx_len);
         int32_t pid[KPL];
 #pragma unroll
         for (int kk = 0; kk < KPL; ++kk) pid[kk] = nx_pid[kk];
         const double xi[3] = {bcast(nx_xc, 0), bcast(nx_xc, 1), bcast(nx_xc, 2)};  // zero past dim
-        fetch_ids(col + cstep);
+        c_cur = __builtin_amdgcn_readfirstlane(c_nx);
+        fetch_ids(c_cur);
+        c_nx = col_load(pos + 2 * pstep);
+        if (col < 0 || col >= T) {  // an order entry out of range
+            fetch_xi();
+            continue;
+        }
         const bool bad = tgt < 0 || (int64_t)tgt >= p.n || C < 0 || C > lim;
         bool my_bad = false;
 #pragma unroll
@@ -819,18 +843,39 @@ __global__ __launch_bounds__(64) void mlp_forward_kernel(MlpTrainArgs p, float* 
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// Persistent grid: as many blocks as fit on the device at once (a multiple of
+// 8, one share per XCD), fewer for small inputs; each wave loops over its
+// segment of the processing order.
+template <int RPL, int NCH>
+static hipError_t launch_screen_t(const ScreenArgs& a, hipStream_t s) {
+    static int resident[64] = {};  // blocks per device, by device id
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+    if (resident[dev] == 0) {
+        int per_cu = 0, cus = 0;
+        e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, screen_kernel<RPL, NCH>, kScrWaves * 64, 0);
+        if (e != hipSuccess) return e;
+        e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e != hipSuccess) return e;
+        resident[dev] = std::max(8, (std::max(per_cu, 1) * cus) / 8 * 8);
+    }
+    const int64_t need = ((a.n_targets + kScrWaves - 1) / kScrWaves + 7) / 8 * 8;
+    const unsigned grid = (unsigned)std::min<int64_t>(need, resident[dev]);
+    hipLaunchKernelGGL((screen_kernel<RPL, NCH>), dim3(grid), dim3(kScrWaves * 64), 0, s, a);
+    return hipGetLastError();
+}
+
 hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
     if (a.n_targets == 0) return hipSuccess;
-    // enough waves to fill the chip several times over; each loops over columns
-    const unsigned grid = (unsigned)std::min<int64_t>((a.n_targets + kScrWaves - 1) / kScrWaves, 8192);
     switch (rpl) {
-        case 1: hipLaunchKernelGGL((screen_kernel<1, 1>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
-        case 2: hipLaunchKernelGGL((screen_kernel<2, 1>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
-        case 4: hipLaunchKernelGGL((screen_kernel<4, 1>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
-        case 8: hipLaunchKernelGGL((screen_kernel<4, 2>), dim3(grid), dim3(kScrWaves * 64), 0, s, a); break;
+        case 1: return launch_screen_t<1, 1>(a, s);
+        case 2: return launch_screen_t<2, 1>(a, s);
+        case 4: return launch_screen_t<4, 1>(a, s);
+        case 8: return launch_screen_t<4, 2>(a, s);
         default: return hipErrorInvalidValue;
     }
-    return hipGetLastError();
 }
 
 int mlp_nparams() { return kNParams; }

@@ -87,10 +87,12 @@ def mean_loss(p, pb, X, y, chunk: int = 1 << 20) -> float:
 
 
 def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep: int, precision: str = "mixed",
-                    fallback_threshold: float = 0.5, out=None, scr=None):
+                    fallback_threshold: float = 0.5, out=None, scr=None, order=None):
     """The screened hot path: screen, exact selection on the kept candidates,
-    exact selection on the full pool for the fallback columns (no host sync)."""
-    scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr)
+    exact selection on the full pool for the fallback columns (no host sync).
+    `order` is the screen's column processing order (csel.spatial_order)."""
+    scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr,
+                      order=order)
     out = csel.select_and_factor(points, kernel, targets, scr["kept"], scr["kept_len"], k, precision, out=out)
     csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, scr["fallback_list"],
                                 scr["fallback_count"], targets.shape[0], out)

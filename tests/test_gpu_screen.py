@@ -273,3 +273,78 @@ def test_screen_ragged_dims_and_bad_rows(d, C, keep):
         fr = so.features(w.points, w.kernel, int(tg[t]), pool[t, :L])
         zr, _ = so.mlp_forward(fr, pn, bf16=True)
         assert np.linalg.norm(z[t, :L] - zr) <= 5e-3 * np.linalg.norm(zr) + 1e-5, t
+
+
+def _morton_reference(points, targets):
+    """Morton codes as the schedule defines them (coordinates of in-range
+    targets quantised over the targets' bounding box with separately rounded
+    FP64 operations, bits interleaved coordinate-minor), stable-sorted."""
+    n, dim = points.shape
+    ok = (targets >= 0) & (targets < n)
+    X = np.zeros((len(targets), 3))
+    X[ok, :dim] = points[targets[ok]]
+    bits = 10 if dim >= 3 else (15 if dim == 2 else 30)
+    step = 3 if dim >= 3 else dim
+    cells = float((1 << bits) - 1)
+    code = np.zeros(len(targets), np.uint64)
+    for c in range(dim):
+        lo, hi = X[:, c].min(), X[:, c].max()
+        ext = hi - lo
+        u = (X[:, c] - lo) / ext if ext > 0 else np.zeros(len(targets))
+        u = np.clip(u, 0.0, 1.0)
+        q = np.floor(u * cells + 0.5).astype(np.uint64)  # numpy rounds the product, then the sum
+        for b in range(bits):
+            code |= ((q >> np.uint64(b)) & np.uint64(1)) << np.uint64(b * step + c)
+    return np.argsort(code, kind="stable").astype(np.int32)
+
+
+@pytest.mark.parametrize("dim", [1, 2, 3])
+def test_spatial_order_matches_reference(dim):
+    print(f"case: spatial order d={dim}", flush=True)
+    pts = inputs.uniform_points(3000, dim, 70 + dim)
+    tg = np.random.default_rng(dim).permutation(3000)[:2500].astype(np.int32)
+    tg[7] = -5  # out of range: placed at the origin of the box
+    tg[8] = tg[9]  # a repeated target: equal codes keep column order
+    order, ws = csel.spatial_order(_t(pts, torch.float64), _t(tg, torch.int32))
+    got = order.cpu().numpy()
+    assert np.array_equal(np.sort(got), np.arange(len(tg)))
+    assert np.array_equal(got, _morton_reference(pts, tg))
+    empty, _ = csel.spatial_order(_t(pts, torch.float64), _t(tg[:0], torch.int32))
+    assert empty.numel() == 0
+
+
+def test_screen_order_does_not_change_results(clustered):
+    """Outputs under the spatial order, a random order and the natural order
+    are identical; an order entry out of range is skipped and a column left
+    out of the order keeps its outputs untouched."""
+    print("case: screen processing orders", flush=True)
+    w, d = clustered
+    p, pb = _rand_params(44)
+    T = len(w.targets)
+    ref = csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, 128, 0.6, want_logits=True)
+    sp, _ = csel.spatial_order(d["pts"], d["tg"])
+    rnd = _t(np.random.default_rng(5).permutation(T).astype(np.int32), torch.int32)
+    for name, order in (("spatial", sp), ("random", rnd)):
+        o = csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, 128, 0.6, want_logits=True, order=order)
+        torch.cuda.synchronize()
+        for key in ("kept", "kept_len", "fallback", "logits", "fallback_count"):
+            assert torch.equal(o[key], ref[key]), (name, key)
+        nfb = int(ref["fallback_count"].item())
+        assert set(o["fallback_list"][:nfb].cpu().tolist()) == set(ref["fallback_list"][:nfb].cpu().tolist())
+    # drop column 11 from the order, put an out-of-range entry in its place
+    od = sp.clone()
+    pos = int(torch.nonzero(od == 11)[0].item())
+    od[pos] = T + 3
+    o = {"kept": torch.full((T, 128), -7, dtype=torch.int32, device="cuda"),
+         "kept_len": torch.full((T,), -7, dtype=torch.int32, device="cuda"),
+         "fallback": torch.full((T,), 9, dtype=torch.uint8, device="cuda"),
+         "fallback_list": torch.empty(T, dtype=torch.int32, device="cuda"),
+         "fallback_count": torch.empty(1, dtype=torch.int32, device="cuda")}
+    csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, 128, 0.6, out=o, order=od)
+    torch.cuda.synchronize()
+    keep_rows = torch.ones(T, dtype=torch.bool, device="cuda")
+    keep_rows[11] = False
+    assert int(o["kept_len"][11].item()) == -7 and int(o["fallback"][11].item()) == 9
+    assert bool(torch.all(o["kept"][11] == -7))
+    for key in ("kept", "kept_len", "fallback"):
+        assert torch.equal(o[key][keep_rows], ref[key][keep_rows]), key
