@@ -50,6 +50,18 @@ __device__ __forceinline__ double rcp64(double v) {
     return r * fma(-v, r, 2.0);
 }
 
+// 1/sqrt(v) in FP64 (v > 0 normal): hardware reciprocal square root refined
+// by two Newton steps r <- r + r/2 (1 - v r^2) (about 1 ulp)
+__device__ __forceinline__ double rsq64(double v) {
+    double r = __builtin_amdgcn_rsq(v);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-(v * r), r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
 template <typename T, int TWO_NU>
 __device__ __forceinline__ T matern(T r, T c, T s2) {
     if constexpr (sizeof(T) == 4) return matern_f32<TWO_NU>(r, c, s2);
@@ -89,7 +101,6 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     T dx[RPL][3];
     double var[RPL], cov[RPL];
     int32_t pid[RPL];
-    uint32_t live = 0;
     const T cnu = (T)p.c_nu, s2 = (T)p.s2;
     const double prior = p.s2 + p.nugget;
     const double thr = 1e-12 * prior;
@@ -111,12 +122,12 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
             } else {
                 pid[rr] = q;
                 for (int d = 0; d < dim; ++d) dx[rr][d] = (T)(p.pts[(int64_t)q * dim + d] - xi[d]);
-                live |= 1u << rr;
             }
         }
         const T r = tsqrt(dx[rr][0] * dx[rr][0] + dx[rr][1] * dx[rr][1] + dx[rr][2] * dx[rr][2]);
         cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
-        var[rr] = prior;
+        // var = -1 marks a slot that can never be picked (empty, or selected)
+        var[rr] = pid[rr] >= 0 ? prior : -1.0;
     }
     bad = bad || __any(bad_idx);
     if (bad) {
@@ -150,7 +161,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 Top2 loc = {0ull, 0ull};
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
-                    if (((live >> rr) & 1u) && var[rr] > thr) {
+                    if (var[rr] > thr) {
                         const double sc = cov[rr] * cov[rr] * rcp64(var[rr]);
                         insert(loc, make_key(sc, rr * kWave + lane));
                     }
@@ -161,7 +172,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
                     const double sc = cov[rr] * cov[rr] * rcp64(var[rr]);
-                    const uint64_t key = (((live >> rr) & 1u) && var[rr] > thr) ? make_key(sc, rr * kWave + lane) : 0ull;
+                    const uint64_t key = var[rr] > thr ? make_key(sc, rr * kWave + lane) : 0ull;
                     best = key > best ? key : best;
                 }
                 w.k1 = wave_max64(best);
@@ -174,7 +185,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 for (int rr = 0; rr < RPL; ++rr) {
                     const float cf = (float)cov[rr];
                     const float sc = cf * cf * __builtin_amdgcn_rcpf((float)var[rr]);
-                    key[rr] = (((live >> rr) & 1u) && var[rr] > thr) ? (__float_as_uint(sc) | 0x80000000u) : 0u;
+                    key[rr] = var[rr] > thr ? (__float_as_uint(sc) | 0x80000000u) : 0u;
                     best = max(best, key[rr]);
                 }
                 best = wave_max32(best);
@@ -224,7 +235,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 const T dk0 = bc[KMAX], dk1 = bc[KMAX + 1], dk2 = bc[KMAX + 2];
                 const double vk = bcd[0], ck = bcd[1];
                 const int32_t idk = (int32_t)bcd[2];
-                const double inv_sd = 1.0 / sqrt(vk);
+                const double inv_sd = rsq64(vk);
                 const double ui = ck * inv_sd;
                 const T inv_sd_t = (T)inv_sd;
                 T acc[RPL];
@@ -254,7 +265,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 }
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr)
-                    if (rr == rs && lane == ls) live &= ~(1u << rr);
+                    if (rr == rs && lane == ls) var[rr] = -1.0;
                 if (lane == t) {
                     my_sel = idk;
                     my_gap = g;
@@ -311,6 +322,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     // LDS copy, which rows > j read in later steps.  Entries a lane computes
     // above its diagonal are never read.
     bool pd = true;
+    double dinv = 0.0;  // lane j: 1 / R[j][j]
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j >= M || !pd) continue;
@@ -322,8 +334,9 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
             pd = false;
             continue;
         }
-        const double dj = sqrt(piv);
-        a[j] = lane == j ? dj : sj * rcp64(dj);
+        const double inv = rsq64(piv);
+        a[j] = lane == j ? piv * inv : sj * inv;
+        if (lane == j) dinv = inv;
         if (lane < M) TH[lane][j] = a[j];
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -338,13 +351,13 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 #pragma unroll
         for (int c = KMAX; c >= 0; --c) {
             if (c > l) continue;
-            const double rcc = bcast(a[c], c);
+            const double rinv = bcast(dinv, c);  // 1 / R[c][c]
             double yc;
             if (c == l) {
-                yc = 1.0 / rcc;
-                if (lane == 0 && p.logcv) p.logcv[col] = 2.0 * log(rcc);
+                yc = rinv;
+                if (lane == 0 && p.logcv) p.logcv[col] = -2.0 * log(rinv);
             } else {
-                yc = -bcast(acc, c) / rcc;
+                yc = -bcast(acc, c) * rinv;
             }
             if (lane == c) y = yc;
             if (lane < c) acc += R[c][lane] * yc;
