@@ -262,6 +262,315 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
 }
 
 // ---------------------------------------------------------------------------
+// register-resident multi-target selection (mixed precision, C <= 512,
+// m <= 32, k <= KA): one workgroup of 512 threads per group, thread r owning
+// pool row r with its rows of both partial factors in VGPRs
+// ---------------------------------------------------------------------------
+// The targets are conditioned first through chol(Theta_TT), computed in FP64
+// by one wave (left-looking, lane r owning row r) and kept in LDS: each
+// candidate row then solves for its B entries over the targets (forward
+// substitution, FP32).  Factor A's row and B's target columns stay in
+// VGPRs; B's pick columns live in LDS, column-major [t][row] (128 KB at
+// k = 64), where each thread reads its own entries and the winner's as a
+// broadcast.  A pick: FP64 score 1 - var2/var1 -> wave top-two -> LDS ->
+// every thread merges the eight wave results; the winner stores its
+// register rows, offset and variances in LDS; every thread evaluates
+// Theta(row, winner) in FP32, runs both GEMVs and downdates var1, var2 in
+// FP64.  Offsets are taken from the group's first
+// member so FP32 differences stay accurate.  Posterior variances (target
+// rows) are not tracked here: that mode uses the slab kernel.
+constexpr int kAggRegThreads = 512;
+constexpr int kAggRegMaxM = 32;
+
+// a running product held as mantissa * 2^exponent, so a sum of logarithms
+// costs one log at the end
+struct LogProd {
+    double mant = 1.0;
+    int expo = 0;
+    __device__ void mul(double x) {
+        int e;
+        mant = frexp(mant * x, &e);
+        expo += e;
+    }
+    __device__ double log_value() const { return log(mant) + (double)expo * 0.69314718055994530942; }
+};
+
+template <int KA, bool GAP>
+__global__ __launch_bounds__(kAggRegThreads, 1) void agg_select_reg_kernel(AggArgs p) {
+    constexpr int MM = kAggRegMaxM;
+    constexpr int NW = kAggRegThreads / 64;
+    constexpr int NR = kAggRegThreads;  // rows (pool slots) per group
+    extern __shared__ __align__(16) float sh_bp[];  // B pick columns [KA][NR]
+    __shared__ double sh_th[MM][MM + 1];  // Theta_TT, then its Cholesky factor (rows)
+    __shared__ float sh_lt[MM][MM];       // the factor in FP32 for the forward substitution
+    __shared__ float sh_ltinv[MM];        // 1 / diagonal
+    __shared__ float sh_tx[MM][4];        // target offsets from the reference point
+    __shared__ int32_t sh_tid[MM];        // target ids
+    __shared__ __align__(16) float sh_row[KA + MM + 4];  // winner: A row, B target part, offset
+    __shared__ double sh_wv[4];           // winner var1, var2, id
+    __shared__ Top2 sh_top[NW];
+    __shared__ double sh_ldt;
+
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid >> 6;
+    const float cnu = (float)p.c_nu, s2f = (float)p.s2, nugf = (float)p.nugget;
+    const double prior = p.s2 + p.nugget;
+    const double thr = 1e-12 * prior;
+    const int dim = p.dim;
+
+    for (int64_t g = blockIdx.x; g < p.n_groups; g += gridDim.x) {
+        const int32_t b0 = p.group_ptr[g];
+        const int32_t m = p.group_ptr[g + 1] - b0;
+        const int32_t C = p.pool_len[g];
+        int32_t* sel_out = p.sel + g * p.k;
+        bool bad = m < 1 || m > p.max_members || m > MM || C < 0 || C > p.stride || C > kAggRegThreads;
+        // reference point: the first member
+        double ref[3] = {0.0, 0.0, 0.0};
+        int32_t max_member = -1;
+        if (!bad) {
+            const int32_t r0 = p.members[b0];
+            if (r0 < 0 || (int64_t)r0 >= p.n) {
+                bad = true;
+            } else {
+                for (int c = 0; c < dim; ++c) ref[c] = p.pts[(int64_t)r0 * dim + c];
+                for (int q = 0; q < m; ++q) max_member = max(max_member, p.members[b0 + q]);
+            }
+        }
+        bool my_bad = false, my_early = false;
+        // my pool row
+        int32_t rid = -1;
+        float dx0 = 0.f, dx1 = 0.f, dx2 = 0.f;
+        if (!bad && tid < C) {
+            const int32_t id = p.pool[g * p.stride + tid];
+            if (id < 0 || (int64_t)id >= p.n) {
+                my_bad = true;
+            } else {
+                rid = id;
+                dx0 = (float)(p.pts[(int64_t)id * dim] - ref[0]);
+                if (dim > 1) dx1 = (float)(p.pts[(int64_t)id * dim + 1] - ref[1]);
+                if (dim > 2) dx2 = (float)(p.pts[(int64_t)id * dim + 2] - ref[2]);
+                if (p.later_only && id <= max_member) my_early = true;
+            }
+        }
+        // targets -> LDS
+        if (!bad && tid < m) {
+            const int32_t id = p.members[b0 + tid];
+            if (id < 0 || (int64_t)id >= p.n) {
+                my_bad = true;
+            } else {
+                sh_tid[tid] = id;
+                sh_tx[tid][0] = (float)(p.pts[(int64_t)id * dim] - ref[0]);
+                sh_tx[tid][1] = dim > 1 ? (float)(p.pts[(int64_t)id * dim + 1] - ref[1]) : 0.f;
+                sh_tx[tid][2] = dim > 2 ? (float)(p.pts[(int64_t)id * dim + 2] - ref[2]) : 0.f;
+            }
+        }
+        bad = __syncthreads_or(bad || my_bad);
+        const bool early = __syncthreads_or(my_early);
+        if (bad || early) {
+            for (int t = tid; t < p.k; t += kAggRegThreads) {
+                sel_out[t] = -1;
+                if (p.gap) p.gap[g * p.k + t] = __builtin_nanf("");
+            }
+            if (tid == 0) {
+                if (p.logdet) p.logdet[g] = __builtin_nan("");
+                p.status[g] = bad ? 3 : 4;
+            }
+            __syncthreads();
+            continue;
+        }
+        // ---- Theta_TT (FP64, one entry per thread) and its Cholesky factor --
+        for (int e = tid; e < MM * (MM + 1) / 2; e += kAggRegThreads) {
+            int r = (int)((sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
+            while ((r + 1) * (r + 2) / 2 <= e) ++r;
+            while (r * (r + 1) / 2 > e) --r;
+            const int c = e - r * (r + 1) / 2;
+            if (r < m) {
+                const int32_t ir = p.members[b0 + r], ic = p.members[b0 + c];
+                double d2 = 0.0;
+                for (int q = 0; q < dim; ++q) {
+                    const double df = p.pts[(int64_t)ir * dim + q] - p.pts[(int64_t)ic * dim + q];
+                    d2 += df * df;
+                }
+                sh_th[r][c] = matern_f64_rt(p.two_nu, sqrt(d2), p.c_nu, p.s2) + (ir == ic ? p.nugget : 0.0);
+            }
+        }
+        __syncthreads();
+        bool pd = true;
+        if (wave == 0) {
+            // left-looking, lane r finishing row r of the factor in LDS
+            LogProd ldt;
+            for (int j = 0; j < m; ++j) {
+                double sj = 0.0;
+                if (lane >= j && lane < m) {
+                    sj = sh_th[lane][j];
+                    for (int c = 0; c < j; ++c) sj -= sh_th[lane][c] * sh_th[j][c];
+                }
+                const double piv = bcast(sj, j);
+                if (!(piv > 0.0)) {
+                    pd = false;
+                    break;
+                }
+                const double inv = rsq64(piv);
+                ldt.mul(piv);
+                if (lane >= j && lane < m) sh_th[lane][j] = lane == j ? piv * inv : sj * inv;
+                if (lane == j) sh_ltinv[j] = (float)inv;
+                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+            }
+            for (int e = lane; e < MM * MM; e += 64) {
+                const int r = e / MM, c = e - (e / MM) * MM;
+                sh_lt[r][c] = (c < r && r < m) ? (float)sh_th[r][c] : 0.0f;
+            }
+            if (lane == 0) sh_ldt = pd ? ldt.log_value() : __builtin_nan("");
+        }
+        pd = __syncthreads_and(wave != 0 || pd);
+        if (!pd) {  // Theta_TT not positive definite in FP64: no selection
+            for (int t = tid; t < p.k; t += kAggRegThreads) {
+                sel_out[t] = -1;
+                if (p.gap) p.gap[g * p.k + t] = __builtin_nanf("");
+            }
+            if (tid == 0) {
+                if (p.logdet) p.logdet[g] = __builtin_nan("");
+                p.status[g] = 2;
+            }
+            __syncthreads();
+            continue;
+        }
+        // ---- condition my row on the targets: B[0, m) --------------------------
+        float A[KA], B[MM];
+#pragma unroll
+        for (int q = 0; q < KA; ++q) A[q] = 0.0f;
+#pragma unroll
+        for (int q = 0; q < MM; ++q) B[q] = 0.0f;
+        double v1 = rid >= 0 ? prior : -1.0;  // -1: never a candidate
+        double v2 = prior;
+#pragma unroll
+        for (int c = 0; c < MM; ++c) {
+            asm volatile("" ::: "memory");  // one row of the factor's LDS copy at a time
+            if (c < m) {
+                const float e0 = dx0 - sh_tx[c][0], e1 = dx1 - sh_tx[c][1], e2 = dx2 - sh_tx[c][2];
+                float acc = matern_any<float>(p.two_nu, __builtin_amdgcn_sqrtf(e0 * e0 + e1 * e1 + e2 * e2), cnu, s2f);
+                if (rid == sh_tid[c]) acc += nugf;
+#pragma unroll
+                for (int q = 0; q < c; ++q) acc -= B[q] * sh_lt[c][q];
+                B[c] = acc * sh_ltinv[c];
+                v2 -= (double)B[c] * (double)B[c];
+            }
+        }
+        // ---- greedy multi-target selection ---------------------------------------
+        const int kk = min(p.k, C);
+        LogProd ld;  // prod of var2 / var1 of the winners (thread 0)
+        int nsel = 0;
+        int st = 0;
+        bool stopped = false;
+#pragma unroll
+        for (int t = 0; t < KA; ++t) {
+            if (t < kk && !stopped) {
+                const bool valid = v1 > thr && v2 > thr;
+                const uint64_t key = valid ? make_key(fmax(0.0, (v1 - v2) * rcp64(v1)), tid) : 0ull;
+                Top2 w;
+                if constexpr (GAP) {
+                    w = wave_top2(Top2{key, 0ull});
+                } else {
+                    w.k1 = wave_max64(key);
+                    w.k2 = 0ull;
+                }
+                if (lane == 0) sh_top[wave] = w;
+                __syncthreads();  // also: every thread is done reading the previous winner
+                w = sh_top[0];
+#pragma unroll
+                for (int q = 1; q < NW; ++q) {
+                    if constexpr (GAP) {
+                        w = merge(w, sh_top[q]);
+                    } else {
+                        w.k1 = max(w.k1, sh_top[q].k1);
+                    }
+                }
+                if (w.k1 == 0ull) {
+                    st = 1;
+                    stopped = true;
+                } else {
+                    const int slot = key_slot(w.k1);
+                    if (tid == slot) {
+#pragma unroll
+                        for (int q = 0; q < t; ++q) sh_row[q] = A[q];
+#pragma unroll
+                        for (int q = 0; q < MM; ++q) sh_row[KA + q] = B[q];
+                        sh_row[KA + MM] = dx0;
+                        sh_row[KA + MM + 1] = dx1;
+                        sh_row[KA + MM + 2] = dx2;
+                        sh_wv[0] = v1;
+                        sh_wv[1] = v2;
+                        sh_wv[2] = (double)rid;
+                        v1 = -1.0;  // taken
+                    }
+                    __syncthreads();
+                    const double w1 = sh_wv[0], w2 = sh_wv[1];
+                    const int32_t idw = (int32_t)sh_wv[2];
+                    if (tid == 0) {
+                        sel_out[t] = idw;
+                        ld.mul(w2 * rcp64(w1));
+                        if constexpr (GAP) {
+                            const double sa = key_score(w.k1), sb = key_score(w.k2);
+                            if (p.gap)
+                                p.gap[g * p.k + t] =
+                                    (w.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
+                        }
+                    }
+                    const float inv1 = (float)rsq64(w1), inv2 = (float)rsq64(w2);
+                    const float e0 = dx0 - sh_row[KA + MM], e1 = dx1 - sh_row[KA + MM + 1],
+                                e2 = dx2 - sh_row[KA + MM + 2];
+                    float th = matern_any<float>(p.two_nu, __builtin_amdgcn_sqrtf(e0 * e0 + e1 * e1 + e2 * e2), cnu, s2f);
+                    if (rid == idw) th += nugf;
+                    // GEMVs against the broadcast rows, 32 LDS values at a time
+                    // (the empty asm keeps the compiler from hoisting every
+                    // broadcast load of the pick into registers at once)
+                    float a = th, b = th;
+#pragma unroll
+                    for (int q0 = 0; q0 < t; q0 += 32) {
+                        asm volatile("" ::: "memory");
+#pragma unroll
+                        for (int q = q0; q < q0 + 32 && q < t; ++q) a -= A[q] * sh_row[q];
+                    }
+                    asm volatile("" ::: "memory");
+#pragma unroll
+                    for (int q4 = 0; q4 < MM / 4; ++q4) {
+                        if (4 * q4 < m) {  // entries past m are zero on both sides
+#pragma unroll
+                            for (int q = 4 * q4; q < 4 * q4 + 4; ++q) b -= B[q] * sh_row[KA + q];
+                        }
+                    }
+                    // B's pick columns: my entry and the winner's (a broadcast)
+#pragma unroll
+                    for (int q0 = 0; q0 < t; q0 += 32) {
+                        asm volatile("" ::: "memory");
+#pragma unroll
+                        for (int q = q0; q < q0 + 32 && q < t; ++q) b -= sh_bp[q * NR + tid] * sh_bp[q * NR + slot];
+                    }
+                    const float u1 = a * inv1, u2 = b * inv2;
+                    A[t] = u1;
+                    sh_bp[t * NR + tid] = u2;
+                    v1 -= (double)u1 * (double)u1;
+                    v2 -= (double)u2 * (double)u2;
+                    nsel = t + 1;
+                }
+            }
+        }
+        // ---- outputs ----------------------------------------------------------
+        for (int t = nsel + tid; t < p.k; t += kAggRegThreads) {
+            sel_out[t] = -1;
+            if (p.gap) p.gap[g * p.k + t] = __builtin_nanf("");
+        }
+        if (tid == 0) {
+            if (p.logdet) p.logdet[g] = sh_ldt + ld.log_value();
+            p.status[g] = (uint8_t)st;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // aggregated factor columns (FP64)
 // ---------------------------------------------------------------------------
 constexpr int kAggFacMaxM = 96;  // |s_g| = m + selected
@@ -430,10 +739,40 @@ AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, i
     return pl;
 }
 
+template <int KA, bool GAP>
+static hipError_t launch_reg(const AggArgs& a, hipStream_t s) {
+    // one 512-thread workgroup per CU (its LDS holds B's pick columns)
+    const size_t smem = (size_t)KA * kAggRegThreads * sizeof(float);
+    auto kern = agg_select_reg_kernel<KA, GAP>;
+    hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+    if (e != hipSuccess) return e;
+    const unsigned grid = (unsigned)std::min<int64_t>(a.n_groups, 4096);
+    hipLaunchKernelGGL(kern, dim3(grid), dim3(kAggRegThreads), smem, s, a);
+    return hipGetLastError();
+}
+
+// the register-resident kernel applies to mixed precision without posterior
+// variances, pools <= 512, groups <= 32 and k <= 64
+bool agg_reg_applies(int32_t stride, int32_t max_members, int32_t k, int precision, bool want_post_var) {
+    return precision != 0 && !want_post_var && stride <= kAggRegThreads && max_members <= kAggRegMaxM && k <= 64;
+}
+
 hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s) {
     if (a.n_groups == 0) return hipSuccess;
     hipError_t e;
     const unsigned grid = (unsigned)pl.slots;
+    if (agg_reg_applies(a.stride, a.max_members, a.k, precision, a.post_var != nullptr)) {
+        const bool gap = a.gap != nullptr;
+        e = a.k <= 16 ? (gap ? launch_reg<16, true>(a, s) : launch_reg<16, false>(a, s))
+            : a.k <= 32 ? (gap ? launch_reg<32, true>(a, s) : launch_reg<32, false>(a, s))
+                        : (gap ? launch_reg<64, true>(a, s) : launch_reg<64, false>(a, s));
+        if (e != hipSuccess) return e;
+        if (want_factor) {
+            hipLaunchKernelGGL(agg_factor_kernel, dim3((unsigned)a.n_groups), dim3(kAggFacThreads), 0, s, a);
+            e = hipGetLastError();
+        }
+        return e;
+    }
     if (precision == 0) {
         e = pl.rpt == 1 ? launch_sel<double, 1>(a, pl.threads, grid, pl.smem, s)
             : pl.rpt == 2 ? launch_sel<double, 2>(a, pl.threads, grid, pl.smem, s)

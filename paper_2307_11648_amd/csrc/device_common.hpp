@@ -136,6 +136,24 @@ __device__ __forceinline__ double key_score(uint64_t key) {
     return __longlong_as_double((long long)(key & ~kSlotMask));
 }
 
+// 1/v in FP64: hardware reciprocal refined by one Newton step (about 1 ulp)
+__device__ __forceinline__ double rcp64(double v) {
+    const double r = __builtin_amdgcn_rcp(v);
+    return r * fma(-v, r, 2.0);
+}
+
+// 1/sqrt(v) in FP64 (v > 0 normal): hardware reciprocal square root refined
+// by two Newton steps r <- r + r/2 (1 - v r^2) (about 1 ulp)
+__device__ __forceinline__ double rsq64(double v) {
+    double r = __builtin_amdgcn_rsq(v);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) {
+        const double e = fma(-(v * r), r, 1.0);
+        r = fma(0.5 * r, e, r);
+    }
+    return r;
+}
+
 // ---------------------------------------------------------------------------
 // Matern kernels (half-integer smoothness).  `c` = sqrt(2 nu) / length_scale.
 // ---------------------------------------------------------------------------

@@ -44,24 +44,6 @@ __device__ __forceinline__ T tsqrt(T x) {
     else return sqrt(x);
 }
 
-// 1/v in FP64: hardware reciprocal refined by one Newton step (about 1 ulp)
-__device__ __forceinline__ double rcp64(double v) {
-    const double r = __builtin_amdgcn_rcp(v);
-    return r * fma(-v, r, 2.0);
-}
-
-// 1/sqrt(v) in FP64 (v > 0 normal): hardware reciprocal square root refined
-// by two Newton steps r <- r + r/2 (1 - v r^2) (about 1 ulp)
-__device__ __forceinline__ double rsq64(double v) {
-    double r = __builtin_amdgcn_rsq(v);
-#pragma unroll
-    for (int it = 0; it < 2; ++it) {
-        const double e = fma(-(v * r), r, 1.0);
-        r = fma(0.5 * r, e, r);
-    }
-    return r;
-}
-
 template <typename T, int TWO_NU>
 __device__ __forceinline__ T matern(T r, T c, T s2) {
     if constexpr (sizeof(T) == 4) return matern_f32<TWO_NU>(r, c, s2);

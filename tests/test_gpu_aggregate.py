@@ -209,3 +209,46 @@ def test_apply_factor():
                                atol=1e-10)
     # L^T x is deterministic
     assert torch.equal(ylt, csel.apply_factor(cp, rows, vals, x, True))
+
+
+@pytest.mark.parametrize("want_gap", [True, False])
+def test_aggregated_mixed_register_kernel(want_gap):
+    """Mixed precision without posterior variances, pools <= 512, groups <= 32,
+    k <= 64 (the register-resident kernel): FP64 replay of every pick, the
+    tracked log det against FP64 on the same selection, and the aggregated
+    columns; with and without the gap output the picks agree."""
+    print(f"case: aggregated mixed register kernel gap={want_gap}", flush=True)
+    w = inputs.workload_aggregated(n=9000, seed=33, C=256, k=48, mmin=8, mmax=32)
+    mm = int(np.max(np.diff(w.group_ptr)))
+    args = (_t(w.points, torch.float64), w.kernel, _t(w.group_ptr, torch.int32), _t(w.members, torch.int32), mm,
+            _t(w.pool, torch.int32), _t(w.pool_len, torch.int32), w.k, "mixed")
+    out = csel.aggregated_select(*args, want_factor=True, want_post_var=False, want_gap=want_gap)
+    other = csel.aggregated_select(*args, want_factor=False, want_post_var=False, want_gap=not want_gap)
+    torch.cuda.synchronize()
+    g = {key: v.cpu().numpy() for key, v in out.items() if key != "workspace"}
+    assert np.array_equal(g["sel"], other["sel"].cpu().numpy())
+    G = len(w.group_ptr) - 1
+    assert np.all(g["status"] <= 1)
+    worst_loss = worst_val = 0.0
+    for gi in range(0, G, 3):
+        b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+        T = w.members[b:e]
+        r = oracle.multi_replay_one(w.points, w.kernel, T, w.pool[gi, : w.pool_len[gi]], w.k, g["sel"][gi])
+        assert r["status"] != 5, f"group {gi}: a GPU pick is not a valid candidate"
+        n = int(np.sum(g["sel"][gi] >= 0))
+        for s in range(n):
+            loss = math.log1p(-r["pick"][s]) - math.log1p(-r["best"][s])
+            worst_loss = max(worst_loss, loss)
+            assert loss <= TAU_LOGDET, f"group {gi} step {s}: log det loss {loss}"
+        assert g["logdet"][gi] == pytest.approx(r["logdet"], rel=1e-3, abs=1e-3)
+        cols = oracle.aggregated_columns(w.points, w.kernel, T, g["sel"][gi])
+        for a in range(b, e):
+            gv = g["vals"][g["val_ptr"][a]:g["val_ptr"][a + 1]]
+            off = sum(len(T) - q + n for q in range(a - b))
+            ov = cols["vals"][off: off + len(T) - (a - b) + n]
+            err = float(np.max(np.abs(gv[: len(ov)] - ov)) / np.max(np.abs(ov)))
+            worst_val = max(worst_val, err)
+            assert err <= 1e-3
+        if want_gap:
+            assert np.all(np.isfinite(g["gap"][gi, :n])) and np.all(np.isnan(g["gap"][gi, n:]))
+    print(f"mixed register kernel: worst per-step log det loss {worst_loss:.2e}, worst column error {worst_val:.2e}")
