@@ -574,13 +574,22 @@ __global__ __launch_bounds__(kAggRegThreads, 1) void agg_select_reg_kernel(AggAr
 // aggregated factor columns (FP64)
 // ---------------------------------------------------------------------------
 constexpr int kAggFacMaxM = 96;  // |s_g| = m + selected
-constexpr int kAggFacThreads = 256;
+constexpr int kAggFacThreads = 128;
 
 __host__ __device__ constexpr int tri(int i) { return i * (i + 1) / 2; }
 
+// One 128-thread workgroup per group.  The reversed Theta_sg is built in
+// packed LDS rows (its lower triangle spread evenly over the threads), then
+// factored left-looking by columns: thread r keeps row r in VGPRs, reads
+// row j of the factor from LDS as a broadcast, and stores its column-j entry
+// back for the rows after it (two barriers per column).  One wave per member
+// then back-substitutes its column against the stored rows.
 __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
-    __shared__ double A[tri(kAggFacMaxM + 1)];  // reversed Theta_sg, packed lower, then its Cholesky factor
-    __shared__ int32_t sg[kAggFacMaxM];
+    constexpr int MF = kAggFacMaxM;
+    __shared__ double A[tri(MF)];       // reversed Theta_sg, then its Cholesky factor (packed rows)
+    __shared__ double pc[MF][3];        // coordinates of s_g in reversed order
+    __shared__ double dinv[MF];         // 1 / R[j][j]
+    __shared__ int32_t sg[MF];
     __shared__ int32_t bad_piv;
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -594,11 +603,12 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
     int nsel = 0;
     while (nsel < p.k && sel[nsel] >= 0) ++nsel;
     const int M = m + nsel;
-    if (M > kAggFacMaxM) {
+    if (M > MF) {
         if (tid == 0) p.status[g] = 5;
         return;
     }
-    // s_g sorted ascending: rank sort (ids are distinct)
+    const int dim = p.dim;
+    // s_g sorted ascending: rank sort (ids are distinct); coordinates in reversed order
     for (int a = tid; a < M; a += kAggFacThreads) {
         const int32_t v = a < m ? p.members[b0 + a] : sel[a - m];
         int rank = 0;
@@ -607,54 +617,58 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
             rank += (w < v);
         }
         sg[rank] = v;
+        for (int d = 0; d < 3; ++d) pc[M - 1 - rank][d] = d < dim ? p.pts[(int64_t)v * dim + d] : 0.0;
     }
     if (tid == 0) bad_piv = 0;
     __syncthreads();
     // reversed order: index i' = M-1-i; packed lower entries (i', c') with c' <= i'
     const double cnu = p.c_nu;
-    const int dim = p.dim;
     for (int e = tid; e < tri(M); e += kAggFacThreads) {
-        int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+        int i = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
         while (tri(i + 1) <= e) ++i;
         while (tri(i) > e) --i;
         const int c = e - tri(i);
-        const int32_t a = sg[M - 1 - i], bq = sg[M - 1 - c];
-        double s = 0.0;
-        for (int d = 0; d < dim; ++d) {
-            const double df = p.pts[(int64_t)a * dim + d] - p.pts[(int64_t)bq * dim + d];
-            s += df * df;
-        }
-        A[e] = matern_f64_rt(p.two_nu, sqrt(s), cnu, p.s2) + (a == bq ? p.nugget : 0.0);
+        const double d0 = pc[i][0] - pc[c][0], d1 = pc[i][1] - pc[c][1], d2 = pc[i][2] - pc[c][2];
+        const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        const double r = r2 > 0.0 ? r2 * rsq64(r2) : 0.0;
+        A[e] = matern_f64_rt(p.two_nu, r, cnu, p.s2) + (i == c ? p.nugget : 0.0);
     }
     __syncthreads();
-    // right-looking Cholesky, one barrier per column: in step j the column j-1
-    // is scaled while the trailing block takes the rank-one update of column j
-    for (int j = 0; j <= M; ++j) {
-        if (j > 0) {
-            const double djm = sqrt(A[tri(j - 1) + j - 1]);
-            for (int i = j + tid; i < M; i += kAggFacThreads) A[tri(i) + j - 1] /= djm;
-        }
-        if (j < M) {
-            const double piv = A[tri(j) + j];
-            if (!(piv > 0.0)) {
-                if (tid == 0) bad_piv = 1;
-            } else {
-                const int nt = M - 1 - j;  // trailing size
-                for (int e = tid; e < tri(nt); e += kAggFacThreads) {
-                    int i = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
-                    while (tri(i + 1) <= e) ++i;
-                    while (tri(i) > e) --i;
-                    const int c = e - tri(i);
-                    const int ii = j + 1 + i, cc = j + 1 + c;
-                    A[tri(ii) + cc] -= A[tri(ii) + j] * A[tri(cc) + j] / piv;
+    // left-looking Cholesky, row r in thread r's registers
+    {
+        double a[MF];
+#pragma unroll
+        for (int c = 0; c < MF; ++c) a[c] = (c <= tid && tid < M) ? A[tri(tid) + c] : 0.0;
+        __syncthreads();
+        bool stop = false;  // uniform: past M or a non-positive pivot
+#pragma unroll
+        for (int j = 0; j < MF; ++j) {
+            if (j >= M || stop) continue;
+            double sj = a[j];
+#pragma unroll
+            for (int c = 0; c < j; ++c) sj -= a[c] * A[tri(j) + c];
+            if (tid == j) {
+                if (sj > 0.0) {
+                    const double inv = rsq64(sj);
+                    a[j] = sj * inv;
+                    A[tri(j) + j] = a[j];
+                    dinv[j] = inv;
+                } else {
+                    bad_piv = 1;
                 }
             }
+            __syncthreads();
+            if (bad_piv) {
+                stop = true;
+                continue;
+            }
+            if (tid > j && tid < M) {
+                a[j] = sj * dinv[j];
+                A[tri(tid) + j] = a[j];
+            }
+            __syncthreads();
         }
-        __syncthreads();
-        if (bad_piv) break;
     }
-    for (int j = tid; j < M; j += kAggFacThreads) A[tri(j) + j] = bad_piv ? 0.0 : sqrt(A[tri(j) + j]);
-    __syncthreads();
     // member columns: member at sorted position pos -> reversed index jr = M-1-pos;
     // z = R^{-T} e_jr (entries z_i, i <= jr): column-oriented back-substitution.
     const int nw = kAggFacThreads / kWave;
@@ -677,13 +691,13 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
         // lanes own reversed indices i = lane and lane + 64 (M <= 128)
         double acc0 = 0.0, acc1 = 0.0, z0 = 0.0, z1 = 0.0;
         for (int l = jr; l >= 0; --l) {
-            const double rll = A[tri(l) + l];
+            const double il = dinv[l];  // 1 / R[l][l]
             double zl;
             if (l == jr) {
-                zl = 1.0 / rll;
+                zl = il;
             } else {
                 const double al = (l < kWave) ? bcast(acc0, l) : bcast(acc1, l - kWave);
-                zl = -al / rll;
+                zl = -al * il;
             }
             if (lane == l) z0 = zl;
             if (lane + kWave == l) z1 = zl;
@@ -702,7 +716,7 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
             vals[o] = z1;
             rows[o] = sg[M - 1 - lane - kWave];
         }
-        if (lane == 0 && p.member_logcv) p.member_logcv[b0 + a] = 2.0 * log(A[tri(jr) + jr]);
+        if (lane == 0 && p.member_logcv) p.member_logcv[b0 + a] = -2.0 * log(dinv[jr]);
         // pad the member's slot range if fewer points were selected than budgeted
         const int64_t budget = p.val_ptr[b0 + a + 1] - p.val_ptr[b0 + a];
         for (int64_t l = len + lane; l < budget; l += kWave) {
