@@ -263,18 +263,19 @@ int csel_screen_features(const double *pts, int64_t n, int32_t dim, const csel_k
  * deterministic).  fallback = 3 marks bad input.  logits [n_targets]
  * [pool_stride] is optional.  pool_stride <= 512.
  *
- * order (optional, device int32 [n_targets]): the order in which the columns
- * are processed, e.g. from csel_spatial_order; results do not depend on it.
- * A column absent from it is not processed (its outputs are left as they
- * were); entries outside [0, n_targets) are skipped; a column listed twice
- * is processed twice (its fallback index is then appended twice).  NULL
- * processes 0, 1, ..., n_targets - 1.
+ * order, n_order (optional): the device int32 list order[0 .. n_order) of the
+ * columns to process, in that order, e.g. csel_spatial_order's output or a
+ * slice of it; results do not depend on the order.  A column absent from it
+ * is not processed (its outputs are left as they were); entries outside
+ * [0, n_targets) are skipped; a column listed twice is processed twice (its
+ * fallback index is then appended twice).  With order NULL, n_order is
+ * ignored and 0, 1, ..., n_targets - 1 are processed.
  */
 int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_targets,
                 const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride,
                 const float *params, const uint16_t *params_bf16, int32_t keep, float fallback_threshold,
                 int32_t *kept_idx, int32_t *kept_len, uint8_t *fallback, float *logits, int32_t *fallback_list,
-                int32_t *fallback_count, const int32_t *order, hipStream_t stream);
+                int32_t *fallback_count, const int32_t *order, int64_t n_order, hipStream_t stream);
 
 /*
  * csel_spatial_order -- a processing order of the columns by the Morton

@@ -59,8 +59,10 @@ def hip_units():
     return [(os.path.join(CSRC, src), defs) for src, defs in HIP_UNITS if os.path.exists(os.path.join(CSRC, src))]
 
 
-def build_hip(extra_flags=None, jobs=None) -> str:
-    """Compile every unit to an object (in parallel), then link libcsel.so."""
+def build_hip(extra_flags=None, jobs=None, only=None) -> str:
+    """Compile every unit to an object (in parallel), then link libcsel.so.
+    `only` (a set of source file names) recompiles just those units and
+    relinks with the other units' existing objects (a development shortcut)."""
     from concurrent.futures import ThreadPoolExecutor
 
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -73,6 +75,8 @@ def build_hip(extra_flags=None, jobs=None) -> str:
         src, defs = u
         tag = "_".join(d.split("=")[-1] for d in defs)
         obj = os.path.join(objdir, os.path.basename(src) + (("." + tag) if tag else "") + ".o")
+        if only is not None and os.path.basename(src) not in only and os.path.exists(obj):
+            return obj
         _run([hipcc] + HIPCC_FLAGS + (extra_flags or []) + defs + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
         return obj
 

@@ -80,7 +80,7 @@ def load():
     lib.csel_screen_features.restype = ctypes.c_int
     lib.csel_screen.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64, _vp, _vp,
                                 _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_float, _vp, _vp, _vp, _vp, _vp, _vp,
-                                _vp, _vp]
+                                _vp, _c.c_int64, _vp]
     lib.csel_screen.restype = ctypes.c_int
     lib.csel_spatial_order_workspace_size.argtypes = [_c.c_int64]
     lib.csel_spatial_order_workspace_size.restype = ctypes.c_int64
@@ -236,9 +236,12 @@ def screen(points, kernel, targets, pool, pool_len, params, params_bf16, keep: i
            want_logits=False, out=None, order=None, stream=None) -> dict:
     """csel_screen: kept [T, keep] ids in distance order, kept_len [T],
     fallback [T] u8, fallback_list [T] int32 with fallback_count [1].
-    `order` (int32 [T], optional) is the processing order of the columns."""
+    `order` (int32 device tensor, optional) lists the columns to process, in
+    processing order (all of them, e.g. csel.spatial_order, or a subset)."""
     lib = load()
     _dev(params, torch.float32, "params")
+    if order is not None:
+        _dev(order, torch.int32, "order")
     T = targets.shape[0]
     stride = pool.shape[1]
     dev = points.device
@@ -256,7 +259,7 @@ def screen(points, kernel, targets, pool, pool_len, params, params_bf16, keep: i
                            params_bf16.data_ptr(), int(keep), float(fallback_threshold), out["kept"].data_ptr(),
                            out["kept_len"].data_ptr(), out["fallback"].data_ptr(), _ptr(out.get("logits")),
                            out["fallback_list"].data_ptr(), out["fallback_count"].data_ptr(), _ptr(order),
-                           _stream(stream)))
+                           0 if order is None else order.numel(), _stream(stream)))
     return out
 
 

@@ -332,7 +332,7 @@ CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_k
                          int32_t pool_stride, const float* params, const uint16_t* params_bf16, int32_t keep,
                          float fallback_threshold, int32_t* kept_idx, int32_t* kept_len, uint8_t* fallback,
                          float* logits, int32_t* fallback_list, int32_t* fallback_count, const int32_t* order,
-                         hipStream_t stream) {
+                         int64_t n_order, hipStream_t stream) {
     g_err[0] = 0;
     csel::ScreenArgs a;
     int rc = screen_common(pts, n, dim, kernel, n_targets, targets, pool_idx, pool_len, pool_stride, a);
@@ -361,7 +361,10 @@ CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_k
     a.fallback = fallback;
     a.fb_list = fallback_list;
     a.fb_count = fallback_count;
+    if (order && (n_order < 0 || n_order > INT32_MAX))
+        return fail(CSEL_EINVAL, "n_order must be in [0, 2^31) (got %lld)", (long long)n_order);
     a.order = order;
+    a.n_order = order ? n_order : n_targets;
     if (fallback_count) {
         hipError_t e = csel::launch_fill_i32(fallback_count, 1, 0, stream);
         if (e != hipSuccess) return hip_fail(e, "fill launch");

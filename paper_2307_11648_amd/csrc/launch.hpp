@@ -59,6 +59,7 @@ struct ScreenArgs {
     int32_t* fb_list;
     int32_t* fb_count;
     const int32_t* order;  // processing order of the columns (nullptr: 0, 1, ...)
+    int64_t n_order;       // positions of `order` to process (n_targets without an order)
 };
 
 struct MlpTrainArgs {

@@ -26,9 +26,6 @@
 #include "device_common.hpp"
 #include "launch.hpp"
 
-#ifndef KNT
-#define KNT 4
-#endif
 
 namespace csel {
 
@@ -157,9 +154,20 @@ struct MlpLds {
     uint2 a1[4][64];
     uint4 a2[4][2][64];  // [h2][q][lane]
     uint4 a3[2][64];     // [q][lane]
+    float4 b1[4][4];     // [h][lane group]: b1[16h + 4g + i]
+    float4 b2[4][4];
+    float b3;
 };
 
-__device__ __forceinline__ void stage_mlp(MlpLds& L, const uint16_t* __restrict__ pb) {
+__device__ __forceinline__ void stage_mlp(MlpLds& L, const float* __restrict__ pf, const uint16_t* __restrict__ pb) {
+    for (int e = threadIdx.x; e < 16; e += blockDim.x) {
+        const int h = e >> 2, g = e & 3;
+        L.b1[h][g] = float4{pf[kOffB1 + 16 * h + 4 * g], pf[kOffB1 + 16 * h + 4 * g + 1],
+                            pf[kOffB1 + 16 * h + 4 * g + 2], pf[kOffB1 + 16 * h + 4 * g + 3]};
+        L.b2[h][g] = float4{pf[kOffB2 + 16 * h + 4 * g], pf[kOffB2 + 16 * h + 4 * g + 1],
+                            pf[kOffB2 + 16 * h + 4 * g + 2], pf[kOffB2 + 16 * h + 4 * g + 3]};
+    }
+    if (threadIdx.x == 0) L.b3 = pf[kOffB3];
     for (int e = threadIdx.x; e < 14 * 64; e += blockDim.x) {
         const int f = e >> 6, l = e & 63, c = l & 15, g = l >> 4;
         if (f >= 12) {
@@ -192,55 +200,21 @@ __device__ __forceinline__ void stage_mlp(MlpLds& L, const uint16_t* __restrict_
     }
 }
 
-// As mlp_tile, with the MFMA weight operands read from LDS.
-__device__ __forceinline__ float mlp_tile_lds(const MlpRegs& R, const MlpLds& L, short4_t xb, int lane) {
-    short4_t h1q[4];
-#pragma unroll
-    for (int h = 0; h < 4; ++h) {
-        float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
-        acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(__builtin_bit_cast(short4_t, L.a1[h][lane]), xb, acc, 0, 0, 0);
-        h1q[h] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
-    }
-    bf16x8_t b2op[2];
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const uint2 lo = __builtin_bit_cast(uint2, h1q[2 * q]), hi = __builtin_bit_cast(uint2, h1q[2 * q + 1]);
-        b2op[q] = __builtin_bit_cast(bf16x8_t, uint4{lo.x, lo.y, hi.x, hi.y});
-    }
-    short4_t h2q[4];
-#pragma unroll
-    for (int h2 = 0; h2 < 4; ++h2) {
-        float4_t acc = {R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
-#pragma unroll
-        for (int q = 0; q < 2; ++q)
-            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, L.a2[h2][q][lane]), b2op[q],
-                                                          acc, 0, 0, 0);
-        h2q[h2] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
-    }
-    float4_t acc = {R.b3, R.b3, R.b3, R.b3};
-#pragma unroll
-    for (int q = 0; q < 2; ++q) {
-        const uint2 lo = __builtin_bit_cast(uint2, h2q[2 * q]), hi = __builtin_bit_cast(uint2, h2q[2 * q + 1]);
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16x8_t, L.a3[q][lane]),
-                                                      __builtin_bit_cast(bf16x8_t, uint4{lo.x, lo.y, hi.x, hi.y}),
-                                                      acc, 0, 0, 0);
-    }
-    return acc[0];  // row 0 of D: the logit of candidate l % 16 in lanes 0..15
-}
-
-// As mlp_tile_lds for NT independent tiles at once: each weight operand is
+// The forward of mlp_tile for NT independent tiles at once, with the MFMA
+// weight operands and the biases read from LDS: each weight operand is
 // read from LDS once and applied to every tile, and the tiles' MFMA chains
 // interleave.
 template <int NT>
-__device__ __forceinline__ void mlp_tiles_lds(const MlpRegs& R, const MlpLds& L, const short4_t (&xb)[NT],
-                                              float (&z)[NT], int lane) {
+__device__ __forceinline__ void mlp_tiles_lds(const MlpLds& L, const short4_t (&xb)[NT], float (&z)[NT], int lane) {
+    const int g = lane >> 4;
     short4_t h1q[NT][4];
 #pragma unroll
     for (int h = 0; h < 4; ++h) {
         const short4_t a = __builtin_bit_cast(short4_t, L.a1[h][lane]);
+        const float4 bb = L.b1[h][g];
 #pragma unroll
         for (int t = 0; t < NT; ++t) {
-            float4_t acc = {R.b1[h][0], R.b1[h][1], R.b1[h][2], R.b1[h][3]};
+            float4_t acc = {bb.x, bb.y, bb.z, bb.w};
             acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, xb[t], acc, 0, 0, 0);
             h1q[t][h] = relu_bf16x4(pack_bf16x4(acc[0], acc[1], acc[2], acc[3]));
         }
@@ -249,8 +223,9 @@ __device__ __forceinline__ void mlp_tiles_lds(const MlpRegs& R, const MlpLds& L,
 #pragma unroll
     for (int h2 = 0; h2 < 4; ++h2) {
         float4_t acc[NT];
+        const float4 bb = L.b2[h2][g];
 #pragma unroll
-        for (int t = 0; t < NT; ++t) acc[t] = float4_t{R.b2[h2][0], R.b2[h2][1], R.b2[h2][2], R.b2[h2][3]};
+        for (int t = 0; t < NT; ++t) acc[t] = float4_t{bb.x, bb.y, bb.z, bb.w};
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
             const bf16x8_t a = __builtin_bit_cast(bf16x8_t, L.a2[h2][q][lane]);
@@ -266,8 +241,9 @@ __device__ __forceinline__ void mlp_tiles_lds(const MlpRegs& R, const MlpLds& L,
         for (int t = 0; t < NT; ++t) h2q[t][h2] = relu_bf16x4(pack_bf16x4(acc[t][0], acc[t][1], acc[t][2], acc[t][3]));
     }
     float4_t acc[NT];
+    const float b3 = L.b3;
 #pragma unroll
-    for (int t = 0; t < NT; ++t) acc[t] = float4_t{R.b3, R.b3, R.b3, R.b3};
+    for (int t = 0; t < NT; ++t) acc[t] = float4_t{b3, b3, b3, b3};
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const bf16x8_t a = __builtin_bit_cast(bf16x8_t, L.a3[q][lane]);
@@ -282,20 +258,6 @@ __device__ __forceinline__ void mlp_tiles_lds(const MlpRegs& R, const MlpLds& L,
     for (int t = 0; t < NT; ++t) z[t] = acc[t][0];
 }
 
-// biases and w3 only (the screen keeps the MFMA operands in LDS)
-__device__ __forceinline__ void load_mlp_vec(MlpRegs& R, const float* __restrict__ p, const uint16_t* __restrict__ pb,
-                                             int lane) {
-    const int g = lane >> 4;
-#pragma unroll
-    for (int h = 0; h < 4; ++h)
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            R.b1[h][i] = p[kOffB1 + 16 * h + 4 * g + i];
-            R.b2[h][i] = p[kOffB2 + 16 * h + 4 * g + i];
-            R.w3[h][i] = bf16_to_f32(pb[kOffW3 + 16 * h + 4 * g + i]);
-        }
-    R.b3 = p[kOffB3];
-}
 
 // ---------------------------------------------------------------------------
 // features of one candidate (FP32); see the feature list in the header
@@ -345,7 +307,7 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
     constexpr int CH = 64 * RPL;
     constexpr int MAXC = CH * NCH;
     constexpr int KPL = RPL * NCH;  // keys per lane
-    constexpr int kNT = KNT;
+    constexpr int kNT = 2;  // MLP tiles per LDS weight read
     static_assert((CH / 16) % kNT == 0, "tile groups must divide a chunk");
     __shared__ __align__(16) uint16_t sh_x[kScrWaves][CH][kF];
     __shared__ float sh_z[kScrWaves][MAXC];
@@ -354,11 +316,7 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
     const int cl = lane & 15, g = lane >> 4;
-    MlpRegs R;
-    if (p.mode == 0) {
-        stage_mlp(sh_w, p.params_bf16);
-        load_mlp_vec(R, p.params, p.params_bf16, lane);
-    }
+    if (p.mode == 0) stage_mlp(sh_w, p.params, p.params_bf16);
     __syncthreads();
     const int dim = p.dim;
     ColumnConsts kc0;
@@ -373,9 +331,10 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
     // b runs on XCD b % 8): the waves of one XCD walk through their segment
     // side by side and share that XCD's L2.  The grid is a multiple of 8.
     const int64_t T = p.n_targets;
-    const int64_t seg = (T + 7) / 8;
+    const int64_t NP = p.order ? p.n_order : T;  // positions to process
+    const int64_t seg = (NP + 7) / 8;
     const int64_t seg0 = (int64_t)(blockIdx.x & 7u) * seg;
-    const int64_t seg1 = min(seg0 + seg, T);
+    const int64_t seg1 = min(seg0 + seg, NP);
     const int64_t pstep = (int64_t)(gridDim.x >> 3) * kScrWaves;
     int64_t pos = seg0 + (int64_t)(blockIdx.x >> 3) * kScrWaves + wib;
     // the column at a position (-1 past the segment), loaded by lane 0
@@ -551,7 +510,7 @@ __global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
                 for (int t = 0; t < kNT; ++t)
                     xb[t] = __builtin_bit_cast(short4_t,
                                                *reinterpret_cast<const uint2*>(&sh_x[wib][(tile + t) * 16 + cl][4 * g]));
-                mlp_tiles_lds<kNT>(R, sh_w, xb, z, lane);
+                mlp_tiles_lds<kNT>(sh_w, xb, z, lane);
 #pragma unroll
                 for (int t = 0; t < kNT; ++t)
                     if (g == 0) sh_z[wib][ch * CH + (tile + t) * 16 + cl] = z[t];
@@ -861,19 +820,22 @@ static hipError_t launch_screen_t(const ScreenArgs& a, hipStream_t s) {
         if (e != hipSuccess) return e;
         resident[dev] = std::max(8, (std::max(per_cu, 1) * cus) / 8 * 8);
     }
-    const int64_t need = ((a.n_targets + kScrWaves - 1) / kScrWaves + 7) / 8 * 8;
+    const int64_t np = a.order ? a.n_order : a.n_targets;
+    const int64_t need = ((np + kScrWaves - 1) / kScrWaves + 7) / 8 * 8;
     const unsigned grid = (unsigned)std::min<int64_t>(need, resident[dev]);
     hipLaunchKernelGGL((screen_kernel<RPL, NCH>), dim3(grid), dim3(kScrWaves * 64), 0, s, a);
     return hipGetLastError();
 }
 
 hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
-    if (a.n_targets == 0) return hipSuccess;
+    if (a.n_targets == 0 || (a.order && a.n_order == 0)) return hipSuccess;
     switch (rpl) {
         case 1: return launch_screen_t<1, 1>(a, s);
         case 2: return launch_screen_t<2, 1>(a, s);
-        case 4: return launch_screen_t<4, 1>(a, s);
-        case 8: return launch_screen_t<4, 2>(a, s);
+        // two rows per lane keeps the kernel at 161 VGPRs and 25 KB of LDS per
+        // block: three waves per SIMD, which this latency-bound kernel needs
+        case 4: return launch_screen_t<2, 2>(a, s);
+        case 8: return launch_screen_t<2, 4>(a, s);
         default: return hipErrorInvalidValue;
     }
 }

@@ -331,6 +331,19 @@ def test_screen_order_does_not_change_results(clustered):
             assert torch.equal(o[key], ref[key]), (name, key)
         nfb = int(ref["fallback_count"].item())
         assert set(o["fallback_list"][:nfb].cpu().tolist()) == set(ref["fallback_list"][:nfb].cpu().tolist())
+    # the order in three slices (separate fallback outputs) covers every column once
+    o = {key: torch.empty_like(v) for key, v in ref.items() if key != "logits"}
+    fb_all = []
+    for a, b in ((0, 1000), (1000, 5000), (5000, T)):
+        part = dict(o, fallback_list=torch.empty(b - a, dtype=torch.int32, device="cuda"),
+                    fallback_count=torch.empty(1, dtype=torch.int32, device="cuda"))
+        csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, 128, 0.6, out=part, order=sp[a:b])
+        torch.cuda.synchronize()
+        fb_all += part["fallback_list"][: int(part["fallback_count"].item())].cpu().tolist()
+    for key in ("kept", "kept_len", "fallback"):
+        assert torch.equal(o[key], ref[key]), ("slices", key)
+    nfb = int(ref["fallback_count"].item())
+    assert sorted(fb_all) == sorted(ref["fallback_list"][:nfb].cpu().tolist())
     # drop column 11 from the order, put an out-of-range entry in its place
     od = sp.clone()
     pos = int(torch.nonzero(od == 11)[0].item())
