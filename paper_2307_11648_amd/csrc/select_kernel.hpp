@@ -58,6 +58,7 @@ template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
 __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
     __shared__ double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
+    __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
 
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
@@ -260,35 +261,32 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     // ---- factor column: Theta' over [selected..., target], FP64 ------------
     const int M = nsel + 1;
     const int32_t my_id = lane < nsel ? my_sel : (lane == nsel ? tgt : -1);
-    double xr0 = 0.0, xr1 = 0.0, xr2 = 0.0;
-    if (my_id >= 0) {
-        xr0 = p.pts[(int64_t)my_id * dim + 0];
-        if (dim > 1) xr1 = p.pts[(int64_t)my_id * dim + 1];
-        if (dim > 2) xr2 = p.pts[(int64_t)my_id * dim + 2];
+    // the points of s (lane r: selected point r, lane nsel: the target) -> LDS
+    double(*PT)[4] = sh_pt[wib];
+    if (lane < M) {
+        const int64_t b = (int64_t)my_id * dim;
+        PT[lane][0] = p.pts[b];
+        PT[lane][1] = dim > 1 ? p.pts[b + 1] : 0.0;
+        PT[lane][2] = dim > 2 ? p.pts[b + 2] : 0.0;
+        PT[lane][3] = (double)my_id;
     }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
     const double cnu64 = p.c_nu, s264 = p.s2, nug64 = p.nugget;
     // Theta' lower triangle, its tri(M) entries spread over the 64 lanes, staged
     // in LDS; then lane r loads its row
     double(*TH)[KMAX + 2] = sh_r[wib];
     {
         const int ne = M * (M + 1) / 2;
-        // uniform trip count: every lane takes part in the cross-lane reads
-        for (int e0 = 0; e0 < ne; e0 += kWave) {
-            const int e = min(e0 + lane, ne - 1);
+        for (int e = lane; e < ne; e += kWave) {
             int r = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
             while ((r + 1) * (r + 2) / 2 <= e) ++r;
             while (r * (r + 1) / 2 > e) --r;
             const int c = e - r * (r + 1) / 2;
-            const int32_t sr = bcast_dyn(my_sel, r), sc_ = bcast_dyn(my_sel, c);
-            const int32_t ir = r < nsel ? sr : tgt;
-            const int32_t ic = c < nsel ? sc_ : tgt;
-            if (e0 + lane >= ne) continue;
-            double s = 0.0;
-            for (int q = 0; q < dim; ++q) {
-                const double df = p.pts[(int64_t)ir * dim + q] - p.pts[(int64_t)ic * dim + q];
-                s += df * df;
-            }
-            TH[r][c] = matern_f64<TWO_NU>(sqrt(s), cnu64, s264) + (ir == ic ? nug64 : 0.0);
+            const double d0 = PT[r][0] - PT[c][0], d1 = PT[r][1] - PT[c][1], d2 = PT[r][2] - PT[c][2];
+            const double s2d = d0 * d0 + d1 * d1 + d2 * d2;
+            const double rr = s2d > 0.0 ? s2d * rsq64(s2d) : 0.0;
+            TH[r][c] = matern_f64<TWO_NU>(rr, cnu64, s264) + (PT[r][3] == PT[c][3] ? nug64 : 0.0);
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
