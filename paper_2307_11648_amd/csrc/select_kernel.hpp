@@ -332,15 +332,14 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         for (int c = KMAX; c >= 0; --c) {
             if (c > l) continue;
             const double rinv = bcast(dinv, c);  // 1 / R[c][c]
-            double yc;
-            if (c == l) {
-                yc = rinv;
-                if (lane == 0 && p.logcv) p.logcv[col] = -2.0 * log(rinv);
-            } else {
-                yc = -bcast(acc, c) * rinv;
-            }
+            const double yc = c == l ? rinv : -bcast(acc, c) * rinv;
             if (lane == c) y = yc;
             if (lane < c) acc += R[c][lane] * yc;
+        }
+        // log Theta_ii|s = -2 log(1 / R_ll)
+        if (p.logcv) {
+            const double rl = bcast(dinv, l);
+            if (lane == 0) p.logcv[col] = -2.0 * log(rl);
         }
     } else {
         st = 2;
