@@ -302,9 +302,9 @@ def _source_digest(*names):
 # this script (copy-probe calibrated), keyed by the digest of the kernel's
 # sources at measurement time; a changed kernel reports null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE x 2.000 (a 1 GiB device copy reads as 524,316 KiB) + WRITE_SIZE x 1.000
-    ("select_factor_kernel (kept pools)", "cf0f57f73c4d7ace"): 5511585 * 1.99989 * 1024 + 398456 * 1024,
-    ("screen_kernel", "815a311744bccb92"): 24388585 * 1.99989 * 1024 + 549197 * 1024,
+    # FETCH_SIZE x 2.000 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.000, in bytes
+    ("select_factor_kernel (kept pools)", "ff0ccc04dcd8ae09"): (5404817 * 1.99989 + 398457) * 1024,
+    ("screen_kernel", "a793b4ae2aab4d78"): (1981490 * 1.99989 + 564169) * 1024,
 }
 
 
