@@ -389,6 +389,17 @@ def bench_screened(args):
         if ev is not None:
             ev[1].record()
 
+    # plain selection with the columns in the screen's Morton order (the list
+    # form of the same kernel): the baseline gets its faster schedule too
+    n_all = torch.tensor([T], dtype=torch.int32, device=dev)
+
+    def plain_ordered_step(ev=None):
+        if ev is not None:
+            ev[0].record()
+        csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, order, n_all, T, plain)
+        if ev is not None:
+            ev[1].record()
+
     def timed(fn, nev):
         for _ in range(args.warmup):
             fn()
@@ -404,7 +415,9 @@ def bench_screened(args):
         return total, parts, wall / args.steps
 
     print("bench: timing plain", file=sys.stderr, flush=True)
-    ms_plain, _, _ = timed(plain_step, 2)
+    ms_plain_natural, _, _ = timed(plain_step, 2)
+    ms_plain_ordered, _, _ = timed(plain_ordered_step, 2)
+    ms_plain = min(ms_plain_natural, ms_plain_ordered)
     print("bench: timing screened", file=sys.stderr, flush=True)
     ms_screen, (ms_scr, ms_kept, ms_fb), wall_screen = timed(screened_step, 4)
     nfb = int(scr["fallback_count"].item())
@@ -445,6 +458,7 @@ def bench_screened(args):
                                f"uniform), Matern 3/2, l=0.05, pools of 512 -> keep {keep}, k={k}, {prec}; MLP "
                                f"16-64-64-1 trained on the GPU on {rows} rows from {len(tr.targets)} exact selections",
                    "columns": T, "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain,
+                   "plain_natural_order_ms": ms_plain_natural, "plain_morton_order_ms": ms_plain_ordered,
                    "screened_ms": ms_screen, "screened_wall_ms_per_step": wall_screen,
                    "screen_kernel_ms": ms_scr, "kept_select_ms": ms_kept, "fallback_select_ms": ms_fb,
                    "spatial_order_setup_ms": ms_order,

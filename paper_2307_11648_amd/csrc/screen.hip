@@ -295,7 +295,11 @@ __device__ __forceinline__ void candidate_features(const ScreenArgs& p, const Co
     for (int q = 12; q < kF; ++q) f[q] = 0.0f;
 }
 
-constexpr int kScrWaves = 2;
+// four waves per block share the staged MLP operands; with at most 128
+// VGPRs (one spilled value) four waves per SIMD fit, which this latency-bound
+// kernel turns into throughput
+constexpr int kScrWaves = 4;
+constexpr int kScrWavesPerSimd = 4;
 
 // One wave per column; persistent waves walk through the processing order
 // (each wave stages the MLP weights once).  The pool (<= 64*RPL*NCH candidates) is processed in NCH
@@ -303,7 +307,7 @@ constexpr int kScrWaves = 2;
 // chunk's candidate state is live; the logits of the whole pool then go
 // through the top-keep selection.
 template <int RPL, int NCH>
-__global__ __launch_bounds__(kScrWaves * 64) void screen_kernel(ScreenArgs p) {
+__global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kernel(ScreenArgs p) {
     constexpr int CH = 64 * RPL;
     constexpr int MAXC = CH * NCH;
     constexpr int KPL = RPL * NCH;  // keys per lane
@@ -832,8 +836,8 @@ hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
     switch (rpl) {
         case 1: return launch_screen_t<1, 1>(a, s);
         case 2: return launch_screen_t<2, 1>(a, s);
-        // two rows per lane keeps the kernel at 161 VGPRs and 25 KB of LDS per
-        // block: three waves per SIMD, which this latency-bound kernel needs
+        // two rows per lane keeps the live state small enough for the 128-VGPR
+        // budget of four waves per SIMD, and LDS at 37 KB per 4-wave block
         case 4: return launch_screen_t<2, 2>(a, s);
         case 8: return launch_screen_t<2, 4>(a, s);
         default: return hipErrorInvalidValue;

@@ -62,11 +62,19 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
-    const int64_t w_index = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
-    int64_t col = w_index;
+    int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
     if (p.col_list) {
-        if (w_index >= (int64_t)*p.col_count) return;
-        col = p.col_list[w_index];
+        // the list's positions in eight contiguous segments, one per XCD
+        // (blocks go to the XCDs round-robin; the launch rounds the grid up to
+        // a multiple of 8), so the columns of a spatially sorted list that run
+        // together on one XCD share its L2.  Segments follow the list's actual
+        // length, so a short list still spreads over every XCD.
+        const int64_t cnt = min((int64_t)*p.col_count, p.n_waves);
+        const int64_t seg = ((cnt + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock * kSelWavesPerBlock;
+        const int64_t lb = (int64_t)(blockIdx.x >> 3) * kSelWavesPerBlock + wib;
+        const int64_t pos = (int64_t)(blockIdx.x & 7u) * seg + lb;
+        if (lb >= seg || pos >= cnt) return;
+        col = p.col_list[pos];
     }
     if (col < 0 || col >= p.n_targets) return;
 
@@ -357,7 +365,11 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
 static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
-    const int64_t blocks = (a.n_waves + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
+    int64_t blocks = (a.n_waves + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
+    if (a.col_list) {  // eight segments of whole blocks
+        const int64_t seg = ((a.n_waves + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
+        blocks = 8 * seg;
+    }
     hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX, GAP>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
