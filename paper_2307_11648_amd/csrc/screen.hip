@@ -541,14 +541,20 @@ __global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kerne
         uint32_t thr = 1u;  // kept = key >= thr
         bool fb = false;
         if (C > keep) {
-            // bisection for the keep-th largest key (keys are distinct)
+            // bisection for the keep-th largest key (keys are distinct); it
+            // stops as soon as a midpoint has exactly `keep` keys at or above
+            // it, which selects the same set as the keep-th largest key itself
             uint32_t lo = 0u, hi = 0xFFFFFFFFu;
             while (lo < hi) {
                 const uint32_t mid = lo + (hi - lo) / 2u + 1u;
                 int cntk = 0;
 #pragma unroll
                 for (int kk = 0; kk < KPL; ++kk) cntk += __popcll(__ballot(key[kk] >= mid));
-                if (cntk >= keep) lo = mid;
+                if (cntk == keep) {
+                    lo = mid;
+                    break;
+                }
+                if (cntk > keep) lo = mid;
                 else hi = mid - 1u;
             }
             thr = lo;

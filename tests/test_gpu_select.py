@@ -241,3 +241,35 @@ def test_gap_and_no_gap_variants_agree():
         for g in (ga, gb):
             short, fac = replay_check(g, w.points, w.kernel, w.targets, w.pool, w.pool_len, 32, cols, TAU_MIXED, 1e-3)
             print("mixed replay worst shortfall", short, "factor", fac)
+
+
+@pytest.mark.parametrize("prec,C", [("mixed", 128), ("fp64", 128), ("mixed", 512)])
+def test_list_variant_matches_full_run(prec, C):
+    """csel_select_and_factor_list on an odd-length random subset of the
+    columns (capacity larger than the count, list positions split over the
+    eight XCD segments) reproduces the full run bit for bit on the listed
+    columns and leaves every other column's outputs untouched."""
+    print(f"case: list variant {prec} C={C}", flush=True)
+    x = inputs.cluster_points(6001, 3, 21)
+    w = inputs.single_target("list", x, inputs.Kernel(3, 0.05), C, 32, targets=np.arange(0, 6001, 3))
+    k, T = 32, len(w.targets)
+    pts, tg = _dev(w.points, torch.float64), _dev(w.targets, torch.int32)
+    pl, ln = _dev(w.pool, torch.int32), _dev(w.pool_len, torch.int32)
+    ref = {key: v.cpu().numpy() for key, v in csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec).items()}
+    cols = np.random.default_rng(8).choice(T, 333, replace=False).astype(np.int32)
+    lst = np.full(T, -1, np.int32)
+    lst[: len(cols)] = cols
+    out = {
+        "sel": torch.full((T, k), -7, dtype=torch.int32, device="cuda"),
+        "factor": torch.full((T, k + 1), 7.0, dtype=torch.float64, device="cuda"),
+        "log_condvar": torch.full((T,), 7.0, dtype=torch.float64, device="cuda"),
+        "status": torch.full((T,), 9, dtype=torch.uint8, device="cuda"),
+    }
+    csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, _dev(lst, torch.int32),
+                                _dev(np.array([len(cols)], np.int32), torch.int32), T, out)
+    g = {key: v.cpu().numpy() for key, v in out.items()}
+    for key in ("sel", "factor", "log_condvar", "status"):
+        assert np.array_equal(g[key][cols], ref[key][cols], equal_nan=True), key
+    rest = np.setdiff1d(np.arange(T), cols)
+    assert np.all(g["sel"][rest] == -7) and np.all(g["status"][rest] == 9)
+    assert np.all(g["factor"][rest] == 7.0) and np.all(g["log_condvar"][rest] == 7.0)
