@@ -303,8 +303,8 @@ def _source_digest(*names):
 # sources at measurement time; a changed kernel reports null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 2.000 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.000, in bytes
-    ("select_factor_kernel (kept pools)", "ff0ccc04dcd8ae09"): (5404817 * 1.99989 + 398457) * 1024,
-    ("screen_kernel", "a793b4ae2aab4d78"): (1981490 * 1.99989 + 564169) * 1024,
+    ("select_factor_kernel (kept pools)", "bd379fce7ad5d83a"): (5404276 * 1.99989 + 398460) * 1024,
+    ("screen_kernel", "341d79d822182aca"): (2167848 * 1.99989 + 565047) * 1024,
 }
 
 
