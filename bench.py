@@ -314,7 +314,7 @@ def bench_screened(args):
     import numpy as np
     import torch
 
-    from paper_2307_11648_amd import csel, inputs, screen_train
+    from paper_2307_11648_amd import autotune, csel, inputs, screen_train
 
     n = args.n or 1_000_000
     dev = torch.device("cuda:0")
@@ -364,6 +364,11 @@ def bench_screened(args):
     ms_order = e0.elapsed_time(e1)
     scr_out, scr = screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
                                                 fallback_threshold=fbt, order=order)
+    # column schedules (natural or Morton order) of the plain and the kept-pool
+    # selections, each tuned once here, untimed
+    tuner = autotune.SelectTuner()
+    tuner.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, order=order, out=plain)
+    tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
     torch.cuda.synchronize()
 
     def screened_step(ev=None):
@@ -374,7 +379,7 @@ def bench_screened(args):
         csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr, order=order)
         if ev is not None:
             ev[1].record()
-        csel.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, out=scr_out)
+        tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
         if ev is not None:
             ev[2].record()
         csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, scr["fallback_list"],
@@ -385,12 +390,18 @@ def bench_screened(args):
     def plain_step(ev=None):
         if ev is not None:
             ev[0].record()
+        tuner.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, order=order, out=plain)
+        if ev is not None:
+            ev[1].record()
+
+    # both schedules of the plain selection, timed on their own as well
+    def plain_natural_step(ev=None):
+        if ev is not None:
+            ev[0].record()
         csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, out=plain)
         if ev is not None:
             ev[1].record()
 
-    # plain selection with the columns in the screen's Morton order (the list
-    # form of the same kernel): the baseline gets its faster schedule too
     n_all = torch.tensor([T], dtype=torch.int32, device=dev)
 
     def plain_ordered_step(ev=None):
@@ -415,9 +426,9 @@ def bench_screened(args):
         return total, parts, wall / args.steps
 
     print("bench: timing plain", file=sys.stderr, flush=True)
-    ms_plain_natural, _, _ = timed(plain_step, 2)
+    ms_plain_natural, _, _ = timed(plain_natural_step, 2)
     ms_plain_ordered, _, _ = timed(plain_ordered_step, 2)
-    ms_plain = min(ms_plain_natural, ms_plain_ordered)
+    ms_plain, _, _ = timed(plain_step, 2)
     print("bench: timing screened", file=sys.stderr, flush=True)
     ms_screen, (ms_scr, ms_kept, ms_fb), wall_screen = timed(screened_step, 4)
     nfb = int(scr["fallback_count"].item())
@@ -459,6 +470,7 @@ def bench_screened(args):
                                f"16-64-64-1 trained on the GPU on {rows} rows from {len(tr.targets)} exact selections",
                    "columns": T, "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain,
                    "plain_natural_order_ms": ms_plain_natural, "plain_morton_order_ms": ms_plain_ordered,
+                   "autotuned_schedules": tuner.choices,
                    "screened_ms": ms_screen, "screened_wall_ms_per_step": wall_screen,
                    "screen_kernel_ms": ms_scr, "kept_select_ms": ms_kept, "fallback_select_ms": ms_fb,
                    "spatial_order_setup_ms": ms_order,

@@ -1,0 +1,152 @@
+"""Autotuned column schedule for the single-target selection.
+
+Columns are independent, so the order in which one launch walks them
+changes only the speed, never a result: csel_select_and_factor takes the
+columns in their natural order, and csel_select_and_factor_list can take them
+in a spatial (Morton) order from csel_spatial_order, under which columns whose
+candidate pools overlap run side by side on an XCD and share its L2.  Which
+schedule wins depends on the pool size and the point cloud (pools of 512:
+the spatial order is faster; pools of 128: no difference), so the first call
+for a shape class times both on the stream it runs on and keeps the faster;
+later calls of the class reuse the choice.  Choices can persist in a JSON
+file, which a later process reads back.
+
+The tuner only chooses between launches of the library's kernels; every step
+of the selection runs in them.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+from . import csel
+
+SCHEDULES = ("natural", "spatial")
+_FORMAT_VERSION = 1
+
+
+def shape_key(dim: int, two_nu: int, n_targets: int, stride: int, k: int, precision: str) -> str:
+    """Shape class of a selection problem: the kernel instantiation it runs
+    (pool rows per lane, pick capacity, precision, smoothness, dimension) and
+    the column count to the nearest power of two."""
+    rpl = 1 if stride <= 64 else 2 if stride <= 128 else 4 if stride <= 256 else 8
+    kmax = 16 if k <= 16 else 32
+    tb = max(0, int(math.ceil(math.log2(max(1, n_targets)))))
+    return f"d{dim}/nu{two_nu}/pool{64 * rpl}/k{kmax}/{precision}/T2^{tb}"
+
+
+def _event_timer(run, stream):
+    """Milliseconds of one call of `run` on `stream`, by HIP events recorded
+    on that stream (the kernels are enqueued there)."""
+    import torch
+
+    s = stream if stream is not None else torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(s)
+    run()
+    e1.record(s)
+    e1.synchronize()
+    return e0.elapsed_time(e1)
+
+
+class SelectTuner:
+    """Chooses, per shape class, the faster column schedule of
+    csel_select_and_factor.
+
+    path        -- optional JSON file the choices are read from and written to
+    min_columns -- below this many columns the natural order is used untimed
+    timer       -- timer(run, stream) -> ms; HIP events by default
+    """
+
+    def __init__(self, path: str | None = None, min_columns: int = 4096, timer=None):
+        self.path = path
+        self.min_columns = int(min_columns)
+        self._timer = timer or _event_timer
+        self.choices: dict[str, dict] = {}
+        self.tuning_runs = 0
+        self._counts = {}
+        if path and os.path.exists(path):
+            self.choices = self._read(path)
+
+    @staticmethod
+    def _read(path: str) -> dict:
+        try:
+            with open(path) as f:
+                doc = json.load(f)
+        except (OSError, ValueError):
+            return {}
+        if not isinstance(doc, dict) or doc.get("version") != _FORMAT_VERSION:
+            return {}
+        ch = doc.get("choices", {})
+        return {key: v for key, v in ch.items() if isinstance(v, dict) and v.get("schedule") in SCHEDULES}
+
+    def save(self) -> None:
+        if not self.path:
+            return
+        tmp = self.path + ".tmp"
+        with open(tmp, "w") as f:
+            json.dump({"version": _FORMAT_VERSION, "choices": self.choices}, f, indent=1, sort_keys=True)
+        os.replace(tmp, self.path)
+
+    def choose(self, key: str, runners: dict, stream=None) -> str:
+        """The recorded schedule of `key`, or, on its first use, the faster of
+        `runners` (schedule name -> callable), each run once to warm up and
+        once timed."""
+        got = self.choices.get(key)
+        if got is not None and got["schedule"] in runners:
+            return got["schedule"]
+        ms = {}
+        for name, run in runners.items():
+            run()
+            ms[name] = float(self._timer(run, stream))
+        self.tuning_runs += 1
+        best = min(ms, key=lambda name: (ms[name], SCHEDULES.index(name)))
+        self.choices[key] = {"schedule": best, "ms": ms}
+        self.save()
+        return best
+
+    def _count(self, n: int, device):
+        import torch
+
+        t = self._counts.get((n, str(device)))
+        if t is None:
+            t = torch.tensor([n], dtype=torch.int32, device=device)
+            self._counts[(n, str(device))] = t
+        return t
+
+    def select_and_factor(self, points, kernel, targets, pool, pool_len, k: int, precision: str = "mixed",
+                          order=None, out: dict | None = None, stream=None) -> dict:
+        """csel_select_and_factor under the tuned schedule.  `order` is a
+        spatial order of the columns (csel.spatial_order); without it, or for
+        fewer than min_columns columns, the natural order runs."""
+        T = targets.shape[0]
+        if out is None:
+            import torch
+
+            dev = points.device
+            out = {
+                "sel": torch.empty((T, k), dtype=torch.int32, device=dev),
+                "factor": torch.empty((T, k + 1), dtype=torch.float64, device=dev),
+                "log_condvar": torch.empty(T, dtype=torch.float64, device=dev),
+                "status": torch.empty(T, dtype=torch.uint8, device=dev),
+            }
+        if order is None or T < self.min_columns:
+            return csel.select_and_factor(points, kernel, targets, pool, pool_len, k, precision, out=out,
+                                          stream=stream)
+        if order.shape[0] != T:
+            raise ValueError("order must hold every column once")
+        n_all = self._count(T, targets.device)
+
+        def natural():
+            csel.select_and_factor(points, kernel, targets, pool, pool_len, k, precision, out=out, stream=stream)
+
+        def spatial():
+            csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, order, n_all, T, out,
+                                        stream=stream)
+
+        stride = pool.shape[1] if pool.dim() == 2 else 0
+        key = shape_key(points.shape[1], int(kernel.two_nu), T, stride, k, precision)
+        runners = {"natural": natural, "spatial": spatial}
+        runners[self.choose(key, runners, stream)]()
+        return out
