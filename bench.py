@@ -198,11 +198,94 @@ def bench_groups(args):
                      "algorithmic_gflop_per_launch": float(np.sum(flops)) / 1e9,
                      "algorithmic_mb_per_launch": float(np.sum(byt)) / 1e6},
     }
+    if args.workload == "gp":
+        res["config"].update(gp_screened(args, w, pts, gp_t, mem_t, mm, pl, ln, out, ms))
     if args.cpu_seconds > 0:
         print("bench: cpu baseline", file=sys.stderr, flush=True)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
         res["cpu_baseline"] = cpu_baseline_groups(w, k, args.cpu_seconds, threads, want_factor, want_post_var)
     print(json.dumps(res), flush=True)
+
+
+def gp_screened(args, w, pts, gp_t, mem_t, mm, pl, ln, plain, ms_plain, keeps=(512, 1024)):
+    """The learned-screened GP runs beside the plain one: the group screen is
+    trained (untimed set-up) on the exact multi-target selections of GP
+    batches of four separate training clouds of the same distribution and
+    batch geometry; then each batch's 2048 candidates are screened to `keep`
+    (no fallback) before the selection.  For each keep: time, and the gap of
+    the screened selection to the plain one, sum_g (log det Theta_TT|s_screen
+    - log det Theta_TT|s_plain) relative to sum_g (log det Theta_TT - log det
+    Theta_TT|s_plain), plus the largest relative change of a posterior
+    variance."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs, screen_train
+
+    dev = pts.device
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    k = w.k
+    print("bench: gp screen training", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    clouds = [inputs.workload_gp(n_train=w.meta["n_train"], n_pred=len(w.members), C=w.pool.shape[1], k=k, seed=sd)
+              for sd in (8, 9, 10, 11)]
+    sets = [screen_train.group_training_set(t(tr.points, torch.float64), tr.kernel, t(tr.group_ptr, torch.int32),
+                                            t(tr.members, torch.int32), 64, t(tr.pool, torch.int32),
+                                            t(tr.pool_len, torch.int32), k, "fp64") for tr in clouds]
+    X = torch.cat([a for a, _ in sets])
+    y = torch.cat([b for _, b in sets])
+    del sets
+    p, pb, losses = screen_train.train(X, y, steps=3000, batch=8192, lr=3e-3, seed=1, log_every=1000)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    rows = int(X.shape[0])
+    del X, y
+    # log det Theta_TT of every batch (dense FP64 Cholesky on the GPU)
+    G = len(w.group_ptr) - 1
+    ld_prior = 0.0
+    for g in range(G):
+        xm = pts[w.members[w.group_ptr[g]:w.group_ptr[g + 1]]]
+        a = torch.sqrt(torch.tensor(float(w.kernel.two_nu), dtype=torch.float64, device=dev)) * \
+            torch.cdist(xm, xm) / w.kernel.length_scale
+        th = w.kernel.variance * _matern_torch(w.kernel.two_nu, a) + \
+            w.kernel.nugget * torch.eye(len(xm), dtype=torch.float64, device=dev)
+        ld_prior += float(2.0 * torch.log(torch.diagonal(torch.linalg.cholesky(th))).sum().item())
+    ld_plain = float(plain["logdet"].sum().item())
+    prior = float(w.kernel.variance + w.kernel.nugget)
+    pv_p = plain["post_var"].cpu().numpy()
+    runs = {}
+    for keep in keeps:
+        out, scr, nfb = screen_train.screened_group_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, p, pb, keep,
+                                                           args.precision, fallback_threshold=1e30)
+
+        def step():
+            screen_train.screened_group_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, p, pb, keep,
+                                               args.precision, fallback_threshold=1e30, scr=scr, out=out)
+
+        for _ in range(args.warmup):
+            step()
+        torch.cuda.synchronize()
+        times = []
+        for _ in range(args.steps):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            step()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1))
+        ms = float(np.mean(times))
+        pv_s = out["post_var"].cpu().numpy()
+        runs[str(keep)] = {
+            "screened_ms": ms, "speedup_vs_plain": ms_plain / ms,
+            "groups_identical_to_plain": int(np.sum(np.all(out["sel"].cpu().numpy() == plain["sel"].cpu().numpy(),
+                                                           axis=1))),
+            "logdet_gap_relative": (float(out["logdet"].sum().item()) - ld_plain) / (ld_prior - ld_plain),
+            "post_var_max_rel_change": float(np.max(np.abs(pv_s - pv_p) / pv_p)),
+            "post_var_mean_rel_change": float(np.mean((pv_s - pv_p) / pv_p)),
+            "post_var_max_change_over_prior": float(np.max(np.abs(pv_s - pv_p))) / prior}
+    return {"plain_ms": ms_plain, "screened": runs,
+            "screen_training": f"{rows} rows from {4 * G} exact FP64 batch selections of four separate clouds "
+                               f"(seeds 8-11), {t_train:.1f} s set-up; losses {losses}"}
 
 
 def _matern_torch(two_nu, a):

@@ -278,6 +278,47 @@ int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *ke
                 int32_t *fallback_count, const int32_t *order, int64_t n_order, hipStream_t stream);
 
 /*
+ * csel_screen_groups -- the learned screen for multi-target groups (the
+ * aggregated selection of Sec. 5 and GP prediction batches, Alg.
+ * infer_select): prunes each group's candidate pool to the `keep`
+ * candidates the MLP scores highest, before csel_aggregated_select runs on
+ * the kept pools.  Not part of the paper.  One workgroup per group.
+ *
+ *   group_ptr [n_groups + 1], members [n_members]   CSR groups of 1..64
+ *              member ids (as for csel_aggregated_select)
+ *   pool_idx [n_groups][pool_stride] (pool_stride <= 2048), pool_len
+ *              [n_groups]: candidates sorted by the distance to the nearest
+ *              member, nearest first
+ *   features   with r_q the distances of candidate j (slot s of C) to the m
+ *              members, r1 <= r2 the two smallest (r2 = r1 when m = 1), rho
+ *              the kernel correlation, l the length scale:
+ *              log(r1_s / r1_0), s/C, rho(r1), r1/l, rho(r2), mean rho(r_q),
+ *              mean rho(r_q)^2, mean r_q / l, m/64, [s == 0],
+ *              log(1+s)/log(1+C), then zeros to 16; FP32, the MLP sees them
+ *              in BF16
+ *   MLP        as in csel_screen (same parameter layout; trained on group
+ *              selections)
+ *   keep, kept_idx [n_groups][keep], kept_len, fallback
+ *              the `keep` largest logits ranked by their order-preserving
+ *              32-bit image with the low 11 bits replaced by (2047 - slot),
+ *              kept in slot order, -1 padded; fallback 1 when the dropped
+ *              candidates' summed sigmoid(logit) exceeds fallback_threshold,
+ *              3 for a bad group (member range or id, pool length or id out
+ *              of range; kept_len 0)
+ *   logits     optional [n_groups][pool_stride]
+ *   features   optional FP32 [n_groups][pool_stride][16]; with params NULL
+ *              the call computes features only (keep and the outputs of the
+ *              screen are then ignored and may be NULL; bad groups are
+ *              skipped)
+ */
+int csel_screen_groups(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_groups,
+                       const int32_t *group_ptr, const int32_t *members, int64_t n_members,
+                       const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride,
+                       const float *params, const uint16_t *params_bf16, int32_t keep, float fallback_threshold,
+                       int32_t *kept_idx, int32_t *kept_len, uint8_t *fallback, float *logits, float *features,
+                       hipStream_t stream);
+
+/*
  * csel_spatial_order -- a processing order of the columns by the Morton
  * (Z-order) code of their target points: coordinates quantised over the
  * targets' bounding box (10 bits per coordinate in 3-D, 15 in 2-D, 30 in

@@ -120,6 +120,60 @@ def features(x, kernel, target, pool):
     return out
 
 
+def group_features(x, kernel, members, pool):
+    """Features [C, 16] (FP64) of the candidates `pool` of a group of targets
+    `members` (multi-target selection, Sec. 5; pool sorted by the distance to
+    the nearest member, slot s, nearest slot 0).  With r_q = |x_j - x_q| over
+    the m members, r1 and r2 the smallest and second smallest (r2 = r1 when
+    m = 1) and rho the kernel correlation:
+
+      f0  log(r1_s / r1_0)          f5  mean_q rho(r_q)
+      f1  s / C                     f6  mean_q rho(r_q)^2
+      f2  rho(r1)                   f7  mean_q r_q / length_scale
+      f3  r1 / length_scale         f8  m / 64
+      f4  rho(r2)                   f9  [s == 0]
+                                    f10 log(1 + s) / log(1 + C)
+      f11 log min_q (r_q / dmin_q)  f12 mean_q exp(1 - r_q / dmin_q)
+      f13..f15 = 0
+    with dmin_q the distance from member q to its nearest candidate of the
+    pool (f11 = 0 for a candidate that is some member's nearest); distances
+    guarded against zero as in `features`."""
+    x = np.asarray(x, np.float64)
+    pool = np.asarray(pool)
+    members = np.asarray(members)
+    C = len(pool)
+    out = np.zeros((C, F))
+    m = len(members)
+    if C == 0 or m == 0:
+        return out
+    ell = float(kernel.length_scale)
+    c = np.sqrt(float(kernel.two_nu)) / ell
+    tiny = 1e-9 * ell
+    d = x[pool][:, None, :] - x[members][None, :, :]
+    r = np.sqrt(np.sum(d * d, axis=2))  # [C, m]
+    rsort = np.sort(r, axis=1)
+    r1 = rsort[:, 0]
+    r2 = rsort[:, 1] if m > 1 else r1
+    rho = matern_corr(kernel.two_nu, c * r)
+    s = np.arange(C)
+    out[:, 0] = np.log(np.maximum(r1, tiny) / max(r1[0], tiny))
+    out[:, 1] = s / C
+    out[:, 2] = matern_corr(kernel.two_nu, c * r1)
+    out[:, 3] = r1 / ell
+    out[:, 4] = matern_corr(kernel.two_nu, c * r2)
+    out[:, 5] = np.mean(rho, axis=1)
+    out[:, 6] = np.mean(rho * rho, axis=1)
+    out[:, 7] = np.mean(r, axis=1) / ell
+    out[:, 8] = m / 64.0
+    out[0, 9] = 1.0
+    out[:, 10] = np.log1p(s) / np.log1p(C)
+    dmin = np.maximum(np.min(r, axis=0), tiny)  # [m]
+    ratio = np.maximum(r, tiny) / dmin[None, :]
+    out[:, 11] = np.log(np.min(ratio, axis=1))
+    out[:, 12] = np.mean(np.exp(1.0 - ratio), axis=1)
+    return out
+
+
 def mlp_forward(X, p, bf16=True):
     """Logits [N] and the intermediate activations (FP64)."""
     W1, b1, W2, b2, w3, b3 = unpack(p)
@@ -170,24 +224,27 @@ def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def rank_key(z, s):
-    """Ranking key of a candidate: the float32 logit compared at 2^-14
-    relative resolution (its order-preserving 32-bit image with the low 9 bits
-    cleared), ties to the smaller slot."""
+def rank_key(z, s, slot_bits=9):
+    """Ranking key of a candidate: the float32 logit compared at 2^-(23-slot_bits)
+    relative resolution (its order-preserving 32-bit image with the low
+    slot_bits bits cleared), ties to the smaller slot.  Column screens use 9
+    slot bits (pools up to 512), group screens 11 (pools up to 2048)."""
     b = int(np.float32(z).view(np.uint32))
     mono = (~b & 0xFFFFFFFF) if b & 0x80000000 else (b | 0x80000000)
-    return ((mono & ~0x1FF) & 0xFFFFFFFF, -s)
+    mask = (1 << slot_bits) - 1
+    return ((mono & ~mask) & 0xFFFFFFFF, -s)
 
 
-def screen_keep(logits, pool_len, keep, fallback_threshold=0.5):
-    """Kept slots (ascending) of one column: the `keep` largest logits by
-    rank_key; and the fallback flag: the expected number of true selections
-    among the dropped candidates, sum sigmoid(logit), exceeds the threshold."""
+def screen_keep(logits, pool_len, keep, fallback_threshold=0.5, slot_bits=9):
+    """Kept slots (ascending) of one column (or group): the `keep` largest
+    logits by rank_key; and the fallback flag: the expected number of true
+    selections among the dropped candidates, sum sigmoid(logit), exceeds the
+    threshold."""
     z = np.asarray(logits[:pool_len], np.float64)
     C = len(z)
     if C <= keep:
         return np.arange(C), False
-    order = sorted(range(C), key=lambda s: rank_key(z[s], s), reverse=True)
+    order = sorted(range(C), key=lambda s: rank_key(z[s], s, slot_bits), reverse=True)
     kept = np.sort(np.array(order[:keep]))
     dropped = np.array(order[keep:])
     fb = float(np.sum(1.0 / (1.0 + np.exp(-z[dropped])))) > fallback_threshold

@@ -82,6 +82,10 @@ def load():
                                 _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_float, _vp, _vp, _vp, _vp, _vp, _vp,
                                 _vp, _c.c_int64, _vp]
     lib.csel_screen.restype = ctypes.c_int
+    lib.csel_screen_groups.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64,
+                                       _vp, _vp, _c.c_int64, _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32,
+                                       _c.c_float, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_screen_groups.restype = ctypes.c_int
     lib.csel_spatial_order_workspace_size.argtypes = [_c.c_int64]
     lib.csel_spatial_order_workspace_size.restype = ctypes.c_int64
     lib.csel_spatial_order.argtypes = [_vp, _c.c_int64, _c.c_int32, _c.c_int64, _vp, _vp, _c.c_int64, _vp, _vp]
@@ -260,6 +264,40 @@ def screen(points, kernel, targets, pool, pool_len, params, params_bf16, keep: i
                            out["kept_len"].data_ptr(), out["fallback"].data_ptr(), _ptr(out.get("logits")),
                            out["fallback_list"].data_ptr(), out["fallback_count"].data_ptr(), _ptr(order),
                            0 if order is None else order.numel(), _stream(stream)))
+    return out
+
+
+def screen_groups(points, kernel, group_ptr, members, pool, pool_len, params, params_bf16, keep: int,
+                  fallback_threshold=0.5, want_logits=False, want_features=False, out=None, stream=None) -> dict:
+    """csel_screen_groups: kept [G, keep] ids in slot order, kept_len [G],
+    fallback [G] u8; optionally logits [G, stride] and features [G, stride,
+    16].  With params None only the features are computed."""
+    lib = load()
+    for t, nm in ((group_ptr, "group_ptr"), (members, "members"), (pool, "pool"), (pool_len, "pool_len")):
+        _dev(t, torch.int32, nm)
+    _dev(points, torch.float64, "points")
+    if params is not None:
+        _dev(params, torch.float32, "params")
+    G = group_ptr.numel() - 1
+    stride = pool.shape[1]
+    dev = points.device
+    if out is None:
+        out = {}
+        if params is not None:
+            out.update(kept=torch.empty((G, keep), dtype=torch.int32, device=dev),
+                       kept_len=torch.empty(G, dtype=torch.int32, device=dev),
+                       fallback=torch.empty(G, dtype=torch.uint8, device=dev))
+        if want_logits:
+            out["logits"] = torch.zeros((G, stride), dtype=torch.float32, device=dev)
+        if want_features or params is None:
+            out["features"] = torch.zeros((G, stride, 16), dtype=torch.float32, device=dev)
+    kp = kernel_struct(kernel)
+    _check(lib.csel_screen_groups(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), G,
+                                  group_ptr.data_ptr(), members.data_ptr(), members.numel(), pool.data_ptr(),
+                                  pool_len.data_ptr(), stride, _ptr(params), _ptr(params_bf16), int(keep),
+                                  float(fallback_threshold), _ptr(out.get("kept")), _ptr(out.get("kept_len")),
+                                  _ptr(out.get("fallback")), _ptr(out.get("logits")), _ptr(out.get("features")),
+                                  _stream(stream)))
     return out
 
 

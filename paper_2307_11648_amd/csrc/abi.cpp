@@ -374,6 +374,62 @@ CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_k
     return CSEL_OK;
 }
 
+CSEL_API int csel_screen_groups(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
+                                int64_t n_members, const int32_t* pool_idx, const int32_t* pool_len,
+                                int32_t pool_stride, const float* params, const uint16_t* params_bf16,
+                                int32_t keep, float fallback_threshold, int32_t* kept_idx, int32_t* kept_len,
+                                uint8_t* fallback, float* logits, float* features, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_groups < 0 || n_groups > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_groups must be in [0, 2^31) (got %lld)", (long long)n_groups);
+    if (n_members < 0) return fail(CSEL_EINVAL, "n_members must be >= 0");
+    if (pool_stride < 1 || pool_stride > csel::kGroupScreenMaxPool)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [1, %d] (got %d)", csel::kGroupScreenMaxPool,
+                    pool_stride);
+    const bool features_only = params == nullptr;
+    if (features_only && !features) return fail(CSEL_EINVAL, "params and features are both NULL");
+    if (!features_only) {
+        if (keep < 1 || keep > pool_stride) return fail(CSEL_EINVAL, "keep must be in [1, pool_stride]");
+        if (!(fallback_threshold >= 0.0f)) return fail(CSEL_EINVAL, "fallback_threshold must be >= 0");
+    }
+    if (n_groups == 0) return CSEL_OK;
+    if (!pts || !group_ptr || !members || !pool_idx || !pool_len) return fail(CSEL_EINVAL, "a required array is NULL");
+    if (!features_only && (!params_bf16 || !kept_idx || !kept_len || !fallback))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    csel::GroupScreenArgs a{};
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.ell = kernel->length_scale;
+    a.n_groups = n_groups;
+    a.group_ptr = group_ptr;
+    a.members = members;
+    a.n_members = n_members;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    a.params = params;
+    a.params_bf16 = params_bf16;
+    a.keep = keep;
+    a.fb_thr = fallback_threshold;
+    a.mode = features_only ? 1 : 0;
+    a.feats = features;
+    a.logits = logits;
+    a.kept = kept_idx;
+    a.kept_len = kept_len;
+    a.fallback = fallback;
+    hipError_t e = csel::launch_screen_groups(a, stream);
+    if (e != hipSuccess) return hip_fail(e, "screen_groups launch");
+    return CSEL_OK;
+}
+
 CSEL_API int64_t csel_spatial_order_workspace_size(int64_t n_targets) {
     g_err[0] = 0;
     if (n_targets < 0 || n_targets > INT32_MAX)

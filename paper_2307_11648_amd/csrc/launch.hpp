@@ -62,6 +62,36 @@ struct ScreenArgs {
     int64_t n_order;       // positions of `order` to process (n_targets without an order)
 };
 
+// learned screen of multi-target groups: one workgroup per group
+struct GroupScreenArgs {
+    const double* pts;
+    int64_t n;
+    int32_t dim;
+    int32_t two_nu;
+    double c_nu;
+    double ell;
+    int64_t n_groups;
+    const int32_t* group_ptr;  // [n_groups + 1] offsets into members
+    const int32_t* members;
+    int64_t n_members;         // length of members
+    const int32_t* pool;       // [n_groups][stride], sorted by distance to the nearest member
+    const int32_t* pool_len;
+    int32_t stride;
+    const float* params;
+    const uint16_t* params_bf16;
+    int32_t keep;
+    float fb_thr;
+    int32_t mode;  // 0 screen, 1 features only
+    float* feats;
+    float* logits;
+    int32_t* kept;
+    int32_t* kept_len;
+    uint8_t* fallback;
+};
+
+constexpr int kGroupScreenMaxPool = 2048;
+constexpr int kGroupScreenMaxMembers = 64;
+
 struct MlpTrainArgs {
     const float* params;
     const uint16_t* params_bf16;
@@ -74,6 +104,7 @@ struct MlpTrainArgs {
 };
 
 hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s);
+hipError_t launch_screen_groups(const GroupScreenArgs& a, hipStream_t s);
 int mlp_nparams();
 int64_t mlp_grad_nparts(int64_t n_rows);
 hipError_t launch_mlp_grad(const MlpTrainArgs& a, float* grad, hipStream_t s);

@@ -850,6 +850,282 @@ hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// screen of multi-target groups (GP prediction batches, supernodes)
+// ---------------------------------------------------------------------------
+// One 256-thread workgroup per group: pools of up to 2048 candidates (sorted
+// by the distance to the nearest member) against up to 64 members.  Features
+// (distances to the members, FP32) of a chunk of 512 candidates -> LDS (BF16)
+// -> the same MLP as the column screen, each wave on its quarter of the
+// chunk's tiles -> logits in LDS; then a workgroup-wide bisection for the
+// keep-th largest key (11 slot bits) and the kept list in slot order.
+constexpr int kGrpThreads = 256;
+constexpr int kGrpWaves = kGrpThreads / 64;
+constexpr int kGrpChunk = 512;
+constexpr int kGrpSlots = kGroupScreenMaxPool / kGrpThreads;  // slots per thread: tid + 256 i
+
+__device__ __forceinline__ uint32_t wave_min32(uint32_t v) {
+    v = min(v, dpp32<kDppQuadXor1>(v));
+    v = min(v, dpp32<kDppQuadXor2>(v));
+    v = min(v, dpp32<kDppRowRor4>(v));
+    v = min(v, dpp32<kDppRowRor8>(v));
+    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
+    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
+    return min(min(a, b), min(c, d));
+}
+
+// distance of a candidate to a member (FP64 difference, FP32 norm); the one
+// expression both passes use
+__device__ __forceinline__ float member_dist(const double xj[3], const double* mq) {
+    const float e0 = (float)(xj[0] - mq[0]), e1 = (float)(xj[1] - mq[1]), e2 = (float)(xj[2] - mq[2]);
+    return __builtin_amdgcn_sqrtf(e0 * e0 + e1 * e1 + e2 * e2);
+}
+
+__device__ __forceinline__ void group_candidate_features(const GroupScreenArgs& p, const double (*mem)[3], int m,
+                                                         const uint32_t* dmin_bits, const double xj[3], int s, int C,
+                                                         float log_r10, float f[kF]) {
+    const float cnu = (float)p.c_nu, inv_ell = (float)(1.0 / p.ell), tiny = 1e-9f * (float)p.ell;
+    float r1 = INFINITY, r2 = INFINITY, sr = 0.0f, sr2 = 0.0f, sd = 0.0f, rmin = INFINITY, sx = 0.0f;
+    for (int q = 0; q < m; ++q) {
+        const float r = member_dist(xj, mem[q]);
+        const float ratio = fmaxf(r, tiny) * frcp(fmaxf(__uint_as_float(dmin_bits[q]), tiny));
+        rmin = fminf(rmin, ratio);
+        sx += __expf(1.0f - ratio);
+        if (r < r1) {
+            r2 = r1;
+            r1 = r;
+        } else if (r < r2) {
+            r2 = r;
+        }
+        const float rho = corr(p.two_nu, cnu * r);
+        sr += rho;
+        sr2 += rho * rho;
+        sd += r;
+    }
+    if (m == 1) r2 = r1;
+    const float inv_m = frcp((float)m);
+    f[0] = __logf(fmaxf(r1, tiny)) - log_r10;
+    f[1] = (float)s * frcp((float)C);
+    f[2] = corr(p.two_nu, cnu * r1);
+    f[3] = r1 * inv_ell;
+    f[4] = corr(p.two_nu, cnu * r2);
+    f[5] = sr * inv_m;
+    f[6] = sr2 * inv_m;
+    f[7] = sd * inv_m * inv_ell;
+    f[8] = (float)m * (1.0f / 64.0f);
+    f[9] = s == 0 ? 1.0f : 0.0f;
+    f[10] = __logf(1.0f + (float)s) * frcp(__logf(1.0f + (float)C));
+    f[11] = __logf(rmin);
+    f[12] = sx * inv_m;
+#pragma unroll
+    for (int q = 13; q < kF; ++q) f[q] = 0.0f;
+}
+
+__global__ __launch_bounds__(kGrpThreads) void screen_group_kernel(GroupScreenArgs p) {
+    __shared__ MlpLds sh_w;
+    __shared__ double sh_m[kGroupScreenMaxMembers][3];
+    __shared__ __align__(16) uint16_t sh_x[kGrpChunk][kF];
+    __shared__ float sh_z[kGroupScreenMaxPool];
+    __shared__ int sh_cnt[kGrpSlots * kGrpWaves];
+    __shared__ float sh_drop[kGrpWaves];
+    __shared__ uint32_t sh_dmin[kGroupScreenMaxMembers];  // bits of each member's nearest-candidate distance
+    const int tid = threadIdx.x, lane = lane_id(), wib = tid >> 6;
+    const int cl = lane & 15, g4 = lane >> 4;
+    const int64_t g = blockIdx.x;
+    const int dim = p.dim;
+    if (p.mode == 0) stage_mlp(sh_w, p.params, p.params_bf16);
+    // group, pool length and member coordinates; a bad group (member range or
+    // id, pool length or pool id out of range) is reported, not read past
+    const int64_t b = p.group_ptr[g], e = p.group_ptr[g + 1];
+    const int64_t m64 = e - b;
+    const int C = p.pool_len[g];
+    bool bad = b < 0 || e > p.n_members || m64 < 1 || m64 > kGroupScreenMaxMembers || C < 0 || C > p.stride ||
+               C > kGroupScreenMaxPool;
+    const int m = bad ? 0 : (int)m64;
+    if (tid < kGroupScreenMaxMembers) sh_dmin[tid] = 0x7F800000u;  // +inf
+    if (tid < m) {
+        const int32_t id = p.members[b + tid];
+        if (id < 0 || (int64_t)id >= p.n) {
+            bad = true;
+        } else {
+#pragma unroll
+            for (int c = 0; c < 3; ++c) sh_m[tid][c] = c < dim ? p.pts[(int64_t)id * dim + c] : 0.0;
+        }
+    }
+    for (int i = 0; i < kGrpSlots && !bad; ++i) {
+        const int s = tid + kGrpThreads * i;
+        if (s < C) {
+            const int32_t q = p.pool[g * p.stride + s];
+            if (q < 0 || (int64_t)q >= p.n) bad = true;
+        }
+    }
+    if (__syncthreads_or(bad ? 1 : 0)) {
+        if (tid == 0 && p.mode == 0) {
+            p.kept_len[g] = 0;
+            p.fallback[g] = 3;
+        }
+        return;
+    }
+    auto load_x = [&](int s, double xj[3]) {
+        const int64_t q = p.pool[g * p.stride + s];
+#pragma unroll
+        for (int c = 0; c < 3; ++c) xj[c] = c < dim ? p.pts[q * dim + c] : 0.0;
+    };
+    // log of the nearest member distance of slot 0 (every thread computes it)
+    float log_r10 = 0.0f;
+    if (C > 0) {
+        double x0[3];
+        load_x(0, x0);
+        float r1 = INFINITY;
+        for (int q = 0; q < m; ++q) r1 = fminf(r1, member_dist(x0, sh_m[q]));
+        log_r10 = __logf(fmaxf(r1, 1e-9f * (float)p.ell));
+    }
+    // each member's nearest-candidate distance: per member the minimum over a
+    // thread's slots, over the wave (non-negative floats order as their bits),
+    // then over the waves by LDS atomics
+    {
+        double xs[kGrpSlots][3];
+#pragma unroll
+        for (int i = 0; i < kGrpSlots; ++i) {
+            const int s = tid + kGrpThreads * i;
+            if (s < C) load_x(s, xs[i]);
+        }
+        for (int q = 0; q < m; ++q) {
+            uint32_t best = 0x7F800000u;
+#pragma unroll
+            for (int i = 0; i < kGrpSlots; ++i)
+                if (tid + kGrpThreads * i < C) best = min(best, __float_as_uint(member_dist(xs[i], sh_m[q])));
+            best = wave_min32(best);
+            if (lane == 0) atomicMin(&sh_dmin[q], best);
+        }
+    }
+    __syncthreads();
+    for (int c0 = 0; c0 < C; c0 += kGrpChunk) {
+        for (int sl = tid; sl < kGrpChunk; sl += kGrpThreads) {
+            const int s = c0 + sl;
+            float f[kF];
+            if (s < C) {
+                double xj[3];
+                load_x(s, xj);
+                group_candidate_features(p, sh_m, m, sh_dmin, xj, s, C, log_r10, f);
+                if (p.feats)
+#pragma unroll
+                    for (int q = 0; q < kF; ++q) p.feats[(g * p.stride + s) * kF + q] = f[q];
+            } else {
+                // rows past the pool: finite, and their logits are never read
+#pragma unroll
+                for (int q = 0; q < kF; ++q) f[q] = 0.0f;
+            }
+            uint4* row = reinterpret_cast<uint4*>(&sh_x[sl][0]);
+            row[0] = uint4{pack_bf16x2(f[0], f[1]), pack_bf16x2(f[2], f[3]), pack_bf16x2(f[4], f[5]),
+                           pack_bf16x2(f[6], f[7])};
+            row[1] = uint4{pack_bf16x2(f[8], f[9]), pack_bf16x2(f[10], f[11]), pack_bf16x2(f[12], f[13]),
+                           pack_bf16x2(f[14], f[15])};
+        }
+        __syncthreads();
+        if (p.mode == 0) {
+            // this chunk's 32 tiles of 16 candidates, 8 per wave, 2 at a time
+            constexpr int kTilesPerWave = kGrpChunk / 16 / kGrpWaves;
+            const int ntiles = (min(C - c0, kGrpChunk) + 15) >> 4;
+            for (int t0 = wib * kTilesPerWave; t0 < (wib + 1) * kTilesPerWave && t0 < ntiles; t0 += 2) {
+                short4_t xb[2];
+                float z[2];
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    xb[t] = __builtin_bit_cast(short4_t, *reinterpret_cast<const uint2*>(&sh_x[(t0 + t) * 16 + cl][4 * g4]));
+                mlp_tiles_lds<2>(sh_w, xb, z, lane);
+#pragma unroll
+                for (int t = 0; t < 2; ++t)
+                    if (g4 == 0) sh_z[c0 + (t0 + t) * 16 + cl] = z[t];
+            }
+        }
+        __syncthreads();
+    }
+    if (p.mode == 1) return;
+    // keys: the monotone image of the logit with its low 11 bits replaced by
+    // (2047 - slot); 0 marks an empty slot.  Slot s = tid + 256 i.
+    uint32_t key[kGrpSlots];
+    float zz[kGrpSlots];
+#pragma unroll
+    for (int i = 0; i < kGrpSlots; ++i) {
+        const int s = tid + kGrpThreads * i;
+        zz[i] = s < C ? sh_z[s] : 0.0f;
+        const uint32_t bz = __float_as_uint(zz[i]);
+        const uint32_t mono = (bz & 0x80000000u) ? ~bz : (bz | 0x80000000u);
+        key[i] = s < C ? ((mono & ~0x7FFu) | (uint32_t)(2047 - s)) : 0u;
+        if (p.logits && s < C) p.logits[g * p.stride + s] = zz[i];
+    }
+    const int keep = p.keep;
+    uint32_t thr = 1u;
+    bool fb = false;
+    if (C > keep) {
+        uint32_t lo = 0u, hi = 0xFFFFFFFFu;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2u + 1u;
+            int cw = 0;
+#pragma unroll
+            for (int i = 0; i < kGrpSlots; ++i) cw += __popcll(__ballot(key[i] >= mid));
+            if (lane == 0) sh_cnt[wib] = cw;
+            __syncthreads();
+            int cnt = 0;
+#pragma unroll
+            for (int w = 0; w < kGrpWaves; ++w) cnt += sh_cnt[w];
+            __syncthreads();
+            if (cnt == keep) {
+                lo = mid;
+                break;
+            }
+            if (cnt > keep) lo = mid;
+            else hi = mid - 1u;
+        }
+        thr = lo;
+        float drop = 0.0f;
+#pragma unroll
+        for (int i = 0; i < kGrpSlots; ++i)
+            if (key[i] != 0u && key[i] < thr) drop += frcp(1.0f + __expf(-zz[i]));
+        for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+        if (lane == 0) sh_drop[wib] = drop;
+        __syncthreads();
+        float tot = 0.0f;
+#pragma unroll
+        for (int w = 0; w < kGrpWaves; ++w) tot += sh_drop[w];
+        fb = tot > p.fb_thr;
+    }
+    // kept candidates in slot order: slot chunks (i, wave) hold slots
+    // 256 i + 64 w .. +63, so a chunk's offset counts the kept slots of every
+    // chunk before it in (i, w) order
+    const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t mk[kGrpSlots];
+#pragma unroll
+    for (int i = 0; i < kGrpSlots; ++i) {
+        mk[i] = __ballot(key[i] != 0u && key[i] >= thr);
+        if (lane == 0) sh_cnt[i * kGrpWaves + wib] = __popcll(mk[i]);
+    }
+    __syncthreads();
+    int total = 0;
+    for (int c = 0; c < kGrpSlots * kGrpWaves; ++c) total += sh_cnt[c];
+#pragma unroll
+    for (int i = 0; i < kGrpSlots; ++i) {
+        const int s = tid + kGrpThreads * i;
+        if (key[i] != 0u && key[i] >= thr) {
+            int off = 0;
+            for (int c = 0; c < i * kGrpWaves + wib; ++c) off += sh_cnt[c];
+            p.kept[g * keep + off + __popcll(mk[i] & below)] = p.pool[g * p.stride + s];
+        }
+    }
+    for (int q = total + tid; q < keep; q += kGrpThreads) p.kept[g * keep + q] = -1;
+    if (tid == 0) {
+        p.kept_len[g] = total;
+        p.fallback[g] = fb ? 1 : 0;
+    }
+}
+
+hipError_t launch_screen_groups(const GroupScreenArgs& a, hipStream_t s) {
+    if (a.n_groups == 0) return hipSuccess;
+    hipLaunchKernelGGL(screen_group_kernel, dim3((unsigned)a.n_groups), dim3(kGrpThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 int mlp_nparams() { return kNParams; }
 int64_t mlp_grad_nparts(int64_t n_rows) { return (n_rows + kTrainTilesPerWave * 16 - 1) / (kTrainTilesPerWave * 16); }
 

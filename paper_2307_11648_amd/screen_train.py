@@ -97,3 +97,53 @@ def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep
     csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, scr["fallback_list"],
                                 scr["fallback_count"], targets.shape[0], out)
     return out, scr
+
+
+# ---------------------------------------------------------------------------
+# groups (multi-target selection: GP prediction batches, supernodes)
+# ---------------------------------------------------------------------------
+def group_training_set(points, kernel, group_ptr, members, max_members: int, pool, pool_len, k: int,
+                       precision: str = "fp64"):
+    """(X [rows, 16] float32, y [rows] uint8) for every valid pool slot of the
+    given groups; y = 1 where the exact multi-target greedy selection
+    (csel_aggregated_select on the full pool) picks the slot."""
+    sel = csel.aggregated_select(points, kernel, group_ptr, members, max_members, pool, pool_len, k, precision)["sel"]
+    feats = csel.screen_groups(points, kernel, group_ptr, members, pool, pool_len, None, None, 0)["features"]
+    G, C = pool.shape
+    valid = torch.arange(C, device=pool.device)[None, :] < pool_len[:, None]
+    chosen = torch.zeros((G, C), dtype=torch.bool, device=pool.device)
+    for g0 in range(0, G, 64):
+        g1 = min(G, g0 + 64)
+        chosen[g0:g1] = (pool[g0:g1, :, None] == sel[g0:g1, None, :]).any(-1)
+    chosen &= valid
+    return feats[valid].contiguous(), chosen[valid].to(torch.uint8).contiguous()
+
+
+def screened_group_select(points, kernel, group_ptr, members, max_members: int, pool, pool_len, k: int, p, pb,
+                          keep: int, precision: str = "mixed", fallback_threshold: float = 0.5, want_post_var=True,
+                          scr=None, out=None):
+    """Screened multi-target selection: csel_screen_groups, then
+    csel_aggregated_select on the kept pools; groups whose screen falls back
+    are selected again on their full pools (their count is read on the host,
+    the one synchronisation of this path).  Returns (out, scr, n_fallback)."""
+    scr = csel.screen_groups(points, kernel, group_ptr, members, pool, pool_len, p, pb, keep, fallback_threshold,
+                             out=scr)
+    out = csel.aggregated_select(points, kernel, group_ptr, members, max_members, scr["kept"], scr["kept_len"], k,
+                                 precision, want_post_var=want_post_var, out=out, workspace=(out or {}).get("workspace"))
+    fb = torch.nonzero(scr["fallback"] == 1).flatten()
+    nfb = int(fb.numel())
+    if nfb:
+        gp = group_ptr.to(torch.int64)
+        sizes = (gp[1:] - gp[:-1])[fb]
+        sub_ptr = torch.zeros(nfb + 1, dtype=torch.int64, device=gp.device)
+        sub_ptr[1:] = torch.cumsum(sizes, 0)
+        idx = torch.cat([torch.arange(int(gp[g]), int(gp[g + 1]), device=gp.device) for g in fb.tolist()])
+        sub = csel.aggregated_select(points, kernel, sub_ptr.to(torch.int32), members[idx].contiguous(), max_members,
+                                     pool[fb].contiguous(), pool_len[fb].contiguous(), k, precision,
+                                     want_post_var=want_post_var)
+        for key in ("sel", "logdet", "status"):
+            out[key][fb] = sub[key]
+        if want_post_var:
+            out["post_var"][idx] = sub["post_var"]
+    return out, scr, nfb
+

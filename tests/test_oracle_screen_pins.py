@@ -142,3 +142,80 @@ def test_bf16_forward_and_backward_match_torch_straight_through():
     np.testing.assert_allclose(z, zt.detach().numpy(), rtol=1e-12, atol=1e-12)
     assert loss == pytest.approx(lt.item(), rel=1e-12)
     np.testing.assert_allclose(g, pt.grad.numpy(), rtol=1e-10, atol=1e-14)
+
+
+# ---- group screen (multi-target) features and keys ---------------------------
+def test_group_features_with_one_member_reduce_to_column_features():
+    """With a single member the group features are the column screen's
+    distance features of that member as the target."""
+    x = inputs.uniform_points(400, 2, 17)
+    ker = inputs.Kernel(5, 0.07)
+    tgt = 11
+    d = np.sqrt(np.sum((x - x[tgt]) ** 2, axis=1))
+    pool = [j for j in np.argsort(d, kind="stable") if j != tgt][:60]
+    fc = so.features(x, ker, tgt, pool)
+    fg = so.group_features(x, ker, [tgt], pool)
+    for gcol, ccol in ((0, 0), (1, 1), (2, 2), (3, 3), (9, 10), (10, 11)):
+        np.testing.assert_allclose(fg[:, gcol], fc[:, ccol], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(fg[:, 4], fc[:, 2], rtol=1e-12)  # r2 = r1
+    np.testing.assert_allclose(fg[:, 5], fc[:, 2], rtol=1e-12)  # mean over one member
+    np.testing.assert_allclose(fg[:, 6], fc[:, 2] ** 2, rtol=1e-12)
+    np.testing.assert_allclose(fg[:, 7], fc[:, 3], rtol=1e-12)
+    assert np.all(fg[:, 8] == 1.0 / 64.0) and np.all(fg[:, 13:] == 0.0)
+    # the member's nearest candidate is slot 0: ratio r_s / r_0
+    np.testing.assert_allclose(fg[:, 11], fc[:, 0], rtol=1e-12, atol=1e-14)
+    np.testing.assert_allclose(fg[:, 12], np.exp(1.0 - np.exp(fc[:, 0])), rtol=1e-12)
+
+
+def test_group_features_hand_worked():
+    """Members at 0 and 1 on a line, candidates at 0.25, 0.6 and 3 (sorted by
+    the distance to the nearest member); exponential kernel, l = 0.5."""
+    x = np.array([[0.0], [1.0], [0.25], [0.6], [3.0]])
+    ker = inputs.Kernel(1, 0.5)
+    f = so.group_features(x, ker, [0, 1], [2, 3, 4])
+    rho = lambda r: math.exp(-r / 0.5)  # noqa: E731
+    # slot 0: r = (0.25, 0.75); slot 1: r = (0.6, 0.4); slot 2: r = (3, 2)
+    for s, (ra, rb) in enumerate(((0.25, 0.75), (0.6, 0.4), (3.0, 2.0))):
+        r1, r2 = min(ra, rb), max(ra, rb)
+        assert f[s, 0] == pytest.approx(math.log(r1 / 0.25))
+        assert f[s, 1] == pytest.approx(s / 3)
+        assert f[s, 2] == pytest.approx(rho(r1))
+        assert f[s, 3] == pytest.approx(r1 / 0.5)
+        assert f[s, 4] == pytest.approx(rho(r2))
+        assert f[s, 5] == pytest.approx((rho(ra) + rho(rb)) / 2)
+        assert f[s, 6] == pytest.approx((rho(ra) ** 2 + rho(rb) ** 2) / 2)
+        assert f[s, 7] == pytest.approx((ra + rb) / 2 / 0.5)
+        assert f[s, 8] == pytest.approx(2 / 64)
+        assert f[s, 9] == (1.0 if s == 0 else 0.0)
+        assert f[s, 10] == pytest.approx(math.log1p(s) / math.log1p(3))
+        # nearest candidates: member 0 -> 0.25 (slot 0), member 1 -> 0.4 (slot 1)
+        qa, qb = ra / 0.25, rb / 0.4
+        assert f[s, 11] == pytest.approx(math.log(min(qa, qb)))
+        assert f[s, 12] == pytest.approx((math.exp(1 - qa) + math.exp(1 - qb)) / 2)
+
+
+def test_group_features_rigid_motion_invariant():
+    rng = np.random.default_rng(5)
+    x = rng.random((300, 3))
+    ker = inputs.Kernel(3, 0.1)
+    members = [3, 8, 21, 40]
+    pool = list(range(100, 180))
+    a = rng.standard_normal((3, 3))
+    q, _ = np.linalg.qr(a)
+    y = x @ q.T + np.array([0.3, -2.0, 5.0])
+    np.testing.assert_allclose(so.group_features(y, ker, members, pool), so.group_features(x, ker, members, pool),
+                               rtol=1e-9, atol=1e-12)
+
+
+def test_group_rank_key_uses_eleven_slot_bits():
+    """The low 11 bits of a logit's 32-bit image carry the slot: logits that
+    differ only there (below 2^-12 relative) tie and go to the smaller slot.
+    The column screen's 9 bits resolve 2^-14."""
+    z = np.array([1.0, 1.0 + 2.0 ** -14, 1.0 + 2.0 ** -8, 0.5], np.float32)
+    assert list(so.screen_keep(z, 4, 2, fallback_threshold=10.0, slot_bits=11)[0]) == [0, 2]
+    assert list(so.screen_keep(z, 4, 2, fallback_threshold=10.0, slot_bits=9)[0]) == [1, 2]
+    z2 = np.array([1.0, 1.0 + 2.0 ** -13, 0.1], np.float32)
+    assert list(so.screen_keep(z2, 3, 1, 10.0, slot_bits=9)[0]) == [1]
+    assert list(so.screen_keep(z2, 3, 1, 10.0, slot_bits=11)[0]) == [0]
+    z3 = np.array([1.0, 1.0 + 2.0 ** -11, 0.1], np.float32)
+    assert list(so.screen_keep(z3, 3, 1, 10.0, slot_bits=11)[0]) == [1]
