@@ -382,12 +382,14 @@ def _source_digest(*names):
 
 
 # HBM traffic per launch measured with rocprofv3 FETCH_SIZE / WRITE_SIZE runs of
-# this script (copy-probe calibrated), keyed by the digest of the kernel's
-# sources at measurement time; a changed kernel reports null.
+# this script (copy-probe calibrated), keyed by the kernel, its column schedule
+# and the digest of its sources at measurement time; a changed kernel reports
+# null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE x 2.000 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.000, in bytes
-    ("select_factor_kernel (kept pools)", "bd379fce7ad5d83a"): (5404276 * 1.99989 + 398460) * 1024,
-    ("screen_kernel", "341d79d822182aca"): (2167848 * 1.99989 + 565047) * 1024,
+    # FETCH_SIZE x 1.99992 (a 1 GiB device copy reads as 524,308 KiB) + WRITE_SIZE x 1.0, in bytes
+    ("select_factor_kernel (kept pools)", "natural", "bd379fce7ad5d83a"): (5404966 * 1.99992 + 398460) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "bd379fce7ad5d83a"): (540744 * 1.99992 + 471992) * 1024,
+    ("screen_kernel", "spatial", "9cd92089adc32410"): (2158917 * 1.99992 + 565053) * 1024,
 }
 
 
@@ -527,21 +529,23 @@ def bench_screened(args):
     flops_kept, _ = column_work(kl_len, k, 3, 3)
     flops_plain, _ = column_work(w.pool_len, k, 3, 3)
     mlp_flops = 2.0 * (16 * 64 + 64 * 64 + 64) * float(np.sum(w.pool_len))
+    kept_key = autotune.shape_key(pts.shape[1], int(w.kernel.two_nu), T, keep, k, prec)
     kernels = {
         "select_factor_kernel (kept pools)": {"bound": "alu", "ms": ms_kept, "work": float(np.sum(flops_kept)),
-                                              "peak": PEAK_ALU_TFLOPS, "src": ("select_kernel.hpp", "device_common.hpp")},
+                                              "peak": PEAK_ALU_TFLOPS, "src": ("select_kernel.hpp", "device_common.hpp"),
+                                              "schedule": tuner.choices[kept_key]["schedule"]},
         "screen_kernel": {"bound": "mfma", "ms": ms_scr, "work": mlp_flops, "peak": PEAK_BF16_TFLOPS,
-                          "src": ("screen.hip", "device_common.hpp")},
+                          "src": ("screen.hip", "device_common.hpp"), "schedule": "spatial"},
     }
     dom = max(kernels, key=lambda kname: kernels[kname]["ms"])
 
     def roof(kname):
         kd = kernels[kname]
         ach = kd["work"] / (kd["ms"] * 1e-3) / 1e12
-        tr = MEASURED_TRAFFIC.get((kname, _source_digest(*kd["src"])))
+        tr = MEASURED_TRAFFIC.get((kname, kd["schedule"], _source_digest(*kd["src"])))
         return {"bound": kd["bound"], "kernel": kname, "achieved": ach, "peak": kd["peak"], "unit": "TFLOP/s",
                 "frac": ach / kd["peak"], "traffic": tr, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE "
-                "+ WRITE_SIZE, copy-calibrated)", "kernel_ms": kd["ms"],
+                "+ WRITE_SIZE, copy-calibrated)", "schedule": kd["schedule"], "kernel_ms": kd["ms"],
                 "algorithmic_tflop_per_launch": kd["work"] / 1e12}
 
     res = {
