@@ -68,3 +68,35 @@ def test_argument_validation_without_gpu():
                                     None, None, None)
     assert rc == 0
     assert lib.csel_sum(None, -1, None, None) == -1
+
+
+def test_screen_groups_validation_without_gpu():
+    """csel_screen_groups rejects bad sizes and missing arrays on the host."""
+    if not os.path.exists(csel.LIB_PATH):
+        pytest.skip("libcsel.so not built")
+    lib = csel.load()
+    kp = csel.KernelParams(5, 0.03, 1.0, 0.0)
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation first
+
+    def call(dim=2, n_groups=1, n_members=4, stride=2048, params=fake, keep=512, thr=0.5, kept=fake, features=None,
+             group_ptr=fake):
+        return lib.csel_screen_groups(fake, 100, dim, ctypes.byref(kp), n_groups, group_ptr, fake, n_members, fake,
+                                      fake, stride, params, fake if params is not None else None, keep, thr, kept,
+                                      fake, fake, None, features, None)
+
+    assert call(dim=4) == -1 and b"dim" in lib.csel_last_error()
+    assert call(stride=2049) == -4 and b"pool_stride" in lib.csel_last_error()
+    assert call(stride=0) == -4
+    assert call(keep=0) == -1 and b"keep" in lib.csel_last_error()
+    assert call(keep=600, stride=512) == -1
+    assert call(thr=-1.0) == -1 and b"fallback_threshold" in lib.csel_last_error()
+    assert call(n_groups=-1) == -1
+    assert call(n_members=-1) == -1
+    assert call(params=None, features=None) == -1 and b"features" in lib.csel_last_error()
+    assert call(kept=None) == -1 and b"NULL" in lib.csel_last_error()
+    assert call(group_ptr=None) == -1 and b"NULL" in lib.csel_last_error()
+    # no groups: nothing to do
+    assert call(n_groups=0) == 0
+    kp_bad = csel.KernelParams(2, 0.03, 1.0, 0.0)
+    assert lib.csel_screen_groups(fake, 100, 2, ctypes.byref(kp_bad), 1, fake, fake, 4, fake, fake, 64, fake, fake,
+                                  8, 0.5, fake, fake, fake, None, None, None) == -4
