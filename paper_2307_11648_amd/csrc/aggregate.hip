@@ -644,9 +644,17 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
 #pragma unroll
         for (int j = 0; j < MF; ++j) {
             if (j >= M || stop) continue;
-            double sj = a[j];
+            // the row dot product in four independent partial sums (short
+            // dependent FP64 chains), combined in a fixed order; the compiler
+            // barrier every 16 entries keeps the row's LDS loads from all
+            // being hoisted into registers at once
+            double s4[4] = {a[j], 0.0, 0.0, 0.0};
 #pragma unroll
-            for (int c = 0; c < j; ++c) sj -= a[c] * A[tri(j) + c];
+            for (int c = 0; c < j; ++c) {
+                if (c % 16 == 0 && c > 0) asm volatile("" ::: "memory");
+                s4[c & 3] -= a[c] * A[tri(j) + c];
+            }
+            const double sj = (s4[0] + s4[1]) + (s4[2] + s4[3]);
             if (tid == j) {
                 if (sj > 0.0) {
                     const double inv = rsq64(sj);
