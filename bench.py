@@ -389,7 +389,7 @@ MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.99992 (a 1 GiB device copy reads as 524,308 KiB) + WRITE_SIZE x 1.0, in bytes
     ("select_factor_kernel (kept pools)", "natural", "bd379fce7ad5d83a"): (5404966 * 1.99992 + 398460) * 1024,
     ("select_factor_kernel (kept pools)", "spatial", "bd379fce7ad5d83a"): (540744 * 1.99992 + 471992) * 1024,
-    ("screen_kernel", "spatial", "9cd92089adc32410"): (2158917 * 1.99992 + 565053) * 1024,
+    ("screen_kernel", "spatial", "0caa05e7704000cb"): (2159458 * 1.99992 + 565053) * 1024,
 }
 
 

@@ -260,7 +260,10 @@ int csel_screen_features(const double *pts, int64_t n, int32_t dim, const csel_k
  * selections) exceeds fallback_threshold; such columns should be selected on
  * their full pool, and when fallback_list/fallback_count are given their
  * indices are appended there (count reset by this call; list order is not
- * deterministic).  fallback = 3 marks bad input.  logits [n_targets]
+ * deterministic).  fallback = 3 marks bad input (target, pool index or pool
+ * length out of range): nothing is kept, and the column is appended to
+ * fallback_list as well, so the full-pool selection reports it (status 3)
+ * rather than the kept-pool selection answering for an empty pool.  logits [n_targets]
  * [pool_stride] is optional.  pool_stride <= 512.
  *
  * order, n_order (optional): the device int32 list order[0 .. n_order) of the
@@ -304,7 +307,8 @@ int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *ke
  *              kept in slot order, -1 padded; fallback 1 when the dropped
  *              candidates' summed sigmoid(logit) exceeds fallback_threshold,
  *              3 for a bad group (member range or id, pool length or id out
- *              of range; kept_len 0)
+ *              of range; kept_len 0; a caller re-selects it on its full pool
+ *              like a fallback group, where csel_aggregated_select reports it)
  *   logits     optional [n_groups][pool_stride]
  *   features   optional FP32 [n_groups][pool_stride][16]; with params NULL
  *              the call computes features only (keep and the outputs of the

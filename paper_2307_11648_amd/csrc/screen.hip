@@ -399,9 +399,15 @@ __global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kerne
         for (int kk = 0; kk < KPL; ++kk)
             if (kk * 64 + lane < C) my_bad |= pid[kk] < 0 || (int64_t)pid[kk] >= p.n;
         if (__any(my_bad) || bad) {
+            // bad input: nothing kept; the column is listed with the fallback
+            // columns, so the full-pool selection validates it and reports it
             if (lane == 0 && p.mode == 0) {
                 p.kept_len[col] = 0;
                 p.fallback[col] = 3;
+                if (p.fb_list) {
+                    const int fpos = atomicAdd(p.fb_count, 1);
+                    p.fb_list[fpos] = (int32_t)col;
+                }
             }
             fetch_xi();
             continue;

@@ -124,26 +124,39 @@ def screened_group_select(points, kernel, group_ptr, members, max_members: int, 
                           scr=None, out=None):
     """Screened multi-target selection: csel_screen_groups, then
     csel_aggregated_select on the kept pools; groups whose screen falls back
-    are selected again on their full pools (their count is read on the host,
-    the one synchronisation of this path).  Returns (out, scr, n_fallback)."""
+    (or rejects them as bad input) are selected again on their full pools
+    (their count is read on the host, the one synchronisation of this path).
+    Returns (out, scr, n_fallback)."""
     scr = csel.screen_groups(points, kernel, group_ptr, members, pool, pool_len, p, pb, keep, fallback_threshold,
                              out=scr)
     out = csel.aggregated_select(points, kernel, group_ptr, members, max_members, scr["kept"], scr["kept_len"], k,
                                  precision, want_post_var=want_post_var, out=out, workspace=(out or {}).get("workspace"))
-    fb = torch.nonzero(scr["fallback"] == 1).flatten()
+    fb = torch.nonzero(scr["fallback"] >= 1).flatten()  # 1: fallback, 3: bad group (reported on its full pool)
     nfb = int(fb.numel())
     if nfb:
-        gp = group_ptr.to(torch.int64)
-        sizes = (gp[1:] - gp[:-1])[fb]
-        sub_ptr = torch.zeros(nfb + 1, dtype=torch.int64, device=gp.device)
-        sub_ptr[1:] = torch.cumsum(sizes, 0)
-        idx = torch.cat([torch.arange(int(gp[g]), int(gp[g + 1]), device=gp.device) for g in fb.tolist()])
-        sub = csel.aggregated_select(points, kernel, sub_ptr.to(torch.int32), members[idx].contiguous(), max_members,
-                                     pool[fb].contiguous(), pool_len[fb].contiguous(), k, precision,
-                                     want_post_var=want_post_var)
-        for key in ("sel", "logdet", "status"):
-            out[key][fb] = sub[key]
-        if want_post_var:
-            out["post_var"][idx] = sub["post_var"]
+        # member ranges read on the host, so a bad range is never used to index
+        gp = group_ptr.to(torch.int64).cpu()
+        n_members = members.numel()
+        ok, dead = [], []
+        for g in fb.tolist():
+            b, e = int(gp[g]), int(gp[g + 1])
+            (ok if 0 <= b <= e <= n_members else dead).append(g)
+        for g in dead:  # no member range to select for: reported as bad input
+            out["sel"][g] = -1
+            out["logdet"][g] = float("nan")
+            out["status"][g] = 3
+        if ok:
+            sizes = [int(gp[g + 1] - gp[g]) for g in ok]
+            sub_ptr = torch.zeros(len(ok) + 1, dtype=torch.int64)
+            sub_ptr[1:] = torch.cumsum(torch.tensor(sizes, dtype=torch.int64), 0)
+            idx = torch.cat([torch.arange(int(gp[g]), int(gp[g + 1]), dtype=torch.int64) for g in ok]).to(pool.device)
+            okd = torch.tensor(ok, dtype=torch.int64, device=pool.device)
+            sub = csel.aggregated_select(points, kernel, sub_ptr.to(torch.int32).to(pool.device),
+                                         members[idx].contiguous(), max_members, pool[okd].contiguous(),
+                                         pool_len[okd].contiguous(), k, precision, want_post_var=want_post_var)
+            for key in ("sel", "logdet", "status"):
+                out[key][okd] = sub[key]
+            if want_post_var:
+                out["post_var"][idx] = sub["post_var"]
     return out, scr, nfb
 

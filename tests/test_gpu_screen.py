@@ -114,8 +114,8 @@ def test_screen_keep_and_fallback_match_oracle(clustered):
     kl = out["kept_len"].cpu().numpy()
     fb = out["fallback"].cpu().numpy()
     nfb = int(out["fallback_count"].item())
-    assert nfb == int(np.sum(fb == 1))
-    assert set(out["fallback_list"].cpu().numpy()[:nfb].tolist()) == set(np.where(fb == 1)[0].tolist())
+    assert nfb == int(np.sum(fb >= 1))
+    assert set(out["fallback_list"].cpu().numpy()[:nfb].tolist()) == set(np.where(fb >= 1)[0].tolist())
     for t in range(len(w.targets)):
         C = int(w.pool_len[t])
         ks, f = so.screen_keep(z[t], C, keep, 0.5)
@@ -249,7 +249,8 @@ def test_screen_ragged_dims_and_bad_rows(d, C, keep):
     kept, kl = out["kept"].cpu().numpy(), out["kept_len"].cpu().numpy()
     fb = out["fallback"].cpu().numpy()
     nfb = int(out["fallback_count"].item())
-    assert set(out["fallback_list"].cpu().numpy()[:nfb].tolist()) == set(np.where(fb == 1)[0].tolist())
+    # fallback columns and rejected columns (fallback 3) are both listed
+    assert set(out["fallback_list"].cpu().numpy()[:nfb].tolist()) == set(np.where(fb >= 1)[0].tolist())
     for t in range(T):
         if t in bad:
             assert kl[t] == 0 and fb[t] == 3, (t, bad[t])
@@ -265,6 +266,17 @@ def test_screen_ragged_dims_and_bad_rows(d, C, keep):
                 assert bool(fb[t]) == f, t
         else:
             assert fb[t] == 0
+    # the screened pipeline reports the rejected columns as bad input (status 3)
+    # from their full-pool selection, instead of answering for an empty pool
+    sel_out, _ = screen_train.screened_select(_t(w.points, torch.float64), w.kernel, _t(tg, torch.int32),
+                                              _t(pool, torch.int32), _t(plen, torch.int32), 8, p, pb, keep,
+                                              "mixed", fallback_threshold=0.7)
+    torch.cuda.synchronize()
+    st = sel_out["status"].cpu().numpy()
+    for t in bad:
+        assert st[t] == 3, (t, bad[t])
+        assert np.all(sel_out["sel"][t].cpu().numpy() == -1)
+    assert np.all(np.delete(st, list(bad)) < 2)
     pn = p.cpu().numpy().astype(np.float64)
     for t in list(range(0, T, 97)) + [T - 2, T - 5, T - 9, T - 70]:
         L = int(plen[t])

@@ -140,6 +140,13 @@ def test_group_screen_bad_groups(gpw):
     assert got3["fallback"][G - 1] == 3 and got3["kept_len"][G - 1] == 0
     for key in ("kept", "kept_len", "fallback"):
         assert np.array_equal(got3[key][: G - 1], ref[key][: G - 1]), key
+    # the screened selection reports the two bad groups from their full pools
+    sel, _, _ = screen_train.screened_group_select(pts, w.kernel, gpt, _t(mem2, torch.int32), 64,
+                                                   _t(pool2, torch.int32), ln, 16, p, pb, 256, "fp64",
+                                                   fallback_threshold=1e30)
+    st = sel["status"].cpu().numpy()
+    assert st[3] == 3 and st[7] == 3
+    assert np.all(np.delete(st, [3, 7]) < 2)
 
 
 def test_screened_gp_selection_parity(gpw):
