@@ -36,6 +36,19 @@ def shape_key(dim: int, two_nu: int, n_targets: int, stride: int, k: int, precis
     return f"d{dim}/nu{two_nu}/pool{64 * rpl}/k{kmax}/{precision}/T2^{tb}"
 
 
+def check_permutation(order, n: int) -> None:
+    """Raise ValueError unless `order` holds each of 0 .. n-1 exactly once:
+    the spatial schedule writes only the columns it lists."""
+    import torch
+
+    if order.dim() != 1 or order.shape[0] != n:
+        raise ValueError("order must hold every column once")
+    o = order.to(torch.int64)
+    if n and (bool((o < 0).any()) or bool((o >= n).any())
+              or not bool((torch.bincount(o, minlength=n) == 1).all())):
+        raise ValueError("order must be a permutation of the columns")
+
+
 def _event_timer(run, stream):
     """Milliseconds of one call of `run` on `stream`, by HIP events recorded
     on that stream (the kernels are enqueued there)."""
@@ -134,8 +147,6 @@ class SelectTuner:
         if order is None or T < self.min_columns:
             return csel.select_and_factor(points, kernel, targets, pool, pool_len, k, precision, out=out,
                                           stream=stream)
-        if order.shape[0] != T:
-            raise ValueError("order must hold every column once")
         n_all = self._count(T, targets.device)
 
         def natural():
@@ -147,6 +158,8 @@ class SelectTuner:
 
         stride = pool.shape[1] if pool.dim() == 2 else 0
         key = shape_key(points.shape[1], int(kernel.two_nu), T, stride, k, precision)
+        if key not in self.choices or order.shape[0] != T:
+            check_permutation(order, T)  # once per shape class (it reads the order back)
         runners = {"natural": natural, "spatial": spatial}
         runners[self.choose(key, runners, stream)]()
         return out

@@ -75,3 +75,14 @@ def test_json_cache_round_trip_and_bad_files(tmp_path):
                  json.dumps({"version": 1, "choices": {"x": {"schedule": "sideways"}}})):
         open(path, "w").write(text)
         assert autotune.SelectTuner(path=path, timer=g.timer).choices == {}
+
+
+def test_order_must_be_a_permutation():
+    import pytest
+    import torch
+
+    autotune.check_permutation(torch.tensor([2, 0, 1], dtype=torch.int32), 3)
+    autotune.check_permutation(torch.zeros(0, dtype=torch.int32), 0)
+    for bad in ([0, 1], [0, 1, 1], [0, 1, 3], [0, -1, 2]):
+        with pytest.raises(ValueError):
+            autotune.check_permutation(torch.tensor(bad, dtype=torch.int32), 3)
