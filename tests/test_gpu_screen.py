@@ -373,3 +373,27 @@ def test_screen_order_does_not_change_results(clustered):
     assert bool(torch.all(o["kept"][11] == -7))
     for key in ("kept", "kept_len", "fallback"):
         assert torch.equal(o[key][keep_rows], ref[key][keep_rows]), key
+
+
+def test_spatial_order_degenerate_inputs():
+    """One target, all targets at one point (a zero-extent box: every code is
+    0, so the order is the column order), and collinear targets along each
+    axis of a 3-D cloud (one coordinate varies)."""
+    print("case: spatial order degenerate inputs", flush=True)
+    pts = inputs.uniform_points(500, 3, 91)
+    one, _ = csel.spatial_order(_t(pts, torch.float64), _t(np.array([42], np.int32), torch.int32))
+    assert one.cpu().numpy().tolist() == [0]
+    same = np.full(37, 11, np.int32)
+    o, _ = csel.spatial_order(_t(pts, torch.float64), _t(same, torch.int32))
+    assert np.array_equal(o.cpu().numpy(), np.arange(37))
+    for axis in range(3):
+        line = np.zeros((200, 3))
+        line[:, axis] = np.random.default_rng(axis).random(200)
+        tg = np.arange(200, dtype=np.int32)
+        o, _ = csel.spatial_order(_t(line, torch.float64), _t(tg, torch.int32))
+        got = o.cpu().numpy()
+        assert np.array_equal(got, _morton_reference(line, tg))
+        # one coordinate varies: the order sorts its quantised value (ties by column)
+        x = line[:, axis]
+        q = np.floor((x - x.min()) / (x.max() - x.min()) * 1023 + 0.5)
+        assert np.all(np.diff(q[got]) >= 0)

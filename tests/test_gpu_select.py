@@ -273,3 +273,49 @@ def test_list_variant_matches_full_run(prec, C):
     rest = np.setdiff1d(np.arange(T), cols)
     assert np.all(g["sel"][rest] == -7) and np.all(g["status"][rest] == 9)
     assert np.all(g["factor"][rest] == 7.0) and np.all(g["log_condvar"][rest] == 7.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+def test_full_pool_selection_at_capacity(prec):
+    """k = 32 (the largest pick capacity) on pools of exactly 32 and 33
+    candidates: with C = k every candidate is selected, so the column is the
+    exact KL-optimal column on the whole pool, checked against a dense FP64
+    solve; with C = k + 1 one candidate is left out."""
+    print(f"case: k = C = 32 {prec}", flush=True)
+    x = inputs.uniform_points(1200, 2, 77)
+    for C in (32, 33):
+        w = inputs.single_target("cap", x, inputs.Kernel(3, 0.05), C, 32, targets=np.arange(0, 1100, 7))
+        g = run_gpu(w, 32, prec)
+        rep, _ = check(prec, g, w, 32)
+        full = w.pool_len == 32
+        if C == 32:
+            assert np.all(np.sum(g["sel"][full] >= 0, axis=1) == 32)
+            for t in np.where(full)[0][:12]:
+                s = np.concatenate([[w.targets[t]], g["sel"][t]])
+                th = oracle.covariance(w.points[s], w.kernel)
+                e = np.zeros(len(s))
+                e[0] = 1.0
+                col = np.linalg.solve(th, e)
+                col /= math.sqrt(col[0])
+                tol = 1e-9 if prec == "fp64" else 1e-6
+                np.testing.assert_allclose(g["factor"][t], col, rtol=0, atol=tol * np.max(np.abs(col)))
+
+
+def test_list_variant_with_zero_count():
+    """A column list whose device count is 0 writes nothing."""
+    print("case: list variant, count 0", flush=True)
+    w = inputs.workload_plain_fp64(n=300, seed=6)
+    T = len(w.targets)
+    out = {
+        "sel": torch.full((T, 16), -7, dtype=torch.int32, device="cuda"),
+        "factor": torch.full((T, 17), 7.0, dtype=torch.float64, device="cuda"),
+        "log_condvar": torch.full((T,), 7.0, dtype=torch.float64, device="cuda"),
+        "status": torch.full((T,), 9, dtype=torch.uint8, device="cuda"),
+    }
+    csel.select_and_factor_list(_dev(w.points, torch.float64), w.kernel, _dev(w.targets, torch.int32),
+                                _dev(w.pool, torch.int32), _dev(w.pool_len, torch.int32), 16, "mixed",
+                                _dev(np.arange(T, dtype=np.int32), torch.int32),
+                                _dev(np.array([0], np.int32), torch.int32), T, out)
+    torch.cuda.synchronize()
+    assert torch.all(out["sel"] == -7) and torch.all(out["status"] == 9)
+    assert torch.all(out["factor"] == 7.0) and torch.all(out["log_condvar"] == 7.0)
