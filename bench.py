@@ -14,7 +14,8 @@ same way.  Inputs are resident in HBM before timing; ordering, pools and
 training are set-up.
 
 Other workloads: plain (N = 100,000 uniform in [0,1]^3, Matern 5/2, pools of
-256, k = 32, replayed as a HIP graph), aggregated and gp.
+256, k = 32, replayed as a HIP graph), aggregated, gp (plain and screened) and
+apply (products with a built factor, L^T x and L x).
 
 Prints ONE JSON line (rank 0, N = 1 GPU).
 """
@@ -579,12 +580,87 @@ def bench_screened(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_apply(args):
+    """Products with a built factor (csel_apply_factor): y = L^T x and y = L x
+    for the sparse inverse-Cholesky factor of N = 1e6 clustered points (pools of
+    the 64 nearest later points, k = 32, mixed precision; built untimed).  L x
+    runs as the gather on L^T (csel_transpose_factor, built once, its time
+    reported as set-up); the atomic scatter is timed beside it.  HBM-bound:
+    the roofline counts the algorithmic bytes of each product."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs
+
+    n = args.n or 1_000_000
+    print("bench: building the factor", file=sys.stderr, flush=True)
+    w = inputs.workload_clustered(n=n, C=64, k=32)
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    pts, tg = t(w.points, torch.float64), t(w.targets, torch.int32)
+    f = csel.select_and_factor(pts, w.kernel, tg, t(w.pool, torch.int32), t(w.pool_len, torch.int32), 32,
+                               args.precision)
+    col_ptr, rows, vals = csel.single_target_csc(tg, f["sel"], f["factor"])
+    nnz = int((rows >= 0).sum().item())
+    # L^T in CSC form, built once (set-up): L x then runs as a gather
+    tf = csel.transpose_factor(col_ptr, rows, vals)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    tf = csel.transpose_factor(col_ptr, rows, vals, out=tf)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_transpose = e0.elapsed_time(e1)
+    x = torch.from_numpy(np.random.default_rng(3).standard_normal(n)).to(dev)
+    y = torch.empty_like(x)
+    slots = int(rows.numel())
+    # algorithmic bytes: per stored entry its row index and value (12 B) and
+    # one gathered x (8 B); per column one y write (8 B).  The atomic L x reads
+    # x once per column and read-modify-writes y per entry, after clearing y.
+    cases = {"lt": (col_ptr, rows, vals, True, 12 * slots + 8 * nnz + 8 * n),
+             "l": (tf[0], tf[1], tf[2], True, 12 * slots + 8 * nnz + 8 * n),
+             "l_atomic": (col_ptr, rows, vals, False, 12 * slots + 16 * nnz + 16 * n)}
+    res = {}
+    for name, (cp_, r_, v_, tr, byt) in cases.items():
+        for _ in range(args.warmup):
+            csel.apply_factor(cp_, r_, v_, x, tr, out=y)
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(args.steps):
+            csel.apply_factor(cp_, r_, v_, x, tr, out=y)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        res[name] = {"ms": ms, "bytes": byt, "gbs": byt / (ms * 1e-3) / 1e9}
+    ms = res["lt"]["ms"] + res["l"]["ms"]
+    dom = max(("lt", "l"), key=lambda key: res[key]["ms"])
+    out = {
+        "metric": "factor columns applied/s (y = L^T x then y = L x)", "value": n / (ms * 1e-3),
+        "unit": "columns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"apply_factor, N={n} clustered points in [0,1]^3, factor from pools of the 64 "
+                               f"nearest later points, k=32, {args.precision}", "columns": n, "nnz": nnz,
+                   "stored_slots": slots, "lt_ms": res["lt"]["ms"], "l_ms": res["l"]["ms"],
+                   "l_atomic_ms": res["l_atomic"]["ms"], "transpose_setup_ms": ms_transpose},
+        "roofline": {"bound": "hbm", "kernel": f"apply_lt_kernel ({'L^T x' if dom == 'lt' else 'L x on L^T'})",
+                     "achieved": res[dom]["gbs"], "peak": PEAK_HBM_GBS, "unit": "GB/s",
+                     "frac": res[dom]["gbs"] / PEAK_HBM_GBS, "traffic": None, "kernel_ms": res[dom]["ms"],
+                     "algorithmic_bytes_per_launch": res[dom]["bytes"]},
+        "roofline_other": [{"bound": "hbm", "kernel": name, "achieved": res[key]["gbs"], "peak": PEAK_HBM_GBS,
+                            "unit": "GB/s", "frac": res[key]["gbs"] / PEAK_HBM_GBS, "kernel_ms": res[key]["ms"]}
+                           for key, name in (("lt", "apply_lt_kernel (L^T x)"), ("l", "apply_lt_kernel (L x on L^T)"),
+                                             ("l_atomic", "apply_l_kernel (L x, atomic scatter)")) if key != dom],
+    }
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="screened", choices=["screened", "plain", "aggregated", "gp"])
+    ap.add_argument("--workload", default="screened", choices=["screened", "plain", "aggregated", "gp", "apply"])
     ap.add_argument("--train-steps", type=int, default=3000, help="screened workload: Adam steps")
     ap.add_argument("--fallback-threshold", type=float, default=2.0,
                     help="screened workload: fall back to the full pool when the dropped candidates' summed "
@@ -618,6 +694,8 @@ def main():
         args.precision = "fp64" if args.workload == "gp" else "mixed"
     if args.workload == "screened":
         return bench_screened(args)
+    if args.workload == "apply":
+        return bench_apply(args)
     if args.workload != "plain":
         return bench_groups(args)
     args.n = args.n or 100_000

@@ -211,6 +211,30 @@ int csel_apply_factor(int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
                       int32_t transpose, const double *x, double *y, hipStream_t stream);
 
 /*
+ * csel_transpose_factor -- the CSC form of L^T from the CSC form of L (that
+ * is, L by rows), for y = L x as a deterministic gather: csel_apply_factor
+ * with transpose = 1 on the result computes y = (L^T)^T x = L x with the
+ * same per-column gather as y = L^T x, without the atomics of transpose = 0.
+ * Build it once per factor.
+ *
+ *   n, col_ptr [n+1], row_idx, val   L as for csel_apply_factor, with
+ *              0 <= col_ptr[j] <= col_ptr[j+1] and n_slots = col_ptr[n]
+ *              stored slots (n < 2^31 - 1, n_slots < 2^31)
+ *   t_col_ptr  [n+1] int64 out: column r of L^T (row r of L) is
+ *              [t_col_ptr[r], t_col_ptr[r+1])
+ *   t_row_idx, t_val  [n_slots] out: the column of L and the value of each
+ *              entry, ascending column inside a row (a stable sort of the
+ *              slots by row); slots with a row outside [0, n) are dropped,
+ *              and the slots past t_col_ptr[n] get row -1 and value 0
+ *   workspace  device memory of csel_transpose_factor_workspace_size(n,
+ *              n_slots) bytes, caller-owned, not kept after the call's work
+ */
+int64_t csel_transpose_factor_workspace_size(int64_t n, int64_t n_slots);
+int csel_transpose_factor(int64_t n, const int64_t *col_ptr, const int32_t *row_idx, const double *val,
+                          int64_t n_slots, int64_t *t_col_ptr, int32_t *t_row_idx, double *t_val, void *workspace,
+                          int64_t workspace_bytes, hipStream_t stream);
+
+/*
  * csel_select_and_factor_list -- csel_select_and_factor restricted to the
  * columns col_list[0 .. *col_count) (device int32 list and count), e.g. the
  * fallback columns reported by csel_screen.  Array arguments are indexed by

@@ -25,7 +25,7 @@ GEO_LIB = os.path.join(PKG, "inputs", "libcsel_geometry.so")
 HIP_UNITS = [("abi.cpp", []), ("select.hip", [])] + [
     ("select_inst.hip", [f"-DCSEL_SEL_T={t}", f"-DCSEL_SEL_NU={nu}", f"-DCSEL_SEL_GAP={g}"])
     for t in ("float", "double") for nu in (1, 3, 5) for g in (0, 1)
-] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip")] + [
+] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip")] + [
     # the screen's ReLU/min/max need no NaN handling: plain v_max/v_min without
     # the IEEE-mode quieting of their inputs
     ("screen.hip", ["-mno-amdgpu-ieee", "-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]),

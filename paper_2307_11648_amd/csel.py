@@ -63,6 +63,10 @@ def load():
     lib.csel_select_and_factor.restype = ctypes.c_int
     lib.csel_apply_factor.argtypes = [_c.c_int64, _vp, _vp, _vp, _c.c_int32, _vp, _vp, _vp]
     lib.csel_apply_factor.restype = ctypes.c_int
+    lib.csel_transpose_factor_workspace_size.argtypes = [_c.c_int64, _c.c_int64]
+    lib.csel_transpose_factor_workspace_size.restype = ctypes.c_int64
+    lib.csel_transpose_factor.argtypes = [_c.c_int64, _vp, _vp, _vp, _c.c_int64, _vp, _vp, _vp, _vp, _c.c_int64, _vp]
+    lib.csel_transpose_factor.restype = ctypes.c_int
     lib.csel_aggregated_workspace_size.argtypes = [_c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32]
     lib.csel_aggregated_workspace_size.restype = ctypes.c_int64
     lib.csel_aggregated_max_block.restype = ctypes.c_int32
@@ -413,6 +417,31 @@ def apply_factor(col_ptr, row_idx, val, x, transpose: bool, out=None, stream=Non
         out = torch.empty(n, dtype=torch.float64, device=x.device)
     _check(lib.csel_apply_factor(n, col_ptr.data_ptr(), row_idx.data_ptr(), val.data_ptr(), int(bool(transpose)),
                                  x.data_ptr(), out.data_ptr(), _stream(stream)))
+    return out
+
+
+def transpose_factor(col_ptr, row_idx, val, out=None, workspace=None, stream=None):
+    """(t_col_ptr, t_row_idx, t_val): L^T in CSC form (csel_transpose_factor),
+    so that apply_factor(..., transpose=True) on it computes L x."""
+    lib = load()
+    _dev(col_ptr, torch.int64, "col_ptr")
+    _dev(row_idx, torch.int32, "row_idx")
+    _dev(val, torch.float64, "val")
+    n = col_ptr.numel() - 1
+    n_slots = row_idx.numel()
+    dev = col_ptr.device
+    if out is None:
+        out = (torch.empty(n + 1, dtype=torch.int64, device=dev),
+               torch.empty(max(n_slots, 1), dtype=torch.int32, device=dev),
+               torch.empty(max(n_slots, 1), dtype=torch.float64, device=dev))
+    need = lib.csel_transpose_factor_workspace_size(n, n_slots)
+    if need < 0:
+        _check(-1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib.csel_transpose_factor(n, col_ptr.data_ptr(), row_idx.data_ptr(), val.data_ptr(), n_slots,
+                                     out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(), workspace.data_ptr(),
+                                     workspace.numel(), _stream(stream)))
     return out
 
 

@@ -127,6 +127,32 @@ CSEL_API int csel_apply_factor(int64_t n, const int64_t* col_ptr, const int32_t*
     return CSEL_OK;
 }
 
+CSEL_API int64_t csel_transpose_factor_workspace_size(int64_t n, int64_t n_slots) {
+    g_err[0] = 0;
+    if (n < 0 || n >= INT32_MAX) return fail(CSEL_EINVAL, "n must be in [0, 2^31 - 1) (got %lld)", (long long)n);
+    if (n_slots < 0 || n_slots > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_slots must be in [0, 2^31) (got %lld)", (long long)n_slots);
+    const int64_t w = csel::transpose_factor_workspace(n, n_slots);
+    if (w < 0) return fail(CSEL_EHIP, "radix sort could not size its temporary storage");
+    return w;
+}
+
+CSEL_API int csel_transpose_factor(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val,
+                                   int64_t n_slots, int64_t* t_col_ptr, int32_t* t_row_idx, double* t_val,
+                                   void* workspace, int64_t workspace_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    const int64_t need = csel_transpose_factor_workspace_size(n, n_slots);
+    if (need < 0) return (int)need;
+    if (!col_ptr || !t_col_ptr) return fail(CSEL_EINVAL, "a required array is NULL");
+    if (n_slots > 0 && (!row_idx || !val || !t_row_idx || !t_val)) return fail(CSEL_EINVAL, "a required array is NULL");
+    if (n_slots > 0 && (!workspace || workspace_bytes < need))
+        return fail(CSEL_EINVAL, "workspace too small: %lld bytes needed", (long long)need);
+    hipError_t e = csel::launch_transpose_factor(n, col_ptr, row_idx, val, n_slots, t_col_ptr, t_row_idx, t_val,
+                                                 workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "transpose_factor launch");
+    return CSEL_OK;
+}
+
 namespace {
 constexpr int kAggMaxPool = 4096;
 constexpr int kAggMaxMembers = 256;

@@ -162,6 +162,10 @@ int agg_factor_max_m();
 
 // rpl: pool rows per lane (1, 2, 4, 8); kmax: 16 or 32.
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s);
+int64_t transpose_factor_workspace(int64_t n, int64_t n_slots);
+hipError_t launch_transpose_factor(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val,
+                                   int64_t n_slots, int64_t* t_col_ptr, int32_t* t_row_idx, double* t_val,
+                                   void* workspace, hipStream_t s);
 hipError_t launch_apply(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val, int transpose,
                         const double* x, double* y, hipStream_t s);
 hipError_t launch_sum(const double* x, int64_t n, double* out, hipStream_t s);

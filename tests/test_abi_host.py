@@ -100,3 +100,20 @@ def test_screen_groups_validation_without_gpu():
     kp_bad = csel.KernelParams(2, 0.03, 1.0, 0.0)
     assert lib.csel_screen_groups(fake, 100, 2, ctypes.byref(kp_bad), 1, fake, fake, 4, fake, fake, 64, fake, fake,
                                   8, 0.5, fake, fake, fake, None, None, None) == -4
+
+
+def test_transpose_factor_validation_without_gpu():
+    if not os.path.exists(csel.LIB_PATH):
+        pytest.skip("libcsel.so not built")
+    lib = csel.load()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation first
+    assert lib.csel_transpose_factor_workspace_size(-1, 0) == -1
+    assert lib.csel_transpose_factor_workspace_size(10, -1) == -1
+    assert lib.csel_transpose_factor_workspace_size(2 ** 31, 0) == -1
+    assert lib.csel_transpose_factor_workspace_size(10, 2 ** 31) == -1
+    assert lib.csel_transpose_factor_workspace_size(10, 0) == 0
+    assert lib.csel_transpose_factor(10, None, fake, fake, 5, fake, fake, fake, fake, 1 << 30, None) == -1
+    assert b"NULL" in lib.csel_last_error()
+    assert lib.csel_transpose_factor(10, fake, None, fake, 5, fake, fake, fake, fake, 1 << 30, None) == -1
+    assert lib.csel_transpose_factor(10, fake, fake, fake, 5, fake, fake, fake, None, 0, None) == -1
+    assert b"workspace" in lib.csel_last_error()

@@ -211,6 +211,57 @@ def test_apply_factor():
     assert torch.equal(ylt, csel.apply_factor(cp, rows, vals, x, True))
 
 
+def test_transpose_factor_and_gather_products():
+    """L^T in CSC form (csel_transpose_factor) equals scipy's CSR of L entry
+    for entry (padding slots dropped, columns ascending inside a row), and
+    the gather on it, y = (L^T)^T x, equals L x from the dense product and
+    from the atomic scatter."""
+    import scipy.sparse as sp
+
+    print("case: transpose factor", flush=True)
+    w = inputs.workload_plain_fp64(n=900, seed=13)
+    plen = w.pool_len.copy()
+    plen[::5] = np.minimum(plen[::5], 3)  # short pools: padding slots in the [T][k+1] layout
+    g = csel.select_and_factor(_t(w.points, torch.float64), w.kernel, _t(w.targets, torch.int32),
+                               _t(w.pool, torch.int32), _t(plen, torch.int32), 16, "fp64")
+    cp, rows, vals = csel.single_target_csc(_t(w.targets, torch.int32), g["sel"], g["factor"])
+    n = len(w.targets)
+    tcp, trow, tval = csel.transpose_factor(cp, rows, vals)
+    torch.cuda.synchronize()
+    tcp, trow, tval = tcp.cpu().numpy(), trow.cpu().numpy(), tval.cpu().numpy()
+    r, v = rows.cpu().numpy(), vals.cpu().numpy()
+    cols = np.repeat(np.arange(n), 17)
+    keep = r >= 0
+    L = sp.csc_matrix((v[keep], (r[keep], cols[keep])), shape=(n, n))
+    csr = L.tocsr()
+    csr.sort_indices()
+    nnz = int(keep.sum())
+    np.testing.assert_array_equal(tcp, csr.indptr.astype(np.int64))
+    np.testing.assert_array_equal(trow[:nnz], csr.indices)
+    np.testing.assert_array_equal(tval[:nnz], csr.data)
+    assert np.all(trow[nnz:] == -1) and np.all(tval[nnz:] == 0.0)
+    x = np.random.default_rng(5).standard_normal(n)
+    xt = torch.from_numpy(x).cuda()
+    tcp_d, trow_d, tval_d = csel.transpose_factor(cp, rows, vals)
+    y_gather = csel.apply_factor(tcp_d, trow_d, tval_d, xt, True).cpu().numpy()
+    y_atomic = csel.apply_factor(cp, rows, vals, xt, False).cpu().numpy()
+    ref = L @ x
+    np.testing.assert_allclose(y_gather, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+    np.testing.assert_allclose(y_atomic, ref, rtol=1e-12, atol=1e-12 * np.max(np.abs(ref)))
+    # deterministic: the same bits on a second run
+    y2 = csel.apply_factor(tcp_d, trow_d, tval_d, xt, True).cpu().numpy()
+    assert np.array_equal(y2, y_gather)
+    # an empty factor and one without stored slots
+    e0 = csel.transpose_factor(torch.zeros(1, dtype=torch.int64, device="cuda"),
+                               torch.zeros(0, dtype=torch.int32, device="cuda"),
+                               torch.zeros(0, dtype=torch.float64, device="cuda"))
+    e1 = csel.transpose_factor(torch.zeros(4, dtype=torch.int64, device="cuda"),
+                               torch.zeros(0, dtype=torch.int32, device="cuda"),
+                               torch.zeros(0, dtype=torch.float64, device="cuda"))
+    torch.cuda.synchronize()
+    assert e0[0].cpu().tolist() == [0] and e1[0].cpu().tolist() == [0, 0, 0, 0]
+
+
 @pytest.mark.parametrize("want_gap", [True, False])
 def test_aggregated_mixed_register_kernel(want_gap):
     """Mixed precision without posterior variances, pools <= 512, groups <= 32,
