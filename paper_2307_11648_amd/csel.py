@@ -180,6 +180,8 @@ def select_and_factor_list(points, kernel, targets, pool, pool_len, k: int, prec
     lib = load()
     _dev(col_list, torch.int32, "col_list")
     _dev(col_count, torch.int32, "col_count")
+    if col_list.numel() < max_cols or col_count.numel() < 1:
+        raise ValueError("col_list must hold max_cols entries and col_count one")
     T = targets.shape[0]
     stride = pool.shape[1] if pool.dim() == 2 else 0
     kp = kernel_struct(kernel)

@@ -209,6 +209,10 @@ def test_host_validation_errors():
         csel.select_and_factor(x, inputs.Kernel(3, 0.1), t, p, t, 40)
     with pytest.raises(ValueError):
         csel.select_and_factor(x.cpu(), inputs.Kernel(3, 0.1), t, p, t, 2)
+    # a column list shorter than the capacity it claims is refused before launch
+    out = csel.select_and_factor(x, inputs.Kernel(3, 0.1), t, p, t, 2)
+    with pytest.raises(ValueError):
+        csel.select_and_factor_list(x, inputs.Kernel(3, 0.1), t, p, t, 2, "mixed", t, t, 5, out)
 
 
 def test_gap_and_no_gap_variants_agree():
