@@ -676,8 +676,8 @@ def main():
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
-        print("bench.py runs on one GPU only: this build has no multi-GPU path (columns shard with no "
-              "communication; see the design notes).", file=sys.stderr)
+        print("bench.py runs on one GPU only: the library has no multi-GPU path (its columns would shard with "
+              "no communication but an 8-byte sum).", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

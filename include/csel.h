@@ -49,7 +49,7 @@ typedef enum {
     CSEL_EINVAL = -1,       /* an argument is invalid (see csel_last_error) */
     CSEL_EHIP = -2,         /* a HIP runtime call failed */
     CSEL_ENOMEM = -3,       /* device workspace could not be allocated */
-    CSEL_EUNSUPPORTED = -4  /* valid request outside what this build handles */
+    CSEL_EUNSUPPORTED = -4  /* valid request outside what the library supports */
 } csel_error;
 
 enum { CSEL_FP64 = 0, CSEL_MIXED = 1 };
