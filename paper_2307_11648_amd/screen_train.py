@@ -90,7 +90,13 @@ def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep
                     fallback_threshold: float = 0.5, out=None, scr=None, order=None):
     """The screened hot path: screen, exact selection on the kept candidates,
     exact selection on the full pool for the fallback columns (no host sync).
-    `order` is the screen's column processing order (csel.spatial_order)."""
+    `order` is the screen's column processing order (csel.spatial_order): it
+    must list every column once, since the kept-pool selection runs on all of
+    them (checked here, which reads the order back)."""
+    if order is not None:
+        from .autotune import check_permutation
+
+        check_permutation(order, targets.shape[0])
     scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr,
                       order=order)
     out = csel.select_and_factor(points, kernel, targets, scr["kept"], scr["kept_len"], k, precision, out=out)
