@@ -387,10 +387,13 @@ def _source_digest(*names):
 # and the digest of its sources at measurement time; a changed kernel reports
 # null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE x 1.99992 (a 1 GiB device copy reads as 524,308 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "bd379fce7ad5d83a"): (5404966 * 1.99992 + 398460) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "bd379fce7ad5d83a"): (540744 * 1.99992 + 471992) * 1024,
+    # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.0, in bytes
+    ("select_factor_kernel (kept pools)", "natural", "c76af895f5bead61"): (5405010 * 1.9999 + 398458) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "c76af895f5bead61"): (540820 * 1.9999 + 471975) * 1024,
     ("screen_kernel", "spatial", "0caa05e7704000cb"): (2159458 * 1.99992 + 565053) * 1024,
+    # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
+    ("select_factor_kernel (plain batched)", "natural", "c76af895f5bead61"): (63195 * 1.9999 + 39844) * 1024,
+    ("select_factor_kernel (plain batched)", "spatial", "c76af895f5bead61"): (73725 * 1.9999 + 47875) * 1024,
 }
 
 
@@ -405,14 +408,6 @@ def bench_screened(args):
     n = args.n or 1_000_000
     dev = torch.device("cuda:0")
     t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
-    if args.copy_probe:
-        # a plain copy of known size (1 GiB read + 1 GiB written) for calibrating
-        # the HBM byte counters of a profiler run
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        del src, dst
     print("bench: training cloud", file=sys.stderr, flush=True)
     t0 = time.perf_counter()
     tr = inputs.workload_clustered_training(n=n, n_columns=min(50_000, n))
@@ -533,7 +528,8 @@ def bench_screened(args):
     kept_key = autotune.shape_key(pts.shape[1], int(w.kernel.two_nu), T, keep, k, prec)
     kernels = {
         "select_factor_kernel (kept pools)": {"bound": "alu", "ms": ms_kept, "work": float(np.sum(flops_kept)),
-                                              "peak": PEAK_ALU_TFLOPS, "src": ("select_kernel.hpp", "device_common.hpp"),
+                                              "peak": PEAK_ALU_TFLOPS,
+                                              "src": ("select_kernel.hpp", "select_inst.hip", "device_common.hpp"),
                                               "schedule": tuner.choices[kept_key]["schedule"]},
         "screen_kernel": {"bound": "mfma", "ms": ms_scr, "work": mlp_flops, "peak": PEAK_BF16_TFLOPS,
                           "src": ("screen.hip", "device_common.hpp"), "schedule": "spatial"},
@@ -672,7 +668,7 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
     ap.add_argument("--graph", type=int, default=1, help="plain workload: replay the step as a captured HIP graph")
     ap.add_argument("--copy-probe", type=int, default=0,
-                    help="screened workload: run one 1 GiB device copy first (profiler byte-counter calibration)")
+                    help="run one 1 GiB device copy first (profiler byte-counter calibration)")
     args = ap.parse_args()
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -692,6 +688,14 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     if not args.precision:
         args.precision = "fp64" if args.workload == "gp" else "mixed"
+    if args.copy_probe:
+        # a plain copy of known size (1 GiB read + 1 GiB written) for calibrating
+        # the HBM byte counters of a profiler run
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda:0")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     if args.workload == "screened":
         return bench_screened(args)
     if args.workload == "apply":
@@ -781,6 +785,8 @@ def main():
     kern_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in ev]))
 
     flops, byt = column_work(w.pool_len, k, w.points.shape[1], w.kernel.two_nu)
+    plain_schedule = tuner.choices[autotune.shape_key(pts.shape[1], int(w.kernel.two_nu), T, pl.shape[1], k,
+                                                      args.precision)]["schedule"]
     flops_launch = float(np.sum(flops))
     bytes_launch = float(np.sum(byt)) + w.points.nbytes
     achieved = flops_launch / (kern_ms * 1e-3) / 1e12
@@ -819,7 +825,11 @@ def main():
             "peak": PEAK_ALU_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_ALU_TFLOPS,
-            "traffic": None,
+            "traffic": MEASURED_TRAFFIC.get(("select_factor_kernel (plain batched)", plain_schedule,
+                                             _source_digest("select_kernel.hpp", "select_inst.hip",
+                                                            "device_common.hpp"))),
+            "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, copy-calibrated)",
+            "schedule": plain_schedule,
             "kernel_ms": kern_ms,
             "algorithmic_gflop_per_launch": flops_launch / 1e9,
             "algorithmic_mb_per_launch": bytes_launch / 1e6,

@@ -1,14 +1,21 @@
 // select.hip -- dispatch of the single-target kernel families and the
 // deterministic FP64 sum.  The kernels themselves live in select_kernel.hpp
-// and are instantiated by select_inst.hip (one object per family).
+// and are instantiated by select_inst.hip (one object per family and pool width).
 #include "device_common.hpp"
 #include "launch.hpp"
 
 namespace csel {
 
-#define CSEL_DECL(T, NU)                                                              \
-    hipError_t launch_select_##T##_##NU##_0(const SelectArgs&, int, int, hipStream_t); \
-    hipError_t launch_select_##T##_##NU##_1(const SelectArgs&, int, int, hipStream_t);
+#define CSEL_DECL1(T, NU, G, R) hipError_t launch_select_##T##_##NU##_##G##_##R(const SelectArgs&, int, hipStream_t);
+#define CSEL_DECL(T, NU)        \
+    CSEL_DECL1(T, NU, 0, 1)     \
+    CSEL_DECL1(T, NU, 0, 2)     \
+    CSEL_DECL1(T, NU, 0, 4)     \
+    CSEL_DECL1(T, NU, 0, 8)     \
+    CSEL_DECL1(T, NU, 1, 1)     \
+    CSEL_DECL1(T, NU, 1, 2)     \
+    CSEL_DECL1(T, NU, 1, 4)     \
+    CSEL_DECL1(T, NU, 1, 8)
 CSEL_DECL(float, 1)
 CSEL_DECL(float, 3)
 CSEL_DECL(float, 5)
@@ -16,26 +23,54 @@ CSEL_DECL(double, 1)
 CSEL_DECL(double, 3)
 CSEL_DECL(double, 5)
 #undef CSEL_DECL
+#undef CSEL_DECL1
+
+// the family's launcher for pool width rpl (1, 2, 4 or 8 entries per lane)
+#define CSEL_RPL(T, NU, G)                                               \
+    switch (rpl) {                                                       \
+        case 1: return launch_select_##T##_##NU##_##G##_1(a, kmax, s); \
+        case 2: return launch_select_##T##_##NU##_##G##_2(a, kmax, s); \
+        case 4: return launch_select_##T##_##NU##_##G##_4(a, kmax, s); \
+        case 8: return launch_select_##T##_##NU##_##G##_8(a, kmax, s); \
+    }                                                                    \
+    return hipErrorInvalidValue;
+
+template <int PREC, int NU>
+static hipError_t launch_family(const SelectArgs& a, bool gap, int rpl, int kmax, hipStream_t s);
+
+#define CSEL_FAMILY(PREC, T, NU)                                                                              \
+    template <>                                                                                              \
+    hipError_t launch_family<PREC, NU>(const SelectArgs& a, bool gap, int rpl, int kmax, hipStream_t s) { \
+        if (gap) {                                                                                           \
+            CSEL_RPL(T, NU, 1)                                                                               \
+        }                                                                                                    \
+        CSEL_RPL(T, NU, 0)                                                                                   \
+    }
+CSEL_FAMILY(0, double, 1)
+CSEL_FAMILY(0, double, 3)
+CSEL_FAMILY(0, double, 5)
+CSEL_FAMILY(1, float, 1)
+CSEL_FAMILY(1, float, 3)
+CSEL_FAMILY(1, float, 5)
+#undef CSEL_FAMILY
+#undef CSEL_RPL
 
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s) {
     if (a.n_targets == 0 || a.n_waves == 0) return hipSuccess;
     const bool gap = a.gap != nullptr;
-#define CSEL_CASE(T, NU) \
-    return gap ? launch_select_##T##_##NU##_1(a, rpl, kmax, s) : launch_select_##T##_##NU##_0(a, rpl, kmax, s);
     if (precision == 0) {
         switch (a.two_nu) {
-            case 1: CSEL_CASE(double, 1)
-            case 3: CSEL_CASE(double, 3)
-            case 5: CSEL_CASE(double, 5)
+            case 1: return launch_family<0, 1>(a, gap, rpl, kmax, s);
+            case 3: return launch_family<0, 3>(a, gap, rpl, kmax, s);
+            case 5: return launch_family<0, 5>(a, gap, rpl, kmax, s);
         }
     } else {
         switch (a.two_nu) {
-            case 1: CSEL_CASE(float, 1)
-            case 3: CSEL_CASE(float, 3)
-            case 5: CSEL_CASE(float, 5)
+            case 1: return launch_family<1, 1>(a, gap, rpl, kmax, s);
+            case 3: return launch_family<1, 3>(a, gap, rpl, kmax, s);
+            case 5: return launch_family<1, 5>(a, gap, rpl, kmax, s);
         }
     }
-#undef CSEL_CASE
     return hipErrorInvalidValue;
 }
 

@@ -374,23 +374,11 @@ static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
     return hipGetLastError();
 }
 
-template <typename T, int TWO_NU, bool GAP>
-static hipError_t launch_nu_impl(const SelectArgs& a, int rpl, int kmax, hipStream_t s) {
-    if (kmax == 16) {
-        switch (rpl) {
-            case 1: return launch_one<T, TWO_NU, 1, 16, GAP>(a, s);
-            case 2: return launch_one<T, TWO_NU, 2, 16, GAP>(a, s);
-            case 4: return launch_one<T, TWO_NU, 4, 16, GAP>(a, s);
-            case 8: return launch_one<T, TWO_NU, 8, 16, GAP>(a, s);
-        }
-    } else if (kmax == 32) {
-        switch (rpl) {
-            case 1: return launch_one<T, TWO_NU, 1, 32, GAP>(a, s);
-            case 2: return launch_one<T, TWO_NU, 2, 32, GAP>(a, s);
-            case 4: return launch_one<T, TWO_NU, 4, 32, GAP>(a, s);
-            case 8: return launch_one<T, TWO_NU, 8, 32, GAP>(a, s);
-        }
-    }
+// one pool width (RPL pool entries per lane) at either pick capacity
+template <typename T, int TWO_NU, int RPL, bool GAP>
+static hipError_t launch_rpl_impl(const SelectArgs& a, int kmax, hipStream_t s) {
+    if (kmax == 16) return launch_one<T, TWO_NU, RPL, 16, GAP>(a, s);
+    if (kmax == 32) return launch_one<T, TWO_NU, RPL, 32, GAP>(a, s);
     return hipErrorInvalidValue;
 }
 
