@@ -387,13 +387,13 @@ def _source_digest(*names):
 # and the digest of its sources at measurement time; a changed kernel reports
 # null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "c76af895f5bead61"): (5405010 * 1.9999 + 398458) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "c76af895f5bead61"): (540820 * 1.9999 + 471975) * 1024,
-    ("screen_kernel", "spatial", "0caa05e7704000cb"): (2159458 * 1.99992 + 565053) * 1024,
+    # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,308 - 524,316 KiB) + WRITE_SIZE x 1.0, in bytes
+    ("select_factor_kernel (kept pools)", "natural", "e7a4f309d7e4d0b7"): (5411983 * 1.9999 + 398457) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "e7a4f309d7e4d0b7"): (540730 * 1.9999 + 471981) * 1024,
+    ("screen_kernel", "spatial", "049ffbb9f5d9bd83"): (2160851 * 1.9999 + 565050) * 1024,
     # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
-    ("select_factor_kernel (plain batched)", "natural", "c76af895f5bead61"): (63195 * 1.9999 + 39844) * 1024,
-    ("select_factor_kernel (plain batched)", "spatial", "c76af895f5bead61"): (73725 * 1.9999 + 47875) * 1024,
+    ("select_factor_kernel (plain batched)", "natural", "e7a4f309d7e4d0b7"): (63150 * 1.9999 + 39844) * 1024,
+    ("select_factor_kernel (plain batched)", "spatial", "e7a4f309d7e4d0b7"): (73562 * 1.9999 + 47867) * 1024,
 }
 
 

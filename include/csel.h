@@ -92,7 +92,7 @@ int32_t csel_max_select(void);
  * conditional variance exceeds 1e-12 times its prior variance.  Ties in score
  * go to the smaller pool slot.  The column on s = [i, selected...] is then
  * L_{s,i} = Theta_ss^{-1} e_1 / sqrt(e_1^T Theta_ss^{-1} e_1) (eq. L_col),
- * from an FP64 Cholesky factorization of Theta_ss.
+ * from an FP64 square-root-free Cholesky factorization (L D L^T) of Theta_ss.
  *
  *   pts        [n][dim] FP64 coordinates
  *   targets    [n_targets] int32 column ids
@@ -102,7 +102,7 @@ int32_t csel_max_select(void);
  *   precision  CSEL_FP64: everything in FP64.
  *              CSEL_MIXED: covariance evaluation and the left-looking GEMV of
  *              the selection in FP32; conditional variances/covariances, the
- *              scores, Theta_ss and its Cholesky factorization in FP64.
+ *              scores, Theta_ss and its L D L^T factorization in FP64.
  * Outputs (per column c):
  *   sel_idx    [n_targets][k] selected ids in selection order, -1 padded
  *   factor_val [n_targets][k+1]: [0] = L_ii, [1+t] = entry of row sel_idx[t];

@@ -142,6 +142,27 @@ __device__ __forceinline__ double rcp64(double v) {
     return r * fma(-v, r, 2.0);
 }
 
+// 1/v in FP64 (v > 0 normal): hardware reciprocal refined by two Newton
+// steps r <- r + r (1 - v r) (about 1 ulp)
+__device__ __forceinline__ double rcp64_acc(double v) {
+    double r = __builtin_amdgcn_rcp(v);
+#pragma unroll
+    for (int it = 0; it < 2; ++it) r = fma(r, fma(-v, r, 1.0), r);
+    return r;
+}
+
+// x of lane i plus x of lane i ^ 32, the same bits in both lanes of the pair
+// (gfx950's cross-half swap, once per 32-bit word; the two operands are added
+// in either order, which rounds identically)
+__device__ __forceinline__ double pair_sum(double x) {
+    const uint64_t b = (uint64_t)__double_as_longlong(x);
+    const auto lo = __builtin_amdgcn_permlane32_swap((uint32_t)b, (uint32_t)b, false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap((uint32_t)(b >> 32), (uint32_t)(b >> 32), false, false);
+    const double a0 = __longlong_as_double((long long)(((uint64_t)hi[0] << 32) | lo[0]));
+    const double a1 = __longlong_as_double((long long)(((uint64_t)hi[1] << 32) | lo[1]));
+    return a0 + a1;
+}
+
 // 1/sqrt(v) in FP64 (v > 0 normal): hardware reciprocal square root refined
 // by two Newton steps r <- r + r/2 (1 - v r^2) (about 1 ulp)
 __device__ __forceinline__ double rsq64(double v) {

@@ -57,7 +57,7 @@ constexpr int kSelWavesPerBlock = 4;
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
 __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
-    __shared__ double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
+    __shared__ __align__(16) double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
     __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
 
     const int lane = lane_id();
@@ -281,8 +281,17 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     const double cnu64 = p.c_nu, s264 = p.s2, nug64 = p.nugget;
-    // Theta' lower triangle, its tri(M) entries spread over the 64 lanes, staged
-    // in LDS; then lane r loads its row
+    // Theta' = L D L^T (L unit lower triangular), FP64.  Row r >= 1 of Theta'
+    // belongs to the lane pair (r - 1, r - 1 + 32): the low lane holds the
+    // row's even columns, the high lane its odd columns, so each dot product
+    // is split over two lanes and joined by one cross-half swap.  Row r of the
+    // LDS buffer TH keeps column c at slot pos(c) = (c & 1) * HALF + (c >> 1):
+    // each half's columns contiguous and 16-byte aligned, the even half in
+    // slots 0 .. KMAX/2, the diagonal in slot HALF - 1, the odd half in slots
+    // HALF .. KMAX + 1.  The slot pos(r) of row r holds 0.
+    constexpr int HALF = KMAX / 2 + 2;
+    constexpr int DIAG = HALF - 1;
+    static_assert(HALF + (KMAX - 1) / 2 <= KMAX + 1 && DIAG > KMAX / 2, "row layout");
     double(*TH)[KMAX + 2] = sh_r[wib];
     {
         const int ne = M * (M + 1) / 2;
@@ -294,61 +303,80 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
             const double d0 = PT[r][0] - PT[c][0], d1 = PT[r][1] - PT[c][1], d2 = PT[r][2] - PT[c][2];
             const double s2d = d0 * d0 + d1 * d1 + d2 * d2;
             const double rr = s2d > 0.0 ? s2d * rsq64(s2d) : 0.0;
-            TH[r][c] = matern_f64<TWO_NU>(rr, cnu64, s264) + (PT[r][3] == PT[c][3] ? nug64 : 0.0);
+            const double th = matern_f64<TWO_NU>(rr, cnu64, s264) + (PT[r][3] == PT[c][3] ? nug64 : 0.0);
+            if (c < r) {
+                TH[r][(c & 1) * HALF + (c >> 1)] = th;
+            } else {
+                TH[r][DIAG] = th;
+                TH[r][(r & 1) * HALF + (r >> 1)] = 0.0;
+            }
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    double a[KMAX + 1];
+    const int hi = lane >> 5;
+    const int my_row = (lane & 31) + 1;
+    const bool row_ok = my_row < M;
+    // h[q]: column 2q + hi of my row (Theta' until that column is done, then L)
+    double h[KMAX / 2 + 1];
+    const double* my_th = &TH[row_ok ? my_row : 0][hi * HALF];
 #pragma unroll
-    for (int c = 0; c <= KMAX; ++c) a[c] = (c <= lane && lane < M) ? TH[lane][c] : 0.0;
+    for (int q = 0; q <= KMAX / 2; ++q) h[q] = (row_ok && 2 * q + hi <= KMAX) ? my_th[q] : 0.0;
+    const double diag = row_ok ? TH[my_row][DIAG] : 0.0;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
-    // Left-looking Cholesky Theta' = R R^T by columns: lane r finishes R[r][j]
-    // from its own row (registers) and row j of R, read from LDS as a
-    // broadcast; every lane then stores its column-j entry into row r of the
-    // LDS copy, which rows > j read in later steps.  Entries a lane computes
-    // above its diagonal are never read.
+    // Left-looking by columns: with W[j][c] = d_c L[j][c] (row j of TH, written
+    // as column c finished), every row r >= j needs v_r = Theta'[r][j] -
+    // sum_{c<j} L[r][c] W[j][c]; then d_j = v_j and L[r][j] = v_r / d_j.  The
+    // high lane's sum for odd j reads the zero slot pos(j) of row j as its last
+    // term.  Entries of rows below j and lanes past the last row are never
+    // read.
     bool pd = true;
-    double dinv = 0.0;  // lane j: 1 / R[j][j]
+    double dinv = 0.0;   // lane c: 1 / d_c
+    double dlast = 0.0;  // d of the last row (the target's conditional variance)
 #pragma unroll
     for (int j = 0; j <= KMAX; ++j) {
         if (j >= M || !pd) continue;
-        double sj = a[j];
+        double part = 0.0;
+        const double* wj = &TH[j][hi * HALF];
 #pragma unroll
-        for (int c = 0; c < j; ++c) sj -= a[c] * TH[j][c];
-        const double piv = bcast(sj, j);
-        if (!(piv > 0.0)) {
+        for (int q = 0; q < (j + 1) / 2; ++q) part = fma(h[q], wj[q], part);
+        const double tot = pair_sum(part);
+        const double dj = j == 0 ? TH[0][DIAG] : bcast(diag - tot, j - 1);
+        if (!(dj > 0.0)) {
             pd = false;
             continue;
         }
-        const double inv = rsq64(piv);
-        a[j] = lane == j ? piv * inv : sj * inv;
+        const double inv = rcp64_acc(dj);
         if (lane == j) dinv = inv;
-        if (lane < M) TH[lane][j] = a[j];
+        dlast = dj;
+        if (hi == (j & 1) && my_row > j && row_ok) {
+            const double v = h[j >> 1] - tot;
+            h[j >> 1] = v * inv;
+            TH[my_row][(j & 1) * HALF + (j >> 1)] = v;
+        }
         __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
         __builtin_amdgcn_wave_barrier();
     }
 
     double y = 0.0;
     if (pd) {
-        // back-substitution with the rows of R left in LDS by the factorisation
-        double(*R)[KMAX + 2] = sh_r[wib];
+        // Theta'^{-1} e_last = L^{-T} e_last / d_last and e_last^T Theta'^{-1}
+        // e_last = 1 / d_last, so the column is z / sqrt(d_last) with L^T z =
+        // e_last: z_last = 1, z_c = -(1 / d_c) sum_{r>c} W[r][c] z_r, lane c
+        // accumulating its sum from the rows left in TH.
         const int l = nsel;
-        double acc = 0.0;
+        const int my_pos = lane <= KMAX ? (lane & 1) * HALF + (lane >> 1) : 0;
+        double acc = 0.0, z = 0.0;
 #pragma unroll
         for (int c = KMAX; c >= 0; --c) {
             if (c > l) continue;
-            const double rinv = bcast(dinv, c);  // 1 / R[c][c]
-            const double yc = c == l ? rinv : -bcast(acc, c) * rinv;
-            if (lane == c) y = yc;
-            if (lane < c) acc += R[c][lane] * yc;
+            const double zc = c == l ? 1.0 : bcast(-acc * dinv, c);
+            if (lane == c) z = zc;
+            if (lane < c) acc = fma(TH[c][my_pos], zc, acc);
         }
-        // log Theta_ii|s = -2 log(1 / R_ll)
-        if (p.logcv) {
-            const double rl = bcast(dinv, l);
-            if (lane == 0) p.logcv[col] = -2.0 * log(rl);
-        }
+        y = z * rsq64(dlast);
+        if (p.logcv && lane == 0) p.logcv[col] = log(dlast);
     } else {
         st = 2;
         y = __builtin_nan("");
