@@ -388,12 +388,12 @@ def _source_digest(*names):
 # null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,308 - 524,316 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "e7a4f309d7e4d0b7"): (5411983 * 1.9999 + 398457) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "e7a4f309d7e4d0b7"): (540730 * 1.9999 + 471981) * 1024,
+    ("select_factor_kernel (kept pools)", "natural", "dad9aa120417cfa9"): (5417751 * 1.9999 + 398459) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "dad9aa120417cfa9"): (540766 * 1.9999 + 471983) * 1024,
     ("screen_kernel", "spatial", "049ffbb9f5d9bd83"): (2160851 * 1.9999 + 565050) * 1024,
     # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
-    ("select_factor_kernel (plain batched)", "natural", "e7a4f309d7e4d0b7"): (63150 * 1.9999 + 39844) * 1024,
-    ("select_factor_kernel (plain batched)", "spatial", "e7a4f309d7e4d0b7"): (73562 * 1.9999 + 47867) * 1024,
+    ("select_factor_kernel (plain batched)", "natural", "dad9aa120417cfa9"): (63154 * 1.9999 + 39844) * 1024,
+    ("select_factor_kernel (plain batched)", "spatial", "dad9aa120417cfa9"): (73483 * 1.9999 + 47860) * 1024,
 }
 
 

@@ -295,10 +295,13 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     double(*TH)[KMAX + 2] = sh_r[wib];
     {
         const int ne = M * (M + 1) / 2;
+        // entry e of the row-major lower triangle is (r, c) with r = floor(x),
+        // x = (sqrt(8e + 1) - 1) / 2: for rows r <= 32, x lies in
+        // [r, r + 1 - 2 / (2r + 3)], so x + 1e-3 truncates to r under a
+        // square root within one ulp
+        static_assert(KMAX <= 32, "triangle index bound");
         for (int e = lane; e < ne; e += kWave) {
-            int r = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f);
-            while ((r + 1) * (r + 2) / 2 <= e) ++r;
-            while (r * (r + 1) / 2 > e) --r;
+            const int r = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f + 1e-3f);
             const int c = e - r * (r + 1) / 2;
             const double d0 = PT[r][0] - PT[c][0], d1 = PT[r][1] - PT[c][1], d2 = PT[r][2] - PT[c][2];
             const double s2d = d0 * d0 + d1 * d1 + d2 * d2;
@@ -317,12 +320,15 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     const int hi = lane >> 5;
     const int my_row = (lane & 31) + 1;
     const bool row_ok = my_row < M;
-    // h[q]: column 2q + hi of my row (Theta' until that column is done, then L)
+    // h[q]: column 2q + hi of my row (Theta' until that column is done, then L).
+    // Every lane loads a whole half row (lanes past the last row read row 0 and
+    // never use it); the odd half has one column fewer, so its last register
+    // repeats the slot before, keeping the read inside the row.
     double h[KMAX / 2 + 1];
     const double* my_th = &TH[row_ok ? my_row : 0][hi * HALF];
 #pragma unroll
-    for (int q = 0; q <= KMAX / 2; ++q) h[q] = (row_ok && 2 * q + hi <= KMAX) ? my_th[q] : 0.0;
-    const double diag = row_ok ? TH[my_row][DIAG] : 0.0;
+    for (int q = 0; q <= KMAX / 2; ++q) h[q] = my_th[q == KMAX / 2 ? q - hi : q];
+    const double diag = TH[row_ok ? my_row : 0][DIAG];
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
     __builtin_amdgcn_wave_barrier();
     // Left-looking by columns: with W[j][c] = d_c L[j][c] (row j of TH, written
