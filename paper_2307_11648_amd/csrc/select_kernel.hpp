@@ -373,14 +373,15 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         // accumulating its sum from the rows left in TH.
         const int l = nsel;
         const int my_pos = lane <= KMAX ? (lane & 1) * HALF + (lane >> 1) : 0;
-        double acc = 0.0, z = 0.0;
+        double acc = 0.0;
 #pragma unroll
         for (int c = KMAX; c >= 0; --c) {
             if (c > l) continue;
             const double zc = c == l ? 1.0 : bcast(-acc * dinv, c);
-            if (lane == c) z = zc;
             if (lane < c) acc = fma(TH[c][my_pos], zc, acc);
         }
+        // lane c's sum was complete at its own step and untouched after it
+        const double z = lane == l ? 1.0 : (lane < l ? -acc * dinv : 0.0);
         y = z * rsq64(dlast);
         if (p.logcv && lane == 0) p.logcv[col] = log(dlast);
     } else {
