@@ -388,12 +388,12 @@ def _source_digest(*names):
 # null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,308 - 524,316 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "10ac10f17846d92b"): (5420349 * 1.9999 + 398463) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "10ac10f17846d92b"): (540686 * 1.9999 + 471978) * 1024,
-    ("screen_kernel", "spatial", "049ffbb9f5d9bd83"): (2160851 * 1.9999 + 565050) * 1024,
+    ("select_factor_kernel (kept pools)", "natural", "d85905b3a928b8a5"): (5419792 * 1.9999 + 398462) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "d85905b3a928b8a5"): (540729 * 1.9999 + 471979) * 1024,
+    ("screen_kernel", "spatial", "5b7a6ca795fbd16e"): (2172896 * 1.9999 + 565030) * 1024,
     # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
-    ("select_factor_kernel (plain batched)", "natural", "10ac10f17846d92b"): (63148 * 1.9999 + 39844) * 1024,
-    ("select_factor_kernel (plain batched)", "spatial", "10ac10f17846d92b"): (73622 * 1.9999 + 47857) * 1024,
+    ("select_factor_kernel (plain batched)", "natural", "d85905b3a928b8a5"): (63142 * 1.9999 + 39844) * 1024,
+    ("select_factor_kernel (plain batched)", "spatial", "d85905b3a928b8a5"): (73567 * 1.9999 + 47751) * 1024,
 }
 
 

@@ -41,6 +41,9 @@ constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
 constexpr int kDppRowRor4 = 0x124;  // row_ror:4
 constexpr int kDppRowRor8 = 0x128;  // row_ror:8
+// gfx9-family broadcasts across rows (rows not in the row mask keep `old`)
+constexpr int kDppRowBcast15 = 0x142;  // row r + 1 reads lane 15 of row r
+constexpr int kDppRowBcast31 = 0x143;  // rows 2 and 3 read lane 31
 
 template <int CTRL>
 __device__ __forceinline__ uint64_t dpp64(uint64_t v) {
@@ -89,7 +92,9 @@ __device__ __forceinline__ Top2 wave_top2(Top2 v) {
 }
 
 // Wave-wide max of a 32-bit key (uniform result): DPP inside each row of 16
-// lanes, readlane across the rows.
+// lanes, then DPP broadcasts across rows -- rows 1 and 3 take the last lane of
+// the row before, rows 2 and 3 take lane 31 -- so lane 63 holds the maximum.
+// Rows outside a broadcast's row mask see 0, the identity of the maximum.
 template <int CTRL>
 __device__ __forceinline__ uint32_t dpp32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, 0xF, 0xF, false);
@@ -99,9 +104,9 @@ __device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
     v = max(v, dpp32<kDppQuadXor2>(v));
     v = max(v, dpp32<kDppRowRor4>(v));
     v = max(v, dpp32<kDppRowRor8>(v));
-    const uint32_t a = (uint32_t)__builtin_amdgcn_readlane((int)v, 0), b = (uint32_t)__builtin_amdgcn_readlane((int)v, 16);
-    const uint32_t c = (uint32_t)__builtin_amdgcn_readlane((int)v, 32), d = (uint32_t)__builtin_amdgcn_readlane((int)v, 48);
-    return max(max(a, b), max(c, d));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast15, 0xA, 0xF, false));
+    v = max(v, (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, kDppRowBcast31, 0xC, 0xF, false));
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 // Wave-wide max of a 64-bit key (uniform result).

@@ -462,25 +462,27 @@ __global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kerne
             // nearest-eight terms, neighbour outermost: squared distance to the
             // nearest other of slots 0..7 (f6) and the count of closer ones inside
             // the cos > 0.7 cone (f7, tested as d.d_l > 0.7 r_s max(r_l, tiny))
-            float best2[RPL], cnt[RPL];
+            float best2[RPL];
+            int cnt[RPL];
 #pragma unroll
             for (int rr = 0; rr < RPL; ++rr) {
                 best2[rr] = INFINITY;
-                cnt[rr] = 0.0f;
+                cnt[rr] = 0;
             }
             for (int l = 0; l < nnear; ++l) {
                 const float4 nl = sh_nb[wib][l];
                 const float cone = 0.7f * fmaxf(nl.w, kc.tiny);
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
-                    const int s = ch * CH + rr * 64 + lane;
                     const float e0 = d[rr][0] - nl.x, e1 = d[rr][1] - nl.y, e2 = d[rr][2] - nl.z;
                     const float e2s = e0 * e0 + e1 * e1 + e2 * e2;
                     const float dl = d[rr][0] * nl.x + d[rr][1] * nl.y + d[rr][2] * nl.z;
-                    const bool other = s != l;
+                    // slot ch * CH + rr * 64 + lane is neighbour l (< 8) itself
+                    // only in row 0 of chunk 0
+                    const bool other = rr > 0 || ch > 0 || lane != l;
                     best2[rr] = other ? fminf(best2[rr], e2s) : best2[rr];
                     const float rsv = fmaxf(r[rr], kc.tiny);
-                    cnt[rr] += (other && nl.w < r[rr] && dl > rsv * cone) ? 1.0f : 0.0f;
+                    cnt[rr] += (other && nl.w < r[rr] && dl > rsv * cone) ? 1 : 0;
                 }
             }
             // features -> LDS (bf16), optionally -> global (fp32)
@@ -492,7 +494,7 @@ __global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kerne
                 candidate_features(p, kc, s, d[rr], r[rr], d0, f);
                 const float rsv = fmaxf(r[rr], kc.tiny);
                 f[6] = best2[rr] < INFINITY ? __builtin_amdgcn_sqrtf(best2[rr]) * frcp(rsv) : 0.0f;
-                f[7] = cnt[rr] * 0.125f;
+                f[7] = (float)cnt[rr] * 0.125f;
                 // rows of slots >= C hold finite values (of the target's own
                 // offset); the MLP keeps candidates apart (one B column each)
                 // and their logits are never read
