@@ -373,12 +373,18 @@ def cpu_baseline_screened(w, k, keep, fbt, p_np, seconds):
 
 
 def _source_digest(*names):
+    """Digest of the named sources and of the compiler flags of the units
+    built from them (a flag change alters the kernel as much as an edit)."""
     import hashlib
+
+    from paper_2307_11648_amd import build
 
     h = hashlib.sha256()
     for n in names:
         with open(os.path.join(ROOT, "paper_2307_11648_amd", "csrc", n), "rb") as f:
             h.update(f.read())
+        h.update(repr(sorted(repr(d) for src, d in build.HIP_UNITS if src == n)).encode())
+    h.update(repr(build.HIPCC_FLAGS).encode())
     return h.hexdigest()[:16]
 
 
@@ -388,12 +394,12 @@ def _source_digest(*names):
 # null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,308 - 524,316 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "d85905b3a928b8a5"): (5419792 * 1.9999 + 398462) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "d85905b3a928b8a5"): (540729 * 1.9999 + 471979) * 1024,
-    ("screen_kernel", "spatial", "5b7a6ca795fbd16e"): (2172896 * 1.9999 + 565030) * 1024,
+    ("select_factor_kernel (kept pools)", "natural", "399c5b7240a425c3"): (5418899 * 1.9999 + 398462) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "399c5b7240a425c3"): (540679 * 1.9999 + 471983) * 1024,
+    ("screen_kernel", "spatial", "95eec300ad84d5cd"): (2571307 * 1.9999 + 567927) * 1024,
     # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
-    ("select_factor_kernel (plain batched)", "natural", "d85905b3a928b8a5"): (63142 * 1.9999 + 39844) * 1024,
-    ("select_factor_kernel (plain batched)", "spatial", "d85905b3a928b8a5"): (73567 * 1.9999 + 47751) * 1024,
+    ("select_factor_kernel (plain batched)", "natural", "399c5b7240a425c3"): (63143 * 1.9999 + 39844) * 1024,
+    ("select_factor_kernel (plain batched)", "spatial", "399c5b7240a425c3"): (73595 * 1.9999 + 47877) * 1024,
 }
 
 

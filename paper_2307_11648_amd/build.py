@@ -41,8 +41,10 @@ HIP_UNITS = [("abi.cpp", []), ("select.hip", [])] + [
     for t in ("float", "double") for nu in (1, 3, 5) for g in (0, 1) for rpl in (1, 2, 4, 8)
 ] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip")] + [
     # the screen's ReLU/min/max need no NaN handling: plain v_max/v_min without
-    # the IEEE-mode quieting of their inputs
-    ("screen.hip", ["-mno-amdgpu-ieee", "-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1"]),
+    # the IEEE-mode quieting of their inputs; the max-ilp machine scheduler runs
+    # the column screen 1% faster (identical results)
+    ("screen.hip", ["-mno-amdgpu-ieee", "-fno-honor-nans", "-mllvm", "-amdgpu-mfma-vgpr-form=1",
+                    "-mllvm", "-amdgpu-sched-strategy=max-ilp"]),
 ]
 
 HIPCC_FLAGS = [
