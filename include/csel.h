@@ -73,7 +73,7 @@ const char *csel_last_error(void);
 /* ABI version, currently 1. */
 int32_t csel_version(void);
 
-/* Largest pool size and number of selections per column this build handles
+/* Largest pool size and number of selections per column the library handles
  * for csel_select_and_factor. */
 int32_t csel_max_pool(void);
 int32_t csel_max_select(void);
