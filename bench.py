@@ -394,12 +394,12 @@ def _source_digest(*names):
 # null.
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,308 - 524,316 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "399c5b7240a425c3"): (5418899 * 1.9999 + 398462) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "399c5b7240a425c3"): (540679 * 1.9999 + 471983) * 1024,
+    ("select_factor_kernel (kept pools)", "natural", "b927a454ec063414"): (5418899 * 1.9999 + 398462) * 1024,
+    ("select_factor_kernel (kept pools)", "spatial", "b927a454ec063414"): (540679 * 1.9999 + 471983) * 1024,
     ("screen_kernel", "spatial", "95eec300ad84d5cd"): (2571307 * 1.9999 + 567927) * 1024,
     # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
-    ("select_factor_kernel (plain batched)", "natural", "399c5b7240a425c3"): (63143 * 1.9999 + 39844) * 1024,
-    ("select_factor_kernel (plain batched)", "spatial", "399c5b7240a425c3"): (73595 * 1.9999 + 47877) * 1024,
+    ("select_factor_kernel (plain batched)", "natural", "b927a454ec063414"): (63143 * 1.9999 + 39844) * 1024,
+    ("select_factor_kernel (plain batched)", "spatial", "b927a454ec063414"): (73595 * 1.9999 + 47877) * 1024,
 }
 
 

@@ -16,13 +16,13 @@
 // The target's own factor row is never formed: its entry for pick t is
 // cov_winner / sqrt(var_winner), the quantity eq. cond_select defines.
 //
-// Factor column (eq. L_col): lanes 0..s-1 hold the selected points and lane s
+// Factor column (eq. L_col): rows 0..s-1 are the selected points and row s
 // the target.  Theta' = Theta over [selected..., target] is built in FP64
-// (its lower triangle spread over the lanes, staged in LDS; lane r then owns
-// row r), factored by a left-looking Cholesky that reads the finished rows of
-// R back from LDS as broadcasts, and L_{s,i} follows from one
-// back-substitution with the last unit vector: with Theta' = R R^T,
-// Theta'^{-1} e_last = R^{-T} e_last / R_ll.
+// (its lower triangle spread over the lanes, staged in LDS) and factored as
+// L D L^T, left-looking by columns, each row's dot products split over a lane
+// pair; L_{s,i} follows from one back-substitution with the last unit vector:
+// Theta'^{-1} e_last = L^{-T} e_last / d_last and e_last^T Theta'^{-1} e_last =
+// 1 / d_last, so the column is L^{-T} e_last / sqrt(d_last).
 //
 // Argmax keys: 64-bit (the FP64 score with the slot in its low mantissa bits)
 // for FP64 and for the top-two variant; the mixed-precision kernel without
