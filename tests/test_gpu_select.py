@@ -176,6 +176,20 @@ def test_status_codes():
         assert o["status"][0] == 1
         assert g["sel"][0, 0] == o["sel"][0, 0]
         np.testing.assert_allclose(g["factor"][0, :2], o["factor"][0, :2], rtol=1e-6)
+    # the target's own location in its pool, no nugget: the copy is picked first
+    # (score 1, the largest possible), and Theta' over [copy, ..., target] is
+    # singular -- its last pivot is exactly 0 -- so the column is not defined
+    # (status 2, all NaN), in the oracle's Cholesky and in the kernel's L D L^T
+    x3 = np.array([[0.2, 0.2], [0.2, 0.2], [0.6, 0.1], [0.9, 0.9]])
+    w3 = inputs.SingleTargetWorkload("twin", x3, np.zeros(4), inputs.Kernel(3, 0.3), np.array([0], np.int32),
+                                     np.array([[1, 2, -1, -1]], np.int32), np.array([2], np.int32), 2)
+    o3 = run_orc(w3, 2)
+    assert o3["status"][0] == 2 and o3["sel"][0, 0] == 1
+    for prec in ("fp64", "mixed"):
+        g3 = run_gpu(w3, 2, prec)
+        assert g3["status"][0] == 2, (prec, g3["status"])
+        assert g3["sel"][0, 0] == 1
+        assert np.all(np.isnan(g3["factor"][0])) and np.isnan(g3["log_condvar"][0])
     # out-of-range pool index and target: status 3, nothing read out of bounds
     w2 = inputs.SingleTargetWorkload("bad", x, np.zeros(4), inputs.Kernel(3, 0.3), np.array([0, 7, 1], np.int32),
                                      np.array([[1, 9, -1, -1], [1, 2, 3, -1], [2, 3, -1, -1]], np.int32),
