@@ -47,9 +47,22 @@ __global__ __launch_bounds__(256) void apply_lt_kernel(int64_t n, const int64_t*
     const bool active = col < n;
     if (active) {
         const int64_t b = col_ptr[col], e = col_ptr[col + 1];
-        for (int64_t p = b + sub; p < e; p += kApplyLanesPerCol) {
-            const int32_t r = row_idx[p];
-            if (r >= 0 && (int64_t)r < n) s += val[p] * x[r];
+        // three entries per lane in flight: the index and value loads of a
+        // chunk of 48 entries first, then their x gathers, so a column of up to
+        // 48 entries waits for two dependent memory round trips instead of six;
+        // the sum runs over the lane's entries in the same order as one at a time
+        for (int64_t p0 = b + sub; p0 < e; p0 += 3 * kApplyLanesPerCol) {
+            int32_t r[3];
+            double v[3];
+#pragma unroll
+            for (int u = 0; u < 3; ++u) {
+                const int64_t p = p0 + u * kApplyLanesPerCol;
+                r[u] = p < e ? row_idx[p] : -1;
+                v[u] = p < e ? val[p] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 3; ++u)
+                if (r[u] >= 0 && (int64_t)r[u] < n) s += v[u] * x[r[u]];
         }
     }
     s = row16_sum(s);
