@@ -9,8 +9,9 @@ precision.  The screen's MLP is first trained on the GPU (untimed set-up) on
 exact selections of a separate cloud.  One timed step = screen every column
 (features, BF16 MLP, top-128 and the fallback flag), exact greedy selection
 with the factor column (Sec. 3.1, eq. L_col) on the kept pools, and full-pool
-selection of the fallback columns; plain full-pool selection is timed the
-same way.  Inputs are resident in HBM before timing; ordering, pools and
+selection of the fallback columns (its launch sized by the fallback count,
+which the host reads while the kept pools' selection runs); plain full-pool
+selection is timed the same way.  Inputs are resident in HBM before timing; ordering, pools and
 training are set-up.
 
 Other workloads: plain (N = 100,000 uniform in [0,1]^3, Matern 5/2, pools of
@@ -458,19 +459,26 @@ def bench_screened(args):
     tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
     torch.cuda.synchronize()
 
+    count_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
+
     def screened_step(ev=None):
         # screen, exact selection on the kept pools, full-pool selection of the
-        # fallback columns (device-side list, no host synchronisation)
+        # fallback columns (device-side list).  The fallback count is copied to
+        # the host behind the screen and read while the kept-pool selection
+        # runs, so the fallback launch covers only the listed columns.
         if ev is not None:
             ev[0].record()
         csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr, order=order)
         if ev is not None:
             ev[1].record()
+        fev = screen_train.fallback_grid(scr, count_host)
         tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
         if ev is not None:
             ev[2].record()
-        csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, scr["fallback_list"],
-                                    scr["fallback_count"], T, scr_out)
+        max_cols = screen_train.fallback_max_cols(fev, count_host, T)
+        if max_cols > 0:
+            csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, scr["fallback_list"],
+                                        scr["fallback_count"], max_cols, scr_out)
         if ev is not None:
             ev[3].record()
 

@@ -86,22 +86,52 @@ def mean_loss(p, pb, X, y, chunk: int = 1 << 20) -> float:
     return tot / X.shape[0]
 
 
+def fallback_grid(scr, count_host):
+    """Start the copy of the screen's fallback count into `count_host` (a
+    pinned int32 host tensor of one element) on the current stream, and return
+    the event that marks it done.  Record it right after the screen."""
+    count_host.copy_(scr["fallback_count"], non_blocking=True)
+    ev = torch.cuda.Event()
+    ev.record()
+    return ev
+
+
+def fallback_max_cols(ev, count_host, n_targets: int) -> int:
+    """The list capacity for the fallback launch: the screen's fallback count,
+    once the copy started by fallback_grid has landed (the host waits on that
+    event only; work queued behind it keeps the GPU busy), else every column."""
+    if ev is None:
+        return n_targets
+    ev.synchronize()
+    return max(0, min(int(count_host[0]), n_targets))
+
+
 def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep: int, precision: str = "mixed",
-                    fallback_threshold: float = 0.5, out=None, scr=None, order=None):
+                    fallback_threshold: float = 0.5, out=None, scr=None, order=None, count_host=None):
     """The screened hot path: screen, exact selection on the kept candidates,
-    exact selection on the full pool for the fallback columns (no host sync).
-    `order` is the screen's column processing order (csel.spatial_order): it
-    must list every column once, since the kept-pool selection runs on all of
-    them (checked here, which reads the order back)."""
+    exact selection on the full pool for the fallback columns (the fallback
+    list stays on the device).  `order` is the screen's column processing
+    order (csel.spatial_order): it must list every column once, since the
+    kept-pool selection runs on all of them (checked here, which reads the
+    order back).
+
+    With `count_host` (a pinned int32 host tensor of one element) the host
+    reads the fallback count while the kept-pool selection runs, and the
+    fallback launch covers that many list entries instead of one per column:
+    the same work without dispatching a grid for every column."""
     if order is not None:
         from .autotune import check_permutation
 
         check_permutation(order, targets.shape[0])
+    T = targets.shape[0]
     scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr,
                       order=order)
+    ev = fallback_grid(scr, count_host) if count_host is not None else None
     out = csel.select_and_factor(points, kernel, targets, scr["kept"], scr["kept_len"], k, precision, out=out)
-    csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, scr["fallback_list"],
-                                scr["fallback_count"], targets.shape[0], out)
+    max_cols = fallback_max_cols(ev, count_host, T)
+    if max_cols > 0:
+        csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, scr["fallback_list"],
+                                    scr["fallback_count"], max_cols, out)
     return out, scr
 
 

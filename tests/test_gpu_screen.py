@@ -171,6 +171,33 @@ def test_screened_selection_parity(clustered):
     assert rep["identical"] >= 0.97 * rep["columns"]
 
 
+@pytest.mark.parametrize("thr", [0.6, 1e30])
+def test_screened_select_with_host_count_matches(clustered, thr):
+    """The screened pipeline that reads the fallback count on the host (while
+    the kept-pool selection runs) and sizes the fallback launch by it writes
+    exactly what the pipeline with a launch over every column writes, with
+    fallback columns and with none (the launch is then skipped); replayed
+    three times into the same buffers."""
+    print(f"case: screened select, fallback launch sized by the host-read count, threshold {thr}", flush=True)
+    w, d = clustered
+    p, pb = _rand_params(37)
+    args = (d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], 32, p, pb, 128)
+    ref, scr = screen_train.screened_select(*args, precision="mixed", fallback_threshold=thr)
+    torch.cuda.synchronize()
+    nfb = int(scr["fallback_count"].item())
+    assert (nfb > 0) == (thr < 1.0)
+    ref = {key: v.cpu().numpy() for key, v in ref.items()}
+    count_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    out = None
+    for _ in range(3):
+        out, _ = screen_train.screened_select(*args, precision="mixed", fallback_threshold=thr, out=out,
+                                              count_host=count_host)
+        torch.cuda.synchronize()
+        assert int(count_host[0]) == nfb
+        for key in ("sel", "factor", "log_condvar", "status"):
+            assert np.array_equal(out[key].cpu().numpy(), ref[key], equal_nan=True), key
+
+
 def test_trained_screen_gains(tmp_path):
     """Train on a separate cloud of the same distribution (labels from exact
     greedy selections), then screen 512-candidate pools to 128 on a test cloud:
