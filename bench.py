@@ -471,7 +471,7 @@ def bench_screened(args):
         csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr, order=order)
         if ev is not None:
             ev[1].record()
-        fev = screen_train.fallback_grid(scr, count_host)
+        fev = screen_train.start_fallback_count_copy(scr, count_host)
         tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
         if ev is not None:
             ev[2].record()

@@ -86,7 +86,7 @@ def mean_loss(p, pb, X, y, chunk: int = 1 << 20) -> float:
     return tot / X.shape[0]
 
 
-def fallback_grid(scr, count_host):
+def start_fallback_count_copy(scr, count_host):
     """Start the copy of the screen's fallback count into `count_host` (a
     pinned int32 host tensor of one element) on the current stream, and return
     the event that marks it done.  Record it right after the screen."""
@@ -98,8 +98,9 @@ def fallback_grid(scr, count_host):
 
 def fallback_max_cols(ev, count_host, n_targets: int) -> int:
     """The list capacity for the fallback launch: the screen's fallback count,
-    once the copy started by fallback_grid has landed (the host waits on that
-    event only; work queued behind it keeps the GPU busy), else every column."""
+    once the copy started by start_fallback_count_copy has landed (the host
+    waits on that event only; work queued behind it keeps the GPU busy), else
+    every column."""
     if ev is None:
         return n_targets
     ev.synchronize()
@@ -126,7 +127,7 @@ def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep
     T = targets.shape[0]
     scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr,
                       order=order)
-    ev = fallback_grid(scr, count_host) if count_host is not None else None
+    ev = start_fallback_count_copy(scr, count_host) if count_host is not None else None
     out = csel.select_and_factor(points, kernel, targets, scr["kept"], scr["kept_len"], k, precision, out=out)
     max_cols = fallback_max_cols(ev, count_host, T)
     if max_cols > 0:
