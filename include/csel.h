@@ -151,6 +151,8 @@ int32_t csel_aggregated_max_block(void);
  * prior).
  *
  *   members      [sum m] int32 target ids, ascending within each group
+ *                (with factor output, a group whose members are not strictly
+ *                ascending gets status 3)
  *   group_ptr    [n_groups+1] int32 CSR offsets, 1 <= m_g <= max_members
  *   max_members  bound on every m_g (groups above it get status 3)
  *   pool_idx     [n_groups][pool_stride] int32 candidate ids, pool_len [n_groups]
@@ -295,8 +297,10 @@ int csel_screen_features(const double *pts, int64_t n, int32_t dim, const csel_k
  * slice of it; results do not depend on the order.  A column absent from it
  * is not processed (its outputs are left as they were); entries outside
  * [0, n_targets) are skipped; a column listed twice is processed twice (its
- * fallback index is then appended twice).  With order NULL, n_order is
- * ignored and 0, 1, ..., n_targets - 1 are processed.
+ * fallback index is then appended twice).  n_order <= n_targets
+ * (CSEL_EINVAL otherwise), so the fallback list -- n_targets entries -- never
+ * receives more than it holds.  With order NULL, n_order is ignored and 0, 1,
+ * ..., n_targets - 1 are processed.
  */
 int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_targets,
                 const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride,
@@ -326,10 +330,10 @@ int csel_screen(const double *pts, int64_t n, int32_t dim, const csel_kernel *ke
  *   MLP        as in csel_screen (same parameter layout; trained on group
  *              selections)
  *   keep, kept_idx [n_groups][keep], kept_len, fallback
- *              the `keep` largest logits ranked by their order-preserving
- *              32-bit image with the low 11 bits replaced by (2047 - slot),
- *              kept in slot order, -1 padded; fallback 1 when the dropped
- *              candidates' summed sigmoid(logit) exceeds fallback_threshold,
+ *              the `keep` largest logits (equal logits: the smaller slot
+ *              first), kept in slot order, -1 padded; fallback 1 when the
+ *              dropped candidates' summed sigmoid(logit) exceeds
+ *              fallback_threshold,
  *              3 for a bad group (member range or id, pool length or id out
  *              of range; kept_len 0; a caller re-selects it on its full pool
  *              like a fallback group, where csel_aggregated_select reports it)

@@ -54,6 +54,10 @@ def _load():
                                                                       _c.c_int32, _i32p, _f64p, _f64p, _f64p, _u8p,
                                                                       _c.c_int32]
     lib.orc_select_and_factor.restype = None
+    lib.orc_select_and_factor_diag.argtypes = [_f64p, _c.c_int32] + kern + [_c.c_int64, _i32p, _i32p, _i32p,
+                                                                           _c.c_int32, _c.c_int32, _i32p, _f64p,
+                                                                           _f64p, _f64p, _u8p, _f64p, _c.c_int32]
+    lib.orc_select_and_factor_diag.restype = None
     lib.orc_replay_one.argtypes = [_f64p, _c.c_int32] + kern + [_c.c_int32, _i32p, _c.c_int32, _c.c_int32, _i32p,
                                                                _f64p, _f64p, _f64p, _f64p]
     lib.orc_replay_one.restype = _c.c_int
@@ -170,6 +174,29 @@ def select_and_factor(x, kernel, targets, pool, pool_len, k: int, nthreads: int 
                                   _p(pool, _i32p), _p(pool_len, _i32p), stride, k, _p(sel, _i32p), _p(gap, _f64p),
                                   _p(fac, _f64p), _p(lcv, _f64p), _p(st, _u8p), int(nthreads))
     return {"sel": sel, "gap": gap, "factor": fac, "log_condvar": lcv, "status": st}
+
+
+def select_and_factor_diag(x, kernel, targets, pool, pool_len, k: int, nthreads: int = 0) -> dict:
+    """select_and_factor plus, per column and step, the tracked FP64 state of
+    the two best candidates before the pick: diag [T, k, 4] = (var, cov) of
+    the best, (var, cov) of the second best (NaN where there is none)."""
+    x = _pts(x)
+    targets = np.ascontiguousarray(targets, dtype=np.int32)
+    pool = np.ascontiguousarray(pool, dtype=np.int32)
+    pool_len = np.ascontiguousarray(pool_len, dtype=np.int32)
+    T = len(targets)
+    stride = pool.shape[1] if pool.ndim == 2 else 0
+    sel = np.empty((T, k), np.int32)
+    gap = np.empty((T, k), np.float64)
+    fac = np.empty((T, k + 1), np.float64)
+    lcv = np.empty(T, np.float64)
+    st = np.empty(T, np.uint8)
+    diag = np.empty((T, max(k, 1), 4), np.float64)
+    _load().orc_select_and_factor_diag(_p(x, _f64p), x.shape[1], *_kargs(kernel), T, _p(targets, _i32p),
+                                       _p(pool, _i32p), _p(pool_len, _i32p), stride, k, _p(sel, _i32p),
+                                       _p(gap, _f64p), _p(fac, _f64p), _p(lcv, _f64p), _p(st, _u8p), _p(diag, _f64p),
+                                       int(nthreads))
+    return {"sel": sel, "gap": gap, "factor": fac, "log_condvar": lcv, "status": st, "diag": diag[:, :k]}
 
 
 # --------------------------------------------------------------------------

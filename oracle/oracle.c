@@ -129,9 +129,12 @@ static int lcol(const orc_cov *c, const int32_t *s, int m, double *vals, double 
  * run) instead of the argmax and records, in FP64, the best score over valid
  * candidates (best_out[t]) and the forced pick's score (pick_out[t]): a replay
  * of another run's selection under exact arithmetic. */
+/* When `diag` is given, step t records the tracked state of the two best
+ * candidates before the pick: diag[4t..4t+3] = var and cov of the best, var
+ * and cov of the second best (NaN when there is none). */
 static int select_column_impl(const orc_cov *c, int32_t i, const int32_t *pool, int32_t C, int32_t k, int32_t *sel,
                               double *gap, double *factor, double *logcv, double *var_out, double *cov_out,
-                              const int32_t *forced, double *best_out, double *pick_out) {
+                              const int32_t *forced, double *best_out, double *pick_out, double *diag) {
     int32_t R = C + 1;
     int32_t kk = k < C ? k : C;
     double *L = (double *)calloc((size_t)R * (kk > 0 ? kk : 1), sizeof(double));
@@ -155,14 +158,20 @@ static int select_column_impl(const orc_cov *c, int32_t i, const int32_t *pool, 
     int32_t t;
     for (t = 0; t < kk; ++t) {
         /* score every valid candidate: cov^2 / var (eq. obj_gp) */
-        int32_t best = -1, nvalid = 0;
+        int32_t best = -1, second = -1, nvalid = 0;
         double s1 = -INFINITY, s2 = -INFINITY;
         for (int32_t j = 0; j < C; ++j) {
             if (taken[j] || !(var[j] > 1e-12 * prior[j])) continue;
             ++nvalid;
             double sc = cov[j] * cov[j] / var[j];
-            if (sc > s1) { s2 = s1; s1 = sc; best = j; }
-            else if (sc > s2) s2 = sc;
+            if (sc > s1) { s2 = s1; second = best; s1 = sc; best = j; }
+            else if (sc > s2) { s2 = sc; second = j; }
+        }
+        if (diag) {
+            diag[4 * t + 0] = best >= 0 ? var[best] : NAN;
+            diag[4 * t + 1] = best >= 0 ? cov[best] : NAN;
+            diag[4 * t + 2] = second >= 0 ? var[second] : NAN;
+            diag[4 * t + 3] = second >= 0 ? cov[second] : NAN;
         }
         if (forced) {
             /* replay: take the given pick if it is a valid candidate */
@@ -211,7 +220,7 @@ static int select_column_impl(const orc_cov *c, int32_t i, const int32_t *pool, 
 
 int orc_select_column(const orc_cov *c, int32_t i, const int32_t *pool, int32_t C, int32_t k, int32_t *sel,
                       double *gap, double *factor, double *logcv, double *var_out, double *cov_out) {
-    return select_column_impl(c, i, pool, C, k, sel, gap, factor, logcv, var_out, cov_out, NULL, NULL, NULL);
+    return select_column_impl(c, i, pool, C, k, sel, gap, factor, logcv, var_out, cov_out, NULL, NULL, NULL, NULL);
 }
 
 /* Replay of a given selection sequence (see select_column_impl); the factor
@@ -225,7 +234,7 @@ int orc_replay_one(const double *x, int32_t d, int32_t two_nu, double ell, doubl
     double *gap = (double *)malloc(sizeof(double) * (k > 0 ? k : 1));
     for (int32_t t = 0; t < k; ++t) { best_out[t] = NAN; best_out[k + t] = NAN; pick_out[t] = NAN; }
     int st = select_column_impl(&c, target, pool, C, k, sel, gap, factor, logcv, NULL, NULL, forced, best_out,
-                                pick_out);
+                                pick_out, NULL);
     free(sel); free(gap);
     return st;
 }
@@ -242,6 +251,26 @@ void orc_select_and_factor(const double *x, int32_t d, int32_t two_nu, double el
     for (int64_t t = 0; t < n_targets; ++t) {
         status[t] = (uint8_t)orc_select_column(&c, targets[t], pool + t * stride, pool_len[t], k, sel + t * k,
                                                gap + t * k, factor + t * (k + 1), logcv + t, NULL, NULL);
+    }
+}
+
+/* Batched selection that also records, per step, the tracked state of the
+ * two best candidates (diag [n_targets][k][4], see select_column_impl). */
+void orc_select_and_factor_diag(const double *x, int32_t d, int32_t two_nu, double ell, double s2, double nugget,
+                                int64_t n_targets, const int32_t *targets, const int32_t *pool,
+                                const int32_t *pool_len, int32_t stride, int32_t k, int32_t *sel, double *gap,
+                                double *factor, double *logcv, uint8_t *status, double *diag, int32_t nthreads) {
+    orc_cov c = {x, d, two_nu, ell, s2, nugget};
+#ifdef _OPENMP
+    if (nthreads > 0) omp_set_num_threads(nthreads);
+#endif
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t t = 0; t < n_targets; ++t) {
+        double *dg = diag + t * 4 * (int64_t)k;
+        for (int64_t e = 0; e < 4 * (int64_t)k; ++e) dg[e] = NAN;
+        status[t] = (uint8_t)select_column_impl(&c, targets[t], pool + t * stride, pool_len[t], k, sel + t * k,
+                                                gap + t * k, factor + t * (k + 1), logcv + t, NULL, NULL, NULL, NULL,
+                                                NULL, dg);
     }
 }
 

@@ -224,27 +224,18 @@ def adam_step(p, g, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def rank_key(z, s, slot_bits=9):
-    """Ranking key of a candidate: the float32 logit compared at 2^-(23-slot_bits)
-    relative resolution (its order-preserving 32-bit image with the low
-    slot_bits bits cleared), ties to the smaller slot.  Column screens use 9
-    slot bits (pools up to 512), group screens 11 (pools up to 2048)."""
-    b = int(np.float32(z).view(np.uint32))
-    mono = (~b & 0xFFFFFFFF) if b & 0x80000000 else (b | 0x80000000)
-    mask = (1 << slot_bits) - 1
-    return ((mono & ~mask) & 0xFFFFFFFF, -s)
-
-
-def screen_keep(logits, pool_len, keep, fallback_threshold=0.5, slot_bits=9):
+def screen_keep(logits, pool_len, keep, fallback_threshold=0.5):
     """Kept slots (ascending) of one column (or group): the `keep` largest
-    logits by rank_key; and the fallback flag: the expected number of true
-    selections among the dropped candidates, sum sigmoid(logit), exceeds the
-    threshold."""
+    logits, equal logits ordered by the smaller slot; and the fallback flag:
+    the expected number of true selections among the dropped candidates,
+    sum sigmoid(logit), exceeds the threshold.  The rule is the plain
+    definition, with no quantisation of the logits: two logits are equal only
+    when their values are (so -0.0 equals +0.0)."""
     z = np.asarray(logits[:pool_len], np.float64)
     C = len(z)
     if C <= keep:
         return np.arange(C), False
-    order = sorted(range(C), key=lambda s: rank_key(z[s], s, slot_bits), reverse=True)
+    order = sorted(range(C), key=lambda s: (-z[s], s))
     kept = np.sort(np.array(order[:keep]))
     dropped = np.array(order[keep:])
     fb = float(np.sum(1.0 / (1.0 + np.exp(-z[dropped])))) > fallback_threshold

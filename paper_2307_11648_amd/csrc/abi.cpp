@@ -387,8 +387,10 @@ CSEL_API int csel_screen(const double* pts, int64_t n, int32_t dim, const csel_k
     a.fallback = fallback;
     a.fb_list = fallback_list;
     a.fb_count = fallback_count;
-    if (order && (n_order < 0 || n_order > INT32_MAX))
-        return fail(CSEL_EINVAL, "n_order must be in [0, 2^31) (got %lld)", (long long)n_order);
+    // each processed position appends at most one entry to the fallback list,
+    // which holds n_targets entries
+    if (order && (n_order < 0 || n_order > n_targets))
+        return fail(CSEL_EINVAL, "n_order must be in [0, n_targets] (got %lld)", (long long)n_order);
     a.order = order;
     a.n_order = order ? n_order : n_targets;
     if (fallback_count) {

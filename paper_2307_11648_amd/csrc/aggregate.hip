@@ -104,8 +104,14 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
         }
         // later-only check needs the largest member id: members are few, every
         // thread scans them (uniform result)
+        // (the factor columns also need the members strictly ascending: a
+        // member's column length is counted from its rank)
         if (!bad && p.later_only) {
-            for (int q = 0; q < m; ++q) my_max_member = max(my_max_member, p.members[b0 + q]);
+            for (int q = 0; q < m; ++q) {
+                const int32_t v = p.members[b0 + q];
+                if (q > 0 && v <= my_max_member) bad = true;
+                my_max_member = max(my_max_member, v);
+            }
         }
         bool my_early = false;
         if (p.later_only) {
@@ -334,7 +340,12 @@ __global__ __launch_bounds__(kAggRegThreads, 1) void agg_select_reg_kernel(AggAr
                 bad = true;
             } else {
                 for (int c = 0; c < dim; ++c) ref[c] = p.pts[(int64_t)r0 * dim + c];
-                for (int q = 0; q < m; ++q) max_member = max(max_member, p.members[b0 + q]);
+                // factor columns need the members strictly ascending
+                for (int q = 0; q < m; ++q) {
+                    const int32_t v = p.members[b0 + q];
+                    if (p.later_only && q > 0 && v <= max_member) bad = true;
+                    max_member = max(max_member, v);
+                }
             }
         }
         bool my_bad = false, my_early = false;
@@ -683,11 +694,18 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
     for (int a = wave; a < m; a += nw) {
         const int32_t q = p.members[b0 + a];
         int pos = 0;
-        while (sg[pos] != q) ++pos;
+        while (pos < M && sg[pos] != q) ++pos;
         const int jr = M - 1 - pos;
         double* vals = p.fac_val + p.val_ptr[b0 + a];
         int32_t* rows = p.fac_rows + p.val_ptr[b0 + a];
         const int len = M - pos;
+        const int64_t budget = p.val_ptr[b0 + a + 1] - p.val_ptr[b0 + a];
+        if (pos >= M || len > budget) {
+            // members not strictly ascending (rejected by the selection kernels
+            // before this runs): write nothing outside the member's slots
+            if (lane == 0) p.status[g] = 3;
+            continue;
+        }
         if (bad_piv) {
             for (int l = lane; l < len; l += kWave) {
                 vals[l] = __builtin_nan("");
@@ -726,7 +744,6 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
         }
         if (lane == 0 && p.member_logcv) p.member_logcv[b0 + a] = -2.0 * log(dinv[jr]);
         // pad the member's slot range if fewer points were selected than budgeted
-        const int64_t budget = p.val_ptr[b0 + a + 1] - p.val_ptr[b0 + a];
         for (int64_t l = len + lane; l < budget; l += kWave) {
             vals[l] = 0.0;
             rows[l] = -1;

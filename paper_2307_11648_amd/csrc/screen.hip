@@ -271,6 +271,15 @@ struct ColumnConsts {
 
 __device__ __forceinline__ float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
 
+// Order-preserving 32-bit image of a finite float (a larger value gives a
+// larger key); -0 maps to the key of +0, so equal values give equal keys.
+// Every finite value maps to a key >= 2^23, so 0 is free to mark "none".
+__device__ __forceinline__ uint32_t mono_key(float z) {
+    uint32_t b = __float_as_uint(z);
+    if (b == 0x80000000u) b = 0u;
+    return (b & 0x80000000u) ? ~b : (b | 0x80000000u);
+}
+
 __device__ __forceinline__ void candidate_features(const ScreenArgs& p, const ColumnConsts& k, int s, const float d[3],
                                                    float r, const float d0[3], float f[kF]) {
     const float rs = fmaxf(r, k.tiny);
@@ -531,58 +540,66 @@ __global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kerne
             __builtin_amdgcn_wave_barrier();
         }
         if (p.mode == 1) continue;
-        // 32-bit keys: the monotone image of the logit with its low 9 bits replaced
-        // by (511 - slot): larger logit first (at 2^-14 relative resolution), then
-        // the smaller slot; 0 marks an empty slot.  Slot s = kk*64 + lane.
+        // 32-bit keys: the order-preserving image of the logit (equal logits,
+        // equal keys); 0 marks an empty slot.  Slot s = kk*64 + lane.
         uint32_t key[KPL];
         float zz[KPL];
 #pragma unroll
         for (int kk = 0; kk < KPL; ++kk) {
             const int s = kk * 64 + lane;
             zz[kk] = s < C ? sh_z[wib][s] : 0.0f;
-            const uint32_t b = __float_as_uint(zz[kk]);
-            const uint32_t mono = (b & 0x80000000u) ? ~b : (b | 0x80000000u);
-            key[kk] = s < C ? ((mono & ~0x1FFu) | (uint32_t)(511 - s)) : 0u;
+            key[kk] = s < C ? mono_key(zz[kk]) : 0u;
             if (p.logits && s < C) p.logits[col * p.stride + s] = zz[kk];
         }
         const int keep = p.keep;
-        uint32_t thr = 1u;  // kept = key >= thr
-        bool fb = false;
+        // kept = key > thr, plus the first `need` slots with key == thr
+        uint32_t thr = 0u;
+        int need = 0;
         if (C > keep) {
-            // bisection for the keep-th largest key (keys are distinct); it
-            // stops as soon as a midpoint has exactly `keep` keys at or above
-            // it, which selects the same set as the keep-th largest key itself
+            // bisection for the largest key value thr with at least `keep`
+            // keys at or above it; it stops early at a midpoint with exactly
+            // `keep` keys at or above it (that set is then the top `keep`)
             uint32_t lo = 0u, hi = 0xFFFFFFFFu;
+            int cnt_lo = C;
             while (lo < hi) {
                 const uint32_t mid = lo + (hi - lo) / 2u + 1u;
                 int cntk = 0;
 #pragma unroll
                 for (int kk = 0; kk < KPL; ++kk) cntk += __popcll(__ballot(key[kk] >= mid));
-                if (cntk == keep) {
+                if (cntk >= keep) {
                     lo = mid;
-                    break;
+                    cnt_lo = cntk;
+                    if (cntk == keep) break;
+                } else {
+                    hi = mid - 1u;
                 }
-                if (cntk > keep) lo = mid;
-                else hi = mid - 1u;
             }
             thr = lo;
-            float drop = 0.0f;
+            // keys equal to thr: as many as the top `keep` still needs
+            int cnt_eq = 0;
 #pragma unroll
-            for (int kk = 0; kk < KPL; ++kk)
-                if (key[kk] != 0u && key[kk] < thr) drop += frcp(1.0f + __expf(-zz[kk]));
-            for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
-            fb = drop > p.fb_thr;
+            for (int kk = 0; kk < KPL; ++kk) cnt_eq += __popcll(__ballot(key[kk] != 0u && key[kk] == thr));
+            need = keep - (cnt_lo - cnt_eq);
+        } else {
+            need = 0;  // every valid key (>= 1) exceeds thr = 0
         }
-        // kept candidates in slot order
-        int base = 0;
+        // kept candidates in slot order; ties at thr go to the smaller slot
+        int base = 0, tbase = 0;
+        float drop = 0.0f;
         const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
 #pragma unroll
         for (int kk = 0; kk < KPL; ++kk) {
-            const bool k = key[kk] != 0u && key[kk] >= thr;
+            const bool eq = key[kk] != 0u && key[kk] == thr;
+            const uint64_t me = __ballot(eq);
+            const bool k = key[kk] > thr || (eq && tbase + __popcll(me & below) < need);
+            tbase += __popcll(me);
             const uint64_t m = __ballot(k);
             if (k) p.kept[col * keep + base + __popcll(m & below)] = pid[kk];
             base += __popcll(m);
+            if (key[kk] != 0u && !k) drop += frcp(1.0f + __expf(-zz[kk]));
         }
+        for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+        const bool fb = C > keep && drop > p.fb_thr;
         for (int q = base + lane; q < keep; q += 64) p.kept[col * keep + q] = -1;
         if (lane == 0) {
             p.kept_len[col] = base;
@@ -866,7 +883,7 @@ hipError_t launch_screen(const ScreenArgs& a, int rpl, hipStream_t s) {
 // (distances to the members, FP32) of a chunk of 512 candidates -> LDS (BF16)
 // -> the same MLP as the column screen, each wave on its quarter of the
 // chunk's tiles -> logits in LDS; then a workgroup-wide bisection for the
-// keep-th largest key (11 slot bits) and the kept list in slot order.
+// keep-th largest logit (ties to the smaller slot) and the kept list in slot order.
 constexpr int kGrpThreads = 256;
 constexpr int kGrpWaves = kGrpThreads / 64;
 constexpr int kGrpChunk = 512;
@@ -1050,24 +1067,26 @@ __global__ __launch_bounds__(kGrpThreads) void screen_group_kernel(GroupScreenAr
         __syncthreads();
     }
     if (p.mode == 1) return;
-    // keys: the monotone image of the logit with its low 11 bits replaced by
-    // (2047 - slot); 0 marks an empty slot.  Slot s = tid + 256 i.
+    // keys: the order-preserving image of the logit (equal logits, equal
+    // keys); 0 marks an empty slot.  Slot s = tid + 256 i.
     uint32_t key[kGrpSlots];
     float zz[kGrpSlots];
 #pragma unroll
     for (int i = 0; i < kGrpSlots; ++i) {
         const int s = tid + kGrpThreads * i;
         zz[i] = s < C ? sh_z[s] : 0.0f;
-        const uint32_t bz = __float_as_uint(zz[i]);
-        const uint32_t mono = (bz & 0x80000000u) ? ~bz : (bz | 0x80000000u);
-        key[i] = s < C ? ((mono & ~0x7FFu) | (uint32_t)(2047 - s)) : 0u;
+        key[i] = s < C ? mono_key(zz[i]) : 0u;
         if (p.logits && s < C) p.logits[g * p.stride + s] = zz[i];
     }
     const int keep = p.keep;
-    uint32_t thr = 1u;
-    bool fb = false;
+    // kept = key > thr, plus the first `need` slots (in slot order) with key == thr
+    uint32_t thr = 0u;
+    int cnt_ge = 0;  // keys >= thr
     if (C > keep) {
+        // the largest thr with at least `keep` keys at or above it; stops early
+        // at a midpoint with exactly `keep` keys at or above it
         uint32_t lo = 0u, hi = 0xFFFFFFFFu;
+        cnt_ge = C;
         while (lo < hi) {
             const uint32_t mid = lo + (hi - lo) / 2u + 1u;
             int cw = 0;
@@ -1079,43 +1098,61 @@ __global__ __launch_bounds__(kGrpThreads) void screen_group_kernel(GroupScreenAr
 #pragma unroll
             for (int w = 0; w < kGrpWaves; ++w) cnt += sh_cnt[w];
             __syncthreads();
-            if (cnt == keep) {
+            if (cnt >= keep) {
                 lo = mid;
-                break;
+                cnt_ge = cnt;
+                if (cnt == keep) break;
+            } else {
+                hi = mid - 1u;
             }
-            if (cnt > keep) lo = mid;
-            else hi = mid - 1u;
         }
         thr = lo;
-        float drop = 0.0f;
-#pragma unroll
-        for (int i = 0; i < kGrpSlots; ++i)
-            if (key[i] != 0u && key[i] < thr) drop += frcp(1.0f + __expf(-zz[i]));
-        for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
-        if (lane == 0) sh_drop[wib] = drop;
-        __syncthreads();
-        float tot = 0.0f;
-#pragma unroll
-        for (int w = 0; w < kGrpWaves; ++w) tot += sh_drop[w];
-        fb = tot > p.fb_thr;
     }
-    // kept candidates in slot order: slot chunks (i, wave) hold slots
-    // 256 i + 64 w .. +63, so a chunk's offset counts the kept slots of every
-    // chunk before it in (i, w) order
+    // ties at thr: per slot chunk (i, wave) -- slots 256 i + 64 w .. +63 --
+    // the number of keys equal to thr, so a slot's rank among the ties in
+    // slot order is the count of every chunk before it plus the lanes below
     const uint64_t below = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+    uint64_t me[kGrpSlots];
+#pragma unroll
+    for (int i = 0; i < kGrpSlots; ++i) {
+        me[i] = __ballot(key[i] != 0u && key[i] == thr);
+        if (lane == 0) sh_cnt[i * kGrpWaves + wib] = __popcll(me[i]);
+    }
+    __syncthreads();
+    int cnt_eq = 0;
+    for (int c = 0; c < kGrpSlots * kGrpWaves; ++c) cnt_eq += sh_cnt[c];
+    const int need = C > keep ? keep - (cnt_ge - cnt_eq) : 0;
+    bool kp[kGrpSlots];
+    float drop = 0.0f;
+#pragma unroll
+    for (int i = 0; i < kGrpSlots; ++i) {
+        int rank = __popcll(me[i] & below);
+        for (int c = 0; c < i * kGrpWaves + wib; ++c) rank += sh_cnt[c];
+        kp[i] = key[i] > thr || (key[i] != 0u && key[i] == thr && rank < need);
+        if (key[i] != 0u && !kp[i]) drop += frcp(1.0f + __expf(-zz[i]));
+    }
+    for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+    __syncthreads();
+    if (lane == 0) sh_drop[wib] = drop;
+    // kept candidates in slot order: a chunk's offset counts the kept slots of
+    // every chunk before it in (i, w) order
     uint64_t mk[kGrpSlots];
 #pragma unroll
     for (int i = 0; i < kGrpSlots; ++i) {
-        mk[i] = __ballot(key[i] != 0u && key[i] >= thr);
+        mk[i] = __ballot(kp[i]);
         if (lane == 0) sh_cnt[i * kGrpWaves + wib] = __popcll(mk[i]);
     }
     __syncthreads();
+    float tot = 0.0f;
+#pragma unroll
+    for (int w = 0; w < kGrpWaves; ++w) tot += sh_drop[w];
+    const bool fb = C > keep && tot > p.fb_thr;
     int total = 0;
     for (int c = 0; c < kGrpSlots * kGrpWaves; ++c) total += sh_cnt[c];
 #pragma unroll
     for (int i = 0; i < kGrpSlots; ++i) {
         const int s = tid + kGrpThreads * i;
-        if (key[i] != 0u && key[i] >= thr) {
+        if (kp[i]) {
             int off = 0;
             for (int c = 0; c < i * kGrpWaves + wib; ++c) off += sh_cnt[c];
             p.kept[g * keep + off + __popcll(mk[i] & below)] = p.pool[g * p.stride + s];

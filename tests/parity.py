@@ -7,6 +7,8 @@ column; factor values are compared on columns whose whole selection agrees.
 """
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -91,3 +93,74 @@ def replay_check(gpu: dict, points, kernel, targets, pool, pool_len, k, cols, ta
         worst_fac = max(worst_fac, e)
         assert e <= factor_rtol, f"column {t}: factor error {e:.3e} on its own selected set"
     return worst_short, worst_fac
+
+
+# FP32 unit roundoff
+U32 = 2.0 ** -24
+
+
+def mixed_decisive_prefix(diag_row, prior: float, k: int) -> int:
+    """Number of leading steps of a column whose pick an FP32 evaluation and
+    GEMV (the mixed-precision kernel) cannot flip, by a first-order error
+    model of the FP64 oracle's own run on the same pool.
+
+    diag_row [k, 4]: per step, the tracked (var, cov) of the best and of the
+    second-best candidate (oracle.select_and_factor_diag).  The model:
+
+    * the FP32 column of pick s has an absolute error per row of at most
+      e_s = (s + 9) u32 prior / sqrt(var_pick_s): the evaluation (a few
+      roundings of a value <= prior), an s-term GEMV whose terms sum to at
+      most prior in magnitude (Cauchy-Schwarz on the factor rows), and the
+      scaling by the pick's 1/sqrt(var);
+    * a downdate adds u_s * (error of u_s) to a tracked variance or
+      covariance; as sum_s u_s^2 <= prior for every row (the downdates never
+      exceed the prior), Cauchy-Schwarz bounds the accumulated error by
+      sqrt(prior) * sqrt(sum_s e_s^2); with the initial FP32 covariances and
+      the target row's share this gives, for every tracked value,
+      E_t = 8 u32 prior + 4 sqrt(prior) sqrt(sum_{s<t} e_s^2);
+    * a score s = cov^2 / var then moves by at most s (E_t (2/|cov| + 1/var)
+      + 8 u32) (the last term: the FP32 score and its key).
+
+    A step is decisive when s1 - s2 exceeds twice the two scores' bounds; the
+    prefix ends at the first step that is not (there either pick is valid, and
+    the paths may part)."""
+    e2 = 0.0
+    for t in range(k):
+        v1, c1, v2, c2 = (float(a) for a in diag_row[t])
+        if not np.isfinite(v1):
+            return t  # no candidate: the run stopped
+        E = 8.0 * U32 * prior + 4.0 * math.sqrt(prior * e2)
+        if np.isfinite(v2):
+            s1 = c1 * c1 / v1
+            s2 = c2 * c2 / v2
+            d1 = s1 * (E * (2.0 / max(abs(c1), 1e-300) + 1.0 / v1) + 8.0 * U32)
+            d2 = s2 * (E * (2.0 / max(abs(c2), 1e-300) + 1.0 / v2) + 8.0 * U32)
+            if not (s1 - s2 > 2.0 * (d1 + d2)):
+                return t
+        e2 += ((t + 9) * U32 * prior / math.sqrt(v1)) ** 2
+    return k
+
+
+def mixed_decisive_check(gpu_sel, orc: dict, prior: float, k: int):
+    """Assert that the mixed GPU run picks exactly the oracle's candidates on
+    every step of each column's decisive prefix (mixed_decisive_prefix).
+    Returns (decisive steps, all steps, the largest oracle relative gap at a
+    step where the paths parted)."""
+    dec = tot = 0
+    worst_gap = 0.0
+    for t in range(len(gpu_sel)):
+        if orc["status"][t] >= 2:
+            continue
+        n = int(np.sum(orc["sel"][t] >= 0))
+        p = mixed_decisive_prefix(orc["diag"][t], prior, k)
+        p = min(p, n)
+        if not np.array_equal(gpu_sel[t, :p], orc["sel"][t, :p]):
+            s = int(np.where(gpu_sel[t, :p] != orc["sel"][t, :p])[0][0])
+            raise AssertionError(f"column {t}: mixed pick {s} differs on a decisive step (oracle gap "
+                                 f"{orc['gap'][t][s]:.3e})\n gpu {gpu_sel[t]}\n orc {orc['sel'][t]}")
+        dec += p
+        tot += n
+        diff = np.where(gpu_sel[t, :n] != orc["sel"][t, :n])[0]
+        if len(diff):
+            worst_gap = max(worst_gap, float(orc["gap"][t][diff[0]]))
+    return dec, tot, worst_gap

@@ -117,3 +117,21 @@ def test_transpose_factor_validation_without_gpu():
     assert lib.csel_transpose_factor(10, fake, None, fake, 5, fake, fake, fake, fake, 1 << 30, None) == -1
     assert lib.csel_transpose_factor(10, fake, fake, fake, 5, fake, fake, fake, None, 0, None) == -1
     assert b"workspace" in lib.csel_last_error()
+
+
+def test_screen_rejects_order_longer_than_the_fallback_list():
+    """Each processed order position may append one fallback entry, and the
+    list holds n_targets entries: an order longer than that is refused on the
+    host, before anything is enqueued."""
+    if not os.path.exists(csel.LIB_PATH):
+        pytest.skip("libcsel.so not built")
+    lib = csel.load()
+    kp = csel.KernelParams(3, 0.05, 1.0, 0.0)
+    fake = ctypes.c_void_p(16)  # never dereferenced: the call fails validation first
+
+    def call(n_order):
+        return lib.csel_screen(fake, 100, 3, ctypes.byref(kp), 5, fake, fake, fake, 64, fake, fake, 8, 0.5, fake,
+                               fake, fake, None, fake, fake, fake, n_order, None)
+
+    assert call(6) == -1 and b"n_order" in lib.csel_last_error()
+    assert call(-1) == -1 and b"n_order" in lib.csel_last_error()

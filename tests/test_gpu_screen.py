@@ -201,9 +201,9 @@ def test_screened_select_with_host_count_matches(clustered, thr):
 def test_trained_screen_gains(tmp_path):
     """Train on a separate cloud of the same distribution (labels from exact
     greedy selections), then screen 512-candidate pools to 128 on a test cloud:
-    the trained screen keeps the KL within 1% of full-pool selection, beats the
-    untrained network and random screening, and is reported against the
-    128-nearest screen.  KL is exact (dense log det on the GPU, FP64)."""
+    the trained screen keeps the KL within 1% of full-pool selection and beats
+    the untrained network, random screening and the 128-nearest screen.  KL is
+    exact (dense log det on the GPU, FP64)."""
     print("case: trained screen gain, n=12000", flush=True)
     n = 12000
     tr = inputs.workload_clustered(n=n, seed=40, C=512, k=32)
@@ -247,6 +247,8 @@ def test_trained_screen_gains(tmp_path):
     assert gaps["trained"] <= 0.01
     assert gaps["trained"] < gaps["untrained"]
     assert gaps["trained"] < gaps["random128"]
+    # the trained network beats the free truncation to the 128 nearest candidates
+    assert gaps["trained"] < gaps["nearest128"]
 
 
 @pytest.mark.parametrize("d,C,keep", [(1, 64, 16), (2, 128, 40), (3, 256, 128), (2, 512, 128)])

@@ -314,6 +314,54 @@ def test_multi_target_matches_brute_force_logdet(seed):
         np.testing.assert_allclose(r["var1_targets"], pv, rtol=1e-8)
 
 
+@pytest.mark.parametrize("seed", range(3))
+def test_multi_replay_reports_dense_scores(seed):
+    """The multi-target replay judges every mixed-precision aggregated and GP
+    run, so it is pinned to dense linear algebra, not to itself: for a forced
+    sequence of picks (the oracle's own, a swapped one and an arbitrary valid
+    one) each step's reported pick score is 1 - Theta_jj|I,T / Theta_jj|I and
+    its best score the largest such score over the unselected candidates, and
+    the log det and posterior variances after the sequence are the dense
+    Theta_TT|I."""
+    x = _rand_points(40, 2, 70 + seed)
+    kern = inputs.Kernel(5, 0.3)
+    th = oracle.covariance(x, kern)
+    T = np.array([0, 1, 2][: 1 + seed], np.int32)
+    rng = np.random.default_rng(seed)
+    pool = rng.choice(np.arange(4, 40), size=16, replace=False).astype(np.int32)
+    k = 6
+    own = oracle.multi_one(x, kern, T, pool, k)["sel"]
+    swapped = own.copy()
+    swapped[0], swapped[2] = swapped[2], swapped[0]
+    arbitrary = rng.choice(pool, size=k, replace=False).astype(np.int32)
+
+    def dense_score(S, j):
+        v1 = _cond_var(th, j, S)
+        v2 = _cond_var(th, j, list(S) + list(T))
+        return max(0.0, 1.0 - v2 / v1)
+
+    for forced in (own, swapped, arbitrary):
+        r = oracle.multi_replay_one(x, kern, T, pool, k, forced)
+        assert r["status"] == 0
+        S = []
+        for t in range(k):
+            j = int(forced[t])
+            assert r["pick"][t] == pytest.approx(dense_score(S, j), rel=1e-9, abs=1e-12)
+            best = max(dense_score(S, int(c)) for c in pool if int(c) not in S)
+            assert r["best"][t] == pytest.approx(best, rel=1e-9, abs=1e-12)
+            S.append(j)
+        cc = _cond_cov(th, T, S)
+        assert r["logdet"] == pytest.approx(np.linalg.slogdet(cc)[1], rel=1e-9, abs=1e-9)
+        np.testing.assert_allclose(r["post_var"], np.diag(cc), rtol=1e-8)
+    # the oracle's own picks are the greedy ones; the swapped first pick is worse
+    r = oracle.multi_replay_one(x, kern, T, pool, k, swapped)
+    assert r["pick"][0] < r["best"][0]
+    # a pick outside the pool is refused
+    bad = own.copy()
+    bad[1] = 3
+    assert oracle.multi_replay_one(x, kern, T, pool, k, bad)["status"] == 5
+
+
 def test_multi_target_single_member_equals_single_target():
     """m = 1: the D-optimal score 1 - var2/var1 is the squared conditional
     correlation, whose argmax is the single-target argmax (eq. global_obj)."""

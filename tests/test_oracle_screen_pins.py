@@ -68,6 +68,63 @@ def test_adam_matches_closed_form_first_step():
     np.testing.assert_allclose(p1, p - 0.01 * np.sign(g), rtol=1e-7)
 
 
+def test_adam_matches_torch_adam_over_several_steps():
+    """Six FP64 Adam steps with changing gradients against torch.optim.Adam:
+    past step 1 the bias corrections no longer cancel, so a wrong moment
+    update, bias correction or epsilon placement shows."""
+    rng = np.random.default_rng(11)
+    p = rng.standard_normal(7)
+    m = np.zeros(7)
+    v = np.zeros(7)
+    pt = torch.tensor(p.copy(), dtype=torch.float64, requires_grad=True)
+    opt = torch.optim.Adam([pt], lr=0.03, betas=(0.8, 0.95), eps=1e-3)
+    for step in range(1, 7):
+        g = rng.standard_normal(7) * (0.1 + step)
+        p, m, v = so.adam_step(p, g, m, v, step, lr=0.03, beta1=0.8, beta2=0.95, eps=1e-3)
+        opt.zero_grad()
+        pt.grad = torch.tensor(g, dtype=torch.float64)
+        opt.step()
+        np.testing.assert_allclose(p, pt.detach().numpy(), rtol=1e-13, atol=1e-15)
+
+
+def test_column_features_hand_worked():
+    """Target at the origin of the plane; candidates (sorted by distance) at
+    (1, 0), (0, 2), (2.5, 0) and (-3, 0); exponential kernel, l = 2, unit
+    variance.  Every feature worked out by hand."""
+    x = np.array([[0.0, 0.0], [1.0, 0.0], [0.0, 2.0], [2.5, 0.0], [-3.0, 0.0]])
+    ker = inputs.Kernel(1, 2.0)
+    f = so.features(x, ker, 0, [1, 2, 3, 4])
+    rho = lambda r: math.exp(-r / 2.0)  # noqa: E731
+    r = [1.0, 2.0, 2.5, 3.0]
+    # distances between candidates: |p0 p1| = sqrt 5, |p0 p2| = 1.5, |p0 p3| = 4,
+    # |p1 p2| = sqrt 10.25, |p1 p3| = sqrt 13, |p2 p3| = 5.5
+    dj0 = [0.0, math.sqrt(5.0), 1.5, 4.0]
+    nearest_other = [1.5, math.sqrt(5.0), 1.5, math.sqrt(13.0)]
+    cos0 = [1.0, 0.0, 1.0, -1.0]
+    # closer candidates within the 0.7 cone: only p0 for p2 (same direction)
+    cone = [0, 0, 1, 0]
+    for s in range(4):
+        assert f[s, 0] == pytest.approx(math.log(r[s] / 1.0))
+        assert f[s, 1] == pytest.approx(s / 4)
+        assert f[s, 2] == pytest.approx(rho(r[s]))
+        assert f[s, 3] == pytest.approx(r[s] / 2.0)
+        assert f[s, 4] == pytest.approx(0.5)
+        assert f[s, 5] == pytest.approx(cos0[s], abs=1e-15)
+        assert f[s, 6] == pytest.approx(nearest_other[s] / r[s])
+        assert f[s, 7] == pytest.approx(cone[s] / 8)
+        assert f[s, 8] == pytest.approx(rho(dj0[s]))
+        if s == 0:
+            assert f[s, 9] == 1.0
+        else:
+            # after conditioning on p0: cov = rho(r) - rho(1) rho(dj0), var = 1 - rho(dj0)^2
+            cov1 = rho(r[s]) - rho(1.0) * rho(dj0[s])
+            var1 = 1.0 - rho(dj0[s]) ** 2
+            assert f[s, 9] == pytest.approx(cov1 * cov1 / var1)
+        assert f[s, 10] == (1.0 if s == 0 else 0.0)
+        assert f[s, 11] == pytest.approx(math.log1p(s) / math.log1p(4))
+    assert np.all(f[:, 12:] == 0.0)
+
+
 def test_step1_feature_equals_oracle_conditional_score():
     """f9 is the decrease of the target's variance that candidate j brings once
     the nearest candidate is selected: the oracle's tracked cov^2/var after one
@@ -207,15 +264,25 @@ def test_group_features_rigid_motion_invariant():
                                rtol=1e-9, atol=1e-12)
 
 
-def test_group_rank_key_uses_eleven_slot_bits():
-    """The low 11 bits of a logit's 32-bit image carry the slot: logits that
-    differ only there (below 2^-12 relative) tie and go to the smaller slot.
-    The column screen's 9 bits resolve 2^-14."""
-    z = np.array([1.0, 1.0 + 2.0 ** -14, 1.0 + 2.0 ** -8, 0.5], np.float32)
-    assert list(so.screen_keep(z, 4, 2, fallback_threshold=10.0, slot_bits=11)[0]) == [0, 2]
-    assert list(so.screen_keep(z, 4, 2, fallback_threshold=10.0, slot_bits=9)[0]) == [1, 2]
-    z2 = np.array([1.0, 1.0 + 2.0 ** -13, 0.1], np.float32)
-    assert list(so.screen_keep(z2, 3, 1, 10.0, slot_bits=9)[0]) == [1]
-    assert list(so.screen_keep(z2, 3, 1, 10.0, slot_bits=11)[0]) == [0]
-    z3 = np.array([1.0, 1.0 + 2.0 ** -11, 0.1], np.float32)
-    assert list(so.screen_keep(z3, 3, 1, 10.0, slot_bits=11)[0]) == [1]
+def test_screen_keep_is_exact_order_with_ties_to_smaller_slot():
+    """The keep rule is the plain definition: logits that differ in their last
+    bit are ordered by value, equal logits by slot, and -0 equals +0."""
+    from itertools import combinations
+
+    one_ulp = np.nextafter(np.float32(1.0), np.float32(2.0))
+    z = np.array([1.0, one_ulp, 0.5, 1.0], np.float32)
+    assert list(so.screen_keep(z, 4, 1, 10.0)[0]) == [1]
+    assert list(so.screen_keep(z, 4, 2, 10.0)[0]) == [0, 1]
+    assert list(so.screen_keep(z, 4, 3, 10.0)[0]) == [0, 1, 3]
+    z2 = np.array([-0.0, 0.0, -1.0, 0.0], np.float32)
+    assert list(so.screen_keep(z2, 4, 2, 10.0)[0]) == [0, 1]
+    assert list(so.screen_keep(z2, 4, 3, 10.0)[0]) == [0, 1, 3]
+    # brute force: of every subset of `keep` slots, the one whose sorted
+    # (-z, slot) list is smallest
+    rng = np.random.default_rng(5)
+    for _ in range(50):
+        C = int(rng.integers(2, 9))
+        zz = rng.integers(-2, 3, size=C).astype(np.float32) * np.float32(0.5)
+        keep = int(rng.integers(1, C))
+        best = min((sorted((-float(zz[s]), s) for s in sub), sub) for sub in combinations(range(C), keep))
+        assert list(so.screen_keep(zz, C, keep, 1e9)[0]) == list(best[1])
