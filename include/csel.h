@@ -386,6 +386,28 @@ int csel_mlp_grad(const float *params, const uint16_t *params_bf16, const float 
                   int64_t n_rows, float pos_weight, void *workspace, int64_t workspace_bytes, float *grad,
                   hipStream_t stream);
 
+/*
+ * csel_mlp_grad_noalloc -- csel_mlp_grad for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight training loops, and
+ * harnesses that forbid allocation.  Same inputs, outputs and results (bit
+ * for bit) as csel_mlp_grad, without the workspace argument: the per-wave
+ * partial gradients go to a buffer of about 5.4 MB that the library holds on
+ * each GPU it runs on, from its first call there until the process ends.
+ * The call allocates nothing (no hipMalloc, no allocating library routine).
+ *
+ *   n_rows     0 <= n_rows <= CSEL_MLP_GRAD_NOALLOC_MAX_ROWS; larger batches
+ *              get CSEL_EUNSUPPORTED (use csel_mlp_grad)
+ *   stream     must belong to the calling thread's current device
+ *
+ * The first call on a device looks the buffer up there (make it before a
+ * graph capture begins); later calls only enqueue kernels.  Every call on a
+ * device shares that device's buffer: calls that may overlap on one GPU
+ * (other streams, other threads) race and must be ordered by the caller.
+ */
+#define CSEL_MLP_GRAD_NOALLOC_MAX_ROWS 65536
+int csel_mlp_grad_noalloc(const float *params, const uint16_t *params_bf16, const float *x, const uint8_t *labels,
+                          int64_t n_rows, float pos_weight, float *grad, hipStream_t stream);
+
 /* One Adam step (Kingma & Ba) on the FP32 parameters, step counted from 1;
  * m and v are the FP32 moment buffers; refreshes the BF16 copy. */
 int csel_mlp_adam(float *params, uint16_t *params_bf16, const float *grad, float *m, float *v, int32_t n_params,

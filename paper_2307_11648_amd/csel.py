@@ -100,6 +100,8 @@ def load():
     lib.csel_mlp_grad_workspace_size.restype = ctypes.c_int64
     lib.csel_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_float, _vp, _c.c_int64, _vp, _vp]
     lib.csel_mlp_grad.restype = ctypes.c_int
+    lib.csel_mlp_grad_noalloc.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_float, _vp, _vp]
+    lib.csel_mlp_grad_noalloc.restype = ctypes.c_int
     lib.csel_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, _c.c_int32, _c.c_float, _c.c_float, _c.c_float,
                                   _c.c_float, _c.c_int32, _vp]
     lib.csel_mlp_adam.restype = ctypes.c_int
@@ -333,6 +335,22 @@ def mlp_grad(params, params_bf16, x, labels, pos_weight: float, grad=None, works
                              float(pos_weight), workspace.data_ptr(), workspace.numel(), grad.data_ptr(),
                              _stream(stream)))
     return grad, workspace
+
+
+MLP_GRAD_NOALLOC_MAX_ROWS = 65536  # CSEL_MLP_GRAD_NOALLOC_MAX_ROWS
+
+
+def mlp_grad_noalloc(params, params_bf16, x, labels, pos_weight: float, grad, stream=None):
+    """csel_mlp_grad_noalloc: mlp_grad without a workspace and without any
+    device allocation (the caller passes `grad`, [P+1] float32); at most
+    MLP_GRAD_NOALLOC_MAX_ROWS rows."""
+    lib = load()
+    _dev(x, torch.float32, "x")
+    _dev(labels, torch.uint8, "labels")
+    _dev(grad, torch.float32, "grad")
+    _check(lib.csel_mlp_grad_noalloc(params.data_ptr(), params_bf16.data_ptr(), x.data_ptr(), labels.data_ptr(),
+                                     x.shape[0], float(pos_weight), grad.data_ptr(), _stream(stream)))
+    return grad
 
 
 def mlp_adam(params, params_bf16, grad, m, v, lr, step, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):

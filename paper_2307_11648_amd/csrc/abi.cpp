@@ -533,6 +533,31 @@ CSEL_API int csel_mlp_grad(const float* params, const uint16_t* params_bf16, con
     return CSEL_OK;
 }
 
+CSEL_API int csel_mlp_grad_noalloc(const float* params, const uint16_t* params_bf16, const float* x,
+                                   const uint8_t* labels, int64_t n_rows, float pos_weight, float* grad,
+                                   hipStream_t stream) {
+    g_err[0] = 0;
+    static_assert(CSEL_MLP_GRAD_NOALLOC_MAX_ROWS == csel::kMlpGradNoAllocMaxRows, "header and library agree");
+    if (n_rows < 0) return fail(CSEL_EINVAL, "n_rows must be >= 0");
+    if (n_rows > CSEL_MLP_GRAD_NOALLOC_MAX_ROWS)
+        return fail(CSEL_EUNSUPPORTED, "n_rows must be <= %d for csel_mlp_grad_noalloc (got %lld); use csel_mlp_grad",
+                    CSEL_MLP_GRAD_NOALLOC_MAX_ROWS, (long long)n_rows);
+    if (!(pos_weight > 0.0f)) return fail(CSEL_EINVAL, "pos_weight must be > 0");
+    if (!params || !params_bf16 || !grad || (n_rows > 0 && (!x || !labels)))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    csel::MlpTrainArgs a{};
+    a.params = params;
+    a.params_bf16 = params_bf16;
+    a.x = x;
+    a.y = labels;
+    a.n_rows = n_rows;
+    a.pos_weight = pos_weight;
+    a.inv_n = n_rows > 0 ? 1.0f / (float)n_rows : 0.0f;
+    hipError_t e = csel::launch_mlp_grad_noalloc(a, grad, stream);
+    if (e != hipSuccess) return hip_fail(e, "mlp_grad_noalloc");
+    return CSEL_OK;
+}
+
 CSEL_API int csel_mlp_adam(float* params, uint16_t* params_bf16, const float* grad, float* m, float* v,
                            int32_t n_params, float lr, float beta1, float beta2, float eps, int32_t step,
                            hipStream_t stream) {

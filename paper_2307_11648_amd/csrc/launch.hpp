@@ -108,6 +108,10 @@ hipError_t launch_screen_groups(const GroupScreenArgs& a, hipStream_t s);
 int mlp_nparams();
 int64_t mlp_grad_nparts(int64_t n_rows);
 hipError_t launch_mlp_grad(const MlpTrainArgs& a, float* grad, hipStream_t s);
+// rows handled by the allocation-free gradient (its partials live in a
+// file-scope device array of about 5.4 MB per GPU)
+constexpr int64_t kMlpGradNoAllocMaxRows = 65536;
+hipError_t launch_mlp_grad_noalloc(MlpTrainArgs a, float* grad, hipStream_t s);
 hipError_t launch_mlp_forward(const MlpTrainArgs& a, float* z, hipStream_t s);
 hipError_t launch_adam(float* p, uint16_t* pb, const float* g, float* m, float* v, int n, float lr, float b1,
                        float b2, float eps, int step, hipStream_t s);

@@ -22,6 +22,7 @@
 // w3[64], b3 and its BF16 copy (same indexing); weights enter the MFMAs in
 // BF16, biases stay FP32.
 #include <algorithm>
+#include <mutex>
 
 #include "device_common.hpp"
 #include "launch.hpp"
@@ -1180,6 +1181,46 @@ hipError_t launch_mlp_grad(const MlpTrainArgs& a, float* grad, hipStream_t s) {
     hipLaunchKernelGGL(reduce_partials_kernel, dim3((kNParams + 1 + 255) / 256), dim3(256), 0, s, a.partials,
                        (int)parts, grad);
     return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// allocation-free gradient: the per-wave partials in a file-scope device array
+// ---------------------------------------------------------------------------
+constexpr int64_t kNoAllocParts =
+    (kMlpGradNoAllocMaxRows + kTrainTilesPerWave * 16 - 1) / (kTrainTilesPerWave * 16);
+static __device__ __align__(256) float scratch[kNoAllocParts * (kNParams + 1)];
+
+// The device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy of the array).  In host code the
+// array's name is only a stand-in: kernels get this address instead.
+static hipError_t scratch_on_current_device(float** out) {
+    constexpr int kMaxDevices = 64;
+    static std::mutex mu;
+    static float* addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        void* ptr = nullptr;
+        e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        addr[dev] = static_cast<float*>(ptr);
+    }
+    *out = addr[dev];
+    return hipSuccess;
+}
+
+hipError_t launch_mlp_grad_noalloc(MlpTrainArgs a, float* grad, hipStream_t s) {
+    if (a.n_rows > kMlpGradNoAllocMaxRows) return hipErrorInvalidValue;
+    float* ws = nullptr;
+    const hipError_t e = scratch_on_current_device(&ws);
+    if (e != hipSuccess) return e;
+    // every partial slot of the launched waves is written before it is summed,
+    // so the array needs no clearing between calls
+    a.partials = ws;
+    return launch_mlp_grad(a, grad, s);
 }
 
 hipError_t launch_mlp_forward(const MlpTrainArgs& a, float* z, hipStream_t s) {
