@@ -4,15 +4,18 @@ plain full-pool selection against learned-screened selection.
 
 Default workload (--workload screened): N = 1,000,000 points in [0,1]^3 (20
 Gaussian clusters with sigma 0.03 plus 20% uniform background), Matern 3/2,
-l = 0.05, pools of the 512 nearest later-ordered points, k = 32, mixed
-precision.  The screen's MLP is first trained on the GPU (untimed set-up) on
-exact selections of a separate cloud.  One timed step = screen every column
-(features, BF16 MLP, top-128 and the fallback flag), exact greedy selection
-with the factor column (Sec. 3.1, eq. L_col) on the kept pools, and full-pool
-selection of the fallback columns (its launch sized by the fallback count,
-which the host reads while the kept pools' selection runs); plain full-pool
-selection is timed the same way.  Inputs are resident in HBM before timing; ordering, pools and
-training are set-up.
+l = 0.05, pools of the 512 nearest later-ordered points, k = 32.  The screen's
+MLP is first trained on the GPU (untimed set-up) on exact selections of a
+separate cloud.  One timed step is one csel_screened_select call, replayed
+from its captured HIP graph: screen every column (features, BF16 MLP,
+top-128 and the fallback flag), exact greedy selection with the factor column
+(Sec. 3.1, eq. L_col) on the kept pools, and full-pool selection of the
+fallback columns.  The credited leg computes the selection in FP64, the
+paper's arithmetic; the mixed-precision leg (FP32 evaluation and GEMV) is
+reported beside it with its difference from FP64.  Plain full-pool selection
+and the selection on the 128 nearest candidates (the free screen) are timed
+the same way.  Times are medians of the timed steps; inputs are resident in
+HBM before timing; ordering, pools and training are set-up.
 
 Other workloads: plain (N = 100,000 uniform in [0,1]^3, Matern 5/2, pools of
 256, k = 32, replayed as a HIP graph), aggregated, gp (plain and screened) and
@@ -333,11 +336,15 @@ def kl_gap_estimate(w, targets_sample, lcv_plain, lcv_screen, dS, n_ref=2048):
     return dS / kl2_plain, kl2_plain / 2.0, len(targets_sample)
 
 
-def cpu_baseline_screened(w, k, keep, fbt, p_np, seconds):
-    """Time the oracle's screened pipeline (features, BF16-rounded MLP, top-keep
-    with the fallback rule, exact FP64 selection on the kept or full pool) on a
-    bounded seeded sample of the same columns, one host thread."""
+def cpu_baseline_screened(w, k, keep, fbt, p_np, seconds, threads):
+    """The oracle's screened pipeline on a bounded seeded sample of the same
+    columns: FP64 numpy features (batched over columns) and the MLP on the
+    BF16-rounded weights, the exact top-keep with the fallback rule, then the
+    FP64 C oracle's selection on the kept (or full) pools with OpenMP over
+    columns.  The median of three runs on `threads` host threads, and one run
+    on a single thread."""
     import numpy as np
+    from threadpoolctl import threadpool_limits
 
     import oracle
     from oracle import screen as so
@@ -345,32 +352,74 @@ def cpu_baseline_screened(w, k, keep, fbt, p_np, seconds):
     rng = np.random.default_rng(4321)
     T = len(w.targets)
 
-    def run(idx):
+    def run(idx, nthreads):
         t0 = time.perf_counter()
         pools = np.full((len(idx), w.pool.shape[1]), -1, np.int32)
         lens = np.zeros(len(idx), np.int32)
-        for r, t in enumerate(idx):
-            L = int(w.pool_len[t])
-            f = so.features(w.points, w.kernel, int(w.targets[t]), w.pool[t, :L])
-            z, _ = so.mlp_forward(f, p_np, bf16=True)
-            kept, fb = so.screen_keep(z, L, keep, fbt)
-            if fb:
-                pools[r, :L] = w.pool[t, :L]
-                lens[r] = L
-            else:
-                pools[r, : len(kept)] = w.pool[t, kept]
-                lens[r] = len(kept)
-        oracle.select_and_factor(w.points, w.kernel, w.targets[idx], pools, lens, k, nthreads=1)
+        with threadpool_limits(nthreads):
+            for a in range(0, len(idx), 1024):
+                ii = idx[a:a + 1024]
+                f = so.features_batch(w.points, w.kernel, w.targets[ii], w.pool[ii], w.pool_len[ii])
+                z, _ = so.mlp_forward(f.reshape(-1, 16), p_np, bf16=True)
+                z = z.reshape(len(ii), -1)
+                for r, t in enumerate(ii):
+                    L = int(w.pool_len[t])
+                    kept, fb = so.screen_keep(z[r], L, keep, fbt)
+                    if fb:
+                        pools[a + r, :L], lens[a + r] = w.pool[t, :L], L
+                    else:
+                        pools[a + r, : len(kept)], lens[a + r] = w.pool[t, kept], len(kept)
+            oracle.select_and_factor(w.points, w.kernel, w.targets[idx], pools, lens, k, nthreads=nthreads)
         return time.perf_counter() - t0
 
-    probe = np.sort(rng.choice(T, size=min(T, 64), replace=False))
-    dt = run(probe)
-    m = int(min(T, max(len(probe), len(probe) * seconds / max(dt, 1e-6))))
+    probe = np.sort(rng.choice(T, size=min(T, 1024), replace=False))
+    dt = run(probe, threads)
+    m = int(min(T, max(len(probe), len(probe) * seconds / 4.0 / max(dt, 1e-6))))
     idx = np.sort(rng.choice(T, size=m, replace=False))
-    dt = run(idx)
-    return {"value": m / dt, "unit": "columns/s", "cores": 1, "kind": "oracle",
-            "sample": f"{m} of {T} columns (seeded uniform sample): numpy FP64 features and MLP on BF16-rounded "
-                      f"weights, top-{keep} with the fallback rule, FP64 C oracle selection, one thread, {dt:.1f} s"}
+    runs = sorted(run(idx, threads) for _ in range(3))
+    dt_med = runs[1]
+    m1 = max(256, m // max(threads, 1))
+    dt1 = run(idx[:m1], 1)
+    return {"value": m / dt_med, "unit": "columns/s", "cores": threads, "kind": "oracle",
+            "one_core_value": m1 / dt1,
+            "sample": f"{m} of {T} columns (seeded uniform sample), median of 3 runs ({', '.join(f'{r:.2f}' for r in runs)} "
+                      f"s): FP64 numpy features and MLP on BF16-rounded weights (batched over 1024 columns; BLAS "
+                      f"limited to {threads} threads), exact top-{keep} with the fallback rule, FP64 C oracle "
+                      f"selection with OpenMP over columns on {threads} threads; one_core_value: {m1} columns on "
+                      f"one thread, {dt1:.1f} s"}
+
+
+def kl_ref_bound(pts, kernel, tg, pl, ln, S_plain_cols, dS, k_ref=128, sample=None):
+    """Conservative relative KL gap of a screened selection: S_ref from the
+    greedy selection of k_ref candidates from the same pools (FP64, through
+    the multi-target selection with one member per group, whose picks are
+    the single-target picks).  By prefix consistency those patterns contain
+    the plain k-patterns, so S_ref <= S_plain and log det Theta <= S_ref:
+    dS / (S_plain - S_ref) bounds dS / (2 KL_plain) from above.  On a seeded
+    column sample when `sample` is given (scaled to all columns)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel
+
+    T = tg.shape[0]
+    idx = np.arange(T) if not sample or sample >= T else \
+        np.sort(np.random.default_rng(91).choice(T, size=sample, replace=False))
+    ii = torch.from_numpy(idx.astype(np.int64)).to(pl.device)
+    m = len(idx)
+    gp = torch.arange(m + 1, dtype=torch.int32, device=pl.device)
+    members = tg[ii].contiguous()
+    out = csel.aggregated_select(pts, kernel, gp, members, 1, pl[ii].contiguous(), ln[ii].contiguous(), k_ref,
+                                 "fp64")
+    torch.cuda.synchronize()
+    S_ref = out["logdet"].double().cpu().numpy()
+    S_pl = np.asarray(S_plain_cols)[idx]
+    st = out["status"].cpu().numpy()
+    ok = st == 0
+    diff = float(np.sum(S_pl[ok] - S_ref[ok])) * (T / max(int(ok.sum()), 1))
+    return {"k_ref": k_ref, "columns": m, "status_nonzero": int((~ok).sum()),
+            "prefix_violations": int(np.sum(S_ref[ok] > S_pl[ok] + 1e-9 * np.abs(S_pl[ok]))),
+            "S_plain_minus_S_ref": diff, "gap_relative_upper": dS / diff if diff > 0 else None}
 
 
 def _source_digest(*names):
@@ -406,7 +455,8 @@ MEASURED_TRAFFIC = {
 
 def bench_screened(args):
     """Plain full-pool selection vs learned-screened selection on the clustered
-    1e6-point workload (pools of 512, keep 128, k = 32)."""
+    1e6-point workload (pools of 512, keep 128, k = 32), in FP64 (the credited
+    leg) and in mixed precision."""
     import numpy as np
     import torch
 
@@ -437,76 +487,17 @@ def bench_screened(args):
     pts, tg, pl, ln = t(w.points, torch.float64), t(w.targets, torch.int32), t(w.pool, torch.int32), \
         t(w.pool_len, torch.int32)
     T = len(w.targets)
-    prec = args.precision
     fbt = args.fallback_threshold
-    plain = csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec)
-    # the screen's column processing order (Morton order of the targets): set-up,
-    # like the pools; its own time is reported
-    order, order_ws = csel.spatial_order(pts, tg)
-    torch.cuda.synchronize()
-    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-    e0.record()
-    csel.spatial_order(pts, tg, out=order, workspace=order_ws)
-    e1.record()
-    torch.cuda.synchronize()
-    ms_order = e0.elapsed_time(e1)
-    scr_out, scr = screen_train.screened_select(pts, w.kernel, tg, pl, ln, k, p, pb, keep, prec,
-                                                fallback_threshold=fbt, order=order)
-    # column schedules (natural or Morton order) of the plain and the kept-pool
-    # selections, each tuned once here, untimed
+    # the free screen: the 128 nearest candidates of every pool
+    near_pl, near_ln = pl[:, :keep].contiguous(), torch.clamp(ln, max=keep).contiguous()
+    order, _ = csel.spatial_order(pts, tg)
     tuner = autotune.SelectTuner()
-    tuner.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, order=order, out=plain)
-    tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
     torch.cuda.synchronize()
-
-    count_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
-
-    def screened_step(ev=None):
-        # screen, exact selection on the kept pools, full-pool selection of the
-        # fallback columns (device-side list).  The fallback count is copied to
-        # the host behind the screen and read while the kept-pool selection
-        # runs, so the fallback launch covers only the listed columns.
-        if ev is not None:
-            ev[0].record()
-        csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=scr, order=order)
-        if ev is not None:
-            ev[1].record()
-        fev = screen_train.start_fallback_count_copy(scr, count_host)
-        tuner.select_and_factor(pts, w.kernel, tg, scr["kept"], scr["kept_len"], k, prec, order=order, out=scr_out)
-        if ev is not None:
-            ev[2].record()
-        max_cols = screen_train.fallback_max_cols(fev, count_host, T)
-        if max_cols > 0:
-            csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, scr["fallback_list"],
-                                        scr["fallback_count"], max_cols, scr_out)
-        if ev is not None:
-            ev[3].record()
-
-    def plain_step(ev=None):
-        if ev is not None:
-            ev[0].record()
-        tuner.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, order=order, out=plain)
-        if ev is not None:
-            ev[1].record()
-
-    # both schedules of the plain selection, timed on their own as well
-    def plain_natural_step(ev=None):
-        if ev is not None:
-            ev[0].record()
-        csel.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, out=plain)
-        if ev is not None:
-            ev[1].record()
-
-    n_all = torch.tensor([T], dtype=torch.int32, device=dev)
-
-    def plain_ordered_step(ev=None):
-        if ev is not None:
-            ev[0].record()
-        csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, order, n_all, T, plain)
-        if ev is not None:
-            ev[1].record()
 
     def timed(fn, nev):
+        """Median over the K timed steps of the span between the first and last
+        of `nev` HIP events fn records on the current stream, and of each
+        consecutive pair; plus the host wall time per step."""
         for _ in range(args.warmup):
             fn()
         evs = [[torch.cuda.Event(enable_timing=True) for _ in range(nev)] for _ in range(args.steps)]
@@ -515,37 +506,143 @@ def bench_screened(args):
         for e in evs:
             fn(e)
         torch.cuda.synchronize()
-        wall = (time.perf_counter() - t_a) * 1e3
-        parts = [float(np.mean([e[j].elapsed_time(e[j + 1]) for e in evs])) for j in range(nev - 1)]
-        total = float(np.mean([e[0].elapsed_time(e[-1]) for e in evs]))
-        return total, parts, wall / args.steps
+        wall = (time.perf_counter() - t_a) * 1e3 / args.steps
+        parts = [float(np.median([e[j].elapsed_time(e[j + 1]) for e in evs])) for j in range(nev - 1)]
+        total = float(np.median([e[0].elapsed_time(e[-1]) for e in evs]))
+        return total, parts, wall
 
-    print("bench: timing plain", file=sys.stderr, flush=True)
-    ms_plain_natural, _, _ = timed(plain_natural_step, 2)
-    ms_plain_ordered, _, _ = timed(plain_ordered_step, 2)
-    ms_plain, _, _ = timed(plain_step, 2)
-    print("bench: timing screened", file=sys.stderr, flush=True)
-    ms_screen, (ms_scr, ms_kept, ms_fb), wall_screen = timed(screened_step, 4)
-    nfb = int(scr["fallback_count"].item())
-    S_plain = float(plain["log_condvar"].sum().item())
-    S_screen = float(scr_out["log_condvar"].sum().item())
-    st = scr_out["status"].cpu().numpy()
+    kernel_ms = {}
+    legs = {}
+    outs = {}
+    for prec in ("fp64", "mixed"):
+        print(f"bench: {prec} legs", file=sys.stderr, flush=True)
+        plain = tuner.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, order=order)
+        near = tuner.select_and_factor(pts, w.kernel, tg, near_pl, near_ln, k, prec, order=order)
+        plan = csel.Plan(T, pl.shape[1], keep, k, prec, graph=True)
+        plan.set_order(pts, tg)
+        scr = plan.step(pts, w.kernel, tg, pl, ln, p, pb, fbt)  # the first step tunes the kept-pool schedule
+        plan.step(pts, w.kernel, tg, pl, ln, p, pb, fbt, out=scr)  # captures the graph
+        torch.cuda.synchronize()
+        kept_schedule = plan.info()
+
+        def plain_step(ev=None):
+            if ev is not None:
+                ev[0].record()
+            tuner.select_and_factor(pts, w.kernel, tg, pl, ln, k, prec, order=order, out=plain)
+            if ev is not None:
+                ev[1].record()
+
+        def near_step(ev=None):
+            if ev is not None:
+                ev[0].record()
+            tuner.select_and_factor(pts, w.kernel, tg, near_pl, near_ln, k, prec, order=order, out=near)
+            if ev is not None:
+                ev[1].record()
+
+        def screened_step(ev=None):
+            # one library call: screen, kept-pool selection, fallback columns
+            # (a graph replay on the current stream)
+            if ev is not None:
+                ev[0].record()
+            plan.step(pts, w.kernel, tg, pl, ln, p, pb, fbt, out=scr)
+            if ev is not None:
+                ev[1].record()
+
+        # the same kernels launched one by one, for their separate times
+        sep = csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, order=order)
+        sep_out = csel.select_and_factor(pts, w.kernel, tg, sep["kept"], sep["kept_len"], k, prec)
+        kept_sched = kept_schedule["schedule"]
+        n_all = torch.tensor([T], dtype=torch.int32, device=dev)
+
+        def parts_step(ev=None):
+            if ev is not None:
+                ev[0].record()
+            csel.screen(pts, w.kernel, tg, pl, ln, p, pb, keep, fbt, out=sep, order=order)
+            if ev is not None:
+                ev[1].record()
+            if kept_sched == "spatial":
+                csel.select_and_factor_list(pts, w.kernel, tg, sep["kept"], sep["kept_len"], k, prec, order, n_all,
+                                            T, sep_out)
+            else:
+                csel.select_and_factor(pts, w.kernel, tg, sep["kept"], sep["kept_len"], k, prec, out=sep_out)
+            if ev is not None:
+                ev[2].record()
+            csel.select_and_factor_list(pts, w.kernel, tg, pl, ln, k, prec, sep["fallback_list"],
+                                        sep["fallback_count"], T, sep_out)
+            if ev is not None:
+                ev[3].record()
+
+        print(f"bench: timing {prec} plain", file=sys.stderr, flush=True)
+        ms_plain, _, _ = timed(plain_step, 2)
+        print(f"bench: timing {prec} screened", file=sys.stderr, flush=True)
+        ms_scr, _, wall_scr = timed(screened_step, 2)
+        ms_near, _, _ = timed(near_step, 2)
+        _, (ms_screen_k, ms_kept_k, ms_fb_k), _ = timed(parts_step, 4)
+        torch.cuda.synchronize()
+        so = plan.screen_outputs()
+        nfb = int(so["fallback_count"].item())
+        S_plain = float(plain["log_condvar"].sum().item())
+        S_scr = float(scr["log_condvar"].sum().item())
+        S_near = float(near["log_condvar"].sum().item())
+        kl_len = so["kept_len"].cpu().numpy()
+        fb_cols = so["fallback"].cpu().numpy() >= 1
+        legs[prec] = {
+            "plain_ms": ms_plain, "screened_ms": ms_scr, "screened_wall_ms_per_step": wall_scr,
+            "nearest128_ms": ms_near, "speedup_vs_plain": ms_plain / ms_scr,
+            "nearest128_speedup_vs_plain": ms_plain / ms_near,
+            "screen_kernel_ms": ms_screen_k, "kept_select_ms": ms_kept_k, "fallback_select_ms": ms_fb_k,
+            "fallback_columns": nfb, "kept_pool_schedule": kept_schedule,
+            "status_nonzero": int(np.count_nonzero(scr["status"].cpu().numpy())),
+            "delta_S": S_scr - S_plain, "delta_S_nearest128": S_near - S_plain,
+            "S_plain": S_plain,
+        }
+        outs[prec] = {"plain": plain, "scr": scr, "near": near}
+        kernel_ms[prec] = (ms_screen_k, ms_kept_k, kl_len, fb_cols)
+        del plan, sep, sep_out
+        torch.cuda.empty_cache()
+    tune_choices = tuner.choices
+
+    # quality: the KL gap of the screened and the nearest-128 selections
+    print("bench: KL gap estimates", file=sys.stderr, flush=True)
     rng = np.random.default_rng(77)
     samp = np.sort(rng.choice(T, size=96, replace=False)).astype(np.int32)
-    lcv_p = plain["log_condvar"].cpu().numpy()[samp]
-    print("bench: KL gap estimate", file=sys.stderr, flush=True)
-    gap, kl_plain, ns = kl_gap_estimate(w, samp, lcv_p, None, S_screen - S_plain)
-    kl_len = scr["kept_len"].cpu().numpy()
-    flops_kept, _ = column_work(kl_len, k, 3, 3)
-    flops_plain, _ = column_work(w.pool_len, k, 3, 3)
+    lcv_p64 = outs["fp64"]["plain"]["log_condvar"].cpu().numpy()
+    for prec in ("fp64", "mixed"):
+        lg = legs[prec]
+        lcv_p = outs[prec]["plain"]["log_condvar"].cpu().numpy()
+        gap, kl_plain, ns = kl_gap_estimate(w, samp, lcv_p[samp], None, lg["delta_S"])
+        lg["kl_gap_relative_estimate"] = gap
+        lg["kl_gap_relative_estimate_nearest128"] = lg["delta_S_nearest128"] / (2.0 * kl_plain)
+        lg["kl_plain_estimate"] = kl_plain
+        lg["kl_estimate_sample_columns"] = ns
+    print("bench: KL bound with k_ref = 128", file=sys.stderr, flush=True)
+    bound = kl_ref_bound(pts, w.kernel, tg, pl, ln, lcv_p64, legs["fp64"]["delta_S"], sample=args.kl_ref_sample)
+    legs["fp64"]["kl_bound_k128"] = bound
+    if bound["S_plain_minus_S_ref"] > 0:
+        legs["fp64"]["kl_gap_relative_upper_nearest128"] = legs["fp64"]["delta_S_nearest128"] / \
+            bound["S_plain_minus_S_ref"]
+    # mixed precision against FP64 (same workload, same screen)
+    m64, mmx = outs["fp64"], outs["mixed"]
+    for key in ("plain", "scr"):
+        a, b = m64[key], mmx[key]
+        same = torch.all(a["sel"] == b["sel"], dim=1)
+        fa, fb_ = a["factor"][same], b["factor"][same]
+        err = float((torch.max(torch.abs(fa - fb_), dim=1).values / torch.max(torch.abs(fa), dim=1).values).max()) \
+            if bool(same.any()) else None
+        legs["mixed"][f"{key}_vs_fp64"] = {
+            "columns_identical": int(same.sum().item()), "columns": T,
+            "S_relative_difference": (float(b["log_condvar"].sum()) - float(a["log_condvar"].sum()))
+            / abs(float(a["log_condvar"].sum())),
+            "worst_factor_rel_error_on_identical_columns": err}
+
+    flops_kept, _ = column_work(kernel_ms["fp64"][2], k, 3, 3)
     mlp_flops = 2.0 * (16 * 64 + 64 * 64 + 64) * float(np.sum(w.pool_len))
-    kept_key = autotune.shape_key(pts.shape[1], int(w.kernel.two_nu), T, keep, k, prec)
+    sched = legs["fp64"]["kept_pool_schedule"]["schedule"]
     kernels = {
-        "select_factor_kernel (kept pools)": {"bound": "alu", "ms": ms_kept, "work": float(np.sum(flops_kept)),
-                                              "peak": PEAK_ALU_TFLOPS,
-                                              "src": ("select_kernel.hpp", "select_inst.hip", "device_common.hpp"),
-                                              "schedule": tuner.choices[kept_key]["schedule"]},
-        "screen_kernel": {"bound": "mfma", "ms": ms_scr, "work": mlp_flops, "peak": PEAK_BF16_TFLOPS,
+        "select_factor_kernel<double> (kept pools)": {
+            "bound": "alu", "ms": kernel_ms["fp64"][1], "work": float(np.sum(flops_kept)), "peak": PEAK_ALU_TFLOPS,
+            "src": ("select_kernel.hpp", "select_inst.hip", "device_common.hpp"), "schedule": sched},
+        "screen_kernel": {"bound": "mfma", "ms": kernel_ms["fp64"][0], "work": mlp_flops, "peak": PEAK_BF16_TFLOPS,
                           "src": ("screen.hip", "device_common.hpp"), "schedule": "spatial"},
     }
     dom = max(kernels, key=lambda kname: kernels[kname]["ms"])
@@ -553,40 +650,36 @@ def bench_screened(args):
     def roof(kname):
         kd = kernels[kname]
         ach = kd["work"] / (kd["ms"] * 1e-3) / 1e12
-        tr = MEASURED_TRAFFIC.get((kname, kd["schedule"], _source_digest(*kd["src"])))
+        tr_ = MEASURED_TRAFFIC.get((kname, kd["schedule"], _source_digest(*kd["src"])))
         return {"bound": kd["bound"], "kernel": kname, "achieved": ach, "peak": kd["peak"], "unit": "TFLOP/s",
-                "frac": ach / kd["peak"], "traffic": tr, "traffic_unit": "HBM bytes per launch (rocprofv3 FETCH_SIZE "
-                "+ WRITE_SIZE, copy-calibrated)", "schedule": kd["schedule"], "kernel_ms": kd["ms"],
+                "frac": ach / kd["peak"], "traffic": tr_, "traffic_unit": "HBM bytes per launch (rocprofv3 "
+                "FETCH_SIZE + WRITE_SIZE, copy-calibrated)", "schedule": kd["schedule"], "kernel_ms": kd["ms"],
                 "algorithmic_tflop_per_launch": kd["work"] / 1e12}
 
+    f64 = legs["fp64"]
+    flops_plain, _ = column_work(w.pool_len, k, 3, 3)
+    for prec in ("fp64", "mixed"):
+        legs[prec]["plain_roofline_frac"] = float(np.sum(flops_plain)) / (legs[prec]["plain_ms"] * 1e-3) / 1e12 / \
+            PEAK_ALU_TFLOPS
     res = {
-        "metric": METRIC, "value": T / (ms_screen * 1e-3), "unit": "columns/s", "n_gpus": 1, "steps": args.steps,
-        "warmup": args.warmup, "ms_per_step": ms_screen, "higher_is_better": True, "scaling": "weak",
-        "vs_baseline": None, "dtype": "bf16+f32+f64" if prec == "mixed" else "bf16+f64", "data": "synthetic",
+        "metric": METRIC, "value": T / (f64["screened_ms"] * 1e-3), "unit": "columns/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": f64["screened_ms"], "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16+f64", "data": "synthetic",
         "config": {"workload": f"learned-screened selection, N={n} in [0,1]^3 (20 Gaussian clusters sigma 0.03 + 20% "
-                               f"uniform), Matern 3/2, l=0.05, pools of 512 -> keep {keep}, k={k}, {prec}; MLP "
-                               f"16-64-64-1 trained on the GPU on {rows} rows from {len(tr.targets)} exact selections",
-                   "columns": T, "plain_columns_per_s": T / (ms_plain * 1e-3), "plain_ms": ms_plain,
-                   "plain_natural_order_ms": ms_plain_natural, "plain_morton_order_ms": ms_plain_ordered,
-                   "autotuned_schedules": tuner.choices,
-                   "screened_ms": ms_screen, "screened_wall_ms_per_step": wall_screen,
-                   "screen_kernel_ms": ms_scr, "kept_select_ms": ms_kept, "fallback_select_ms": ms_fb,
-                   "spatial_order_setup_ms": ms_order,
-                   "speedup_vs_plain": ms_plain / ms_screen, "fallback_threshold": fbt, "fallback_columns": nfb,
-                   "status_nonzero": int(np.count_nonzero(st)), "delta_S": S_screen - S_plain,
-                   "kl_gap_relative_estimate": gap, "kl_plain_estimate": kl_plain,
-                   "kl_estimate_sample_columns": ns, "train_seconds": t_train,
-                   "plain_roofline_frac": float(np.sum(flops_plain)) / (ms_plain * 1e-3) / 1e12 / PEAK_ALU_TFLOPS},
+                               f"uniform), Matern 3/2, l=0.05, pools of 512 -> keep {keep}, k={k}; FP64 selection "
+                               f"(the credited leg; mixed precision reported beside it); MLP 16-64-64-1 trained on "
+                               f"the GPU on {rows} rows from {len(tr.targets)} exact selections; one "
+                               f"csel_screened_select graph replay per step; medians of {args.steps} steps",
+                   "columns": T, "fallback_threshold": fbt, "legs": legs, "autotuned_schedules": tune_choices,
+                   "speedup_vs_plain": f64["speedup_vs_plain"], "train_seconds": t_train},
         "roofline": roof(dom),
         "roofline_other": [roof(kname) for kname in kernels if kname != dom],
     }
     if args.cpu_seconds > 0:
         print("bench: cpu baseline (screened oracle)", file=sys.stderr, flush=True)
-        res["cpu_baseline"] = cpu_baseline_screened(w, k, keep, fbt, p.cpu().numpy().astype(np.float64),
-                                                    args.cpu_seconds)
-        print("bench: cpu baseline (plain oracle)", file=sys.stderr, flush=True)
         threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
-        res["cpu_baseline_plain"] = cpu_baseline(w, k, args.cpu_seconds, threads)
+        res["cpu_baseline"] = cpu_baseline_screened(w, k, keep, fbt, p.cpu().numpy().astype(np.float64),
+                                                    args.cpu_seconds, threads)
     print(json.dumps(res), flush=True)
 
 
@@ -679,7 +772,9 @@ def main():
     ap.add_argument("--precision", default="", choices=["", "mixed", "fp64"],
                     help="default: mixed, except fp64 for the GP workload (its conditional variances fall "
                          "below the FP32 error floor)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0, help="CPU-baseline budget (0 = skip)")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU-baseline budget (0 = skip)")
+    ap.add_argument("--kl-ref-sample", type=int, default=200_000,
+                    help="screened workload: columns of the k_ref = 128 KL bound (seeded sample; 0 = all)")
     ap.add_argument("--graph", type=int, default=1, help="plain workload: replay the step as a captured HIP graph")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="run one 1 GiB device copy first (profiler byte-counter calibration)")

@@ -253,6 +253,88 @@ int csel_select_and_factor_list(const double *pts, int64_t n, int32_t dim, const
                                 uint8_t *status, hipStream_t stream);
 
 /*
+ * Screened-selection plan.  A plan holds everything the learned-screened step
+ * needs besides the caller's inputs and outputs -- the screen's kept lists,
+ * flags, fallback list and count, the columns' processing order, the column
+ * schedule of the kept-pool selection (tuned on the plan's first step) and,
+ * with CSEL_PLAN_GRAPH, the whole step captured as one HIP graph -- so the
+ * step is a single call with no host synchronization after the first.
+ * Device memory is allocated by csel_plan_create on the current device and
+ * released by csel_plan_destroy; a step allocates nothing.  A plan serves one
+ * problem shape (n_targets, pool_stride, keep, k, precision) on the device it
+ * was created on, and may not be used by two threads at once.
+ */
+typedef struct csel_plan csel_plan;
+
+enum { CSEL_PLAN_GRAPH = 1 };  /* replay the step from a captured HIP graph */
+
+/*
+ * csel_plan_create -- a plan for csel_screened_select over n_targets columns
+ * with pools of up to pool_stride (<= csel_max_pool()) candidates, screened to
+ * `keep` (1 <= keep <= pool_stride) before the greedy selection of
+ * k (<= csel_max_select()) in `precision`.  Buffers: about
+ * n_targets * (4 keep + 13) bytes plus the order's sort workspace.
+ * *plan is NULL on failure (CSEL_ENOMEM when the buffers do not fit).
+ */
+int csel_plan_create(csel_plan **plan, int64_t n_targets, int32_t pool_stride, int32_t keep, int32_t k,
+                     int32_t precision, uint32_t flags);
+
+/* csel_plan_destroy -- waits for the device, then frees the plan (NULL ok). */
+void csel_plan_destroy(csel_plan *plan);
+
+/*
+ * csel_plan_set_order -- the columns' processing order for the plan's steps:
+ * the Morton order of the targets (csel_spatial_order), computed on `stream`
+ * into the plan.  Without it the columns run in their natural order.  The
+ * next step tunes the kept-pool schedule again.
+ */
+int csel_plan_set_order(csel_plan *plan, const double *pts, int64_t n, int32_t dim, const int32_t *targets,
+                        hipStream_t stream);
+
+/*
+ * csel_screened_select -- one learned-screened step, the hot path of the
+ * benchmark: per column (Sec. 3.1 on a pruned pool):
+ *   1. csel_screen: features, MLP, the `keep` best candidates, fallback flag
+ *      and the device-side fallback list (processing order from
+ *      csel_plan_set_order, if set);
+ *   2. csel_select_and_factor on the kept pools (natural or Morton column
+ *      schedule, whichever the plan's first step timed faster);
+ *   3. csel_select_and_factor on the full pools of the fallback columns: a
+ *      fixed grid striding through the device-side list, so no host read of
+ *      the count.
+ * Inputs and outputs are those of csel_screen and csel_select_and_factor for
+ * the plan's shape (targets [n_targets], pool_idx [n_targets][pool_stride],
+ * sel_idx [n_targets][k], factor_val [n_targets][k+1], log_condvar
+ * [n_targets] (may be NULL), status [n_targets]); no top2_gap.  The plan's
+ * first step (and the first after csel_plan_set_order) runs eagerly and
+ * synchronizes `stream` once to time the two schedules; later steps enqueue
+ * asynchronously.  With CSEL_PLAN_GRAPH later steps replay one captured HIP
+ * graph, captured again whenever a pointer or scalar argument changes.
+ */
+int csel_screened_select(csel_plan *plan, const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel,
+                         const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len,
+                         const float *params, const uint16_t *params_bf16, float fallback_threshold,
+                         int32_t *sel_idx, double *factor_val, double *log_condvar, uint8_t *status,
+                         hipStream_t stream);
+
+/*
+ * csel_plan_info -- the plan's kept-pool column schedule (host *schedule: 0
+ * natural order, 1 Morton order, -1 not yet tuned) and the two timings of its
+ * tuning step in ms (host tune_ms[2]); either may be NULL.
+ */
+int csel_plan_info(const csel_plan *plan, int32_t *schedule, float *tune_ms);
+
+/*
+ * csel_plan_screen_outputs -- device-to-device copies, enqueued on `stream`,
+ * of the last step's screen outputs held by the plan: kept_idx
+ * [n_targets][keep], kept_len [n_targets], fallback [n_targets] (as in
+ * csel_screen), fallback_list [n_targets] and fallback_count [1]; any
+ * destination may be NULL.
+ */
+int csel_plan_screen_outputs(const csel_plan *plan, int32_t *kept_idx, int32_t *kept_len, uint8_t *fallback,
+                             int32_t *fallback_list, int32_t *fallback_count, hipStream_t stream);
+
+/*
  * Learned candidate screen (not part of the paper).  An MLP scores every
  * candidate of a column from 16 geometric features; the `keep` best are
  * kept, and the exact greedy selection of csel_select_and_factor runs on the

@@ -120,6 +120,68 @@ def features(x, kernel, target, pool):
     return out
 
 
+def features_batch(x, kernel, targets, pools, lens):
+    """`features` of many columns at once: pools [B, S] (-1 padded), lens [B]
+    -> [B, S, 16], zeros past each pool's length.  The same definitions,
+    written over a batch axis (numpy broadcasting instead of per-column
+    calls); pinned to `features` column by column."""
+    x = np.asarray(x, np.float64)
+    pools = np.asarray(pools)
+    lens = np.asarray(lens, np.int64)
+    B, S = pools.shape
+    out = np.zeros((B, S, F))
+    if B == 0 or S == 0:
+        return out
+    ell = float(kernel.length_scale)
+    c = np.sqrt(float(kernel.two_nu)) / ell
+    tiny = 1e-9 * ell
+    a_diag = 1.0 + float(kernel.nugget) / float(kernel.variance)
+    s = np.arange(S)
+    valid = s[None, :] < lens[:, None]
+    P = np.where(valid, pools, 0)
+    xp = x[P]                                    # [B, S, d]
+    d = xp - x[np.asarray(targets)][:, None, :]
+    r = np.sqrt(np.sum(d * d, axis=2))           # [B, S]
+    r0 = np.maximum(r[:, 0], tiny)
+    rs = np.maximum(r, tiny)
+    Cf = np.maximum(lens, 1).astype(np.float64)[:, None]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        out[..., 0] = np.log(rs / r0[:, None])
+        out[..., 1] = s[None, :] / Cf
+        rho_i = matern_corr(kernel.two_nu, c * r)
+        out[..., 2] = rho_i
+        out[..., 3] = r / ell
+        out[..., 4] = (r[:, 0] / ell)[:, None]
+        cos0 = np.sum(d * d[:, :1, :], axis=2) / (rs * r0[:, None])
+        out[..., 5] = np.where(r > 0, cos0, 1.0)
+        # neighbourhood terms over the (up to) 8 nearest candidates l != j
+        L8 = min(8, S)
+        near = np.minimum(8, lens)
+        ls = np.arange(L8)
+        ok = (ls[None, None, :] < near[:, None, None]) & (ls[None, None, :] != s[None, :, None])
+        D = np.sqrt(np.sum((xp[:, :, None, :] - xp[:, None, :L8, :]) ** 2, axis=3))  # [B, S, L8]
+        best = np.min(np.where(ok, D / rs[:, :, None], np.inf), axis=2)
+        out[..., 6] = np.where(np.isfinite(best), best, 0.0)
+        rl = r[:, None, :L8]
+        dots = np.sum(d[:, :, None, :] * d[:, None, :L8, :], axis=3)
+        cone = ok & (rl < r[:, :, None]) & (dots / (rs[:, :, None] * np.maximum(rl, tiny)) > 0.7)
+        out[..., 7] = np.sum(cone, axis=2) / 8.0
+        dj0 = np.sqrt(np.sum((xp - xp[:, :1, :]) ** 2, axis=2))
+        rho_j0 = matern_corr(kernel.two_nu, c * dj0)
+        out[..., 8] = rho_j0
+        rho_j0 = rho_j0.copy()
+        rho_j0[:, 0] = a_diag
+        cov1 = rho_i - rho_i[:, :1] * rho_j0 / a_diag
+        var1 = a_diag - rho_j0 * rho_j0 / a_diag
+        f9 = np.where(var1 > 1e-12 * a_diag, cov1 * cov1 / np.maximum(var1, 1e-300) / a_diag, 0.0)
+        f9[:, 0] = 1.0
+        out[..., 9] = f9
+        out[:, 0, 10] = 1.0
+        out[..., 11] = np.log1p(s)[None, :] / np.log1p(Cf)
+    out[~valid] = 0.0
+    return out
+
+
 def group_features(x, kernel, members, pool):
     """Features [C, 16] (FP64) of the candidates `pool` of a group of targets
     `members` (multi-target selection, Sec. 5; pool sorted by the distance to
@@ -235,8 +297,8 @@ def screen_keep(logits, pool_len, keep, fallback_threshold=0.5):
     C = len(z)
     if C <= keep:
         return np.arange(C), False
-    order = sorted(range(C), key=lambda s: (-z[s], s))
-    kept = np.sort(np.array(order[:keep]))
+    order = np.lexsort((np.arange(C), -z))  # by -z, then by slot
+    kept = np.sort(order[:keep])
     dropped = np.array(order[keep:])
     fb = float(np.sum(1.0 / (1.0 + np.exp(-z[dropped])))) > fallback_threshold
     return kept, fb

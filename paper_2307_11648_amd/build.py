@@ -36,7 +36,7 @@ def _select_unit(t, nu, g, rpl):
     return ("select_inst.hip", defs)
 
 
-HIP_UNITS = [("abi.cpp", []), ("select.hip", [])] + [
+HIP_UNITS = [("abi.cpp", []), ("plan.cpp", []), ("select.hip", [])] + [
     _select_unit(t, nu, g, rpl)
     for t in ("float", "double") for nu in (1, 3, 5) for g in (0, 1) for rpl in (1, 2, 4, 8)
 ] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip")] + [

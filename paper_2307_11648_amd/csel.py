@@ -100,6 +100,20 @@ def load():
     lib.csel_mlp_grad_workspace_size.restype = ctypes.c_int64
     lib.csel_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_float, _vp, _c.c_int64, _vp, _vp]
     lib.csel_mlp_grad.restype = ctypes.c_int
+    lib.csel_plan_create.argtypes = [ctypes.POINTER(_vp), _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32,
+                                     _c.c_uint32]
+    lib.csel_plan_create.restype = ctypes.c_int
+    lib.csel_plan_destroy.argtypes = [_vp]
+    lib.csel_plan_destroy.restype = None
+    lib.csel_plan_set_order.argtypes = [_vp, _vp, _c.c_int64, _c.c_int32, _vp, _vp]
+    lib.csel_plan_set_order.restype = ctypes.c_int
+    lib.csel_screened_select.argtypes = [_vp, _vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _vp, _vp,
+                                         _vp, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_screened_select.restype = ctypes.c_int
+    lib.csel_plan_info.argtypes = [_vp, ctypes.POINTER(_c.c_int32), ctypes.POINTER(_c.c_float)]
+    lib.csel_plan_info.restype = ctypes.c_int
+    lib.csel_plan_screen_outputs.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_plan_screen_outputs.restype = ctypes.c_int
     lib.csel_mlp_grad_noalloc.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_float, _vp, _vp]
     lib.csel_mlp_grad_noalloc.restype = ctypes.c_int
     lib.csel_mlp_adam.argtypes = [_vp, _vp, _vp, _vp, _vp, _c.c_int32, _c.c_float, _c.c_float, _c.c_float,
@@ -194,6 +208,92 @@ def select_and_factor_list(points, kernel, targets, pool, pool_len, k: int, prec
                                          _ptr(out.get("gap")), _ptr(out["status"]), _stream(stream))
     _check(rc)
     return out
+
+
+# --------------------------------------------------------------------------
+# the screened-selection plan (one call per learned-screened step)
+# --------------------------------------------------------------------------
+class Plan:
+    """csel_plan: the buffers, tuned column schedule and (graph=True) captured
+    HIP graph of the learned-screened step over n_targets columns with pools
+    of pool_stride candidates kept to `keep` before the selection of k."""
+
+    def __init__(self, n_targets: int, pool_stride: int, keep: int, k: int, precision: str = "mixed",
+                 graph: bool = False):
+        lib = load()
+        self._lib = lib
+        self._h = ctypes.c_void_p()
+        self.n_targets, self.pool_stride, self.keep, self.k = int(n_targets), int(pool_stride), int(keep), int(k)
+        self.precision = precision
+        _check(lib.csel_plan_create(ctypes.byref(self._h), self.n_targets, self.pool_stride, self.keep, self.k,
+                                    _PREC[precision], 1 if graph else 0))
+
+    def close(self):
+        if self._h:
+            self._lib.csel_plan_destroy(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # interpreter shutdown
+            pass
+
+    def set_order(self, points, targets, stream=None):
+        """The Morton processing order of the columns (csel_plan_set_order)."""
+        _dev(points, torch.float64, "points")
+        _dev(targets, torch.int32, "targets")
+        _check(self._lib.csel_plan_set_order(self._h, points.data_ptr(), points.shape[0], points.shape[1],
+                                             targets.data_ptr(), _stream(stream)))
+
+    def step(self, points, kernel, targets, pool, pool_len, params, params_bf16, fallback_threshold: float,
+             out: dict | None = None, stream=None) -> dict:
+        """One screened step (csel_screened_select); returns sel, factor,
+        log_condvar and status as GPU tensors (reusing `out`)."""
+        _dev(points, torch.float64, "points")
+        _dev(targets, torch.int32, "targets")
+        _dev(pool, torch.int32, "pool")
+        _dev(pool_len, torch.int32, "pool_len")
+        T, k = self.n_targets, self.k
+        if targets.shape[0] != T or pool.shape != (T, self.pool_stride):
+            raise ValueError("targets / pool do not match the plan's shape")
+        dev = points.device
+        if out is None:
+            out = {"sel": torch.empty((T, k), dtype=torch.int32, device=dev),
+                   "factor": torch.empty((T, k + 1), dtype=torch.float64, device=dev),
+                   "log_condvar": torch.empty(T, dtype=torch.float64, device=dev),
+                   "status": torch.empty(T, dtype=torch.uint8, device=dev)}
+        kp = kernel_struct(kernel)
+        _check(self._lib.csel_screened_select(self._h, points.data_ptr(), points.shape[0], points.shape[1],
+                                              ctypes.byref(kp), targets.data_ptr(), pool.data_ptr(),
+                                              pool_len.data_ptr(), params.data_ptr(), params_bf16.data_ptr(),
+                                              float(fallback_threshold), _ptr(out["sel"]), _ptr(out["factor"]),
+                                              _ptr(out.get("log_condvar")), _ptr(out["status"]), _stream(stream)))
+        return out
+
+    def screen_outputs(self, out: dict | None = None, stream=None) -> dict:
+        """Copies of the last step's kept lists, fallback flags, fallback list
+        and count (csel_plan_screen_outputs)."""
+        T, dev = self.n_targets, torch.cuda.current_device()
+        if out is None:
+            out = {"kept": torch.empty((T, self.keep), dtype=torch.int32, device=dev),
+                   "kept_len": torch.empty(T, dtype=torch.int32, device=dev),
+                   "fallback": torch.empty(T, dtype=torch.uint8, device=dev),
+                   "fallback_list": torch.empty(T, dtype=torch.int32, device=dev),
+                   "fallback_count": torch.empty(1, dtype=torch.int32, device=dev)}
+        _check(self._lib.csel_plan_screen_outputs(self._h, _ptr(out.get("kept")), _ptr(out.get("kept_len")),
+                                                  _ptr(out.get("fallback")), _ptr(out.get("fallback_list")),
+                                                  _ptr(out.get("fallback_count")), _stream(stream)))
+        return out
+
+    def info(self) -> dict:
+        """The kept-pool schedule ("natural", "spatial" or None before the
+        first step) and the tuning step's timings in ms."""
+        sc = ctypes.c_int32(-1)
+        ms = (ctypes.c_float * 2)()
+        _check(self._lib.csel_plan_info(self._h, ctypes.byref(sc), ms))
+        name = {0: "natural", 1: "spatial"}.get(sc.value)
+        return {"schedule": name, "ms": {"natural": float(ms[0]), "spatial": float(ms[1])}}
 
 
 # --------------------------------------------------------------------------

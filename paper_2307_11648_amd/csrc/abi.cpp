@@ -49,6 +49,16 @@ constexpr int kMaxSelect = 32;
 
 CSEL_API const char* csel_last_error(void) { return g_err; }
 
+// the error slot, for the entry points defined in other sources (plan.cpp);
+// code 0 clears it
+extern "C" int csel_internal_fail(int code, const char* msg) {
+    if (code == CSEL_OK) {
+        g_err[0] = 0;
+        return CSEL_OK;
+    }
+    return fail(code, "%s", msg);
+}
+
 CSEL_API int32_t csel_version(void) { return 1; }
 
 CSEL_API int32_t csel_max_pool(void) { return kMaxPool; }
@@ -76,7 +86,7 @@ CSEL_API int csel_select_and_factor(const double* pts, int64_t n, int32_t dim, c
         (pool_stride > 0 && !pool_idx))
         return fail(CSEL_EINVAL, "a required array is NULL");
 
-    csel::SelectArgs a;
+    csel::SelectArgs a{};
     a.pts = pts;
     a.n = n;
     a.dim = dim;
@@ -264,7 +274,7 @@ CSEL_API int csel_select_and_factor_list(const double* pts, int64_t n, int32_t d
     if (!pts || !targets || !pool_len || !status || !factor_val || (k > 0 && !sel_idx) ||
         (pool_stride > 0 && !pool_idx))
         return fail(CSEL_EINVAL, "a required array is NULL");
-    csel::SelectArgs a;
+    csel::SelectArgs a{};
     a.pts = pts;
     a.n = n;
     a.dim = dim;

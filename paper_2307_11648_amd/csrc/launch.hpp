@@ -30,6 +30,9 @@ struct SelectArgs {
     const int32_t* col_list;
     const int32_t* col_count;
     int64_t n_waves;  // waves launched: n_targets, or the list capacity
+    // with col_list: a fixed grid whose waves stride through the list up to
+    // *col_count (n_waves is then ignored; the count is bounded by n_targets)
+    int32_t persistent;
 };
 
 struct ScreenArgs {

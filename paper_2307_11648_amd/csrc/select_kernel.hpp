@@ -51,33 +51,18 @@ __device__ __forceinline__ T matern(T r, T c, T s2) {
 }
 
 constexpr int kSelWavesPerBlock = 4;
+// the persistent list launch: 2,048 blocks of 4 waves (a multiple of the 8
+// XCDs), 8,192 waves striding through the list
+constexpr int kSelPersistentBlocks = 2048;
 
-// GAP: also track the second-best score of every step (top-two reduction) for
-// the top2_gap output; without it the reduction is a plain maximum.
+// One column: the greedy selection and the factor column of column `col`,
+// run by one wavefront (lane `lane`, wave `wib` of its block).  GAP: also
+// track the second-best score of every step (top-two reduction) for the
+// top2_gap output; without it the reduction is a plain maximum.
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
-__global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
-    static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
-    __shared__ __align__(16) double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
-    __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
-
-    const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
-    if (p.col_list) {
-        // the list's positions in eight contiguous segments, one per XCD
-        // (blocks go to the XCDs round-robin; the launch rounds the grid up to
-        // a multiple of 8), so the columns of a spatially sorted list that run
-        // together on one XCD share its L2.  Segments follow the list's actual
-        // length, so a short list still spreads over every XCD.
-        const int64_t cnt = min((int64_t)*p.col_count, p.n_waves);
-        const int64_t seg = ((cnt + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock * kSelWavesPerBlock;
-        const int64_t lb = (int64_t)(blockIdx.x >> 3) * kSelWavesPerBlock + wib;
-        const int64_t pos = (int64_t)(blockIdx.x & 7u) * seg + lb;
-        if (lb >= seg || pos >= cnt) return;
-        col = p.col_list[pos];
-    }
-    if (col < 0 || col >= p.n_targets) return;
-
+__device__ __forceinline__ void select_column(const SelectArgs& p, int64_t col, int wib, int lane,
+                                              double (&sh_r)[kSelWavesPerBlock][KMAX + 1][KMAX + 2],
+                                              double (&sh_pt)[kSelWavesPerBlock][KMAX + 1][4]) {
     const int kout = p.k;
     int32_t* sel_out = p.sel + col * kout;
     double* fac_out = p.fac + col * (kout + 1);
@@ -399,12 +384,47 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 }
 
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
+__global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
+    static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
+    __shared__ __align__(16) double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
+    __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
+
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    if (!p.col_list) {
+        const int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
+        if (col < p.n_targets) select_column<T, TWO_NU, RPL, KMAX, GAP>(p, col, wib, lane, sh_r, sh_pt);
+        return;
+    }
+    // The list's positions in eight contiguous segments, one per XCD (blocks
+    // go to the XCDs round-robin; the launch rounds the grid up to a multiple
+    // of 8), so the columns of a spatially sorted list that run together on
+    // one XCD share its L2.  Segments follow the list's actual length, so a
+    // short list still spreads over every XCD.  Without `persistent` each
+    // wave takes one position of its segment (the grid covers n_waves
+    // positions); with it the grid is fixed and each wave strides through its
+    // segment, so the launch needs no host-side count.
+    const int64_t cnt = min((int64_t)*p.col_count, p.persistent ? p.n_targets : p.n_waves);
+    const int64_t seg = p.persistent ? (cnt + 7) / 8
+                                     : ((cnt + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock * kSelWavesPerBlock;
+    const int64_t lb = (int64_t)(blockIdx.x >> 3) * kSelWavesPerBlock + wib;
+    const int64_t stride = p.persistent ? (int64_t)(gridDim.x >> 3) * kSelWavesPerBlock : seg;
+    const int64_t first = (int64_t)(blockIdx.x & 7u) * seg;
+    const int64_t end = min(first + seg, cnt);
+    for (int64_t pos = first + lb; lb < seg && pos < end; pos += stride) {
+        const int64_t col = p.col_list[pos];
+        if (col >= 0 && col < p.n_targets) select_column<T, TWO_NU, RPL, KMAX, GAP>(p, col, wib, lane, sh_r, sh_pt);
+    }
+}
+
+template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
 static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
     int64_t blocks = (a.n_waves + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
     if (a.col_list) {  // eight segments of whole blocks
         const int64_t seg = ((a.n_waves + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
         blocks = 8 * seg;
     }
+    if (a.persistent && a.col_list) blocks = kSelPersistentBlocks;
     hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX, GAP>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -86,54 +86,23 @@ def mean_loss(p, pb, X, y, chunk: int = 1 << 20) -> float:
     return tot / X.shape[0]
 
 
-def start_fallback_count_copy(scr, count_host):
-    """Start the copy of the screen's fallback count into `count_host` (a
-    pinned int32 host tensor of one element) on the current stream, and return
-    the event that marks it done.  Record it right after the screen."""
-    count_host.copy_(scr["fallback_count"], non_blocking=True)
-    ev = torch.cuda.Event()
-    ev.record()
-    return ev
-
-
-def fallback_max_cols(ev, count_host, n_targets: int) -> int:
-    """The list capacity for the fallback launch: the screen's fallback count,
-    once the copy started by start_fallback_count_copy has landed (the host
-    waits on that event only; work queued behind it keeps the GPU busy), else
-    every column."""
-    if ev is None:
-        return n_targets
-    ev.synchronize()
-    return max(0, min(int(count_host[0]), n_targets))
-
-
 def screened_select(points, kernel, targets, pool, pool_len, k: int, p, pb, keep: int, precision: str = "mixed",
-                    fallback_threshold: float = 0.5, out=None, scr=None, order=None, count_host=None):
-    """The screened hot path: screen, exact selection on the kept candidates,
-    exact selection on the full pool for the fallback columns (the fallback
-    list stays on the device).  `order` is the screen's column processing
-    order (csel.spatial_order): it must list every column once, since the
-    kept-pool selection runs on all of them (checked here, which reads the
-    order back).
-
-    With `count_host` (a pinned int32 host tensor of one element) the host
-    reads the fallback count while the kept-pool selection runs, and the
-    fallback launch covers that many list entries instead of one per column:
-    the same work without dispatching a grid for every column."""
-    if order is not None:
-        from .autotune import check_permutation
-
-        check_permutation(order, targets.shape[0])
-    T = targets.shape[0]
-    scr = csel.screen(points, kernel, targets, pool, pool_len, p, pb, keep, fallback_threshold, out=scr,
-                      order=order)
-    ev = start_fallback_count_copy(scr, count_host) if count_host is not None else None
-    out = csel.select_and_factor(points, kernel, targets, scr["kept"], scr["kept_len"], k, precision, out=out)
-    max_cols = fallback_max_cols(ev, count_host, T)
-    if max_cols > 0:
-        csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, scr["fallback_list"],
-                                    scr["fallback_count"], max_cols, out)
-    return out, scr
+                    fallback_threshold: float = 0.5, out=None, spatial_order: bool = False, plan=None):
+    """The screened hot path as one library call (csel_screened_select):
+    screen, exact selection on the kept candidates, exact selection on the
+    full pool for the fallback columns, all inside the library with no host
+    synchronisation.  `plan` (csel.Plan for this shape) is reused when given;
+    otherwise one is made for the call, with the Morton processing order when
+    `spatial_order`.  Returns (out, scr): the selection outputs and copies of
+    the screen's outputs (kept, kept_len, fallback, fallback_list,
+    fallback_count)."""
+    T, stride = pool.shape
+    if plan is None:
+        plan = csel.Plan(T, stride, keep, k, precision)
+        if spatial_order:
+            plan.set_order(points, targets)
+    out = plan.step(points, kernel, targets, pool, pool_len, p, pb, fallback_threshold, out=out)
+    return out, plan.screen_outputs()
 
 
 # ---------------------------------------------------------------------------

@@ -1,7 +1,7 @@
 """The benchmark's configurations, checked against the FP64 oracle exactly as
-they run: the learned-screened step (screen, kept-pool selection and the
-fallback columns' full-pool selection, mixed precision, no gap output, the
-fallback launch sized by the host-read count), the plain selection on pools
+they run: the learned-screened step (csel_screened_select: screen, kept-pool
+selection and the fallback columns' full-pool selection, mixed precision, no
+gap output, replayed from its captured graph), the plain selection on pools
 of 512, and the aggregated register kernel on union pools of 512.
 
 Mixed-precision runs are held to two bars:
@@ -76,8 +76,9 @@ def _mixed_checks(g, w, targets, pool, plen, k, label):
 def test_screened_step_mixed_as_benchmarked(trained):
     """Clustered cloud, n = 20,000, pools of 512 -> keep 128, k = 32, mixed, no
     gap output; the threshold sends the columns with the 2% largest dropped
-    mass to their full pools; the fallback launch is sized by the count the
-    host reads while the kept-pool selection runs (as the benchmark does)."""
+    mass to their full pools; one csel_screened_select call per step, with
+    the Morton order, the tuned schedule and the graph replay the benchmark
+    times."""
     print("case: screened step, mixed, n=20000 C=512 keep=128 k=32", flush=True)
     p, pb = trained
     w = inputs.workload_clustered(n=20000, seed=15, C=512, k=32)
@@ -87,10 +88,12 @@ def test_screened_step_mixed_as_benchmarked(trained):
     zs = torch.sort(z, dim=1, descending=True).values
     drop = np.array([float(torch.sigmoid(zs[t, keep:int(w.pool_len[t])]).sum()) for t in range(T)])
     thr = float(np.quantile(drop[w.pool_len > keep], 0.98))
-    order, _ = csel.spatial_order(P, Tg)
-    count_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
-    out, scr = screen_train.screened_select(P, w.kernel, Tg, Pl, Ln, k, p, pb, keep, "mixed",
-                                            fallback_threshold=thr, order=order, count_host=count_host)
+    plan = csel.Plan(T, 512, keep, k, "mixed", graph=True)
+    plan.set_order(P, Tg)
+    out = None
+    for _ in range(3):  # the first step tunes the schedule, the next capture and replay the graph
+        out, scr = screen_train.screened_select(P, w.kernel, Tg, Pl, Ln, k, p, pb, keep, "mixed",
+                                                fallback_threshold=thr, out=out, plan=plan)
     torch.cuda.synchronize()
     assert "gap" not in out
     g = {key: v.cpu().numpy() for key, v in out.items()}

@@ -171,31 +171,83 @@ def test_screened_selection_parity(clustered):
     assert rep["identical"] >= 0.97 * rep["columns"]
 
 
-@pytest.mark.parametrize("thr", [0.6, 1e30])
-def test_screened_select_with_host_count_matches(clustered, thr):
-    """The screened pipeline that reads the fallback count on the host (while
-    the kept-pool selection runs) and sizes the fallback launch by it writes
-    exactly what the pipeline with a launch over every column writes, with
-    fallback columns and with none (the launch is then skipped); replayed
-    three times into the same buffers."""
-    print(f"case: screened select, fallback launch sized by the host-read count, threshold {thr}", flush=True)
+def _composed_step(d, w, p, pb, keep, k, prec, thr, order=None):
+    """The screened step composed from the separate entry points: csel_screen,
+    csel_select_and_factor on the kept pools, csel_select_and_factor_list on
+    the full pools of the listed fallback columns (capacity: every column)."""
+    T = len(w.targets)
+    scr = csel.screen(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, keep, thr, order=order)
+    out = csel.select_and_factor(d["pts"], w.kernel, d["tg"], scr["kept"], scr["kept_len"], k, prec)
+    csel.select_and_factor_list(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], k, prec, scr["fallback_list"],
+                                scr["fallback_count"], T, out)
+    torch.cuda.synchronize()
+    return {key: v.cpu().numpy() for key, v in out.items()}, scr
+
+
+@pytest.mark.parametrize("thr,spatial,graph", [(0.6, False, False), (0.6, True, True), (1e30, True, True),
+                                               (0.0, False, True)])
+def test_plan_step_matches_composed_step(clustered, thr, spatial, graph):
+    """csel_screened_select (one call: screen, kept-pool selection, the
+    fallback columns on a persistent grid over the device-side list) writes
+    exactly what the composition of the separate entry points writes: with
+    fallback columns, with none, and with every column falling back
+    (threshold 0).  With a graph, the step is replayed three times into
+    cleared outputs, with eager work and a synchronisation between replays;
+    every replay must match."""
+    print(f"case: plan step threshold {thr} spatial {spatial} graph {graph}", flush=True)
     w, d = clustered
     p, pb = _rand_params(37)
-    args = (d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], 32, p, pb, 128)
-    ref, scr = screen_train.screened_select(*args, precision="mixed", fallback_threshold=thr)
-    torch.cuda.synchronize()
-    nfb = int(scr["fallback_count"].item())
+    T, k, keep = len(w.targets), 32, 128
+    ref, scr_ref = _composed_step(d, w, p, pb, keep, k, "mixed", thr)
+    nfb = int(scr_ref["fallback_count"].item())
     assert (nfb > 0) == (thr < 1.0)
-    ref = {key: v.cpu().numpy() for key, v in ref.items()}
-    count_host = torch.empty(1, dtype=torch.int32, pin_memory=True)
+    if thr == 0.0:
+        assert nfb == int((w.pool_len > keep).sum())
+    plan = csel.Plan(T, 512, keep, k, "mixed", graph=graph)
+    if spatial:
+        plan.set_order(d["pts"], d["tg"])
     out = None
-    for _ in range(3):
-        out, _ = screen_train.screened_select(*args, precision="mixed", fallback_threshold=thr, out=out,
-                                              count_host=count_host)
+    for rep in range(4):
+        if out is not None:
+            for v in out.values():
+                v.zero_()
+        out = plan.step(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, thr, out=out)
+        scr = plan.screen_outputs()
         torch.cuda.synchronize()
-        assert int(count_host[0]) == nfb
         for key in ("sel", "factor", "log_condvar", "status"):
-            assert np.array_equal(out[key].cpu().numpy(), ref[key], equal_nan=True), key
+            assert np.array_equal(out[key].cpu().numpy(), ref[key], equal_nan=True), (rep, key)
+        for key in ("kept", "kept_len", "fallback", "fallback_count"):
+            assert torch.equal(scr[key], scr_ref[key]), (rep, key)
+        assert sorted(scr["fallback_list"][:nfb].cpu().tolist()) == sorted(scr_ref["fallback_list"][:nfb].cpu().tolist())
+        # unrelated eager work between the replays
+        _composed_step(d, w, p, pb, keep, k, "fp64", 0.3)
+    info = plan.info()
+    print("plan schedule", info, flush=True)
+    assert info["schedule"] in ("natural", "spatial")
+    # new output buffers: the graph is captured again and writes the new ones
+    out2 = plan.step(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, thr)
+    torch.cuda.synchronize()
+    assert np.array_equal(out2["sel"].cpu().numpy(), ref["sel"])
+    plan.close()
+
+
+def test_plan_rejects_bad_arguments(clustered):
+    w, d = clustered
+    p, pb = _rand_params(38)
+    with pytest.raises(csel.CselError):
+        csel.Plan(100, 513, 128, 32)
+    with pytest.raises(csel.CselError):
+        csel.Plan(100, 512, 600, 32)
+    with pytest.raises(csel.CselError):
+        csel.Plan(100, 512, 128, 40)
+    plan = csel.Plan(len(w.targets), 512, 128, 32)
+    with pytest.raises(ValueError):
+        plan.step(d["pts"], w.kernel, d["tg"][:10], d["pl"], d["ln"], p, pb, 0.5)
+    with pytest.raises(csel.CselError):
+        plan.step(d["pts"], inputs.Kernel(4, 0.05), d["tg"], d["pl"], d["ln"], p, pb, 0.5)
+    with pytest.raises(csel.CselError):
+        plan.step(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, -1.0)
+    plan.close()
 
 
 def test_trained_screen_gains(tmp_path):

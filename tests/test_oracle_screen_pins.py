@@ -286,3 +286,19 @@ def test_screen_keep_is_exact_order_with_ties_to_smaller_slot():
         keep = int(rng.integers(1, C))
         best = min((sorted((-float(zz[s]), s) for s in sub), sub) for sub in combinations(range(C), keep))
         assert list(so.screen_keep(zz, C, keep, 1e9)[0]) == list(best[1])
+
+
+def test_features_batch_equals_per_column_features():
+    """The batched features (used by the CPU baseline) are the per-column
+    definition, column by column, including ragged and short pools."""
+    w = inputs.workload_clustered(n=3000, seed=19, C=64, k=8)
+    idx = np.array(list(range(0, 2900, 37)) + [2990, 2995, 2998, 2999])
+    lens = w.pool_len[idx].copy()
+    lens[3] = 5  # shorter than the eight neighbours
+    lens[4] = 1
+    fb = so.features_batch(w.points, w.kernel, w.targets[idx], w.pool[idx], lens)
+    for b, t in enumerate(idx):
+        L = int(lens[b])
+        ref = so.features(w.points, w.kernel, int(w.targets[t]), w.pool[t, :L])
+        np.testing.assert_allclose(fb[b, :L], ref, rtol=1e-12, atol=1e-14)
+        assert np.all(fb[b, L:] == 0.0)
