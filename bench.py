@@ -600,6 +600,43 @@ def bench_screened(args):
         kernel_ms[prec] = (ms_screen_k, ms_kept_k, kl_len, fb_cols)
         del plan, sep, sep_out
         torch.cuda.empty_cache()
+    # operating points in FP64 at other keep sizes: the learned screen (its
+    # fallback off, so the screen alone decides) and the nearest truncation
+    # through the same kernels, each with its time and data-term change (the
+    # KL gaps follow below)
+    sweep = {}
+    for kp in args.keep_sweep:
+        if kp == keep or kp < k or kp > pl.shape[1]:
+            continue
+        print(f"bench: keep {kp} operating points", file=sys.stderr, flush=True)
+        plan = csel.Plan(T, pl.shape[1], kp, k, "fp64", graph=True)
+        plan.set_order(pts, tg)
+        o = plan.step(pts, w.kernel, tg, pl, ln, p, pb, 1e30)
+        plan.step(pts, w.kernel, tg, pl, ln, p, pb, 1e30, out=o)
+        npl, nln = pl[:, :kp].contiguous(), torch.clamp(ln, max=kp).contiguous()
+        no = tuner.select_and_factor(pts, w.kernel, tg, npl, nln, k, "fp64", order=order)
+
+        def lstep(ev=None):
+            if ev is not None:
+                ev[0].record()
+            plan.step(pts, w.kernel, tg, pl, ln, p, pb, 1e30, out=o)
+            if ev is not None:
+                ev[1].record()
+
+        def nstep(ev=None):
+            if ev is not None:
+                ev[0].record()
+            tuner.select_and_factor(pts, w.kernel, tg, npl, nln, k, "fp64", order=order, out=no)
+            if ev is not None:
+                ev[1].record()
+
+        ms_l, _, _ = timed(lstep, 2)
+        ms_n, _, _ = timed(nstep, 2)
+        sweep[str(kp)] = {"learned_ms": ms_l, "nearest_ms": ms_n, "learned_fallback": "off",
+                          "learned_delta_S": float(o["log_condvar"].sum()) - legs["fp64"]["S_plain"],
+                          "nearest_delta_S": float(no["log_condvar"].sum()) - legs["fp64"]["S_plain"]}
+        del plan, o, no, npl, nln
+        torch.cuda.empty_cache()
     tune_choices = tuner.choices
 
     # quality: the KL gap of the screened and the nearest-128 selections
@@ -619,8 +656,13 @@ def bench_screened(args):
     bound = kl_ref_bound(pts, w.kernel, tg, pl, ln, lcv_p64, legs["fp64"]["delta_S"], sample=args.kl_ref_sample)
     legs["fp64"]["kl_bound_k128"] = bound
     if bound["S_plain_minus_S_ref"] > 0:
-        legs["fp64"]["kl_gap_relative_upper_nearest128"] = legs["fp64"]["delta_S_nearest128"] / \
-            bound["S_plain_minus_S_ref"]
+        den = bound["S_plain_minus_S_ref"]
+        legs["fp64"]["kl_gap_relative_upper_nearest128"] = legs["fp64"]["delta_S_nearest128"] / den
+        for v in sweep.values():
+            v["learned_kl_gap_relative_upper"] = v["learned_delta_S"] / den
+            v["nearest_kl_gap_relative_upper"] = v["nearest_delta_S"] / den
+            v["learned_speedup_vs_plain"] = legs["fp64"]["plain_ms"] / v["learned_ms"]
+            v["nearest_speedup_vs_plain"] = legs["fp64"]["plain_ms"] / v["nearest_ms"]
     # mixed precision against FP64 (same workload, same screen)
     m64, mmx = outs["fp64"], outs["mixed"]
     for key in ("plain", "scr"):
@@ -670,7 +712,8 @@ def bench_screened(args):
                                f"(the credited leg; mixed precision reported beside it); MLP 16-64-64-1 trained on "
                                f"the GPU on {rows} rows from {len(tr.targets)} exact selections; one "
                                f"csel_screened_select graph replay per step; medians of {args.steps} steps",
-                   "columns": T, "fallback_threshold": fbt, "legs": legs, "autotuned_schedules": tune_choices,
+                   "columns": T, "fallback_threshold": fbt, "legs": legs, "fp64_keep_sweep": sweep,
+                   "autotuned_schedules": tune_choices,
                    "speedup_vs_plain": f64["speedup_vs_plain"], "train_seconds": t_train},
         "roofline": roof(dom),
         "roofline_other": [roof(kname) for kname in kernels if kname != dom],
@@ -773,6 +816,8 @@ def main():
                     help="default: mixed, except fp64 for the GP workload (its conditional variances fall "
                          "below the FP32 error floor)")
     ap.add_argument("--cpu-seconds", type=float, default=20.0, help="CPU-baseline budget (0 = skip)")
+    ap.add_argument("--keep-sweep", type=lambda v: [int(a) for a in v.split(",") if a], default=[48, 64, 96],
+                    help="screened workload: further keep sizes timed in FP64, learned and nearest")
     ap.add_argument("--kl-ref-sample", type=int, default=200_000,
                     help="screened workload: columns of the k_ref = 128 KL bound (seeded sample; 0 = all)")
     ap.add_argument("--graph", type=int, default=1, help="plain workload: replay the step as a captured HIP graph")

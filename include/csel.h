@@ -121,6 +121,30 @@ int csel_select_and_factor(const double *pts, int64_t n, int32_t dim, const csel
                            uint8_t *status, hipStream_t stream);
 
 /*
+ * csel_select_and_factor_sched -- csel_select_and_factor under an explicit
+ * schedule, without the top2_gap output.  Same computation and results, bit
+ * for bit, under every schedule; only the speed differs (chosen by a tuner).
+ *
+ *   col_list, col_count, max_cols  NULL/NULL: every column in its natural
+ *              order (max_cols ignored); else the columns col_list[0 ..
+ *              *col_count), as for csel_select_and_factor_list
+ *   waves_per_column  1: one wavefront holds a column's whole pool (the
+ *              schedule of csel_select_and_factor); or
+ *              csel_select_waves_per_column(pool_stride) (2 for pools <= 128,
+ *              4 up to 512): the pool split over that many wavefronts of a
+ *              workgroup, which exchange each pick's argmax and winning row
+ *              through LDS -- fewer registers per wavefront, so more of them
+ *              resident (CSEL_EUNSUPPORTED for other values)
+ */
+int32_t csel_select_waves_per_column(int32_t pool_stride);
+int csel_select_and_factor_sched(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel,
+                                 int64_t n_targets, const int32_t *targets, const int32_t *pool_idx,
+                                 const int32_t *pool_len, int32_t pool_stride, int32_t k, int32_t precision,
+                                 const int32_t *col_list, const int32_t *col_count, int64_t max_cols,
+                                 int32_t waves_per_column, int32_t *sel_idx, double *factor_val, double *log_condvar,
+                                 uint8_t *status, hipStream_t stream);
+
+/*
  * csel_aggregated_workspace_size -- bytes of device workspace that
  * csel_aggregated_select needs for these sizes (-1 with csel_last_error set if
  * the sizes are not supported).  The workspace holds the two partial Cholesky
@@ -255,8 +279,8 @@ int csel_select_and_factor_list(const double *pts, int64_t n, int32_t dim, const
 /*
  * Screened-selection plan.  A plan holds everything the learned-screened step
  * needs besides the caller's inputs and outputs -- the screen's kept lists,
- * flags, fallback list and count, the columns' processing order, the column
- * schedule of the kept-pool selection (tuned on the plan's first step) and,
+ * flags, fallback list and count, the columns' processing order, the
+ * schedules of the two selections (tuned on the plan's first step) and,
  * with CSEL_PLAN_GRAPH, the whole step captured as one HIP graph -- so the
  * step is a single call with no host synchronization after the first.
  * Device memory is allocated by csel_plan_create on the current device and
@@ -298,16 +322,17 @@ int csel_plan_set_order(csel_plan *plan, const double *pts, int64_t n, int32_t d
  *      and the device-side fallback list (processing order from
  *      csel_plan_set_order, if set);
  *   2. csel_select_and_factor on the kept pools (natural or Morton column
- *      schedule, whichever the plan's first step timed faster);
- *   3. csel_select_and_factor on the full pools of the fallback columns: a
- *      fixed grid striding through the device-side list, so no host read of
- *      the count.
+ *      order, one or several waves per column: whichever the plan's first
+ *      step timed fastest);
+ *   3. csel_select_and_factor on the full pools of the fallback columns
+ *      (csel_select_and_factor_list over the device-side list, its launch
+ *      covering every column: no host read of the count).
  * Inputs and outputs are those of csel_screen and csel_select_and_factor for
  * the plan's shape (targets [n_targets], pool_idx [n_targets][pool_stride],
  * sel_idx [n_targets][k], factor_val [n_targets][k+1], log_condvar
  * [n_targets] (may be NULL), status [n_targets]); no top2_gap.  The plan's
  * first step (and the first after csel_plan_set_order) runs eagerly and
- * synchronizes `stream` once to time the two schedules; later steps enqueue
+ * synchronizes `stream` to time the schedules; later steps enqueue
  * asynchronously.  With CSEL_PLAN_GRAPH later steps replay one captured HIP
  * graph, captured again whenever a pointer or scalar argument changes.
  */
@@ -318,11 +343,15 @@ int csel_screened_select(csel_plan *plan, const double *pts, int64_t n, int32_t 
                          hipStream_t stream);
 
 /*
- * csel_plan_info -- the plan's kept-pool column schedule (host *schedule: 0
- * natural order, 1 Morton order, -1 not yet tuned) and the two timings of its
- * tuning step in ms (host tune_ms[2]); either may be NULL.
+ * csel_plan_info -- the plan's tuned schedules (host outputs, any may be
+ * NULL): *kept_schedule for the kept-pool selection (-1 not yet tuned; bit 0
+ * the Morton column order, else natural; bit 1 the multi-wave schedule of
+ * csel_select_and_factor_sched, else one wave per column), *fallback_waves
+ * for the fallback columns' launch, and tune_ms[6] the tuning step's times in
+ * ms (kept pools under schedules 0-3, 0 where not timed; the fallback launch
+ * under one wave and under the multi-wave schedule).
  */
-int csel_plan_info(const csel_plan *plan, int32_t *schedule, float *tune_ms);
+int csel_plan_info(const csel_plan *plan, int32_t *kept_schedule, int32_t *fallback_waves, float *tune_ms);
 
 /*
  * csel_plan_screen_outputs -- device-to-device copies, enqueued on `stream`,

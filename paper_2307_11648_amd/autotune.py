@@ -1,15 +1,20 @@
-"""Autotuned column schedule for the single-target selection.
+"""Autotuned schedule of the single-target selection.
 
-Columns are independent, so the order in which one launch walks them
-changes only the speed, never a result: csel_select_and_factor takes the
-columns in their natural order, and csel_select_and_factor_list can take them
-in a spatial (Morton) order from csel_spatial_order, under which columns whose
-candidate pools overlap run side by side on an XCD and share its L2.  Which
-schedule wins depends on the pool size and the point cloud (pools of 512:
-the spatial order is faster; pools of 128: no difference), so the first call
-for a shape class times both on the stream it runs on and keeps the faster;
-later calls of the class reuse the choice.  Choices can persist in a JSON
-file, which a later process reads back.
+Columns are independent, so how one launch lays them out changes only the
+speed, never a result.  Two choices are tuned, four schedules in all:
+
+* the column order: the columns' natural order, or a spatial (Morton) order
+  from csel_spatial_order, under which columns whose candidate pools overlap
+  run side by side on an XCD and share its L2;
+* the waves per column: one wavefront holding a column's whole pool, or the
+  pool split over 2 (pools <= 128) or 4 (pools <= 512) wavefronts that
+  exchange each pick's argmax through LDS (csel_select_and_factor_sched):
+  fewer registers per wavefront, so more resident wavefronts.
+
+Which schedule wins depends on the pool size, the precision and the point
+cloud, so the first call for a shape class times each once on the stream it
+runs on and keeps the fastest; later calls of the class reuse the choice.
+Choices can persist in a JSON file, which a later process reads back.
 
 The tuner only chooses between launches of the library's kernels; every step
 of the selection runs in them.
@@ -22,8 +27,8 @@ import os
 
 from . import csel
 
-SCHEDULES = ("natural", "spatial")
-_FORMAT_VERSION = 1
+SCHEDULES = ("natural", "spatial", "natural/mw", "spatial/mw")
+_FORMAT_VERSION = 2
 
 
 def shape_key(dim: int, two_nu: int, n_targets: int, stride: int, k: int, precision: str) -> str:
@@ -148,6 +153,8 @@ class SelectTuner:
             return csel.select_and_factor(points, kernel, targets, pool, pool_len, k, precision, out=out,
                                           stream=stream)
         n_all = self._count(T, targets.device)
+        stride = pool.shape[1] if pool.dim() == 2 else 0
+        mw = csel.select_waves_per_column(stride)
 
         def natural():
             csel.select_and_factor(points, kernel, targets, pool, pool_len, k, precision, out=out, stream=stream)
@@ -156,10 +163,17 @@ class SelectTuner:
             csel.select_and_factor_list(points, kernel, targets, pool, pool_len, k, precision, order, n_all, T, out,
                                         stream=stream)
 
-        stride = pool.shape[1] if pool.dim() == 2 else 0
+        def natural_mw():
+            csel.select_and_factor_sched(points, kernel, targets, pool, pool_len, k, precision, waves=mw, out=out,
+                                         stream=stream)
+
+        def spatial_mw():
+            csel.select_and_factor_sched(points, kernel, targets, pool, pool_len, k, precision, waves=mw,
+                                         col_list=order, col_count=n_all, max_cols=T, out=out, stream=stream)
+
         key = shape_key(points.shape[1], int(kernel.two_nu), T, stride, k, precision)
         if key not in self.choices or order.shape[0] != T:
             check_permutation(order, T)  # once per shape class (it reads the order back)
-        runners = {"natural": natural, "spatial": spatial}
+        runners = {"natural": natural, "spatial": spatial, "natural/mw": natural_mw, "spatial/mw": spatial_mw}
         runners[self.choose(key, runners, stream)]()
         return out

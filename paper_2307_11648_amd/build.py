@@ -39,6 +39,9 @@ def _select_unit(t, nu, g, rpl):
 HIP_UNITS = [("abi.cpp", []), ("plan.cpp", []), ("select.hip", [])] + [
     _select_unit(t, nu, g, rpl)
     for t in ("float", "double") for nu in (1, 3, 5) for g in (0, 1) for rpl in (1, 2, 4, 8)
+] + [
+    (("select_mw_inst.hip", [f"-DCSEL_MW_T={t}", f"-DCSEL_MW_NU={nu}", f"-DCSEL_MW_W={w}", f"-DCSEL_MW_RPL={r}"]))
+    for t in ("float", "double") for nu in (1, 3, 5) for (w, r) in ((2, 1), (4, 1), (4, 2))
 ] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip")] + [
     # the screen's ReLU/min/max need no NaN handling: plain v_max/v_min without
     # the IEEE-mode quieting of their inputs; the max-ilp machine scheduler runs

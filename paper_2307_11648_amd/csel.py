@@ -100,6 +100,12 @@ def load():
     lib.csel_mlp_grad_workspace_size.restype = ctypes.c_int64
     lib.csel_mlp_grad.argtypes = [_vp, _vp, _vp, _vp, _c.c_int64, _c.c_float, _vp, _c.c_int64, _vp, _vp]
     lib.csel_mlp_grad.restype = ctypes.c_int
+    lib.csel_select_waves_per_column.argtypes = [_c.c_int32]
+    lib.csel_select_waves_per_column.restype = ctypes.c_int32
+    lib.csel_select_and_factor_sched.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams),
+                                                 _c.c_int64, _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
+                                                 _vp, _vp, _c.c_int64, _c.c_int32, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_select_and_factor_sched.restype = ctypes.c_int
     lib.csel_plan_create.argtypes = [ctypes.POINTER(_vp), _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32,
                                      _c.c_uint32]
     lib.csel_plan_create.restype = ctypes.c_int
@@ -110,7 +116,8 @@ def load():
     lib.csel_screened_select.argtypes = [_vp, _vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _vp, _vp,
                                          _vp, _vp, _vp, _c.c_float, _vp, _vp, _vp, _vp, _vp]
     lib.csel_screened_select.restype = ctypes.c_int
-    lib.csel_plan_info.argtypes = [_vp, ctypes.POINTER(_c.c_int32), ctypes.POINTER(_c.c_float)]
+    lib.csel_plan_info.argtypes = [_vp, ctypes.POINTER(_c.c_int32), ctypes.POINTER(_c.c_int32),
+                                   ctypes.POINTER(_c.c_float)]
     lib.csel_plan_info.restype = ctypes.c_int
     lib.csel_plan_screen_outputs.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.csel_plan_screen_outputs.restype = ctypes.c_int
@@ -210,6 +217,44 @@ def select_and_factor_list(points, kernel, targets, pool, pool_len, k: int, prec
     return out
 
 
+def select_waves_per_column(pool_stride: int) -> int:
+    """The multi-wave schedule's wavefronts per column for this pool width."""
+    return int(load().csel_select_waves_per_column(int(pool_stride)))
+
+
+def select_and_factor_sched(points, kernel, targets, pool, pool_len, k: int, precision: str = "fp64",
+                            waves: int = 1, col_list=None, col_count=None, max_cols: int = 0,
+                            out: dict | None = None, stream=None) -> dict:
+    """csel_select_and_factor_sched: the selection under an explicit schedule
+    (waves per column, optional column list); the same outputs as
+    select_and_factor without the gap."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    _dev(targets, torch.int32, "targets")
+    _dev(pool, torch.int32, "pool")
+    _dev(pool_len, torch.int32, "pool_len")
+    if col_list is not None:
+        _dev(col_list, torch.int32, "col_list")
+        _dev(col_count, torch.int32, "col_count")
+        if col_list.numel() < max_cols or col_count.numel() < 1:
+            raise ValueError("col_list must hold max_cols entries and col_count one")
+    T = targets.shape[0]
+    stride = pool.shape[1] if pool.dim() == 2 else 0
+    dev = points.device
+    if out is None:
+        out = {"sel": torch.empty((T, k), dtype=torch.int32, device=dev),
+               "factor": torch.empty((T, k + 1), dtype=torch.float64, device=dev),
+               "log_condvar": torch.empty(T, dtype=torch.float64, device=dev),
+               "status": torch.empty(T, dtype=torch.uint8, device=dev)}
+    kp = kernel_struct(kernel)
+    _check(lib.csel_select_and_factor_sched(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), T,
+                                            targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride, int(k),
+                                            _PREC[precision], _ptr(col_list), _ptr(col_count), int(max_cols),
+                                            int(waves), _ptr(out["sel"]), _ptr(out["factor"]),
+                                            _ptr(out.get("log_condvar")), _ptr(out["status"]), _stream(stream)))
+    return out
+
+
 # --------------------------------------------------------------------------
 # the screened-selection plan (one call per learned-screened step)
 # --------------------------------------------------------------------------
@@ -287,13 +332,18 @@ class Plan:
         return out
 
     def info(self) -> dict:
-        """The kept-pool schedule ("natural", "spatial" or None before the
-        first step) and the tuning step's timings in ms."""
+        """The tuned schedules (None before the first step): the kept-pool
+        selection's ("natural", "spatial", "natural/mw" or "spatial/mw") and
+        the fallback launch's waves per column, with the tuning times in ms."""
         sc = ctypes.c_int32(-1)
-        ms = (ctypes.c_float * 2)()
-        _check(self._lib.csel_plan_info(self._h, ctypes.byref(sc), ms))
-        name = {0: "natural", 1: "spatial"}.get(sc.value)
-        return {"schedule": name, "ms": {"natural": float(ms[0]), "spatial": float(ms[1])}}
+        fw = ctypes.c_int32(1)
+        ms = (ctypes.c_float * 6)()
+        _check(self._lib.csel_plan_info(self._h, ctypes.byref(sc), ctypes.byref(fw), ms))
+        names = ("natural", "spatial", "natural/mw", "spatial/mw")
+        name = names[sc.value] if 0 <= sc.value < 4 else None
+        return {"schedule": name, "fallback_waves": int(fw.value) if name else None,
+                "ms": {n: float(ms[i]) for i, n in enumerate(names)},
+                "fallback_ms": {"1": float(ms[4]), "mw": float(ms[5])}}
 
 
 # --------------------------------------------------------------------------

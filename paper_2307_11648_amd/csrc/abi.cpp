@@ -115,6 +115,68 @@ CSEL_API int csel_select_and_factor(const double* pts, int64_t n, int32_t dim, c
     return CSEL_OK;
 }
 
+CSEL_API int32_t csel_select_waves_per_column(int32_t pool_stride) {
+    if (pool_stride < 0 || pool_stride > kMaxPool) return -1;
+    return csel::select_mw_waves(pool_stride);
+}
+
+CSEL_API int csel_select_and_factor_sched(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                          int64_t n_targets, const int32_t* targets, const int32_t* pool_idx,
+                                          const int32_t* pool_len, int32_t pool_stride, int32_t k, int32_t precision,
+                                          const int32_t* col_list, const int32_t* col_count, int64_t max_cols,
+                                          int32_t waves_per_column, int32_t* sel_idx, double* factor_val,
+                                          double* log_condvar, uint8_t* status, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_targets < 0 || max_cols < 0) return fail(CSEL_EINVAL, "n_targets and max_cols must be >= 0");
+    if (pool_stride < 0 || pool_stride > kMaxPool)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [0, %d] (got %d)", kMaxPool, pool_stride);
+    if (k < 0 || k > kMaxSelect) return fail(CSEL_EUNSUPPORTED, "k must be in [0, %d] (got %d)", kMaxSelect, k);
+    if (precision != CSEL_FP64 && precision != CSEL_MIXED)
+        return fail(CSEL_EINVAL, "precision must be CSEL_FP64 or CSEL_MIXED");
+    const int mw = csel::select_mw_waves(pool_stride);
+    if (waves_per_column != 1 && waves_per_column != mw)
+        return fail(CSEL_EUNSUPPORTED, "waves_per_column must be 1 or %d for pool_stride %d (got %d)", mw,
+                    pool_stride, waves_per_column);
+    if ((col_list == nullptr) != (col_count == nullptr)) return fail(CSEL_EINVAL, "col_list and col_count go together");
+    const int64_t cols = col_list ? max_cols : n_targets;
+    if (n_targets == 0 || cols == 0) return CSEL_OK;
+    if (!pts || !targets || !pool_len || !status || !factor_val || (k > 0 && !sel_idx) ||
+        (pool_stride > 0 && !pool_idx))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    csel::SelectArgs a{};
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.s2 = kernel->variance;
+    a.nugget = kernel->nugget;
+    a.n_targets = n_targets;
+    a.targets = targets;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    a.k = k;
+    a.sel = sel_idx;
+    a.fac = factor_val;
+    a.logcv = log_condvar;
+    a.gap = nullptr;
+    a.status = status;
+    a.col_list = col_list;
+    a.col_count = col_count;
+    a.n_waves = cols;
+    const int rpl = pool_stride <= 64 ? 1 : pool_stride <= 128 ? 2 : pool_stride <= 256 ? 4 : 8;
+    const int kmax = k <= 16 ? 16 : 32;
+    hipError_t e = waves_per_column == 1 ? csel::launch_select_factor(a, precision, rpl, kmax, stream)
+                                         : csel::launch_select_factor_mw(a, precision, kmax, stream);
+    if (e != hipSuccess) return hip_fail(e, "select_and_factor_sched launch");
+    return CSEL_OK;
+}
+
 CSEL_API int csel_sum(const double* x, int64_t n, double* out, hipStream_t stream) {
     g_err[0] = 0;
     if (n < 0) return fail(CSEL_EINVAL, "n must be >= 0");

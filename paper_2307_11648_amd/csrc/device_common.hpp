@@ -192,10 +192,55 @@ __device__ __forceinline__ float matern_f32(float r, float c, float s2) {
     return s2 * (1.0f + a + a * a * (1.0f / 3.0f)) * e;
 }
 
+// e^{-a} for finite a >= 0 in FP64, about 2 ulp: Cody-Waite reduction
+// -a = k ln2 + r with k = rint(-a / ln2) and ln2 split into a 32-bit head
+// (k * head exact for |k| < 2^21) and its tail, |r| <= ln2/2; then the
+// degree-12 Taylor polynomial of e^r (truncation below 2.3e-16 relative) in
+// Horner form, scaled by 2^k.  For a past ~745 the scaling underflows to 0.
+// The argument is never infinite or NaN here, so the special-value checks of
+// a general exp are left out.
+__device__ __forceinline__ double exp_neg64(double a) {
+    constexpr double kInvLn2 = 1.4426950408889634;
+    constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
+    constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+    const double x = -a;
+    const double k = __builtin_rint(x * kInvLn2);
+    double r = fma(-k, kLn2Hi, x);
+    r = fma(-k, kLn2Lo, r);
+    double q = 2.08767569878681e-09;  // 1/12!
+    q = fma(q, r, 2.505210838544172e-08);
+    q = fma(q, r, 2.755731922398589e-07);
+    q = fma(q, r, 2.7557319223985893e-06);
+    q = fma(q, r, 2.48015873015873e-05);
+    q = fma(q, r, 0.0001984126984126984);
+    q = fma(q, r, 0.001388888888888889);
+    q = fma(q, r, 0.008333333333333333);
+    q = fma(q, r, 0.041666666666666664);
+    q = fma(q, r, 0.16666666666666666);
+    q = fma(q, r, 0.5);
+    q = fma(q, r, 1.0);
+    q = fma(q, r, 1.0);
+    return __builtin_amdgcn_ldexp(q, (int)k);
+}
+
+// sqrt(s) for s >= 0 in FP64, about 1 ulp: the hardware reciprocal square
+// root, one Goldschmidt step (g -> sqrt(s), h -> 1/(2 sqrt(s))) and one
+// Newton correction of g; 0 for s = 0.
+__device__ __forceinline__ double dist64(double s) {
+    const double y = __builtin_amdgcn_rsq(s);
+    double g = s * y, h = 0.5 * y;
+    const double e = fma(-h, g, 0.5);
+    g = fma(g, e, g);
+    h = fma(h, e, h);
+    const double d = fma(-g, g, s);
+    g = fma(d, h, g);
+    return s > 0.0 ? g : 0.0;
+}
+
 template <int TWO_NU>
 __device__ __forceinline__ double matern_f64(double r, double c, double s2) {
     const double a = c * r;
-    const double e = exp(-a);
+    const double e = exp_neg64(a);
     if constexpr (TWO_NU == 1) return s2 * e;
     if constexpr (TWO_NU == 3) return s2 * (1.0 + a) * e;
     return s2 * (1.0 + a + a * a * (1.0 / 3.0)) * e;

@@ -30,9 +30,6 @@ struct SelectArgs {
     const int32_t* col_list;
     const int32_t* col_count;
     int64_t n_waves;  // waves launched: n_targets, or the list capacity
-    // with col_list: a fixed grid whose waves stride through the list up to
-    // *col_count (n_waves is then ignored; the count is bounded by n_targets)
-    int32_t persistent;
 };
 
 struct ScreenArgs {
@@ -169,6 +166,10 @@ int agg_factor_max_m();
 
 // rpl: pool rows per lane (1, 2, 4, 8); kmax: 16 or 32.
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s);
+// the multi-wave schedule (no gap output): select_mw_waves(stride) waves per
+// column, 2 for pools <= 128, 4 up to 512
+int select_mw_waves(int32_t stride);
+hipError_t launch_select_factor_mw(const SelectArgs& a, int precision, int kmax, hipStream_t s);
 int64_t transpose_factor_workspace(int64_t n, int64_t n_slots);
 hipError_t launch_transpose_factor(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val,
                                    int64_t n_slots, int64_t* t_col_ptr, int32_t* t_row_idx, double* t_val,

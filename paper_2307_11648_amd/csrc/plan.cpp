@@ -82,9 +82,12 @@ struct csel_plan {
     void* order_ws = nullptr;
     int64_t order_ws_bytes = 0;
     bool has_order = false;
-    // the kept-pool selection's column schedule: 0 natural, 1 spatial, -1 untuned
+    // the kept-pool selection's schedule, -1 untuned: bit 0 the Morton column
+    // order (else natural), bit 1 the multi-wave schedule (else one wave per
+    // column); and the fallback launch's waves per column
     int schedule = -1;
-    float tune_ms[2] = {0.0f, 0.0f};
+    int fb_waves = 1;
+    float tune_ms[6] = {0.0f, 0.0f, 0.0f, 0.0f, 0.0f, 0.0f};
     // the captured step
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
@@ -129,17 +132,18 @@ csel::SelectArgs select_args(const csel_plan* p, const StepKey& a) {
 int rpl_of(int32_t stride) { return stride <= 64 ? 1 : stride <= 128 ? 2 : stride <= 256 ? 4 : 8; }
 int kmax_of(int32_t k) { return k <= 16 ? 16 : 32; }
 
-// the greedy selection on the kept pools under a column schedule
+// the greedy selection on the kept pools under a schedule (see csel_plan)
 hipError_t enqueue_kept(const csel_plan* p, const StepKey& a, int schedule, hipStream_t s) {
     csel::SelectArgs sa = select_args(p, a);
     sa.pool = p->kept;
     sa.pool_len = p->kept_len;
     sa.stride = p->keep;
-    if (schedule == 1) {
+    if (schedule & 1) {
         sa.col_list = p->order;
         sa.col_count = p->n_all;
     }
     sa.n_waves = p->n_targets;
+    if (schedule & 2) return csel::launch_select_factor_mw(sa, p->precision, kmax_of(p->k), s);
     return csel::launch_select_factor(sa, p->precision, rpl_of(p->keep), kmax_of(p->k), s);
 }
 
@@ -175,8 +179,11 @@ hipError_t enqueue_screen(const csel_plan* p, const StepKey& a, hipStream_t s) {
     return csel::launch_screen(sa, rpl_of(p->stride), s);
 }
 
-// full-pool selection of the listed fallback columns: a fixed grid striding
-// through the device-side list up to its device-side count
+// full-pool selection of the listed fallback columns: the launch covers
+// every column's list position (the list's capacity), and the waves past the
+// device-side count exit at once, so the launch needs no host read of the
+// count (a grid-stride loop over the list would keep the selection's
+// invariants live across the column body and double its registers)
 hipError_t enqueue_fallback(const csel_plan* p, const StepKey& a, hipStream_t s) {
     csel::SelectArgs sa = select_args(p, a);
     sa.pool = a.pool_idx;
@@ -184,8 +191,8 @@ hipError_t enqueue_fallback(const csel_plan* p, const StepKey& a, hipStream_t s)
     sa.stride = p->stride;
     sa.col_list = p->fb_list;
     sa.col_count = p->fb_count;
-    sa.persistent = 1;
     sa.n_waves = p->n_targets;
+    if (p->fb_waves > 1) return csel::launch_select_factor_mw(sa, p->precision, kmax_of(p->k), s);
     return csel::launch_select_factor(sa, p->precision, rpl_of(p->stride), kmax_of(p->k), s);
 }
 
@@ -196,27 +203,48 @@ hipError_t enqueue_step(const csel_plan* p, const StepKey& a, hipStream_t s) {
     return e;
 }
 
-// time the kept-pool selection under both schedules on the caller's stream
-// (each once to warm up, once timed with HIP events) and keep the faster
+// one warm-up and one timed run of `run` on the caller's stream (HIP events)
+template <typename F>
+hipError_t time_once(F run, hipStream_t s, hipEvent_t e0, hipEvent_t e1, float* ms) {
+    hipError_t e = run();
+    if (e == hipSuccess) e = hipEventRecord(e0, s);
+    if (e == hipSuccess) e = run();
+    if (e == hipSuccess) e = hipEventRecord(e1, s);
+    if (e == hipSuccess) e = hipEventSynchronize(e1);
+    if (e == hipSuccess) e = hipEventElapsedTime(ms, e0, e1);
+    return e;
+}
+
+// time the kept-pool selection under each schedule (natural or Morton order
+// when the plan has one; one wave or several per column) and the fallback
+// launch under one wave or several per column, on the caller's stream after
+// its screen, and keep the fastest of each (ties to the lower number)
 hipError_t tune(csel_plan* p, const StepKey& a, hipStream_t s) {
-    if (!p->has_order || p->n_targets < kTuneMinColumns) {
+    if (p->n_targets < kTuneMinColumns) {
         p->schedule = 0;
+        p->fb_waves = 1;
         return hipSuccess;
     }
     hipEvent_t e0 = nullptr, e1 = nullptr;
     hipError_t e = hipEventCreate(&e0);
     if (e == hipSuccess) e = hipEventCreate(&e1);
-    for (int sc = 0; sc < 2 && e == hipSuccess; ++sc) {
-        e = enqueue_kept(p, a, sc, s);
-        if (e == hipSuccess) e = hipEventRecord(e0, s);
-        if (e == hipSuccess) e = enqueue_kept(p, a, sc, s);
-        if (e == hipSuccess) e = hipEventRecord(e1, s);
-        if (e == hipSuccess) e = hipEventSynchronize(e1);
-        if (e == hipSuccess) e = hipEventElapsedTime(&p->tune_ms[sc], e0, e1);
+    int best = 0;
+    for (int sc = 0; sc < 4 && e == hipSuccess; ++sc) {
+        if ((sc & 1) && !p->has_order) continue;
+        e = time_once([&] { return enqueue_kept(p, a, sc, s); }, s, e0, e1, &p->tune_ms[sc]);
+        if (e == hipSuccess && p->tune_ms[sc] < p->tune_ms[best]) best = sc;
+    }
+    const int mw = csel::select_mw_waves(p->stride);
+    for (int v = 0; v < 2 && e == hipSuccess; ++v) {
+        p->fb_waves = v ? mw : 1;
+        e = time_once([&] { return enqueue_fallback(p, a, s); }, s, e0, e1, &p->tune_ms[4 + v]);
     }
     if (e0) (void)hipEventDestroy(e0);
     if (e1) (void)hipEventDestroy(e1);
-    if (e == hipSuccess) p->schedule = p->tune_ms[1] < p->tune_ms[0] ? 1 : 0;
+    if (e == hipSuccess) {
+        p->schedule = best;
+        p->fb_waves = p->tune_ms[5] < p->tune_ms[4] ? mw : 1;
+    }
     return e;
 }
 
@@ -314,14 +342,13 @@ CSEL_API int csel_plan_set_order(csel_plan* plan, const double* pts, int64_t n, 
     return CSEL_OK;
 }
 
-CSEL_API int csel_plan_info(const csel_plan* plan, int32_t* schedule, float* tune_ms) {
+CSEL_API int csel_plan_info(const csel_plan* plan, int32_t* kept_schedule, int32_t* fallback_waves, float* tune_ms) {
     csel_internal_fail(CSEL_OK, "");
     if (!plan) return pfail(CSEL_EINVAL, "plan is NULL");
-    if (schedule) *schedule = plan->schedule;
-    if (tune_ms) {
-        tune_ms[0] = plan->tune_ms[0];
-        tune_ms[1] = plan->tune_ms[1];
-    }
+    if (kept_schedule) *kept_schedule = plan->schedule;
+    if (fallback_waves) *fallback_waves = plan->fb_waves;
+    if (tune_ms)
+        for (int i = 0; i < 6; ++i) tune_ms[i] = plan->tune_ms[i];
     return CSEL_OK;
 }
 

@@ -75,6 +75,51 @@ hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int
 }
 
 // ---------------------------------------------------------------------------
+// the multi-wave schedule: (waves per column, rows per lane) for each pool width
+// ---------------------------------------------------------------------------
+#define CSEL_MW_DECL1(T, NU, W, R) hipError_t launch_select_mw_##T##_##NU##_##W##_##R(const SelectArgs&, int, hipStream_t);
+#define CSEL_MW_DECL(T, NU)     \
+    CSEL_MW_DECL1(T, NU, 2, 1)  \
+    CSEL_MW_DECL1(T, NU, 4, 1)  \
+    CSEL_MW_DECL1(T, NU, 4, 2)
+CSEL_MW_DECL(float, 1)
+CSEL_MW_DECL(float, 3)
+CSEL_MW_DECL(float, 5)
+CSEL_MW_DECL(double, 1)
+CSEL_MW_DECL(double, 3)
+CSEL_MW_DECL(double, 5)
+#undef CSEL_MW_DECL
+#undef CSEL_MW_DECL1
+
+int select_mw_waves(int32_t stride) { return stride <= 128 ? 2 : 4; }
+
+#define CSEL_MW_PICK(T, NU)                                                            \
+    if (stride <= 128) return launch_select_mw_##T##_##NU##_2_1(a, kmax, s);           \
+    if (stride <= 256) return launch_select_mw_##T##_##NU##_4_1(a, kmax, s);           \
+    return launch_select_mw_##T##_##NU##_4_2(a, kmax, s);
+
+hipError_t launch_select_factor_mw(const SelectArgs& a, int precision, int kmax, hipStream_t s) {
+    if (a.n_targets == 0 || a.n_waves == 0) return hipSuccess;
+    if (a.gap != nullptr || a.stride > 512) return hipErrorInvalidValue;
+    const int32_t stride = a.stride;
+    if (precision == 0) {
+        switch (a.two_nu) {
+            case 1: { CSEL_MW_PICK(double, 1) }
+            case 3: { CSEL_MW_PICK(double, 3) }
+            case 5: { CSEL_MW_PICK(double, 5) }
+        }
+    } else {
+        switch (a.two_nu) {
+            case 1: { CSEL_MW_PICK(float, 1) }
+            case 3: { CSEL_MW_PICK(float, 3) }
+            case 5: { CSEL_MW_PICK(float, 5) }
+        }
+    }
+    return hipErrorInvalidValue;
+}
+#undef CSEL_MW_PICK
+
+// ---------------------------------------------------------------------------
 // deterministic FP64 sum: one block of 1024 threads, fixed order
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(1024) void sum_kernel(const double* __restrict__ x, int64_t n, double* out) {

@@ -36,12 +36,12 @@
 
 namespace csel {
 
-// distance square root: the hardware v_sqrt_f32 (1 ulp) in FP32, the
-// correctly rounded one in FP64
+// distance square root: the hardware v_sqrt_f32 (1 ulp) in FP32, dist64
+// (about 1 ulp) in FP64
 template <typename T>
 __device__ __forceinline__ T tsqrt(T x) {
     if constexpr (sizeof(T) == 4) return __builtin_amdgcn_sqrtf(x);
-    else return sqrt(x);
+    else return dist64(x);
 }
 
 template <typename T, int TWO_NU>
@@ -51,18 +51,176 @@ __device__ __forceinline__ T matern(T r, T c, T s2) {
 }
 
 constexpr int kSelWavesPerBlock = 4;
-// the persistent list launch: 2,048 blocks of 4 waves (a multiple of the 8
-// XCDs), 8,192 waves striding through the list
-constexpr int kSelPersistentBlocks = 2048;
 
-// One column: the greedy selection and the factor column of column `col`,
-// run by one wavefront (lane `lane`, wave `wib` of its block).  GAP: also
-// track the second-best score of every step (top-two reduction) for the
-// top2_gap output; without it the reduction is a plain maximum.
+// Factor column (eq. L_col) of one column on its nsel selected points, by
+// one wavefront: lane t holds pick t in my_sel (and its gap in my_gap).
+// Theta' over [selected..., target] is built in FP64 in LDS (TH, PT: this
+// wave's buffers) and factored as L D L^T on lane pairs; writes the column's
+// sel, factor, log_condvar, gap and status outputs.
+template <int TWO_NU, int KMAX>
+__device__ __forceinline__ void factor_column(const SelectArgs& p, int64_t col, int lane, int nsel, int32_t my_sel,
+                                              float my_gap, int32_t tgt, int st, double (&TH)[KMAX + 1][KMAX + 2],
+                                              double (&PT)[KMAX + 1][4]) {
+    const int kout = p.k;
+    const int dim = p.dim;
+    int32_t* sel_out = p.sel + col * kout;
+    double* fac_out = p.fac + col * (kout + 1);
+    const int M = nsel + 1;
+    const int32_t my_id = lane < nsel ? my_sel : (lane == nsel ? tgt : -1);
+    // the points of s (lane r: selected point r, lane nsel: the target) -> LDS
+    if (lane < M) {
+        const int64_t b = (int64_t)my_id * dim;
+        PT[lane][0] = p.pts[b];
+        PT[lane][1] = dim > 1 ? p.pts[b + 1] : 0.0;
+        PT[lane][2] = dim > 2 ? p.pts[b + 2] : 0.0;
+        PT[lane][3] = (double)my_id;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const double cnu64 = p.c_nu, s264 = p.s2, nug64 = p.nugget;
+    // Theta' = L D L^T (L unit lower triangular), FP64.  Row r >= 1 of Theta'
+    // belongs to the lane pair (r - 1, r - 1 + 32): the low lane holds the
+    // row's even columns, the high lane its odd columns, so each dot product
+    // is split over two lanes and joined by one cross-half swap.  Row r of the
+    // LDS buffer TH keeps column c at slot pos(c) = (c & 1) * HALF + (c >> 1):
+    // each half's columns contiguous and 16-byte aligned, the even half in
+    // slots 0 .. KMAX/2, the diagonal in slot HALF - 1, the odd half in slots
+    // HALF .. KMAX + 1.  The slot pos(r) of row r holds 0.
+    constexpr int HALF = KMAX / 2 + 2;
+    constexpr int DIAG = HALF - 1;
+    static_assert(HALF + (KMAX - 1) / 2 <= KMAX + 1 && DIAG > KMAX / 2, "row layout");
+    {
+        const int ne = M * (M + 1) / 2;
+        // entry e of the row-major lower triangle is (r, c) with r = floor(x),
+        // x = (sqrt(8e + 1) - 1) / 2: for rows r <= 32, x lies in
+        // [r, r + 1 - 2 / (2r + 3)], so x + 1e-3 truncates to r under a
+        // square root within one ulp
+        static_assert(KMAX <= 32, "triangle index bound");
+        for (int e = lane; e < ne; e += kWave) {
+            const int r = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f + 1e-3f);
+            const int c = e - r * (r + 1) / 2;
+            const double d0 = PT[r][0] - PT[c][0], d1 = PT[r][1] - PT[c][1], d2 = PT[r][2] - PT[c][2];
+            const double s2d = d0 * d0 + d1 * d1 + d2 * d2;
+            const double rr = s2d > 0.0 ? s2d * rsq64(s2d) : 0.0;
+            const double th = matern_f64<TWO_NU>(rr, cnu64, s264) + (PT[r][3] == PT[c][3] ? nug64 : 0.0);
+            if (c < r) {
+                TH[r][(c & 1) * HALF + (c >> 1)] = th;
+            } else {
+                TH[r][DIAG] = th;
+                TH[r][(r & 1) * HALF + (r >> 1)] = 0.0;
+            }
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    const int hi = lane >> 5;
+    const int my_row = (lane & 31) + 1;
+    const bool row_ok = my_row < M;
+    // h[q]: column 2q + hi of my row (Theta' until that column is done, then L).
+    // Every lane loads a whole half row (lanes past the last row read row 0 and
+    // never use it); the odd half has one column fewer, so its last register
+    // repeats the slot before, keeping the read inside the row.
+    double h[KMAX / 2 + 1];
+    const double* my_th = &TH[row_ok ? my_row : 0][hi * HALF];
+#pragma unroll
+    for (int q = 0; q <= KMAX / 2; ++q) h[q] = my_th[q == KMAX / 2 ? q - hi : q];
+    const double diag = TH[row_ok ? my_row : 0][DIAG];
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    // Left-looking by columns: with W[j][c] = d_c L[j][c] (row j of TH, written
+    // as column c finished), every row r >= j needs v_r = Theta'[r][j] -
+    // sum_{c<j} L[r][c] W[j][c]; then d_j = v_j and L[r][j] = v_r / d_j.  The
+    // high lane's sum for odd j reads the zero slot pos(j) of row j as its last
+    // term.  Entries of rows below j and lanes past the last row are never
+    // read.
+    bool pd = true;
+    double dinv = 0.0;   // lane c: 1 / d_c
+    double dlast = 0.0;  // d of the last row (the target's conditional variance)
+#pragma unroll
+    for (int j = 0; j <= KMAX; ++j) {
+        if (j >= M || !pd) continue;
+        double part = 0.0;
+        const double* wj = &TH[j][hi * HALF];
+#pragma unroll
+        for (int q = 0; q < (j + 1) / 2; ++q) part = fma(h[q], wj[q], part);
+        const double tot = pair_sum(part);
+        const double dj = j == 0 ? TH[0][DIAG] : bcast(diag - tot, j - 1);
+        if (!(dj > 0.0)) {
+            pd = false;
+            continue;
+        }
+        const double inv = rcp64_acc(dj);
+        if (lane == j) dinv = inv;
+        dlast = dj;
+        if (hi == (j & 1) && my_row > j && row_ok) {
+            const double v = h[j >> 1] - tot;
+            h[j >> 1] = v * inv;
+            TH[my_row][(j & 1) * HALF + (j >> 1)] = v;
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
+
+    double y = 0.0;
+    if (pd) {
+        // Theta'^{-1} e_last = L^{-T} e_last / d_last and e_last^T Theta'^{-1}
+        // e_last = 1 / d_last, so the column is z / sqrt(d_last) with L^T z =
+        // e_last: z_last = 1, z_c = -(1 / d_c) sum_{r>c} W[r][c] z_r, lane c
+        // accumulating its sum from the rows left in TH.
+        const int l = nsel;
+        const int my_pos = lane <= KMAX ? (lane & 1) * HALF + (lane >> 1) : 0;
+        double acc = 0.0;
+#pragma unroll
+        for (int c = KMAX; c >= 0; --c) {
+            if (c > l) continue;
+            const double zc = c == l ? 1.0 : bcast(-acc * dinv, c);
+            if (lane < c) acc = fma(TH[c][my_pos], zc, acc);
+        }
+        // lane c's sum was complete at its own step and untouched after it
+        const double z = lane == l ? 1.0 : (lane < l ? -acc * dinv : 0.0);
+        y = z * rsq64(dlast);
+        if (p.logcv && lane == 0) p.logcv[col] = log(dlast);
+    } else {
+        st = 2;
+        y = __builtin_nan("");
+        if (lane == 0 && p.logcv) p.logcv[col] = __builtin_nan("");
+    }
+    if (lane < kout) {
+        sel_out[lane] = lane < nsel ? my_sel : -1;
+        fac_out[1 + lane] = lane < nsel ? y : (pd ? 0.0 : __builtin_nan(""));
+        if (p.gap) p.gap[col * kout + lane] = my_gap;
+    }
+    if (lane == nsel) fac_out[0] = y;
+    if (lane == 0) p.status[col] = (uint8_t)st;
+}
+
+
+// GAP: also track the second-best score of every step (top-two reduction) for
+// the top2_gap output; without it the reduction is a plain maximum.
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
-__device__ __forceinline__ void select_column(const SelectArgs& p, int64_t col, int wib, int lane,
-                                              double (&sh_r)[kSelWavesPerBlock][KMAX + 1][KMAX + 2],
-                                              double (&sh_pt)[kSelWavesPerBlock][KMAX + 1][4]) {
+__global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
+    static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
+    __shared__ __align__(16) double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
+    __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
+
+    const int lane = lane_id();
+    const int wib = threadIdx.x >> 6;
+    int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
+    if (p.col_list) {
+        // the list's positions in eight contiguous segments, one per XCD
+        // (blocks go to the XCDs round-robin; the launch rounds the grid up to
+        // a multiple of 8), so the columns of a spatially sorted list that run
+        // together on one XCD share its L2.  Segments follow the list's actual
+        // length, so a short list still spreads over every XCD.
+        const int64_t cnt = min((int64_t)*p.col_count, p.n_waves);
+        const int64_t seg = ((cnt + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock * kSelWavesPerBlock;
+        const int64_t lb = (int64_t)(blockIdx.x >> 3) * kSelWavesPerBlock + wib;
+        const int64_t pos = (int64_t)(blockIdx.x & 7u) * seg + lb;
+        if (lb >= seg || pos >= cnt) return;
+        col = p.col_list[pos];
+    }
+    if (col < 0 || col >= p.n_targets) return;
+
     const int kout = p.k;
     int32_t* sel_out = p.sel + col * kout;
     double* fac_out = p.fac + col * (kout + 1);
@@ -251,170 +409,7 @@ __device__ __forceinline__ void select_column(const SelectArgs& p, int64_t col, 
         }
     }
 
-    // ---- factor column: Theta' over [selected..., target], FP64 ------------
-    const int M = nsel + 1;
-    const int32_t my_id = lane < nsel ? my_sel : (lane == nsel ? tgt : -1);
-    // the points of s (lane r: selected point r, lane nsel: the target) -> LDS
-    double(*PT)[4] = sh_pt[wib];
-    if (lane < M) {
-        const int64_t b = (int64_t)my_id * dim;
-        PT[lane][0] = p.pts[b];
-        PT[lane][1] = dim > 1 ? p.pts[b + 1] : 0.0;
-        PT[lane][2] = dim > 2 ? p.pts[b + 2] : 0.0;
-        PT[lane][3] = (double)my_id;
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const double cnu64 = p.c_nu, s264 = p.s2, nug64 = p.nugget;
-    // Theta' = L D L^T (L unit lower triangular), FP64.  Row r >= 1 of Theta'
-    // belongs to the lane pair (r - 1, r - 1 + 32): the low lane holds the
-    // row's even columns, the high lane its odd columns, so each dot product
-    // is split over two lanes and joined by one cross-half swap.  Row r of the
-    // LDS buffer TH keeps column c at slot pos(c) = (c & 1) * HALF + (c >> 1):
-    // each half's columns contiguous and 16-byte aligned, the even half in
-    // slots 0 .. KMAX/2, the diagonal in slot HALF - 1, the odd half in slots
-    // HALF .. KMAX + 1.  The slot pos(r) of row r holds 0.
-    constexpr int HALF = KMAX / 2 + 2;
-    constexpr int DIAG = HALF - 1;
-    static_assert(HALF + (KMAX - 1) / 2 <= KMAX + 1 && DIAG > KMAX / 2, "row layout");
-    double(*TH)[KMAX + 2] = sh_r[wib];
-    {
-        const int ne = M * (M + 1) / 2;
-        // entry e of the row-major lower triangle is (r, c) with r = floor(x),
-        // x = (sqrt(8e + 1) - 1) / 2: for rows r <= 32, x lies in
-        // [r, r + 1 - 2 / (2r + 3)], so x + 1e-3 truncates to r under a
-        // square root within one ulp
-        static_assert(KMAX <= 32, "triangle index bound");
-        for (int e = lane; e < ne; e += kWave) {
-            const int r = (int)((__builtin_amdgcn_sqrtf(8.0f * (float)e + 1.0f) - 1.0f) * 0.5f + 1e-3f);
-            const int c = e - r * (r + 1) / 2;
-            const double d0 = PT[r][0] - PT[c][0], d1 = PT[r][1] - PT[c][1], d2 = PT[r][2] - PT[c][2];
-            const double s2d = d0 * d0 + d1 * d1 + d2 * d2;
-            const double rr = s2d > 0.0 ? s2d * rsq64(s2d) : 0.0;
-            const double th = matern_f64<TWO_NU>(rr, cnu64, s264) + (PT[r][3] == PT[c][3] ? nug64 : 0.0);
-            if (c < r) {
-                TH[r][(c & 1) * HALF + (c >> 1)] = th;
-            } else {
-                TH[r][DIAG] = th;
-                TH[r][(r & 1) * HALF + (r >> 1)] = 0.0;
-            }
-        }
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    const int hi = lane >> 5;
-    const int my_row = (lane & 31) + 1;
-    const bool row_ok = my_row < M;
-    // h[q]: column 2q + hi of my row (Theta' until that column is done, then L).
-    // Every lane loads a whole half row (lanes past the last row read row 0 and
-    // never use it); the odd half has one column fewer, so its last register
-    // repeats the slot before, keeping the read inside the row.
-    double h[KMAX / 2 + 1];
-    const double* my_th = &TH[row_ok ? my_row : 0][hi * HALF];
-#pragma unroll
-    for (int q = 0; q <= KMAX / 2; ++q) h[q] = my_th[q == KMAX / 2 ? q - hi : q];
-    const double diag = TH[row_ok ? my_row : 0][DIAG];
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    // Left-looking by columns: with W[j][c] = d_c L[j][c] (row j of TH, written
-    // as column c finished), every row r >= j needs v_r = Theta'[r][j] -
-    // sum_{c<j} L[r][c] W[j][c]; then d_j = v_j and L[r][j] = v_r / d_j.  The
-    // high lane's sum for odd j reads the zero slot pos(j) of row j as its last
-    // term.  Entries of rows below j and lanes past the last row are never
-    // read.
-    bool pd = true;
-    double dinv = 0.0;   // lane c: 1 / d_c
-    double dlast = 0.0;  // d of the last row (the target's conditional variance)
-#pragma unroll
-    for (int j = 0; j <= KMAX; ++j) {
-        if (j >= M || !pd) continue;
-        double part = 0.0;
-        const double* wj = &TH[j][hi * HALF];
-#pragma unroll
-        for (int q = 0; q < (j + 1) / 2; ++q) part = fma(h[q], wj[q], part);
-        const double tot = pair_sum(part);
-        const double dj = j == 0 ? TH[0][DIAG] : bcast(diag - tot, j - 1);
-        if (!(dj > 0.0)) {
-            pd = false;
-            continue;
-        }
-        const double inv = rcp64_acc(dj);
-        if (lane == j) dinv = inv;
-        dlast = dj;
-        if (hi == (j & 1) && my_row > j && row_ok) {
-            const double v = h[j >> 1] - tot;
-            h[j >> 1] = v * inv;
-            TH[my_row][(j & 1) * HALF + (j >> 1)] = v;
-        }
-        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-        __builtin_amdgcn_wave_barrier();
-    }
-
-    double y = 0.0;
-    if (pd) {
-        // Theta'^{-1} e_last = L^{-T} e_last / d_last and e_last^T Theta'^{-1}
-        // e_last = 1 / d_last, so the column is z / sqrt(d_last) with L^T z =
-        // e_last: z_last = 1, z_c = -(1 / d_c) sum_{r>c} W[r][c] z_r, lane c
-        // accumulating its sum from the rows left in TH.
-        const int l = nsel;
-        const int my_pos = lane <= KMAX ? (lane & 1) * HALF + (lane >> 1) : 0;
-        double acc = 0.0;
-#pragma unroll
-        for (int c = KMAX; c >= 0; --c) {
-            if (c > l) continue;
-            const double zc = c == l ? 1.0 : bcast(-acc * dinv, c);
-            if (lane < c) acc = fma(TH[c][my_pos], zc, acc);
-        }
-        // lane c's sum was complete at its own step and untouched after it
-        const double z = lane == l ? 1.0 : (lane < l ? -acc * dinv : 0.0);
-        y = z * rsq64(dlast);
-        if (p.logcv && lane == 0) p.logcv[col] = log(dlast);
-    } else {
-        st = 2;
-        y = __builtin_nan("");
-        if (lane == 0 && p.logcv) p.logcv[col] = __builtin_nan("");
-    }
-    if (lane < kout) {
-        sel_out[lane] = lane < nsel ? my_sel : -1;
-        fac_out[1 + lane] = lane < nsel ? y : (pd ? 0.0 : __builtin_nan(""));
-        if (p.gap) p.gap[col * kout + lane] = my_gap;
-    }
-    if (lane == nsel) fac_out[0] = y;
-    if (lane == 0) p.status[col] = (uint8_t)st;
-}
-
-template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
-__global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
-    static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
-    __shared__ __align__(16) double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
-    __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
-
-    const int lane = lane_id();
-    const int wib = threadIdx.x >> 6;
-    if (!p.col_list) {
-        const int64_t col = (int64_t)blockIdx.x * kSelWavesPerBlock + wib;
-        if (col < p.n_targets) select_column<T, TWO_NU, RPL, KMAX, GAP>(p, col, wib, lane, sh_r, sh_pt);
-        return;
-    }
-    // The list's positions in eight contiguous segments, one per XCD (blocks
-    // go to the XCDs round-robin; the launch rounds the grid up to a multiple
-    // of 8), so the columns of a spatially sorted list that run together on
-    // one XCD share its L2.  Segments follow the list's actual length, so a
-    // short list still spreads over every XCD.  Without `persistent` each
-    // wave takes one position of its segment (the grid covers n_waves
-    // positions); with it the grid is fixed and each wave strides through its
-    // segment, so the launch needs no host-side count.
-    const int64_t cnt = min((int64_t)*p.col_count, p.persistent ? p.n_targets : p.n_waves);
-    const int64_t seg = p.persistent ? (cnt + 7) / 8
-                                     : ((cnt + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock * kSelWavesPerBlock;
-    const int64_t lb = (int64_t)(blockIdx.x >> 3) * kSelWavesPerBlock + wib;
-    const int64_t stride = p.persistent ? (int64_t)(gridDim.x >> 3) * kSelWavesPerBlock : seg;
-    const int64_t first = (int64_t)(blockIdx.x & 7u) * seg;
-    const int64_t end = min(first + seg, cnt);
-    for (int64_t pos = first + lb; lb < seg && pos < end; pos += stride) {
-        const int64_t col = p.col_list[pos];
-        if (col >= 0 && col < p.n_targets) select_column<T, TWO_NU, RPL, KMAX, GAP>(p, col, wib, lane, sh_r, sh_pt);
-    }
+    factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, my_gap, tgt, st, sh_r[wib], sh_pt[wib]);
 }
 
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>
@@ -424,7 +419,6 @@ static hipError_t launch_one(const SelectArgs& a, hipStream_t s) {
         const int64_t seg = ((a.n_waves + 7) / 8 + kSelWavesPerBlock - 1) / kSelWavesPerBlock;
         blocks = 8 * seg;
     }
-    if (a.persistent && a.col_list) blocks = kSelPersistentBlocks;
     hipLaunchKernelGGL((select_factor_kernel<T, TWO_NU, RPL, KMAX, GAP>), dim3((unsigned)blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

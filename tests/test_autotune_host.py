@@ -64,7 +64,7 @@ def test_json_cache_round_trip_and_bad_files(tmp_path):
     t = autotune.SelectTuner(path=path, timer=f.timer)
     assert t.choose("x", f.runners()) == "natural"
     doc = json.load(open(path))
-    assert doc["version"] == 1 and doc["choices"]["x"]["schedule"] == "natural"
+    assert doc["version"] == 2 and doc["choices"]["x"]["schedule"] == "natural"
     # a new process reads the choice back and times nothing
     g = _Fake({"natural": 99.0, "spatial": 1.0})
     t2 = autotune.SelectTuner(path=path, timer=g.timer)
@@ -72,7 +72,7 @@ def test_json_cache_round_trip_and_bad_files(tmp_path):
     assert g.calls == {"natural": 0, "spatial": 0} and t2.tuning_runs == 0
     # unreadable, other-version or malformed files are ignored
     for text in ("not json", json.dumps({"version": 7, "choices": {"x": {"schedule": "spatial"}}}),
-                 json.dumps({"version": 1, "choices": {"x": {"schedule": "sideways"}}})):
+                 json.dumps({"version": 2, "choices": {"x": {"schedule": "sideways"}}})):
         open(path, "w").write(text)
         assert autotune.SelectTuner(path=path, timer=g.timer).choices == {}
 
@@ -86,3 +86,12 @@ def test_order_must_be_a_permutation():
     for bad in ([0, 1], [0, 1, 1], [0, 1, 3], [0, -1, 2]):
         with pytest.raises(ValueError):
             autotune.check_permutation(torch.tensor(bad, dtype=torch.int32), 3)
+
+
+def test_four_schedules_fastest_wins_and_ties_go_to_the_earlier():
+    f = _Fake({"natural": 30.0, "spatial": 28.0, "natural/mw": 21.0, "spatial/mw": 20.5})
+    t = autotune.SelectTuner(timer=f.timer)
+    assert t.choose("m", f.runners()) == "spatial/mw"
+    g = _Fake({"natural": 10.0, "spatial": 12.0, "natural/mw": 10.0, "spatial/mw": 11.0})
+    assert t.choose("n", g.runners()) == "natural"
+    assert set(autotune.SCHEDULES) == {"natural", "spatial", "natural/mw", "spatial/mw"}

@@ -188,7 +188,7 @@ def _composed_step(d, w, p, pb, keep, k, prec, thr, order=None):
                                                (0.0, False, True)])
 def test_plan_step_matches_composed_step(clustered, thr, spatial, graph):
     """csel_screened_select (one call: screen, kept-pool selection, the
-    fallback columns on a persistent grid over the device-side list) writes
+    fallback columns over the device-side list, no host read) writes
     exactly what the composition of the separate entry points writes: with
     fallback columns, with none, and with every column falling back
     (threshold 0).  With a graph, the step is replayed three times into
@@ -223,7 +223,7 @@ def test_plan_step_matches_composed_step(clustered, thr, spatial, graph):
         _composed_step(d, w, p, pb, keep, k, "fp64", 0.3)
     info = plan.info()
     print("plan schedule", info, flush=True)
-    assert info["schedule"] in ("natural", "spatial")
+    assert info["schedule"] in ("natural", "spatial", "natural/mw", "spatial/mw")
     # new output buffers: the graph is captured again and writes the new ones
     out2 = plan.step(d["pts"], w.kernel, d["tg"], d["pl"], d["ln"], p, pb, thr)
     torch.cuda.synchronize()

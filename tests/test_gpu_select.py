@@ -337,3 +337,59 @@ def test_list_variant_with_zero_count():
     torch.cuda.synchronize()
     assert torch.all(out["sel"] == -7) and torch.all(out["status"] == 9)
     assert torch.all(out["factor"] == 7.0) and torch.all(out["log_condvar"] == 7.0)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "mixed"])
+@pytest.mark.parametrize("C,k", [(64, 16), (128, 32), (200, 32), (512, 32), (512, 7)])
+def test_multi_wave_schedule_matches_one_wave(prec, C, k):
+    """csel_select_and_factor_sched with the pool split over 2 or 4 waves per
+    column gives the one-wave kernel's outputs bit for bit -- in natural order
+    and through a column list -- on ragged pools, empty pools, bad rows
+    (status 3) and a column count that does not fill the last workgroup; the
+    FP64 run also matches the oracle."""
+    print(f"case: multi-wave schedule {prec} C={C} k={k}", flush=True)
+    x = inputs.cluster_points(5003, 3, 61)
+    w = inputs.single_target("mw", x, inputs.Kernel(5, 0.06), C, k, targets=np.arange(0, 5003, 4))
+    plen = w.pool_len.copy()
+    plen[::7] = np.minimum(plen[::7], np.random.default_rng(2).integers(0, C + 1, size=len(plen[::7])))
+    plen[3] = 0
+    pool = w.pool.copy()
+    tg = w.targets.copy()
+    tg[10] = -4                            # bad target
+    pool[20, min(3, plen[20] - 1)] = 99999  # bad pool id
+    T = len(tg)
+    pts = _dev(w.points, torch.float64)
+    args = (pts, w.kernel, _dev(tg, torch.int32), _dev(pool, torch.int32), _dev(plen, torch.int32), k, prec)
+    ref = {key: v.cpu().numpy() for key, v in csel.select_and_factor(*args).items()}
+    waves = csel.select_waves_per_column(C)
+    assert waves == (2 if C <= 128 else 4)
+    got = {key: v.cpu().numpy() for key, v in csel.select_and_factor_sched(*args, waves=waves).items()}
+    torch.cuda.synchronize()
+    for key in ("sel", "factor", "log_condvar", "status"):
+        assert np.array_equal(got[key], ref[key], equal_nan=True), key
+    assert got["status"][10] == 3 and got["status"][20] == 3
+    # through a column list (a random subset, capacity above the count)
+    cols = np.random.default_rng(3).choice(T, 301, replace=False).astype(np.int32)
+    lst = np.full(T, -1, np.int32)
+    lst[: len(cols)] = cols
+    out = {"sel": torch.full((T, k), -7, dtype=torch.int32, device="cuda"),
+           "factor": torch.full((T, k + 1), 7.0, dtype=torch.float64, device="cuda"),
+           "log_condvar": torch.full((T,), 7.0, dtype=torch.float64, device="cuda"),
+           "status": torch.full((T,), 9, dtype=torch.uint8, device="cuda")}
+    csel.select_and_factor_sched(*args, waves=waves, col_list=_dev(lst, torch.int32),
+                                 col_count=_dev(np.array([len(cols)], np.int32), torch.int32), max_cols=T, out=out)
+    g2 = {key: v.cpu().numpy() for key, v in out.items()}
+    for key in ("sel", "factor", "log_condvar", "status"):
+        assert np.array_equal(g2[key][cols], ref[key][cols], equal_nan=True), key
+    rest = np.setdiff1d(np.arange(T), cols)
+    assert np.all(g2["status"][rest] == 9) and np.all(g2["sel"][rest] == -7)
+    if prec == "fp64":
+        good = np.setdiff1d(np.arange(T), [10, 20])
+        o = oracle.select_and_factor(w.points, w.kernel, tg[good], pool[good], plen[good], k)
+        gg = {key: v[good] for key, v in got.items()}
+        gg["gap"] = o["gap"]
+        rep = compare_single(gg, o, THR, factor_rtol=1e-5, logcv_atol=1e-8)
+        assert rep["identical"] >= rep["fully_decisive"]
+    # unsupported wave counts are refused on the host
+    with pytest.raises(csel.CselError):
+        csel.select_and_factor_sched(*args, waves=3)
