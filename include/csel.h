@@ -145,6 +145,40 @@ int csel_select_and_factor_sched(const double *pts, int64_t n, int32_t dim, cons
                                  uint8_t *status, hipStream_t stream);
 
 /*
+ * csel_select_global -- greedy single-target selection with the nonzeros
+ * allocated over the columns by global greedy selection (Sec. 5.4, eq.
+ * global_obj): of a budget of off-diagonal nonzeros, each next one goes to
+ * the column whose next greedy pick removes the largest fraction of its
+ * target's conditional variance (the pick's squared conditional correlation,
+ * a monotone image of its exact decrease of the KL divergence of eq.
+ * obj_chol), equal fractions to the smaller column index; a column never
+ * receives more than k_max or than its greedy selection finds.
+ *
+ * Inputs as csel_select_and_factor (k_max in place of k) plus
+ *   budget     total off-diagonal nonzeros to allocate (>= 0; with more than
+ *              all columns can take, every column gets its whole run)
+ *   workspace  device scratch of csel_select_global_workspace_size(n_targets,
+ *              k_max) bytes, caller-owned, no initialization
+ * Outputs:
+ *   k_alloc    [n_targets] nonzeros allocated to each column
+ *   sel_idx    [n_targets][k_max] the first k_alloc greedy picks, -1 after
+ *   factor_val [n_targets][k_max+1], log_condvar [n_targets] (may be NULL):
+ *              the eq. L_col column on i and its allocated picks, laid out as
+ *              for csel_select_and_factor
+ *   gain       [n_targets][k_max] (may be NULL) the fraction of the target's
+ *              conditional variance removed by each greedy step up to k_max
+ *              (the allocation's keys), NaN past the column's last pick
+ *   status     as for csel_select_and_factor (0 or 3)
+ * The selection runs in its top-two form (FP64 score keys).
+ */
+int64_t csel_select_global_workspace_size(int64_t n_targets, int32_t k_max);
+int csel_select_global(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_targets,
+                       const int32_t *targets, const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride,
+                       int32_t k_max, int64_t budget, int32_t precision, void *workspace, int64_t workspace_bytes,
+                       int32_t *k_alloc, int32_t *sel_idx, double *factor_val, double *log_condvar, double *gain,
+                       uint8_t *status, hipStream_t stream);
+
+/*
  * csel_aggregated_workspace_size -- bytes of device workspace that
  * csel_aggregated_select needs for these sizes (-1 with csel_last_error set if
  * the sizes are not supported).  The workspace holds the two partial Cholesky

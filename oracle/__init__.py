@@ -177,9 +177,10 @@ def select_and_factor(x, kernel, targets, pool, pool_len, k: int, nthreads: int 
 
 
 def select_and_factor_diag(x, kernel, targets, pool, pool_len, k: int, nthreads: int = 0) -> dict:
-    """select_and_factor plus, per column and step, the tracked FP64 state of
-    the two best candidates before the pick: diag [T, k, 4] = (var, cov) of
-    the best, (var, cov) of the second best (NaN where there is none)."""
+    """select_and_factor plus, per column and step, the tracked FP64 state
+    before the pick: diag [T, k, 5] = (var, cov) of the best candidate, (var,
+    cov) of the second best (NaN where there is none), and the target's
+    conditional variance."""
     x = _pts(x)
     targets = np.ascontiguousarray(targets, dtype=np.int32)
     pool = np.ascontiguousarray(pool, dtype=np.int32)
@@ -191,12 +192,68 @@ def select_and_factor_diag(x, kernel, targets, pool, pool_len, k: int, nthreads:
     fac = np.empty((T, k + 1), np.float64)
     lcv = np.empty(T, np.float64)
     st = np.empty(T, np.uint8)
-    diag = np.empty((T, max(k, 1), 4), np.float64)
+    diag = np.empty((T, max(k, 1), 5), np.float64)
     _load().orc_select_and_factor_diag(_p(x, _f64p), x.shape[1], *_kargs(kernel), T, _p(targets, _i32p),
                                        _p(pool, _i32p), _p(pool_len, _i32p), stride, k, _p(sel, _i32p),
                                        _p(gap, _f64p), _p(fac, _f64p), _p(lcv, _f64p), _p(st, _u8p), _p(diag, _f64p),
                                        int(nthreads))
     return {"sel": sel, "gap": gap, "factor": fac, "log_condvar": lcv, "status": st, "diag": diag[:, :k]}
+
+
+# --------------------------------------------------------------------------
+# global greedy allocation of nonzeros (Sec. 5.4, eq. global_obj)
+# --------------------------------------------------------------------------
+def step_gains(diag, sel):
+    """Per column and step, the fraction of the target's conditional variance
+    that the greedy pick removes: its score cov^2/var (eq. obj_gp) over the
+    target's conditional variance before the step -- the squared conditional
+    correlation of eq. global_obj.  NaN past the column's picks."""
+    diag = np.asarray(diag, np.float64)
+    g = diag[..., 1] ** 2 / diag[..., 0] / diag[..., 4]
+    return np.where(np.asarray(sel) >= 0, g, np.nan)
+
+
+def global_allocation(gains, budget: int) -> np.ndarray:
+    """Global greedy allocation with an array-backed binary heap, as Sec. 5.4
+    describes: the queue holds each column's next greedy step keyed by its
+    gain; the largest is removed (equal gains: the smaller column) and the
+    column's following step, if any, is inserted, `budget` times.  Returns the
+    nonzeros per column.  gains [T, k] with NaN past each column's picks."""
+    import heapq
+
+    gains = np.asarray(gains, np.float64)
+    T, K = gains.shape
+    npick = np.array([int(np.sum(~np.isnan(gains[i]))) for i in range(T)])
+    alloc = np.zeros(T, np.int64)
+    heap = [(-gains[i, 0], i) for i in range(T) if npick[i] > 0]
+    heapq.heapify(heap)
+    for _ in range(int(budget)):
+        if not heap:
+            break
+        _, i = heapq.heappop(heap)
+        alloc[i] += 1
+        if alloc[i] < npick[i]:
+            heapq.heappush(heap, (-gains[i, alloc[i]], i))
+    return alloc
+
+
+def global_allocation_naive(gains, budget: int) -> np.ndarray:
+    """The same allocation straight from its definition, for small inputs:
+    each of the `budget` nonzeros goes to the column whose next step has the
+    largest gain (a scan over all columns; the first column wins a tie)."""
+    gains = np.asarray(gains, np.float64)
+    T, K = gains.shape
+    alloc = np.zeros(T, np.int64)
+    for _ in range(int(budget)):
+        best, bi = -np.inf, -1
+        for i in range(T):
+            t = alloc[i]
+            if t < K and not np.isnan(gains[i, t]) and gains[i, t] > best:
+                best, bi = gains[i, t], i
+        if bi < 0:
+            break
+        alloc[bi] += 1
+    return alloc
 
 
 # --------------------------------------------------------------------------

@@ -129,9 +129,10 @@ static int lcol(const orc_cov *c, const int32_t *s, int m, double *vals, double 
  * run) instead of the argmax and records, in FP64, the best score over valid
  * candidates (best_out[t]) and the forced pick's score (pick_out[t]): a replay
  * of another run's selection under exact arithmetic. */
-/* When `diag` is given, step t records the tracked state of the two best
- * candidates before the pick: diag[4t..4t+3] = var and cov of the best, var
- * and cov of the second best (NaN when there is none). */
+/* When `diag` is given, step t records the tracked state before the pick:
+ * diag[5t..5t+4] = var and cov of the best candidate, var and cov of the
+ * second best (NaN when there is none), and the target's own conditional
+ * variance. */
 static int select_column_impl(const orc_cov *c, int32_t i, const int32_t *pool, int32_t C, int32_t k, int32_t *sel,
                               double *gap, double *factor, double *logcv, double *var_out, double *cov_out,
                               const int32_t *forced, double *best_out, double *pick_out, double *diag) {
@@ -168,10 +169,11 @@ static int select_column_impl(const orc_cov *c, int32_t i, const int32_t *pool, 
             else if (sc > s2) { s2 = sc; second = j; }
         }
         if (diag) {
-            diag[4 * t + 0] = best >= 0 ? var[best] : NAN;
-            diag[4 * t + 1] = best >= 0 ? cov[best] : NAN;
-            diag[4 * t + 2] = second >= 0 ? var[second] : NAN;
-            diag[4 * t + 3] = second >= 0 ? cov[second] : NAN;
+            diag[5 * t + 0] = best >= 0 ? var[best] : NAN;
+            diag[5 * t + 1] = best >= 0 ? cov[best] : NAN;
+            diag[5 * t + 2] = second >= 0 ? var[second] : NAN;
+            diag[5 * t + 3] = second >= 0 ? cov[second] : NAN;
+            diag[5 * t + 4] = var[C];
         }
         if (forced) {
             /* replay: take the given pick if it is a valid candidate */
@@ -255,7 +257,8 @@ void orc_select_and_factor(const double *x, int32_t d, int32_t two_nu, double el
 }
 
 /* Batched selection that also records, per step, the tracked state of the
- * two best candidates (diag [n_targets][k][4], see select_column_impl). */
+ * two best candidates and of the target (diag [n_targets][k][5], see
+ * select_column_impl). */
 void orc_select_and_factor_diag(const double *x, int32_t d, int32_t two_nu, double ell, double s2, double nugget,
                                 int64_t n_targets, const int32_t *targets, const int32_t *pool,
                                 const int32_t *pool_len, int32_t stride, int32_t k, int32_t *sel, double *gap,
@@ -266,8 +269,8 @@ void orc_select_and_factor_diag(const double *x, int32_t d, int32_t two_nu, doub
 #endif
 #pragma omp parallel for schedule(dynamic, 16)
     for (int64_t t = 0; t < n_targets; ++t) {
-        double *dg = diag + t * 4 * (int64_t)k;
-        for (int64_t e = 0; e < 4 * (int64_t)k; ++e) dg[e] = NAN;
+        double *dg = diag + t * 5 * (int64_t)k;
+        for (int64_t e = 0; e < 5 * (int64_t)k; ++e) dg[e] = NAN;
         status[t] = (uint8_t)select_column_impl(&c, targets[t], pool + t * stride, pool_len[t], k, sel + t * k,
                                                 gap + t * k, factor + t * (k + 1), logcv + t, NULL, NULL, NULL, NULL,
                                                 NULL, dg);

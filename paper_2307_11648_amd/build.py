@@ -42,7 +42,7 @@ HIP_UNITS = [("abi.cpp", []), ("plan.cpp", []), ("select.hip", [])] + [
 ] + [
     (("select_mw_inst.hip", [f"-DCSEL_MW_T={t}", f"-DCSEL_MW_NU={nu}", f"-DCSEL_MW_W={w}", f"-DCSEL_MW_RPL={r}"]))
     for t in ("float", "double") for nu in (1, 3, 5) for (w, r) in ((2, 1), (4, 1), (4, 2))
-] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip")] + [
+] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip", "global.hip")] + [
     # the screen's ReLU/min/max need no NaN handling: plain v_max/v_min without
     # the IEEE-mode quieting of their inputs; the max-ilp machine scheduler runs
     # the column screen 1% faster (identical results)
@@ -90,11 +90,19 @@ def build_hip(extra_flags=None, jobs=None, only=None) -> str:
     units = hip_units()
     jobs = jobs or int(os.environ.get("MAX_JOBS", "0") or 0) or min(16, os.cpu_count() or 4)
 
+    # the newest header: a unit left out of `only` is still rebuilt when a
+    # header changed after its object (a struct shared through launch.hpp
+    # must have one layout in every object)
+    headers = [os.path.join(CSRC, f) for f in os.listdir(CSRC) if f.endswith(".hpp")] + \
+        [os.path.join(INCLUDE, f) for f in os.listdir(INCLUDE) if f.endswith(".h")]
+    newest_header = max(os.path.getmtime(h) for h in headers)
+
     def compile_one(u):
         src, defs = u
         tag = "_".join(d.split("=")[-1] for d in defs if d.startswith("-D"))
         obj = os.path.join(objdir, os.path.basename(src) + (("." + tag) if tag else "") + ".o")
-        if only is not None and os.path.basename(src) not in only and os.path.exists(obj):
+        if (only is not None and os.path.basename(src) not in only and os.path.exists(obj)
+                and os.path.getmtime(obj) >= newest_header):
             return obj
         _run([hipcc] + HIPCC_FLAGS + (extra_flags or []) + defs + ["-I", INCLUDE, "-I", CSRC, "-c", src, "-o", obj])
         return obj

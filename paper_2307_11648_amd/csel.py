@@ -106,6 +106,12 @@ def load():
                                                  _c.c_int64, _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                                  _vp, _vp, _c.c_int64, _c.c_int32, _vp, _vp, _vp, _vp, _vp]
     lib.csel_select_and_factor_sched.restype = ctypes.c_int
+    lib.csel_select_global_workspace_size.argtypes = [_c.c_int64, _c.c_int32]
+    lib.csel_select_global_workspace_size.restype = ctypes.c_int64
+    lib.csel_select_global.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64, _vp,
+                                       _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_int32, _vp, _c.c_int64,
+                                       _vp, _vp, _vp, _vp, _vp, _vp, _vp]
+    lib.csel_select_global.restype = ctypes.c_int
     lib.csel_plan_create.argtypes = [ctypes.POINTER(_vp), _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32,
                                      _c.c_uint32]
     lib.csel_plan_create.restype = ctypes.c_int
@@ -252,6 +258,44 @@ def select_and_factor_sched(points, kernel, targets, pool, pool_len, k: int, pre
                                             _PREC[precision], _ptr(col_list), _ptr(col_count), int(max_cols),
                                             int(waves), _ptr(out["sel"]), _ptr(out["factor"]),
                                             _ptr(out.get("log_condvar")), _ptr(out["status"]), _stream(stream)))
+    return out
+
+
+def select_global(points, kernel, targets, pool, pool_len, k_max: int, budget: int, precision: str = "fp64",
+                  want_gain: bool = False, out: dict | None = None, workspace=None, stream=None) -> dict:
+    """csel_select_global: greedy selection with the nonzeros allocated over
+    the columns by global greedy selection.  Returns GPU tensors k_alloc [T],
+    sel [T, k_max], factor [T, k_max+1], log_condvar [T], status [T] and,
+    with want_gain, gain [T, k_max]; plus the workspace."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    _dev(targets, torch.int32, "targets")
+    _dev(pool, torch.int32, "pool")
+    _dev(pool_len, torch.int32, "pool_len")
+    T = targets.shape[0]
+    stride = pool.shape[1] if pool.dim() == 2 else 0
+    dev = points.device
+    if out is None:
+        out = {"k_alloc": torch.empty(T, dtype=torch.int32, device=dev),
+               "sel": torch.empty((T, k_max), dtype=torch.int32, device=dev),
+               "factor": torch.empty((T, k_max + 1), dtype=torch.float64, device=dev),
+               "log_condvar": torch.empty(T, dtype=torch.float64, device=dev),
+               "status": torch.empty(T, dtype=torch.uint8, device=dev)}
+        if want_gain:
+            out["gain"] = torch.empty((T, k_max), dtype=torch.float64, device=dev)
+    need = int(lib.csel_select_global_workspace_size(T, int(k_max)))
+    if need < 0:
+        _check(-1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    kp = kernel_struct(kernel)
+    _check(lib.csel_select_global(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), T,
+                                  targets.data_ptr(), pool.data_ptr(), pool_len.data_ptr(), stride, int(k_max),
+                                  int(budget), _PREC[precision], workspace.data_ptr(), workspace.numel(),
+                                  _ptr(out["k_alloc"]), _ptr(out["sel"]), _ptr(out["factor"]),
+                                  _ptr(out.get("log_condvar")), _ptr(out.get("gain")), _ptr(out["status"]),
+                                  _stream(stream)))
+    out["workspace"] = workspace
     return out
 
 

@@ -177,6 +177,66 @@ CSEL_API int csel_select_and_factor_sched(const double* pts, int64_t n, int32_t 
     return CSEL_OK;
 }
 
+CSEL_API int64_t csel_select_global_workspace_size(int64_t n_targets, int32_t k_max) {
+    g_err[0] = 0;
+    if (n_targets < 0 || n_targets > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_targets must be in [0, 2^31) (got %lld)", (long long)n_targets);
+    if (k_max < 1 || k_max > kMaxSelect) return fail(CSEL_EUNSUPPORTED, "k_max must be in [1, %d]", kMaxSelect);
+    return csel::global_workspace(n_targets, k_max);
+}
+
+CSEL_API int csel_select_global(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                int64_t n_targets, const int32_t* targets, const int32_t* pool_idx,
+                                const int32_t* pool_len, int32_t pool_stride, int32_t k_max, int64_t budget,
+                                int32_t precision, void* workspace, int64_t workspace_bytes, int32_t* k_alloc,
+                                int32_t* sel_idx, double* factor_val, double* log_condvar, double* gain,
+                                uint8_t* status, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_targets < 0 || n_targets > INT32_MAX)
+        return fail(CSEL_EINVAL, "n_targets must be in [0, 2^31) (got %lld)", (long long)n_targets);
+    if (pool_stride < 0 || pool_stride > kMaxPool)
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [0, %d] (got %d)", kMaxPool, pool_stride);
+    if (k_max < 1 || k_max > kMaxSelect) return fail(CSEL_EUNSUPPORTED, "k_max must be in [1, %d]", kMaxSelect);
+    if (budget < 0) return fail(CSEL_EINVAL, "budget must be >= 0");
+    if (precision != CSEL_FP64 && precision != CSEL_MIXED)
+        return fail(CSEL_EINVAL, "precision must be CSEL_FP64 or CSEL_MIXED");
+    if (n_targets == 0) return CSEL_OK;
+    if (!pts || !targets || !pool_len || !status || !factor_val || !sel_idx || !k_alloc ||
+        (pool_stride > 0 && !pool_idx))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    const int64_t need = csel::global_workspace(n_targets, k_max);
+    if (!workspace || workspace_bytes < need)
+        return fail(CSEL_EINVAL, "workspace must hold csel_select_global_workspace_size() = %lld bytes",
+                    (long long)need);
+    csel::SelectArgs a{};
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.s2 = kernel->variance;
+    a.nugget = kernel->nugget;
+    a.n_targets = n_targets;
+    a.targets = targets;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    a.k = k_max;
+    a.sel = sel_idx;
+    a.logcv = log_condvar;
+    a.gain = gain;
+    a.status = status;
+    a.n_waves = n_targets;
+    const int rpl = pool_stride <= 64 ? 1 : pool_stride <= 128 ? 2 : pool_stride <= 256 ? 4 : 8;
+    hipError_t e = csel::launch_global(a, precision, rpl, budget, workspace, k_alloc, factor_val, stream);
+    if (e != hipSuccess) return hip_fail(e, "select_global launch");
+    return CSEL_OK;
+}
+
 CSEL_API int csel_sum(const double* x, int64_t n, double* out, hipStream_t stream) {
     g_err[0] = 0;
     if (n < 0) return fail(CSEL_EINVAL, "n must be >= 0");

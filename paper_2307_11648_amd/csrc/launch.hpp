@@ -25,6 +25,10 @@ struct SelectArgs {
     double* fac;
     double* logcv;
     float* gap;
+    // (top-two variant only, may be null) per step, the fraction of the
+    // target's conditional variance the pick removes (its squared conditional
+    // correlation, eq. global_obj)
+    double* gain;
     uint8_t* status;
     // optional indirection: run only columns col_list[0 .. *col_count)
     const int32_t* col_list;
@@ -170,6 +174,10 @@ hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int
 // column, 2 for pools <= 128, 4 up to 512
 int select_mw_waves(int32_t stride);
 hipError_t launch_select_factor_mw(const SelectArgs& a, int precision, int kmax, hipStream_t s);
+// global greedy allocation of nonzeros (global.hip)
+int64_t global_workspace(int64_t n_targets, int k_max);
+hipError_t launch_global(const SelectArgs& sel_args, int precision, int rpl, int64_t budget, void* workspace,
+                         int32_t* k_alloc, double* factor_val, hipStream_t s);
 int64_t transpose_factor_workspace(int64_t n, int64_t n_slots);
 hipError_t launch_transpose_factor(int64_t n, const int64_t* col_ptr, const int32_t* row_idx, const double* val,
                                    int64_t n_slots, int64_t* t_col_ptr, int32_t* t_row_idx, double* t_val,

@@ -57,7 +57,8 @@ CSEL_FAMILY(1, float, 5)
 
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s) {
     if (a.n_targets == 0 || a.n_waves == 0) return hipSuccess;
-    const bool gap = a.gap != nullptr;
+    // the top-two variant also records each step's gain
+    const bool gap = a.gap != nullptr || a.gain != nullptr;
     if (precision == 0) {
         switch (a.two_nu) {
             case 1: return launch_family<0, 1>(a, gap, rpl, kmax, s);

@@ -223,7 +223,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 
     const int kout = p.k;
     int32_t* sel_out = p.sel + col * kout;
-    double* fac_out = p.fac + col * (kout + 1);
+    double* fac_out = p.fac ? p.fac + col * (kout + 1) : nullptr;
 
     const int32_t tgt = __builtin_amdgcn_readfirstlane(p.targets[col]);
     const int32_t C = __builtin_amdgcn_readfirstlane(p.pool_len[col]);
@@ -267,11 +267,12 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     if (bad) {
         for (int r = lane; r < kout; r += kWave) {
             sel_out[r] = -1;
-            fac_out[1 + r] = __builtin_nan("");
+            if (fac_out) fac_out[1 + r] = __builtin_nan("");
             if (p.gap) p.gap[col * kout + r] = __builtin_nanf("");
+            if (GAP && p.gain) p.gain[col * kout + r] = __builtin_nan("");
         }
         if (lane == 0) {
-            fac_out[0] = __builtin_nan("");
+            if (fac_out) fac_out[0] = __builtin_nan("");
             if (p.logcv) p.logcv[col] = __builtin_nan("");
             p.status[col] = 3;
         }
@@ -284,6 +285,10 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     T L[RPL][KMAX];
     int32_t my_sel = -1;
     float my_gap = __builtin_nanf("");
+    // top-two variant: the target's tracked conditional variance and, in lane
+    // t, the fraction of it that pick t removes
+    double vt = p.s2 + p.nugget;
+    double my_gain = __builtin_nan("");
     int nsel = 0;
     int st = 0;
     bool stopped = false;
@@ -400,6 +405,12 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr)
                     if (rr == rs && lane == ls) var[rr] = -1.0;
+                if constexpr (GAP) {
+                    // the pick's score is ck^2 / vk = ui^2 (eq. obj_gp); over
+                    // the target's variance it is eq. global_obj's key
+                    if (lane == t) my_gain = ui * ui / vt;
+                    vt -= ui * ui;
+                }
                 if (lane == t) {
                     my_sel = idk;
                     my_gap = g;
@@ -409,6 +420,18 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         }
     }
 
+    if constexpr (GAP) {
+        if (p.gain && lane < kout) p.gain[col * kout + lane] = lane < nsel ? my_gain : __builtin_nan("");
+    }
+    if (!p.fac) {
+        // selection only: the picks, their gaps and the status
+        if (lane < kout) {
+            p.sel[col * kout + lane] = lane < nsel ? my_sel : -1;
+            if (p.gap) p.gap[col * kout + lane] = my_gap;
+        }
+        if (lane == 0) p.status[col] = (uint8_t)st;
+        return;
+    }
     factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, my_gap, tgt, st, sh_r[wib], sh_pt[wib]);
 }
 

@@ -246,17 +246,22 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
     if (!has_col || w != 0) return;
     if (bad) {
         int32_t* sel_out = p.sel + col * kout;
-        double* fac_out = p.fac + col * (kout + 1);
+        double* fac_out = p.fac ? p.fac + col * (kout + 1) : nullptr;
         for (int r = lane; r < kout; r += kWave) {
             sel_out[r] = -1;
-            fac_out[1 + r] = __builtin_nan("");
-            if (p.gap) p.gap[col * kout + r] = __builtin_nanf("");
+            if (fac_out) fac_out[1 + r] = __builtin_nan("");
         }
         if (lane == 0) {
-            fac_out[0] = __builtin_nan("");
+            if (fac_out) fac_out[0] = __builtin_nan("");
             if (p.logcv) p.logcv[col] = __builtin_nan("");
             p.status[col] = 3;
         }
+        return;
+    }
+    if (!p.fac) {
+        // selection only: the picks and the status
+        if (lane < kout) p.sel[col * kout + lane] = lane < nsel ? my_sel : -1;
+        if (lane == 0) p.status[col] = (uint8_t)st;
         return;
     }
     factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, __builtin_nanf(""), tgt, st, sh_r[cib], sh_pt[cib]);

@@ -104,7 +104,7 @@ def mixed_decisive_prefix(diag_row, prior: float, k: int) -> int:
     GEMV (the mixed-precision kernel) cannot flip, by a first-order error
     model of the FP64 oracle's own run on the same pool.
 
-    diag_row [k, 4]: per step, the tracked (var, cov) of the best and of the
+    diag_row [k, 5]: per step, the tracked (var, cov) of the best and of the
     second-best candidate (oracle.select_and_factor_diag).  The model:
 
     * the FP32 column of pick s has an absolute error per row of at most
@@ -126,7 +126,7 @@ def mixed_decisive_prefix(diag_row, prior: float, k: int) -> int:
     the paths may part)."""
     e2 = 0.0
     for t in range(k):
-        v1, c1, v2, c2 = (float(a) for a in diag_row[t])
+        v1, c1, v2, c2 = (float(a) for a in diag_row[t][:4])
         if not np.isfinite(v1):
             return t  # no candidate: the run stopped
         E = 8.0 * U32 * prior + 4.0 * math.sqrt(prior * e2)

@@ -135,3 +135,33 @@ def test_screen_rejects_order_longer_than_the_fallback_list():
 
     assert call(6) == -1 and b"n_order" in lib.csel_last_error()
     assert call(-1) == -1 and b"n_order" in lib.csel_last_error()
+
+
+def test_select_global_and_sched_validation_without_gpu():
+    if not os.path.exists(csel.LIB_PATH):
+        pytest.skip("libcsel.so not built")
+    lib = csel.load()
+    fake = ctypes.c_void_p(16)  # never dereferenced: every call below fails validation first
+    kp = csel.KernelParams(3, 0.05, 1.0, 0.0)
+    assert lib.csel_select_global_workspace_size(10, 0) == -4
+    assert lib.csel_select_global_workspace_size(10, 33) == -4
+    assert lib.csel_select_global_workspace_size(-1, 8) == -1
+    assert lib.csel_select_global_workspace_size(10, 8) > 0
+
+    def glob(budget=5, k_max=8, ws=fake, ws_bytes=1 << 40):
+        return lib.csel_select_global(fake, 100, 3, ctypes.byref(kp), 10, fake, fake, fake, 64, k_max, budget, 0,
+                                      ws, ws_bytes, fake, fake, fake, None, None, fake, None)
+
+    assert glob(budget=-1) == -1 and b"budget" in lib.csel_last_error()
+    assert glob(k_max=40) == -4
+    assert glob(ws=None) == -1 and b"workspace" in lib.csel_last_error()
+    assert glob(ws_bytes=8) == -1
+    # the scheduled selection: only 1 or the multi-wave count of the pool width
+    assert lib.csel_select_waves_per_column(128) == 2 and lib.csel_select_waves_per_column(512) == 4
+    assert lib.csel_select_waves_per_column(600) == -1
+    rc = lib.csel_select_and_factor_sched(fake, 100, 3, ctypes.byref(kp), 10, fake, fake, fake, 128, 8, 0, None,
+                                          None, 0, 3, fake, fake, None, fake, None)
+    assert rc == -4 and b"waves_per_column" in lib.csel_last_error()
+    rc = lib.csel_select_and_factor_sched(fake, 100, 3, ctypes.byref(kp), 10, fake, fake, fake, 128, 8, 0, fake,
+                                          None, 5, 2, fake, fake, None, fake, None)
+    assert rc == -1 and b"col_list" in lib.csel_last_error()
