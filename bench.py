@@ -801,12 +801,89 @@ def bench_apply(args):
     print(json.dumps(out), flush=True)
 
 
+def bench_pcg(args):
+    """The factor as a preconditioner (Sec. 6.3): N = 2^16 points uniform in
+    [0,1]^3, Matern 1/2, l = 1, y = Theta x for a Gaussian x; the conjugate
+    gradient to a relative residual of 1e-12 with the factor of greedy
+    selection (k of 3k later neighbours, FP64), with the factor on the k
+    nearest later neighbours, and without a preconditioner (capped)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs
+
+    n = args.n or (1 << 16)
+    k = 16
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    kern = inputs.Kernel(1, 1.0)
+    print("bench: building inputs", file=sys.stderr, flush=True)
+    xo, _ = inputs.ordered_cloud(inputs.uniform_points(n, 3, 6))
+    pts = t(xo, torch.float64)
+    tg = t(np.arange(n, dtype=np.int32), torch.int32)
+    sol = t(np.random.default_rng(6).standard_normal(n), torch.float64)
+    y, mv_ws = csel.kernel_matvec(pts, kern, sol)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        csel.kernel_matvec(pts, kern, sol, out=y, workspace=mv_ws)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_mv = e0.elapsed_time(e1) / 3
+    out = {}
+    for name, C in (("conditional", 3 * k), ("knn", k)):
+        pool, plen = inputs.later_knn_pools(xo, C)
+        pl, ln = t(pool, torch.int32), t(plen, torch.int32)
+        f = csel.select_and_factor(pts, kern, tg, pl, ln, k, "fp64")
+        torch.cuda.synchronize()
+        e0.record()
+        f = csel.select_and_factor(pts, kern, tg, pl, ln, k, "fp64", out=f)
+        cp, rows, vals = csel.single_target_csc(tg, f["sel"], f["factor"])
+        ft = csel.transpose_factor(cp, rows, vals)[:3]
+        e1.record()
+        torch.cuda.synchronize()
+        ms_build = e0.elapsed_time(e1)
+        t0 = time.perf_counter()
+        x, it, rel = csel.pcg(pts, kern, y, (cp, rows, vals), ft, rel_tol=1e-12, max_iter=2000)
+        torch.cuda.synchronize()
+        s_cg = time.perf_counter() - t0
+        err = float(torch.linalg.norm(x - sol) / torch.linalg.norm(sol))
+        out[name] = {"iterations": it, "rel_residual": rel, "solution_rel_error": err, "factor_ms": ms_build,
+                     "cg_seconds": s_cg, "ms_per_iteration": s_cg * 1e3 / max(it, 1)}
+    t0 = time.perf_counter()
+    _, it0, rel0 = csel.pcg(pts, kern, y, None, None, rel_tol=1e-12, max_iter=args.pcg_plain_iters)
+    torch.cuda.synchronize()
+    out["none"] = {"iterations": it0, "rel_residual": rel0, "cg_seconds": time.perf_counter() - t0,
+                   "capped": it0 >= args.pcg_plain_iters}
+    # the kernel matvec: n^2 evaluations of the FP64 Matern (each counted as
+    # in column_work) plus the multiply-add
+    flops_mv = float(n) * n * (eval_flops(3, 1) + 2)
+    ach = flops_mv / (ms_mv * 1e-3) / 1e12
+    c = out["conditional"]
+    res = {"metric": "conjugate-gradient solves/s (relative residual 1e-12, preconditioned by the factor)",
+           "value": 1.0 / (c["cg_seconds"] + c["factor_ms"] * 1e-3), "unit": "solves/s", "n_gpus": 1, "steps": 1,
+           "warmup": 0, "ms_per_step": c["cg_seconds"] * 1e3 + c["factor_ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"PCG, N={n} uniform in [0,1]^3, Matern 1/2, l=1, y = Theta x with x Gaussian; "
+                                  f"factor of greedy selection k={k} of {3 * k} later neighbours vs the factor on the "
+                                  f"{k} nearest later neighbours vs none", "k": k, "runs": out,
+                      "kernel_matvec_ms": ms_mv},
+           "roofline": {"bound": "alu", "kernel": "kmatvec_partial_kernel<1>", "achieved": ach,
+                        "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": ach / PEAK_ALU_TFLOPS, "traffic": None,
+                        "kernel_ms": ms_mv, "algorithmic_tflop_per_launch": flops_mv / 1e12}}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="screened", choices=["screened", "plain", "aggregated", "gp", "apply"])
+    ap.add_argument("--workload", default="screened",
+                    choices=["screened", "plain", "aggregated", "gp", "apply", "pcg"])
+    ap.add_argument("--pcg-plain-iters", type=int, default=300,
+                    help="pcg workload: iteration cap of the unpreconditioned run")
     ap.add_argument("--train-steps", type=int, default=3000, help="screened workload: Adam steps")
     ap.add_argument("--fallback-threshold", type=float, default=2.0,
                     help="screened workload: fall back to the full pool when the dropped candidates' summed "
@@ -854,6 +931,8 @@ def main():
         return bench_screened(args)
     if args.workload == "apply":
         return bench_apply(args)
+    if args.workload == "pcg":
+        return bench_pcg(args)
     if args.workload != "plain":
         return bench_groups(args)
     args.n = args.n or 100_000

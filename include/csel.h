@@ -271,6 +271,45 @@ int csel_apply_factor(int64_t n, const int64_t *col_ptr, const int32_t *row_idx,
                       int32_t transpose, const double *x, double *y, hipStream_t stream);
 
 /*
+ * csel_kernel_matvec -- y = Theta x for the dense kernel matrix Theta of the
+ * points (Matern kernel plus the nugget on the diagonal), matrix-free in
+ * FP64: every entry is evaluated as it is used, O(n^2) work and O(n) memory.
+ * Deterministic (partial sums over column chunks added in a fixed order).
+ *
+ *   x, y       [n] FP64, must not alias
+ *   workspace  csel_kernel_matvec_workspace_size(n) bytes of device scratch
+ */
+int64_t csel_kernel_matvec_workspace_size(int64_t n);
+int csel_kernel_matvec(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, const double *x,
+                       double *y, void *workspace, int64_t workspace_bytes, hipStream_t stream);
+
+/*
+ * csel_pcg -- solve Theta x = y by the conjugate gradient preconditioned by
+ * a sparse inverse-Cholesky factor L (L L^T ~ Theta^{-1}, so the
+ * preconditioner is z = L (L^T r)), the use of the factor of Sec. 6.3.  The
+ * points and every vector are in the factor's ordering.
+ *
+ *   l_col_ptr, l_row_idx, l_val     L in CSC form (as for csel_apply_factor);
+ *                                   NULL for the plain conjugate gradient
+ *   lt_col_ptr, lt_row_idx, lt_val  L^T in CSC form (csel_transpose_factor)
+ *   y          [n] right-hand side
+ *   x          [n] in: the initial guess; out: the solution
+ *   rel_tol    stop when ||y - Theta x|| <= rel_tol ||y|| (the residual
+ *              recurrence's norm), or after max_iter iterations
+ *   iterations, rel_residual   HOST outputs: iterations taken, final
+ *              relative residual norm
+ *   workspace  csel_pcg_workspace_size(n) bytes of device scratch
+ * Each iteration is one kernel matrix-vector product, two factor products
+ * and three dot products on `stream`; the call synchronizes `stream` once
+ * per iteration to read the residual norm.
+ */
+int64_t csel_pcg_workspace_size(int64_t n);
+int csel_pcg(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, const int64_t *l_col_ptr,
+             const int32_t *l_row_idx, const double *l_val, const int64_t *lt_col_ptr, const int32_t *lt_row_idx,
+             const double *lt_val, const double *y, double *x, double rel_tol, int32_t max_iter, void *workspace,
+             int64_t workspace_bytes, int32_t *iterations, double *rel_residual, hipStream_t stream);
+
+/*
  * csel_transpose_factor -- the CSC form of L^T from the CSC form of L (that
  * is, L by rows), for y = L x as a deterministic gather: csel_apply_factor
  * with transpose = 1 on the result computes y = (L^T)^T x = L x with the

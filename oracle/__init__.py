@@ -391,6 +391,52 @@ def single_target_csc(n: int, targets, sel, factor):
     return cp, ri, v
 
 
+def pcg(theta, y, L=None, rel_tol: float = 1e-12, max_iter: int = 1000, x0=None):
+    """The preconditioned conjugate gradient for Theta x = y with the
+    preconditioner z = L (L^T r) (L L^T ~ Theta^{-1}, Sec. 6.3), textbook
+    form, dense FP64 numpy; L None is the plain conjugate gradient.  Stops
+    when the recurred residual's norm is at most rel_tol ||y||.  Returns (x,
+    iterations, relative residual)."""
+    theta = np.asarray(theta, np.float64)
+    y = np.asarray(y, np.float64)
+    x = np.zeros_like(y) if x0 is None else np.array(x0, np.float64)
+    r = y - theta @ x
+    ynorm = float(np.linalg.norm(y))
+
+    def prec(v):
+        return v.copy() if L is None else L @ (L.T @ v)
+
+    z = prec(r)
+    p = z.copy()
+    rz = float(r @ z)
+    res = float(np.linalg.norm(r)) / ynorm if ynorm > 0 else 0.0
+    it = 0
+    while it < max_iter and res > rel_tol:
+        q = theta @ p
+        alpha = rz / float(p @ q)
+        x = x + alpha * p
+        r = r - alpha * q
+        z = prec(r)
+        rz_new = float(r @ z)
+        p = z + (rz_new / rz) * p
+        rz = rz_new
+        it += 1
+        res = float(np.linalg.norm(r)) / ynorm
+    return x, it, res
+
+
+def dense_factor(n, col_ptr, row_idx, val):
+    """The dense n x n matrix of a factor in CSC form (entries with a row
+    outside [0, n) are padding)."""
+    L = np.zeros((n, n))
+    for j in range(n):
+        for q in range(int(col_ptr[j]), int(col_ptr[j + 1])):
+            r = int(row_idx[q])
+            if 0 <= r < n:
+                L[r, j] += val[q]
+    return L
+
+
 def logdet(theta: np.ndarray) -> float:
     """log det of an SPD matrix by dense Cholesky (numpy)."""
     return float(2.0 * np.sum(np.log(np.diag(np.linalg.cholesky(theta)))))

@@ -112,6 +112,17 @@ def load():
                                        _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int64, _c.c_int32, _vp, _c.c_int64,
                                        _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.csel_select_global.restype = ctypes.c_int
+    lib.csel_kernel_matvec_workspace_size.argtypes = [_c.c_int64]
+    lib.csel_kernel_matvec_workspace_size.restype = ctypes.c_int64
+    lib.csel_kernel_matvec.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _vp, _vp, _vp,
+                                       _c.c_int64, _vp]
+    lib.csel_kernel_matvec.restype = ctypes.c_int
+    lib.csel_pcg_workspace_size.argtypes = [_c.c_int64]
+    lib.csel_pcg_workspace_size.restype = ctypes.c_int64
+    lib.csel_pcg.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _vp, _vp, _vp, _vp, _vp, _vp,
+                             _vp, _vp, _c.c_double, _c.c_int32, _vp, _c.c_int64, ctypes.POINTER(_c.c_int32),
+                             ctypes.POINTER(_c.c_double), _vp]
+    lib.csel_pcg.restype = ctypes.c_int
     lib.csel_plan_create.argtypes = [ctypes.POINTER(_vp), _c.c_int64, _c.c_int32, _c.c_int32, _c.c_int32, _c.c_int32,
                                      _c.c_uint32]
     lib.csel_plan_create.restype = ctypes.c_int
@@ -297,6 +308,51 @@ def select_global(points, kernel, targets, pool, pool_len, k_max: int, budget: i
                                   _stream(stream)))
     out["workspace"] = workspace
     return out
+
+
+def kernel_matvec(points, kernel, x, out=None, workspace=None, stream=None):
+    """csel_kernel_matvec: y = Theta x, matrix-free in FP64.  Returns (y,
+    workspace)."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    _dev(x, torch.float64, "x")
+    n = points.shape[0]
+    if out is None:
+        out = torch.empty(n, dtype=torch.float64, device=points.device)
+    need = int(lib.csel_kernel_matvec_workspace_size(n))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=points.device)
+    kp = kernel_struct(kernel)
+    _check(lib.csel_kernel_matvec(points.data_ptr(), n, points.shape[1], ctypes.byref(kp), x.data_ptr(),
+                                  out.data_ptr(), workspace.data_ptr(), workspace.numel(), _stream(stream)))
+    return out, workspace
+
+
+def pcg(points, kernel, y, factor=None, factor_t=None, x0=None, rel_tol: float = 1e-12, max_iter: int = 1000,
+        workspace=None, stream=None):
+    """csel_pcg: solve Theta x = y by the conjugate gradient preconditioned by
+    L L^T.  factor = (col_ptr, rows, vals) of L in CSC form, factor_t the same
+    for L^T (transpose_factor); factor None runs the plain conjugate
+    gradient.  Returns (x, iterations, relative residual)."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    _dev(y, torch.float64, "y")
+    n = points.shape[0]
+    x = torch.zeros(n, dtype=torch.float64, device=points.device) if x0 is None else x0.clone()
+    need = int(lib.csel_pcg_workspace_size(n))
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=points.device)
+    lc = lr = lv = tc = tr = tv = None
+    if factor is not None:
+        lc, lr, lv = (_ptr(a) for a in factor)
+        tc, tr, tv = (_ptr(a) for a in factor_t)
+    it = ctypes.c_int32(0)
+    res = ctypes.c_double(0.0)
+    kp = kernel_struct(kernel)
+    _check(lib.csel_pcg(points.data_ptr(), n, points.shape[1], ctypes.byref(kp), lc, lr, lv, tc, tr, tv, y.data_ptr(),
+                        x.data_ptr(), float(rel_tol), int(max_iter), workspace.data_ptr(), workspace.numel(),
+                        ctypes.byref(it), ctypes.byref(res), _stream(stream)))
+    return x, int(it.value), float(res.value)
 
 
 # --------------------------------------------------------------------------

@@ -237,6 +237,69 @@ CSEL_API int csel_select_global(const double* pts, int64_t n, int32_t dim, const
     return CSEL_OK;
 }
 
+CSEL_API int64_t csel_kernel_matvec_workspace_size(int64_t n) {
+    g_err[0] = 0;
+    if (n < 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [0, 2^31) (got %lld)", (long long)n);
+    return csel::kmatvec_workspace(n);
+}
+
+CSEL_API int csel_kernel_matvec(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel, const double* x,
+                                double* y, void* workspace, int64_t workspace_bytes, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n < 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [0, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n == 0) return CSEL_OK;
+    if (!pts || !x || !y) return fail(CSEL_EINVAL, "a required array is NULL");
+    if (x == y) return fail(CSEL_EINVAL, "x and y must not alias");
+    const int64_t need = csel::kmatvec_workspace(n);
+    if (!workspace || workspace_bytes < need)
+        return fail(CSEL_EINVAL, "workspace must hold csel_kernel_matvec_workspace_size() = %lld bytes",
+                    (long long)need);
+    hipError_t e = csel::launch_kmatvec(pts, n, dim, kernel->two_nu, c_nu(kernel), kernel->variance, kernel->nugget,
+                                        x, y, workspace, stream);
+    if (e != hipSuccess) return hip_fail(e, "kernel_matvec launch");
+    return CSEL_OK;
+}
+
+CSEL_API int64_t csel_pcg_workspace_size(int64_t n) {
+    g_err[0] = 0;
+    if (n < 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [0, 2^31) (got %lld)", (long long)n);
+    return csel::pcg_workspace(n);
+}
+
+CSEL_API int csel_pcg(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel, const int64_t* l_col_ptr,
+                      const int32_t* l_row_idx, const double* l_val, const int64_t* lt_col_ptr,
+                      const int32_t* lt_row_idx, const double* lt_val, const double* y, double* x, double rel_tol,
+                      int32_t max_iter, void* workspace, int64_t workspace_bytes, int32_t* iterations,
+                      double* rel_residual, hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n < 1 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (!(rel_tol > 0.0)) return fail(CSEL_EINVAL, "rel_tol must be > 0");
+    if (max_iter < 0) return fail(CSEL_EINVAL, "max_iter must be >= 0");
+    if (!pts || !y || !x || !iterations || !rel_residual) return fail(CSEL_EINVAL, "a required array is NULL");
+    const bool precond = l_col_ptr != nullptr;
+    if (precond && (!l_row_idx || !l_val || !lt_col_ptr || !lt_row_idx || !lt_val))
+        return fail(CSEL_EINVAL, "the preconditioner needs L and L^T in CSC form");
+    if (x == y) return fail(CSEL_EINVAL, "x and y must not alias");
+    const int64_t need = csel::pcg_workspace(n);
+    if (!workspace || workspace_bytes < need)
+        return fail(CSEL_EINVAL, "workspace must hold csel_pcg_workspace_size() = %lld bytes", (long long)need);
+    int it = 0;
+    double res = 0.0;
+    hipError_t e = csel::run_pcg(pts, n, dim, kernel->two_nu, c_nu(kernel), kernel->variance, kernel->nugget,
+                                 l_col_ptr, l_row_idx, l_val, lt_col_ptr, lt_row_idx, lt_val, y, x, rel_tol, max_iter,
+                                 workspace, &it, &res, stream);
+    if (e != hipSuccess) return hip_fail(e, "pcg");
+    *iterations = it;
+    *rel_residual = res;
+    return CSEL_OK;
+}
+
 CSEL_API int csel_sum(const double* x, int64_t n, double* out, hipStream_t stream) {
     g_err[0] = 0;
     if (n < 0) return fail(CSEL_EINVAL, "n must be >= 0");

@@ -174,6 +174,15 @@ hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int
 // column, 2 for pools <= 128, 4 up to 512
 int select_mw_waves(int32_t stride);
 hipError_t launch_select_factor_mw(const SelectArgs& a, int precision, int kmax, hipStream_t s);
+// the kernel matrix-vector product and the preconditioned conjugate gradient (pcg.hip)
+int64_t kmatvec_workspace(int64_t n);
+hipError_t launch_kmatvec(const double* pts, int64_t n, int dim, int two_nu, double c_nu, double s2, double nugget,
+                          const double* v, double* y, void* ws, hipStream_t s);
+int64_t pcg_workspace(int64_t n);
+hipError_t run_pcg(const double* pts, int64_t n, int dim, int two_nu, double c_nu, double s2, double nugget,
+                   const int64_t* l_cp, const int32_t* l_ri, const double* l_v, const int64_t* lt_cp,
+                   const int32_t* lt_ri, const double* lt_v, const double* y, double* x, double rel_tol,
+                   int max_iter, void* ws, int* iterations, double* rel_res, hipStream_t s);
 // global greedy allocation of nonzeros (global.hip)
 int64_t global_workspace(int64_t n_targets, int k_max);
 hipError_t launch_global(const SelectArgs& sel_args, int precision, int rpl, int64_t budget, void* workspace,
