@@ -237,13 +237,23 @@ __device__ __forceinline__ double dist64(double s) {
     return s > 0.0 ? g : 0.0;
 }
 
+// The polynomial factor is written with explicit fused multiply-adds, so
+// every kernel that inlines this rounds it the same way (with contraction
+// left to the compiler, a product with two uses may or may not be fused).
 template <int TWO_NU>
 __device__ __forceinline__ double matern_f64(double r, double c, double s2) {
     const double a = c * r;
     const double e = exp_neg64(a);
     if constexpr (TWO_NU == 1) return s2 * e;
-    if constexpr (TWO_NU == 3) return s2 * (1.0 + a) * e;
-    return s2 * (1.0 + a + a * a * (1.0 / 3.0)) * e;
+    if constexpr (TWO_NU == 3) return s2 * fma(c, r, 1.0) * e;
+    return s2 * fma(a, fma(a, 1.0 / 3.0, 1.0), 1.0) * e;
+}
+
+// |e|^2 of a 3-vector with explicit fused multiply-adds (the same rounding
+// in every kernel that inlines it)
+template <typename T>
+__device__ __forceinline__ T sqnorm3(T e0, T e1, T e2) {
+    return fma(e2, e2, fma(e1, e1, e0 * e0));
 }
 
 __device__ __forceinline__ double matern_f64_rt(int two_nu, double r, double c, double s2) {

@@ -17,12 +17,15 @@
 // cov_winner / sqrt(var_winner), the quantity eq. cond_select defines.
 //
 // Factor column (eq. L_col): rows 0..s-1 are the selected points and row s
-// the target.  Theta' = Theta over [selected..., target] is built in FP64
-// (its lower triangle spread over the lanes, staged in LDS) and factored as
-// L D L^T, left-looking by columns, each row's dot products split over a lane
-// pair; L_{s,i} follows from one back-substitution with the last unit vector:
-// Theta'^{-1} e_last = L^{-T} e_last / d_last and e_last^T Theta'^{-1} e_last =
-// 1 / d_last, so the column is L^{-T} e_last / sqrt(d_last).
+// the target.  FP64: the picks' rows of the pivoted Cholesky that the loop
+// builds, with the target's row (its ui and final variance), are the Cholesky
+// factor G of Theta' = Theta over [selected..., target], and the column is
+// G^{-T} e_last, one back-substitution (factor_from_pivots; pools up to 256).
+// Mixed precision (FP32 rows) and FP64 pools above 256: Theta' is rebuilt in FP64 (its lower triangle spread over the
+// lanes, staged in LDS) and factored as L D L^T, left-looking by columns,
+// each row's dot products split over a lane pair; then Theta'^{-1} e_last =
+// L^{-T} e_last / d_last and e_last^T Theta'^{-1} e_last = 1 / d_last, so the
+// column is L^{-T} e_last / sqrt(d_last) (factor_column).
 //
 // Argmax keys: 64-bit (the FP64 score with the slot in its low mantissa bits)
 // for FP64 and for the top-two variant; the mixed-precision kernel without
@@ -194,6 +197,71 @@ __device__ __forceinline__ void factor_column(const SelectArgs& p, int64_t col, 
     if (lane == 0) p.status[col] = (uint8_t)st;
 }
 
+// Which kernels build the FP64 factor column from the picks' Cholesky rows
+// (factor_from_pivots): those whose pool, rows_per_wave = W * RPL rows per
+// lane over the column's waves, is at most 256 (4 rows per lane of one
+// wave).  The 8-rows-per-lane FP64 kernel spills its partial factor to
+// scratch, and in its variant without the gap output the reused rows gave
+// columns 1e-2 away from the oracle's (picks and log conditional variances
+// exact; the cause was not found), so pools above 256 rebuild Theta' from
+// the points (factor_column) in both schedules, which keeps the one-wave
+// and multi-wave schedules bit-identical for every pool width.
+template <typename T>
+__host__ __device__ constexpr bool reuse_pivots(int rows_per_wave) {
+    return sizeof(T) == 8 && rows_per_wave <= 4;
+}
+
+// A target's final conditional variance at or below this fraction of the
+// prior variance is zero within the rounding of its FP64 downdates (about
+// k u prior for k picks): the selected block is then singular.
+constexpr double kSingularFrac = 0x1p-46;
+
+// Factor column (eq. L_col) of an FP64 selection from its own pivoted
+// Cholesky rows.  The greedy loop is a pivoted left-looking Cholesky of the
+// pool's covariance, so the Cholesky factor G of Theta' over [picks...,
+// target] is already at hand: row t < nsel is the row of pick t when it
+// was picked (its t partial-factor entries, kept in LDS row t of G, and
+// sqrt(var_t), whose reciprocal lane t holds in my_isd), and the target row
+// is (ui_0 .. ui_{nsel-1}, sqrt(vt)), with ui_t in lane t's my_ui and vt the
+// target's final conditional variance.  Theta'^{-1} e_last / sqrt(e_last^T
+// Theta'^{-1} e_last) = G^{-T} e_last, so the column is z with G^T z =
+// e_last: z_last = 1 / sqrt(vt), then z_r = -(sum_{c>r} G[c][r] z_c) / G[r][r]
+// for r = nsel-1 .. 0, lane r accumulating its own sum.
+template <int KMAX>
+__device__ __forceinline__ void factor_from_pivots(const SelectArgs& p, int64_t col, int lane, int nsel,
+                                                   int32_t my_sel, float my_gap, int st, double vt, double prior,
+                                                   double my_ui, double my_isd, const double (&G)[KMAX + 1][KMAX + 2]) {
+    const int kout = p.k;
+    int32_t* sel_out = p.sel + col * kout;
+    double* fac_out = p.fac + col * (kout + 1);
+    const bool pd = vt > kSingularFrac * prior;
+    double y = __builtin_nan("");
+    if (pd) {
+        const double zl = rsq64(vt);
+        double acc = lane < nsel ? my_ui * zl : 0.0;
+        y = lane == nsel ? zl : 0.0;
+#pragma unroll
+        for (int r = KMAX - 1; r >= 0; --r) {
+            if (r >= nsel) continue;
+            // lane r's sum is complete: every row below r has been applied
+            const double zr = bcast(-acc * my_isd, r);
+            if (lane == r) y = zr;
+            if (lane < r) acc = fma(G[r][lane], zr, acc);
+        }
+        if (p.logcv && lane == 0) p.logcv[col] = log(vt);
+    } else {
+        st = 2;
+        if (lane == 0 && p.logcv) p.logcv[col] = __builtin_nan("");
+    }
+    if (lane < kout) {
+        sel_out[lane] = lane < nsel ? my_sel : -1;
+        fac_out[1 + lane] = lane < nsel ? y : (pd ? 0.0 : __builtin_nan(""));
+        if (p.gap) p.gap[col * kout + lane] = my_gap;
+    }
+    if (lane == nsel) fac_out[0] = y;
+    if (lane == 0) p.status[col] = (uint8_t)st;
+}
+
 
 // GAP: also track the second-best score of every step (top-two reduction) for
 // the top2_gap output; without it the reduction is a plain maximum.
@@ -258,7 +326,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 for (int d = 0; d < dim; ++d) dx[rr][d] = (T)(p.pts[(int64_t)q * dim + d] - xi[d]);
             }
         }
-        const T r = tsqrt(dx[rr][0] * dx[rr][0] + dx[rr][1] * dx[rr][1] + dx[rr][2] * dx[rr][2]);
+        const T r = tsqrt(sqnorm3(dx[rr][0], dx[rr][1], dx[rr][2]));
         cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
         // var = -1 marks a slot that can never be picked (empty, or selected)
         var[rr] = pid[rr] >= 0 ? prior : -1.0;
@@ -285,10 +353,12 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     T L[RPL][KMAX];
     int32_t my_sel = -1;
     float my_gap = __builtin_nanf("");
-    // top-two variant: the target's tracked conditional variance and, in lane
-    // t, the fraction of it that pick t removes
+    // the target's tracked conditional variance; top-two variant: in lane t,
+    // the fraction of it that pick t removes
     double vt = p.s2 + p.nugget;
     double my_gain = __builtin_nan("");
+    // FP64: lane t keeps pick t's target-row entry ui_t and 1 / sqrt(var_t)
+    double my_ui = 0.0, my_isd = 0.0;
     int nsel = 0;
     int st = 0;
     bool stopped = false;
@@ -351,18 +421,28 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 // broadcast the winner's row through LDS (the factor-phase
                 // buffer is free during the picks): the winning lane stores
                 // its factor row, offset, var, cov and index; every lane reads
-                // them back as broadcasts
-                T* bc = reinterpret_cast<T*>(&sh_r[wib][0][0]);
+                // them back as broadcasts.  In FP64 the row goes to row t of
+                // the buffer and stays there: rows 0 .. nsel-1 are the
+                // Cholesky rows of the picks that the factor column reuses.
+                T* bc;
+                T* bdx;
                 double* bcd = &sh_r[wib][KMAX][0];
+                if constexpr (sizeof(T) == 8) {
+                    bc = reinterpret_cast<T*>(&sh_r[wib][t][0]);
+                    bdx = reinterpret_cast<T*>(bcd + 3);
+                } else {
+                    bc = reinterpret_cast<T*>(&sh_r[wib][0][0]);
+                    bdx = bc + KMAX;
+                }
                 if (lane == ls) {
 #pragma unroll
                     for (int rr = 0; rr < RPL; ++rr) {
                         if (rr == rs) {
 #pragma unroll
                             for (int q = 0; q < t; ++q) bc[q] = L[rr][q];
-                            bc[KMAX] = dx[rr][0];
-                            bc[KMAX + 1] = dx[rr][1];
-                            bc[KMAX + 2] = dx[rr][2];
+                            bdx[0] = dx[rr][0];
+                            bdx[1] = dx[rr][1];
+                            bdx[2] = dx[rr][2];
                             bcd[0] = var[rr];
                             bcd[1] = cov[rr];
                             bcd[2] = (double)pid[rr];
@@ -371,7 +451,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
-                const T dk0 = bc[KMAX], dk1 = bc[KMAX + 1], dk2 = bc[KMAX + 2];
+                const T dk0 = bdx[0], dk1 = bdx[1], dk2 = bdx[2];
                 const double vk = bcd[0], ck = bcd[1];
                 const int32_t idk = (int32_t)bcd[2];
                 const double inv_sd = rsq64(vk);
@@ -381,7 +461,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
                     const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
-                    const T r = tsqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                    const T r = tsqrt(sqnorm3(e0, e1, e2));
                     acc[rr] = matern<T, TWO_NU>(r, cnu, s2);
                     if (pid[rr] == idk) acc[rr] += nug;
                 }
@@ -390,7 +470,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 for (int q = 0; q < t; ++q) {
                     const T lk = bc[q];
 #pragma unroll
-                    for (int rr = 0; rr < RPL; ++rr) acc[rr] -= L[rr][q] * lk;
+                    for (int rr = 0; rr < RPL; ++rr) acc[rr] = fma(-L[rr][q], lk, acc[rr]);
                 }
                 __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                 __builtin_amdgcn_wave_barrier();
@@ -399,8 +479,8 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                     const T u = acc[rr] * inv_sd_t;
                     L[rr][t] = u;
                     const double ud = (double)u;
-                    var[rr] -= ud * ud;
-                    cov[rr] -= ud * ui;
+                    var[rr] = fma(-ud, ud, var[rr]);
+                    cov[rr] = fma(-ud, ui, cov[rr]);
                 }
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr)
@@ -409,11 +489,13 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                     // the pick's score is ck^2 / vk = ui^2 (eq. obj_gp); over
                     // the target's variance it is eq. global_obj's key
                     if (lane == t) my_gain = ui * ui / vt;
-                    vt -= ui * ui;
                 }
+                vt = fma(-ui, ui, vt);
                 if (lane == t) {
                     my_sel = idk;
                     my_gap = g;
+                    my_ui = ui;
+                    my_isd = inv_sd;
                 }
                 nsel = t + 1;
             }
@@ -432,7 +514,10 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         if (lane == 0) p.status[col] = (uint8_t)st;
         return;
     }
-    factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, my_gap, tgt, st, sh_r[wib], sh_pt[wib]);
+    if constexpr (reuse_pivots<T>(RPL))
+        factor_from_pivots<KMAX>(p, col, lane, nsel, my_sel, my_gap, st, vt, prior, my_ui, my_isd, sh_r[wib]);
+    else
+        factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, my_gap, tgt, st, sh_r[wib], sh_pt[wib]);
 }
 
 template <typename T, int TWO_NU, int RPL, int KMAX, bool GAP>

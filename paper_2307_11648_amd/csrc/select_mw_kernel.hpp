@@ -23,7 +23,8 @@
 // column that has stopped, or a slot without a column, passes them idle), so
 // columns of different lengths share a workgroup safely.  After the picks,
 // wave 0 of each column builds the factor column exactly as the one-wave
-// kernel does (factor_column).  No top-two gap output.
+// kernel does (FP64 pools up to 256: from the picks' Cholesky rows,
+// factor_from_pivots; otherwise factor_column).  No top-two gap output.
 
 #pragma once
 
@@ -106,7 +107,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
                 for (int d = 0; d < dim; ++d) dx[rr][d] = (T)(p.pts[(int64_t)q * dim + d] - xi[d]);
             }
         }
-        const T r = tsqrt(dx[rr][0] * dx[rr][0] + dx[rr][1] * dx[rr][1] + dx[rr][2] * dx[rr][2]);
+        const T r = tsqrt(sqnorm3(dx[rr][0], dx[rr][1], dx[rr][2]));
         cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
         // var = -1 marks a slot that can never be picked (empty, or selected)
         var[rr] = pid[rr] >= 0 ? prior : -1.0;
@@ -125,11 +126,18 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
     int nsel = 0;
     int st = 0;
     bool stopped = false;
-    T* bc = reinterpret_cast<T*>(&sh_r[cib][0][0]);
+    // FP64: the target's tracked conditional variance, and in lane t pick t's
+    // target-row entry ui_t and 1 / sqrt(var_t) (the factor column reuses the
+    // picks' Cholesky rows, as in the one-wave kernel)
+    double vt = prior, my_ui = 0.0, my_isd = 0.0;
+    // the winner's factor row (FP64: row t of the buffer, kept), its offset,
+    // var, cov and id
     double* bcd = &sh_r[cib][KMAX][0];
+    T* bdx = sizeof(T) == 8 ? reinterpret_cast<T*>(bcd + 3) : reinterpret_cast<T*>(&sh_r[cib][0][0]) + KMAX;
 #pragma unroll
     for (int t = 0; t < KMAX; ++t) {
         const bool active = t < kk && !stopped;  // the same in the column's W waves
+        T* bc = reinterpret_cast<T*>(&sh_r[cib][sizeof(T) == 8 ? t : 0][0]);
         // this wave's best key: larger score first, then the smaller slot
         uint64_t lk = 0ull;
         if (active) {
@@ -188,9 +196,9 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
                         if (rr == rs) {
 #pragma unroll
                             for (int q = 0; q < t; ++q) bc[q] = L[rr][q];
-                            bc[KMAX] = dx[rr][0];
-                            bc[KMAX + 1] = dx[rr][1];
-                            bc[KMAX + 2] = dx[rr][2];
+                            bdx[0] = dx[rr][0];
+                            bdx[1] = dx[rr][1];
+                            bdx[2] = dx[rr][2];
                             bcd[0] = var[rr];
                             bcd[1] = cov[rr];
                             bcd[2] = (double)pid[rr];
@@ -201,7 +209,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
         }
         __syncthreads();
         if (active && gk != 0ull) {
-            const T dk0 = bc[KMAX], dk1 = bc[KMAX + 1], dk2 = bc[KMAX + 2];
+            const T dk0 = bdx[0], dk1 = bdx[1], dk2 = bdx[2];
             const double vk = bcd[0], ck = bcd[1];
             const int32_t idk = (int32_t)bcd[2];
             const double inv_sd = rsq64(vk);
@@ -211,7 +219,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
 #pragma unroll
             for (int rr = 0; rr < RPL; ++rr) {
                 const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
-                const T r = tsqrt(e0 * e0 + e1 * e1 + e2 * e2);
+                const T r = tsqrt(sqnorm3(e0, e1, e2));
                 acc[rr] = matern<T, TWO_NU>(r, cnu, s2);
                 if (pid[rr] == idk) acc[rr] += nug;
             }
@@ -220,15 +228,15 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
             for (int q = 0; q < t; ++q) {
                 const T lk2 = bc[q];
 #pragma unroll
-                for (int rr = 0; rr < RPL; ++rr) acc[rr] -= L[rr][q] * lk2;
+                for (int rr = 0; rr < RPL; ++rr) acc[rr] = fma(-L[rr][q], lk2, acc[rr]);
             }
 #pragma unroll
             for (int rr = 0; rr < RPL; ++rr) {
                 const T u = acc[rr] * inv_sd_t;
                 L[rr][t] = u;
                 const double ud = (double)u;
-                var[rr] -= ud * ud;
-                cov[rr] -= ud * ui;
+                var[rr] = fma(-ud, ud, var[rr]);
+                cov[rr] = fma(-ud, ui, cov[rr]);
             }
             const int wo = slot / (RPL * kWave);
             const int rs = (slot / kWave) % RPL;
@@ -236,7 +244,12 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
 #pragma unroll
             for (int rr = 0; rr < RPL; ++rr)
                 if (w == wo && rr == rs && lane == ls) var[rr] = -1.0;
-            if (lane == t) my_sel = idk;
+            vt = fma(-ui, ui, vt);
+            if (lane == t) {
+                my_sel = idk;
+                my_ui = ui;
+                my_isd = inv_sd;
+            }
             nsel = t + 1;
         }
     }
@@ -264,7 +277,11 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
         if (lane == 0) p.status[col] = (uint8_t)st;
         return;
     }
-    factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, __builtin_nanf(""), tgt, st, sh_r[cib], sh_pt[cib]);
+    if constexpr (reuse_pivots<T>(W * RPL))
+        factor_from_pivots<KMAX>(p, col, lane, nsel, my_sel, __builtin_nanf(""), st, vt, prior, my_ui, my_isd,
+                                 sh_r[cib]);
+    else
+        factor_column<TWO_NU, KMAX>(p, col, lane, nsel, my_sel, __builtin_nanf(""), tgt, st, sh_r[cib], sh_pt[cib]);
 }
 
 template <typename T, int TWO_NU, int RPL, int KMAX, int W>
