@@ -46,8 +46,11 @@ def eval_flops(dim: int, two_nu: int) -> int:
     return 3 * dim + 3 + poly
 
 
-def column_work(C, k, dim, two_nu):
-    """Algorithmic flops and bytes of one column (numpy arrays C, k)."""
+def column_work(C, k, dim, two_nu, from_pivots=False):
+    """Algorithmic flops and bytes of one column (numpy arrays C, k).
+    from_pivots: the factor column is one back-substitution with the picks'
+    Cholesky rows (FP64, pools up to 256); otherwise Theta_ss over the picks
+    and the target is built and factored first."""
     import numpy as np
 
     C = np.asarray(C, np.float64)
@@ -58,7 +61,10 @@ def column_work(C, k, dim, two_nu):
     down = 4.0 * C * kk                           # two FP64 FMAs per candidate per pick
     score = 2.0 * C * kk                          # cov^2 and the division
     m = kk + 1
-    tss = fe * m * (m + 1) / 2.0 + m ** 3 / 3.0 + m * m   # Theta_ss build, Cholesky, back-substitution
+    if from_pivots:
+        tss = m * m                                # back-substitution
+    else:
+        tss = fe * m * (m + 1) / 2.0 + m ** 3 / 3.0 + m * m   # Theta_ss build, Cholesky, back-substitution
     flops = fe * evals + gemv + down + score + tss
     # bytes: target + pool_len + pool indices read, outputs written
     # (sel int32 k, factor fp64 k+1, log_condvar fp64, status u8)
@@ -443,10 +449,10 @@ def _source_digest(*names):
 # and the digest of its sources at measurement time; a changed kernel reports
 # null.
 MEASURED_TRAFFIC = {
-    # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,308 - 524,316 KiB) + WRITE_SIZE x 1.0, in bytes
-    ("select_factor_kernel (kept pools)", "natural", "b927a454ec063414"): (5418899 * 1.9999 + 398462) * 1024,
-    ("select_factor_kernel (kept pools)", "spatial", "b927a454ec063414"): (540679 * 1.9999 + 471983) * 1024,
-    ("screen_kernel", "spatial", "95eec300ad84d5cd"): (2571307 * 1.9999 + 567927) * 1024,
+    # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.0, in bytes; medians of
+    # the launches of the default run (learned-screened workload, N = 1e6)
+    ("select_factor_kernel<double> (kept pools)", "spatial", "934c0e6346adbc2b"): (543896 * 1.9999 + 471925) * 1024,
+    ("screen_kernel", "spatial", "4730514d6a132cd8"): (2632670 * 1.9999 + 567916) * 1024,
     # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
     ("select_factor_kernel (plain batched)", "natural", "b927a454ec063414"): (63143 * 1.9999 + 39844) * 1024,
     ("select_factor_kernel (plain batched)", "spatial", "b927a454ec063414"): (73595 * 1.9999 + 47877) * 1024,
@@ -677,7 +683,7 @@ def bench_screened(args):
             / abs(float(a["log_condvar"].sum())),
             "worst_factor_rel_error_on_identical_columns": err}
 
-    flops_kept, _ = column_work(kernel_ms["fp64"][2], k, 3, 3)
+    flops_kept, _ = column_work(kernel_ms["fp64"][2], k, 3, 3, from_pivots=True)
     mlp_flops = 2.0 * (16 * 64 + 64 * 64 + 64) * float(np.sum(w.pool_len))
     sched = legs["fp64"]["kept_pool_schedule"]["schedule"]
     kernels = {
@@ -1017,7 +1023,8 @@ def main():
     # a single 1024-thread block over T doubles (a few microseconds)
     kern_ms = float(np.mean([a.elapsed_time(b_) for a, b_ in ev]))
 
-    flops, byt = column_work(w.pool_len, k, w.points.shape[1], w.kernel.two_nu)
+    flops, byt = column_work(w.pool_len, k, w.points.shape[1], w.kernel.two_nu,
+                             from_pivots=args.precision == "fp64" and pl.shape[1] <= 256)
     plain_schedule = tuner.choices[autotune.shape_key(pts.shape[1], int(w.kernel.two_nu), T, pl.shape[1], k,
                                                       args.precision)]["schedule"]
     flops_launch = float(np.sum(flops))
