@@ -101,8 +101,10 @@ int32_t csel_max_select(void);
  *   k          0 <= k <= csel_max_select()
  *   precision  CSEL_FP64: everything in FP64.
  *              CSEL_MIXED: covariance evaluation and the left-looking GEMV of
- *              the selection in FP32; conditional variances/covariances, the
- *              scores, Theta_ss and its L D L^T factorization in FP64.
+ *              the selection in FP32; conditional variances/covariances,
+ *              Theta_ss and its L D L^T factorization in FP64; candidates
+ *              ranked by the FP32 value of the FP64 score cov^2 / var (equal
+ *              values to the smaller pool slot), with or without top2_gap.
  * Outputs (per column c):
  *   sel_idx    [n_targets][k] selected ids in selection order, -1 padded
  *   factor_val [n_targets][k+1]: [0] = L_ii, [1+t] = entry of row sel_idx[t];
@@ -110,8 +112,9 @@ int32_t csel_max_select(void);
  *   log_condvar[n_targets] log Theta_{ii | s_i \ i} (may be NULL); the sum
  *              over all columns minus log det Theta is 2 KL (eq. obj_chol)
  *   top2_gap   [n_targets][k] relative gap (s1 - s2)/s1 between the best and
- *              second-best scores at each step, 1 with a single eligible
- *              candidate, NaN padded (may be NULL)
+ *              second-best scores at each step (the ranked scores: FP64, or
+ *              FP32 in CSEL_MIXED), 1 with a single eligible candidate, NaN
+ *              padded (may be NULL).  Asking for it changes no other output.
  *   status     [n_targets] per-column status (see above)
  */
 int csel_select_and_factor(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel,

@@ -141,6 +141,23 @@ __device__ __forceinline__ double key_score(uint64_t key) {
     return __longlong_as_double((long long)(key & ~kSlotMask));
 }
 
+// Mixed-precision selection keys: the FP32 score cov^2 / var of the FP64
+// state, its bits above (the top bit set: a valid candidate; scores are
+// >= 0) and the complement of the slot below, so a larger key is a larger
+// FP32 score, then a smaller slot; 0 = none.  The plain-maximum and the
+// top-two reductions rank candidates identically with these keys.
+__device__ __forceinline__ float mixed_score(double cov, double var) {
+    const float cf = (float)cov;
+    return cf * cf * __builtin_amdgcn_rcpf((float)var);
+}
+__device__ __forceinline__ uint64_t mixed_key(float score, int slot) {
+    return ((uint64_t)(__float_as_uint(score) | 0x80000000u) << 32) | (uint64_t)(0xFFFFFFFFu - (uint32_t)slot);
+}
+__device__ __forceinline__ int mixed_key_slot(uint64_t key) { return (int)(0xFFFFFFFFu - (uint32_t)key); }
+__device__ __forceinline__ float mixed_key_score(uint64_t key) {
+    return __uint_as_float((uint32_t)(key >> 32) & 0x7FFFFFFFu);
+}
+
 // 1/v in FP64: hardware reciprocal refined by one Newton step (about 1 ulp)
 __device__ __forceinline__ double rcp64(double v) {
     const double r = __builtin_amdgcn_rcp(v);
@@ -183,13 +200,14 @@ __device__ __forceinline__ double rsq64(double v) {
 // ---------------------------------------------------------------------------
 // Matern kernels (half-integer smoothness).  `c` = sqrt(2 nu) / length_scale.
 // ---------------------------------------------------------------------------
+// (the polynomial factor with explicit fused multiply-adds, as in matern_f64)
 template <int TWO_NU>
 __device__ __forceinline__ float matern_f32(float r, float c, float s2) {
     const float a = c * r;
     const float e = __expf(-a);
     if constexpr (TWO_NU == 1) return s2 * e;
-    if constexpr (TWO_NU == 3) return s2 * (1.0f + a) * e;
-    return s2 * (1.0f + a + a * a * (1.0f / 3.0f)) * e;
+    if constexpr (TWO_NU == 3) return s2 * fmaf(c, r, 1.0f) * e;
+    return s2 * fmaf(a, fmaf(a, 1.0f / 3.0f, 1.0f), 1.0f) * e;
 }
 
 // e^{-a} for finite a >= 0 in FP64, about 2 ulp: Cody-Waite reduction

@@ -27,10 +27,11 @@
 // L^{-T} e_last / d_last and e_last^T Theta'^{-1} e_last = 1 / d_last, so the
 // column is L^{-T} e_last / sqrt(d_last) (factor_column).
 //
-// Argmax keys: 64-bit (the FP64 score with the slot in its low mantissa bits)
-// for FP64 and for the top-two variant; the mixed-precision kernel without
-// the gap output takes the maximum of the FP32 score's bits and resolves
-// equal maxima to the smallest slot with ballots.
+// Argmax keys: FP64, the FP64 score with the slot in its low mantissa bits.
+// Mixed precision ranks by the FP32 score of the FP64 state, equal scores to
+// the smallest slot: without the gap output as the maximum of the score's
+// bits and ballots for the slot, with it as a top-two of 64-bit keys (score
+// bits above, slot below), so both variants pick identically.
 
 #pragma once
 
@@ -367,12 +368,16 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         if (t < kk && !stopped) {
             Top2 w;
             if constexpr (GAP) {
+                // FP64: keys of the FP64 score; mixed: keys of the FP32 score,
+                // which rank as the variant without the gap does
                 Top2 loc = {0ull, 0ull};
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
                     if (var[rr] > thr) {
-                        const double sc = cov[rr] * cov[rr] * rcp64(var[rr]);
-                        insert(loc, make_key(sc, rr * kWave + lane));
+                        if constexpr (sizeof(T) == 8)
+                            insert(loc, make_key(cov[rr] * cov[rr] * rcp64(var[rr]), rr * kWave + lane));
+                        else
+                            insert(loc, mixed_key(mixed_score(cov[rr], var[rr]), rr * kWave + lane));
                     }
                 }
                 w = wave_top2(loc);
@@ -392,8 +397,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 uint32_t key[RPL], best = 0u;
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
-                    const float cf = (float)cov[rr];
-                    const float sc = cf * cf * __builtin_amdgcn_rcpf((float)var[rr]);
+                    const float sc = mixed_score(cov[rr], var[rr]);
                     key[rr] = var[rr] > thr ? (__float_as_uint(sc) | 0x80000000u) : 0u;
                     best = max(best, key[rr]);
                 }
@@ -412,10 +416,12 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 st = 1;
                 stopped = true;
             } else {
-                const int slot = key_slot(w.k1);
+                constexpr bool kMixedKeys = GAP && sizeof(T) == 4;
+                const int slot = kMixedKeys ? mixed_key_slot(w.k1) : key_slot(w.k1);
                 const int rs = slot >> 6;
                 const int ls = slot & (kWave - 1);
-                const double sa = key_score(w.k1), sb = key_score(w.k2);
+                const double sa = kMixedKeys ? (double)mixed_key_score(w.k1) : key_score(w.k1);
+                const double sb = kMixedKeys ? (double)mixed_key_score(w.k2) : key_score(w.k2);
                 const float g = (w.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
 
                 // broadcast the winner's row through LDS (the factor-phase

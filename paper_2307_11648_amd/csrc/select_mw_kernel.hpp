@@ -154,8 +154,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
                 uint32_t key[RPL], best = 0u;
 #pragma unroll
                 for (int rr = 0; rr < RPL; ++rr) {
-                    const float cf = (float)cov[rr];
-                    const float sc = cf * cf * __builtin_amdgcn_rcpf((float)var[rr]);
+                    const float sc = mixed_score(cov[rr], var[rr]);
                     key[rr] = var[rr] > thr ? (__float_as_uint(sc) | 0x80000000u) : 0u;
                     best = max(best, key[rr]);
                 }
