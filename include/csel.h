@@ -255,6 +255,44 @@ int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel
                            hipStream_t stream);
 
 /*
+ * csel_partial_select -- partial (non-adjacent) aggregated selection, FP64
+ * (Sec. 5.1 eq. chol_partial and eq. partial_kl; App. C.3).  As
+ * csel_aggregated_select, but the candidates may lie between the group's
+ * members: a selected point j joins the pattern of every member q < j (it
+ * conditions only the members it follows), and the group term minimized is
+ * sum_{q in T} log Theta_{qq | s_q \ q}, s_q = {j in T u S : j > q}, the log
+ * determinant of the partially conditioned member covariance.  Each pick
+ * maximizes its decrease: over the members j conditions, walking the
+ * columns (selected and member points by decreasing id) with v = Theta_{jj |
+ * columns before}, a member's variance falls by 1 - L_jc^2 / v (eq.
+ * obj_partial) and then v -= L_jc^2 (eq. partial_induct); the score is
+ * 1 - prod (1 - L_jc^2 / v), in [0, 1].  Eligible: v > 1e-12 times the prior
+ * variance after the last column; ties to the smaller pool slot.  With every
+ * candidate after every member this is csel_aggregated_select's selection.
+ *
+ *   members      [sum m] int32 member ids, strictly ascending within a group
+ *   group_ptr    [n_groups+1]; 1 <= m_g <= max_members <= 32
+ *   pool_idx     [n_groups][pool_stride] candidate ids (no member, no repeat),
+ *                pool_len [n_groups]; pool_stride <= 512; k <= 32; every
+ *                group needs m_g + min(k, pool_len) <= 64
+ * Outputs: sel_idx, top2_gap (may be NULL), group_logdet (the group term
+ * after the picks, may be NULL), status (0, 1 stopped early, 2 not positive
+ * definite, 3 bad input: a member or pool id out of range, members not
+ * strictly ascending, a pool id that is a member or repeats, or a size
+ * above the limits), and, with factor_val, the member columns exactly as in
+ * csel_aggregated_select (member a owns m_g - a + k_g slots at val_ptr;
+ * eq. L_col on s_q = {j in sort(T u S) : j >= q}) and member_log_condvar,
+ * whose sum over a group is its group term (eq. partial_kl).
+ * Errors: CSEL_EUNSUPPORTED for sizes above the limits.
+ */
+int csel_partial_select(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_groups,
+                        const int32_t *group_ptr, const int32_t *members, int32_t max_members,
+                        const int32_t *pool_idx, const int32_t *pool_len, int32_t pool_stride, int32_t k,
+                        int32_t *sel_idx, float *top2_gap, double *group_logdet, const int64_t *val_ptr,
+                        int32_t *factor_rows, double *factor_val, double *member_log_condvar, uint8_t *status,
+                        hipStream_t stream);
+
+/*
  * csel_apply_factor -- product with a sparse lower-triangular factor L in CSC
  * form, the way the factor is used once built (L L^T ~ Theta^{-1}; e.g. as a
  * preconditioner, Sec. 6.3).

@@ -74,6 +74,10 @@ def load():
                                            _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                            _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.csel_aggregated_select.restype = ctypes.c_int
+    lib.csel_partial_select.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64,
+                                        _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp,
+                                        _vp, _vp, _vp, _vp, _vp]
+    lib.csel_partial_select.restype = ctypes.c_int
     lib.csel_select_and_factor_list.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams),
                                                 _c.c_int64, _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                                 _vp, _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -671,6 +675,43 @@ def aggregated_select(points, kernel, group_ptr, members, max_members: int, pool
                                     _ptr(out.get("logdet")), _ptr(out.get("post_var")), _ptr(out.get("val_ptr")),
                                     _ptr(out.get("rows")), _ptr(out.get("vals")),
                                     _ptr(out.get("member_log_condvar")), _ptr(out["status"]), _stream(stream))
+    _check(rc)
+    return out
+
+
+def partial_select(points, kernel, group_ptr, members, max_members: int, pool, pool_len, k: int,
+                   want_factor: bool = False, want_gap: bool = False, out: dict | None = None, stream=None) -> dict:
+    """Partial (non-adjacent) aggregated selection, FP64 (csel_partial_select):
+    candidates may lie between a group's members and condition only the
+    members they follow.  Returns GPU tensors sel [G, k], logdet [G] (the
+    group term), status [G]; with want_gap gap; with want_factor val_ptr,
+    rows, vals, member_log_condvar (the aggregated member columns)."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    for t, nm in ((group_ptr, "group_ptr"), (members, "members"), (pool, "pool"), (pool_len, "pool_len")):
+        _dev(t, torch.int32, nm)
+    G = group_ptr.numel() - 1
+    stride = pool.shape[1] if pool.dim() == 2 else 0
+    dev = points.device
+    if out is None:
+        out = {"sel": torch.empty((G, k), dtype=torch.int32, device=dev),
+               "logdet": torch.empty(G, dtype=torch.float64, device=dev),
+               "status": torch.empty(G, dtype=torch.uint8, device=dev)}
+        if want_gap:
+            out["gap"] = torch.empty((G, k), dtype=torch.float32, device=dev)
+        if want_factor:
+            vp = aggregated_val_ptr(group_ptr, pool_len, k)
+            nnz = int(vp[-1].item())
+            out.update(val_ptr=vp, rows=torch.empty(max(nnz, 1), dtype=torch.int32, device=dev),
+                       vals=torch.empty(max(nnz, 1), dtype=torch.float64, device=dev),
+                       member_log_condvar=torch.empty(members.numel(), dtype=torch.float64, device=dev))
+    kp = kernel_struct(kernel)
+    rc = lib.csel_partial_select(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), G,
+                                 group_ptr.data_ptr(), members.data_ptr(), int(max_members), pool.data_ptr(),
+                                 pool_len.data_ptr(), stride, int(k), _ptr(out["sel"]), _ptr(out.get("gap")),
+                                 _ptr(out.get("logdet")), _ptr(out.get("val_ptr")), _ptr(out.get("rows")),
+                                 _ptr(out.get("vals")), _ptr(out.get("member_log_condvar")), _ptr(out["status"]),
+                                 _stream(stream))
     _check(rc)
     return out
 

@@ -437,6 +437,63 @@ CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, c
     return CSEL_OK;
 }
 
+CSEL_API int csel_partial_select(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                 int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
+                                 int32_t max_members, const int32_t* pool_idx, const int32_t* pool_len,
+                                 int32_t pool_stride, int32_t k, int32_t* sel_idx, float* top2_gap,
+                                 double* group_logdet, const int64_t* val_ptr, int32_t* factor_rows,
+                                 double* factor_val, double* member_log_condvar, uint8_t* status,
+                                 hipStream_t stream) {
+    g_err[0] = 0;
+    int rc = check_kernel(kernel);
+    if (rc) return rc;
+    if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (n_groups < 0 || n_groups > INT32_MAX) return fail(CSEL_EINVAL, "n_groups must be in [0, 2^31)");
+    if (pool_stride < 0 || pool_stride > csel::partial_max_pool())
+        return fail(CSEL_EUNSUPPORTED, "pool_stride must be in [0, %d] (got %d)", csel::partial_max_pool(),
+                    pool_stride);
+    if (max_members < 1 || max_members > csel::partial_max_members())
+        return fail(CSEL_EUNSUPPORTED, "max_members must be in [1, %d] (got %d)", csel::partial_max_members(),
+                    max_members);
+    if (k < 0 || k > csel::partial_max_k())
+        return fail(CSEL_EUNSUPPORTED, "k must be in [0, %d] (got %d)", csel::partial_max_k(), k);
+    if (n_groups == 0) return CSEL_OK;
+    const bool want_factor = factor_val != nullptr;
+    if (!pts || !group_ptr || !members || !pool_len || !status || (k > 0 && !sel_idx) ||
+        (pool_stride > 0 && !pool_idx))
+        return fail(CSEL_EINVAL, "a required array is NULL");
+    if (want_factor && (!val_ptr || !factor_rows))
+        return fail(CSEL_EINVAL, "factor output needs val_ptr, factor_rows and factor_val");
+    csel::AggArgs a{};
+    a.pts = pts;
+    a.n = n;
+    a.dim = dim;
+    a.two_nu = kernel->two_nu;
+    a.c_nu = c_nu(kernel);
+    a.s2 = kernel->variance;
+    a.nugget = kernel->nugget;
+    a.n_groups = n_groups;
+    a.group_ptr = group_ptr;
+    a.members = members;
+    a.max_members = max_members;
+    a.pool = pool_idx;
+    a.pool_len = pool_len;
+    a.stride = pool_stride;
+    a.k = k;
+    a.sel = sel_idx;
+    a.gap = top2_gap;
+    a.logdet = group_logdet;
+    a.status = status;
+    a.val_ptr = val_ptr;
+    a.fac_rows = factor_rows;
+    a.fac_val = factor_val;
+    a.member_logcv = member_log_condvar;
+    hipError_t e = csel::launch_partial(a, want_factor, stream);
+    if (e != hipSuccess) return hip_fail(e, "partial_select launch");
+    return CSEL_OK;
+}
+
 CSEL_API int csel_select_and_factor_list(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
                                          int64_t n_targets, const int32_t* targets, const int32_t* pool_idx,
                                          const int32_t* pool_len, int32_t pool_stride, int32_t k, int32_t precision,

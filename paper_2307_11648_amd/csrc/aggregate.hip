@@ -831,4 +831,10 @@ hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision,
 
 int agg_factor_max_m() { return kAggFacMaxM; }
 
+hipError_t launch_agg_factor(const AggArgs& a, hipStream_t s) {
+    if (a.n_groups == 0) return hipSuccess;
+    hipLaunchKernelGGL(agg_factor_kernel, dim3((unsigned)a.n_groups), dim3(kAggFacThreads), 0, s, a);
+    return hipGetLastError();
+}
+
 }  // namespace csel

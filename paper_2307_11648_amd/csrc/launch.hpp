@@ -167,6 +167,15 @@ struct AggPlan {
 AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision);
 hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s);
 int agg_factor_max_m();
+// the aggregated member columns (eq. L_col on s_q = {j in sort(T u S) : j >= q})
+hipError_t launch_agg_factor(const AggArgs& a, hipStream_t s);
+
+// partial (non-adjacent) aggregated selection, FP64, then (want_factor) the
+// member columns
+hipError_t launch_partial(const AggArgs& a, bool want_factor, hipStream_t s);
+int partial_max_members();
+int partial_max_k();
+int partial_max_pool();
 
 // rpl: pool rows per lane (1, 2, 4, 8); kmax: 16 or 32.
 hipError_t launch_select_factor(const SelectArgs& a, int precision, int rpl, int kmax, hipStream_t s);

@@ -147,10 +147,13 @@ def make_groups(x_ordered: np.ndarray, ell: np.ndarray, sizes: np.ndarray, lam: 
 
 
 def group_pools(x: np.ndarray, group_ptr: np.ndarray, members: np.ndarray, C: int,
-                later_only: bool = True, cand_range: tuple[int, int] | None = None):
+                later_only: bool | str = True, cand_range: tuple[int, int] | None = None):
     """Union pools: the C points nearest to any member of the group, either
-    among positions after the group's last member (later_only) or among the
-    ids in cand_range = [c0, c1)."""
+    among positions after the group's last member (later_only True), among
+    the points after at least one member, each member contributing its own
+    later neighbours and the members themselves left out (later_only
+    "member": the partial, non-adjacent case), or among the ids in
+    cand_range = [c0, c1)."""
     x = np.ascontiguousarray(x, dtype=np.float64)
     n, d = x.shape
     gp = np.ascontiguousarray(group_ptr, dtype=np.int32)
@@ -159,7 +162,8 @@ def group_pools(x: np.ndarray, group_ptr: np.ndarray, members: np.ndarray, C: in
     c0, c1 = cand_range if cand_range is not None else (0, n)
     pool = np.empty((G, C), np.int32)
     plen = np.empty(G, np.int32)
-    rc = _load().csel_geo_group_pools(_p(x, _f64p), n, d, G, _p(gp, _i32p), _p(mem, _i32p), int(later_only),
+    mode = 2 if later_only == "member" else int(bool(later_only))
+    rc = _load().csel_geo_group_pools(_p(x, _f64p), n, d, G, _p(gp, _i32p), _p(mem, _i32p), mode,
                                       c0, c1, C, _p(pool, _i32p), _p(plen, _i32p))
     if rc != 0:
         raise ValueError("group_pools: bad arguments")
@@ -282,6 +286,22 @@ def workload_aggregated(n: int = 1_000_000, seed: int = 3, C: int = 512, k: int 
     pool, plen = group_pools(xo, gp, mem, C, later_only=True)
     return GroupWorkload(f"aggregated n={n} d=2 nu=1/2 m={mmin}..{mmax} C={C} k={k}", xo, Kernel(1, 0.02),
                          gp, mem, pool, plen, k, True, {"ell": ell})
+
+
+def workload_partial(n: int = 1_000_000, seed: int = 3, C: int = 512, k: int = 32, mmin: int = 8, mmax: int = 32,
+                     d: int = 2, two_nu: int = 1, ell: float = 0.02):
+    """The aggregated workload's groups with unmodified candidate sets (Sec.
+    5.3): N uniform points in [0,1]^d, Matern, supernodes of m uniform in
+    {mmin..mmax}; each group's pool is the C points nearest to it among the
+    later neighbours of its members (a candidate may precede some members
+    and conditions only those it follows); k per group."""
+    x = uniform_points(n, d, seed)
+    xo, el = ordered_cloud(x)
+    sizes = np.random.default_rng(seed + 1000).integers(mmin, mmax + 1, size=n // mmin + 1).astype(np.int32)
+    gp, mem = make_groups(xo, el, sizes)
+    pool, plen = group_pools(xo, gp, mem, C, later_only="member")
+    return GroupWorkload(f"partial n={n} d={d} nu={two_nu}/2 m={mmin}..{mmax} C={C} k={k}", xo,
+                         Kernel(two_nu, ell), gp, mem, pool, plen, k, False, {"ell": el})
 
 
 def workload_gp(n_train: int = 500_000, n_pred: int = 4096, seed: int = 5, C: int = 2048, k: int = 128,

@@ -406,7 +406,10 @@ int csel_geo_group_pools(const double *x, int32_t n, int32_t d, int32_t n_groups
                          const int32_t *members, int32_t later_only, int32_t cand0, int32_t cand1, int32_t C,
                          int32_t *pool, int32_t *len) {
     if (n <= 0 || d < 1 || d > MAXD || C < 0) return -1;
-    laterforest F; kdtree T; int use_forest = later_only != 0;
+    /* later_only: 0 = the ids in [cand0, cand1); 1 = points after the
+       group's last member; 2 = per member, points after that member (the
+       partial, non-adjacent case), members excluded */
+    laterforest F; kdtree T; int use_forest = later_only != 0; int per_member = later_only == 2;
     int32_t maxnodes = 0;
     if (use_forest) {
         forest_build(&F, x, n, d);
@@ -419,8 +422,8 @@ int csel_geo_group_pools(const double *x, int32_t n, int32_t d, int32_t n_groups
     for (int32_t g = 0; g < n_groups; ++g) if (group_ptr[g + 1] - group_ptr[g] > maxm) maxm = group_ptr[g + 1] - group_ptr[g];
 #pragma omp parallel
     {
-        nbr *h = (nbr *)malloc(sizeof(nbr) * (C > 0 ? C : 1));
-        nbr *all = (nbr *)malloc(sizeof(nbr) * (size_t)(C > 0 ? C : 1) * maxm);
+        nbr *h = (nbr *)malloc(sizeof(nbr) * (size_t)(C + maxm + 1));
+        nbr *all = (nbr *)malloc(sizeof(nbr) * (size_t)(C + maxm + 1) * maxm);
         int32_t *stack = (int32_t *)malloc(sizeof(int32_t) * (maxnodes + 8));
 #pragma omp for schedule(dynamic, 16)
         for (int32_t g = 0; g < n_groups; ++g) {
@@ -430,15 +433,29 @@ int csel_geo_group_pools(const double *x, int32_t n, int32_t d, int32_t n_groups
             const kdtree *tree = use_forest ? forest_pick(&F, mx) : &T;
             kfilter f = {use_forest ? mx : cand0 - 1, NULL, 0.0, NULL};
             int32_t tot = 0;
+            const int32_t m = e - b;
             for (int32_t q = b; q < e; ++q) {
-                int32_t got = kd_knn(tree, x + (int64_t)members[q] * d, C, &f, h, stack);
+                int32_t got;
+                if (per_member) {
+                    /* the member's own later neighbours (m more, as later
+                       members are dropped below) */
+                    kfilter fq = {members[q], NULL, 0.0, NULL};
+                    got = kd_knn(forest_pick(&F, members[q]), x + (int64_t)members[q] * d, C + m, &fq, h, stack);
+                } else {
+                    got = kd_knn(tree, x + (int64_t)members[q] * d, C, &f, h, stack);
+                }
                 memcpy(all + tot, h, sizeof(nbr) * got); tot += got;
             }
-            /* keep each id once with its smallest distance */
+            /* keep each id once with its smallest distance (and no member) */
             qsort(all, tot, sizeof(nbr), nbr_id_cmp);
             int32_t u = 0;
-            for (int32_t j = 0; j < tot; ++j)
-                if (u == 0 || all[u - 1].id != all[j].id) all[u++] = all[j];
+            for (int32_t j = 0; j < tot; ++j) {
+                if (u > 0 && all[u - 1].id == all[j].id) continue;
+                int is_member = 0;
+                if (per_member)
+                    for (int32_t q = b; q < e; ++q) is_member |= members[q] == all[j].id;
+                if (!is_member) all[u++] = all[j];
+            }
             qsort(all, u, sizeof(nbr), nbr_cmp);
             int32_t keep = u < C ? u : C;
             int32_t *row = pool + (int64_t)g * C;

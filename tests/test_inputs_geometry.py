@@ -131,6 +131,50 @@ def test_group_pools_match_brute_force(d, grid):
         np.testing.assert_array_equal(pool[g, : plen[g]], ref)
 
 
+def _brute_member_pool(x, members, C):
+    """Per member its C + m nearest later points (ties to the smaller id);
+    their union without the members, by the smallest distance to a member
+    that listed the point (then id); the first C."""
+    m = len(members)
+    best = {}
+    for q in members:
+        cand = np.arange(q + 1, len(x))
+        d2 = _d2(x[cand], x[q])
+        order = np.lexsort((cand, d2))[: C + m]
+        for j, dj in zip(cand[order], d2[order]):
+            if j not in best or dj < best[j]:
+                best[int(j)] = float(dj)
+    ids = np.array([j for j in best if j not in set(int(q) for q in members)], np.int64)
+    dd = np.array([best[j] for j in ids])
+    return ids[np.lexsort((ids, dd))][:C]
+
+
+@pytest.mark.parametrize("d", [1, 2, 3])
+@pytest.mark.parametrize("grid", [False, True])
+def test_member_later_group_pools_match_brute_force(d, grid):
+    """The partial (non-adjacent) pools: every member's own later neighbours,
+    so a candidate may precede some members; members never enter a pool."""
+    rng = np.random.default_rng(50 + d + 10 * grid)
+    n = 240
+    x = rng.integers(0, 5, size=(n, d)).astype(np.float64) if grid else rng.random((n, d))
+    sizes = rng.integers(1, 7, size=25)
+    gp = np.zeros(len(sizes) + 1, np.int32)
+    gp[1:] = np.cumsum(sizes)
+    mem = np.concatenate([np.sort(rng.choice(220, size=s, replace=False)) for s in sizes]).astype(np.int32)
+    C = 19
+    pool, plen = inputs.group_pools(x, gp, mem, C, later_only="member")
+    interleaved = 0
+    for g in range(len(sizes)):
+        T = mem[gp[g]:gp[g + 1]]
+        ref = _brute_member_pool(x, T, C)
+        assert plen[g] == len(ref)
+        np.testing.assert_array_equal(pool[g, : plen[g]], ref)
+        assert not np.any(np.isin(pool[g, : plen[g]], T))
+        assert np.all(pool[g, : plen[g]] > T.min())
+        interleaved += int(np.any(pool[g, : plen[g]] < T.max()))
+    assert interleaved > 0
+
+
 @pytest.mark.parametrize("d", [2, 3])
 def test_make_groups_matches_brute_force(d):
     rng = np.random.default_rng(40 + d)
