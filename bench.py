@@ -218,6 +218,154 @@ def bench_groups(args):
     print(json.dumps(res), flush=True)
 
 
+def partial_work(group_ptr, members, pool, pool_len, sel, k, dim, two_nu):
+    """Algorithmic flops of partial selection per group (numpy), from the
+    picks the run made: per step t with ncol = m + t columns and the pick
+    inserted after p of them, every remaining candidate's score (2 flops per
+    column, 4 more per member it conditions), every row's new column (one
+    evaluation and p FMAs) and the rank-one downdate of the ncol - p later
+    columns (6 flops per row and column); the member columns' Theta_sg,
+    Cholesky and back-substitutions as in the aggregated count."""
+    import numpy as np
+
+    fe = eval_flops(dim, two_nu)
+    G = len(group_ptr) - 1
+    out = np.zeros(G)
+    for g in range(G):
+        T = members[group_ptr[g]:group_ptr[g + 1]]
+        m = len(T)
+        P = pool[g, : pool_len[g]]
+        C = len(P)
+        R = C + m
+        cond = float(np.mean(np.searchsorted(np.sort(T), P))) if C else 0.0
+        f = fe * R * m + R * m * m  # the members' columns
+        picks = [int(v) for v in sel[g] if v >= 0]
+        for t, j in enumerate(picks):
+            ncol = m + t
+            pp = int(np.sum(T > j)) + sum(1 for v in picks[:t] if v > j)
+            f += (C - t) * (2.0 * ncol + 4.0 * cond) + R * (fe + 2.0 * pp) + 6.0 * R * (ncol - pp)
+        M = m + len(picks)
+        f += fe * M * (M + 1) / 2.0 + M ** 3 / 3.0 + m * M * M
+        out[g] = f
+    return out
+
+
+def bench_partial(args):
+    """Partial (non-adjacent) aggregated selection (Sec. 5.1, App. C.3) on
+    the aggregated workload's groups with unmodified candidate sets: N = 1e6
+    uniform in [0,1]^2, Matern 1/2, l = 0.02, groups of 8-32 members, pools of
+    the 512 points nearest to the group among its members' later neighbours,
+    k = 32, FP64, member columns.  Beside it, the adjacent selection the
+    multi-target algorithm needs (pools cut to the points after the group's
+    last member; csel_aggregated_select, FP64, same k): its time and its KL
+    term, against the partial one's (Sec. 5.3: forcing adjacency loses
+    accuracy)."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs
+
+    n = args.n or 1_000_000
+    k = 32
+    print("bench: building inputs", file=sys.stderr, flush=True)
+    w = inputs.workload_partial(n=n, k=k)
+    pool_adj, plen_adj = inputs.group_pools(w.points, w.group_ptr, w.members, 512, later_only=True)
+    dev = torch.device("cuda:0")
+    t = lambda a, dt: torch.from_numpy(np.ascontiguousarray(a)).to(device=dev, dtype=dt)  # noqa: E731
+    pts = t(w.points, torch.float64)
+    gp_t, mem_t = t(w.group_ptr, torch.int32), t(w.members, torch.int32)
+    pl, ln = t(w.pool, torch.int32), t(w.pool_len, torch.int32)
+    pla, lna = t(pool_adj, torch.int32), t(plen_adj, torch.int32)
+    mm = int(np.max(np.diff(w.group_ptr)))
+    G = len(w.group_ptr) - 1
+    out = csel.partial_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, want_factor=True)
+    sel_only = csel.partial_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, want_factor=False)
+    adj = csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pla, lna, k, "fp64", want_factor=True)
+    torch.cuda.synchronize()
+
+    def timed(fn):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+              for _ in range(args.steps)]
+        for i in range(args.steps):
+            ev[i][0].record()
+            fn()
+            ev[i][1].record()
+        torch.cuda.synchronize()
+        return float(np.median([a.elapsed_time(b_) for a, b_ in ev]))
+
+    print("bench: timing partial selection", file=sys.stderr, flush=True)
+    ms = timed(lambda: csel.partial_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, want_factor=True, out=out))
+    ms_sel = timed(lambda: csel.partial_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, want_factor=False,
+                                               out=sel_only))
+    ws = adj["workspace"]
+    ms_adj = timed(lambda: csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pla, lna, k, "fp64",
+                                                  want_factor=True, out=adj, workspace=ws))
+    st = out["status"].cpu().numpy()
+    sel = out["sel"].cpu().numpy()
+    S_part = float(out["member_log_condvar"].sum())
+    S_adj = float(adj["member_log_condvar"].sum())
+    # the members' term with no selected point: sum over groups of log det Theta_TT, by k = 0
+    zero = csel.partial_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, 0)
+    torch.cuda.synchronize()
+    S_0 = float(zero["logdet"].sum())
+    cols = len(w.members)
+    flops = partial_work(w.group_ptr, w.members, w.pool, w.pool_len, sel, k, 2, w.kernel.two_nu)
+    M = np.diff(w.group_ptr) + np.sum(sel >= 0, axis=1)
+    fe = eval_flops(2, w.kernel.two_nu)
+    m_ = np.diff(w.group_ptr)
+    fac_flops = fe * M * (M + 1) / 2.0 + M ** 3 / 3.0 + m_ * M * M
+    sel_flops = float(np.sum(flops - fac_flops))
+    achieved = sel_flops / (ms_sel * 1e-3) / 1e12
+    res = {
+        "metric": "member factor columns/s (partial aggregated selection)", "value": cols / (ms * 1e-3),
+        "unit": "columns/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"partial aggregated selection, N={n} uniform in [0,1]^2, Matern 1/2, l=0.02, "
+                               f"supernodes of m uniform in 8..32, pools of the 512 points nearest to the group "
+                               f"among its members' later neighbours, k={k}, FP64, member columns; medians of "
+                               f"{args.steps} steps",
+                   "groups": G, "columns": cols, "k": k,
+                   "status_counts": {int(v): int((st == v).sum()) for v in np.unique(st)},
+                   "select_ms": ms_sel, "factor_ms": ms - ms_sel,
+                   "groups_with_interleaved_picks": int(sum(
+                       np.any((sel[g][sel[g] >= 0] < w.members[w.group_ptr[g + 1] - 1])) for g in range(G))),
+                   "adjacent": {"ms": ms_adj, "S": S_adj,
+                                "note": "csel_aggregated_select FP64 on pools cut to the points after the "
+                                        "group's last member, same k"},
+                   "S_partial": S_part, "S_no_selection": S_0,
+                   "kl_term_reduction": {"partial": S_0 - S_part, "adjacent": S_0 - S_adj,
+                                         "partial_over_adjacent": (S_0 - S_part) / (S_0 - S_adj)
+                                         if S_0 != S_adj else None}},
+        "roofline": {"bound": "alu", "kernel": "partial_select_kernel<1>", "achieved": achieved,
+                     "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
+                     "traffic": None, "kernel_ms": ms_sel,
+                     "algorithmic_gflop_per_launch": sel_flops / 1e9},
+    }
+    if args.cpu_seconds > 0:
+        print("bench: cpu baseline (partial oracle)", file=sys.stderr, flush=True)
+        from oracle import partial as opartial
+
+        rng = np.random.default_rng(12345)
+        done = ncols = 0
+        t0 = time.perf_counter()
+        order = rng.permutation(G)
+        while time.perf_counter() - t0 < args.cpu_seconds and done < G:
+            g = int(order[done])
+            opartial.partial_one(w.points, w.kernel, w.members[w.group_ptr[g]:w.group_ptr[g + 1]],
+                                 w.pool[g, : w.pool_len[g]], k)
+            ncols += int(w.group_ptr[g + 1] - w.group_ptr[g])
+            done += 1
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": ncols / dt, "unit": "columns/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{done} of {G} groups ({ncols} member columns, seeded order), the numpy "
+                                         f"FP64 partial-selection oracle (factor rebuilt by left-looking after "
+                                         f"each pick), one process, {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
 def gp_screened(args, w, pts, gp_t, mem_t, mm, pl, ln, plain, ms_plain, keeps=(512, 1024)):
     """The learned-screened GP runs beside the plain one: the group screen is
     trained (untimed set-up) on the exact multi-target selections of GP
@@ -887,7 +1035,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="screened",
-                    choices=["screened", "plain", "aggregated", "gp", "apply", "pcg"])
+                    choices=["screened", "plain", "aggregated", "gp", "apply", "pcg", "partial"])
     ap.add_argument("--pcg-plain-iters", type=int, default=300,
                     help="pcg workload: iteration cap of the unpreconditioned run")
     ap.add_argument("--train-steps", type=int, default=3000, help="screened workload: Adam steps")
@@ -939,6 +1087,8 @@ def main():
         return bench_apply(args)
     if args.workload == "pcg":
         return bench_pcg(args)
+    if args.workload == "partial":
+        return bench_partial(args)
     if args.workload != "plain":
         return bench_groups(args)
     args.n = args.n or 100_000

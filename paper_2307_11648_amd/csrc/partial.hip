@@ -57,7 +57,7 @@ __global__ __launch_bounds__(kPartThreads) void partial_select_kernel(AggArgs p)
     __shared__ double bx[3];
     __shared__ double bv;                         // the winner's variance given the columns before it
     __shared__ int32_t bid, bp;
-    __shared__ double rot_cs[kPartCols], rot_sn[kPartCols];
+    __shared__ double rot_cs[kPartCols], rot_sn[kPartCols], rot_ics[kPartCols];
     __shared__ uint64_t wk1[kPartThreads / kWave], wk2[kPartThreads / kWave];
     __shared__ uint64_t tmask_sh;                 // bit c: column c is a target
     __shared__ int32_t bad_sh, notpd_sh;
@@ -253,9 +253,12 @@ __global__ __launch_bounds__(kPartThreads) void partial_select_kernel(AggArgs p)
             // square part: lane i is column-order row i of the old order
             const bool mine = lane < ncol;
             const int pi = mine ? ord[lane] : 0;
+            // lane l also keeps ord[l] (column c's slot comes by readlane)
+            const int my_ord = mine ? pi : 0;
             double w = 0.0;
             if (mine && lane >= pk) {
                 double acc = part_cov<TWO_NU>(cpt[pi], xk, c_nu, s2);
+#pragma unroll 4
                 for (int c = 0; c < pk; ++c) acc = fma(-Lsq[pi][ord[c]], bk[c], acc);
                 w = acc * inv;
             }
@@ -269,26 +272,36 @@ __global__ __launch_bounds__(kPartThreads) void partial_select_kernel(AggArgs p)
                 cpt[ph][1] = xk[1];
                 cpt[ph][2] = xk[2];
             }
-            // rank-one downdate of the columns after the pick by u
+            // rank-one downdate of the columns after the pick by u: column
+            // c's pivot is row c (lane c), whose diagonal and its inverse
+            // are read before the loop; each lane's entry of the next column
+            // is loaded one column ahead, off the chain through w
+            const double dg = (mine && lane >= pk) ? Lsq[pi][pi] : 1.0;
+            const double idg = rcp64_acc(dg);
+            double cur = 0.0;
+            if (pk < ncol && mine && lane > pk) cur = Lsq[pi][__builtin_amdgcn_readlane(my_ord, pk)];
             for (int c = pk; c < ncol; ++c) {
-                const int pc = ord[c];
-                const double lcc = Lsq[pc][pc];
+                const int pc = __builtin_amdgcn_readlane(my_ord, c);
+                double nxt = 0.0;
+                if (c + 1 < ncol && mine && lane > c + 1) nxt = Lsq[pi][__builtin_amdgcn_readlane(my_ord, c + 1)];
+                const double lcc = bcast(dg, c), il = bcast(idg, c);
                 const double wc = bcast(w, c);
                 const double r2 = (lcc - wc) * (lcc + wc);
                 if (!(r2 > 0.0)) {
                     if (lane == 0) notpd_sh = 1;
                     break;
                 }
-                const double r = r2 * rsq64(r2);
-                const double il = rcp64_acc(lcc);
+                const double rr = rsq64(r2);
+                const double r = r2 * rr;
                 const double cs = r * il, sn = wc * il;
-                const double ics = lcc * rcp64_acc(r);
+                const double ics = lcc * rr;
                 if (lane == 0) {
-                    rot_cs[c] = cs;
                     rot_sn[c] = sn;
+                    rot_cs[c] = cs;
+                    rot_ics[c] = ics;
                 }
                 if (mine && lane > c) {
-                    const double lic = (Lsq[pi][pc] - sn * w) * ics;
+                    const double lic = (cur - sn * w) * ics;
                     w = cs * w - sn * lic;
                     Lsq[pi][pc] = lic;
                 }
@@ -296,6 +309,7 @@ __global__ __launch_bounds__(kPartThreads) void partial_select_kernel(AggArgs p)
                     Lsq[pc][pc] = r;
                     w = 0.0;
                 }
+                cur = nxt;
             }
             __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
             __builtin_amdgcn_wave_barrier();
@@ -318,7 +332,7 @@ __global__ __launch_bounds__(kPartThreads) void partial_select_kernel(AggArgs p)
             for (int c = 0; c < kPartCols; ++c) {
                 if (c >= pk && c < ncol) {
                     const double cs = rot_cs[c], sn = rot_sn[c];
-                    const double lc = (L[c] - sn * w) / cs;
+                    const double lc = (L[c] - sn * w) * rot_ics[c];
                     w = cs * w - sn * lc;
                     L[c] = lc;
                 }
