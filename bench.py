@@ -990,6 +990,8 @@ def bench_pcg(args):
         pool, plen = inputs.later_knn_pools(xo, C)
         pl, ln = t(pool, torch.int32), t(plen, torch.int32)
         f = csel.select_and_factor(pts, kern, tg, pl, ln, k, "fp64")
+        cp, rows, vals = csel.single_target_csc(tg, f["sel"], f["factor"])
+        ft = csel.transpose_factor(cp, rows, vals)[:3]  # a first build: allocations and first launches
         torch.cuda.synchronize()
         e0.record()
         f = csel.select_and_factor(pts, kern, tg, pl, ln, k, "fp64", out=f)

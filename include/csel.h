@@ -255,6 +255,25 @@ int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel
                            hipStream_t stream);
 
 /*
+ * csel_later_knn -- the later-ordered candidate pools of Sec. 4 on the GPU:
+ * for every ordering position i (points in ordering-position order), the C
+ * nearest points among positions i+1 .. n-1, ascending by squared distance
+ * (summed over the coordinates in order, products and sums rounded
+ * separately), then position; the same pools as the host definition, bit
+ * for bit.
+ *   pts          [n][dim] FP64, 1 <= dim <= 3
+ *   C            0 <= C <= 2048
+ *   workspace    device scratch of csel_later_knn_workspace_size(n, dim) bytes
+ *   pool_idx     [n][C] int32 out, -1 padded
+ *   pool_len     [n] int32 out: min(C, n-1-i); -1 (row all -1) only when more
+ *                than 2048 later points tie at one distance around the C-th
+ * Errors: CSEL_EUNSUPPORTED for C above 2048.
+ */
+int64_t csel_later_knn_workspace_size(int64_t n, int32_t dim);
+int csel_later_knn(const double *pts, int64_t n, int32_t dim, int32_t C, void *workspace, int64_t workspace_bytes,
+                   int32_t *pool_idx, int32_t *pool_len, hipStream_t stream);
+
+/*
  * csel_partial_select -- partial (non-adjacent) aggregated selection, FP64
  * (Sec. 5.1 eq. chol_partial and eq. partial_kl; App. C.3).  As
  * csel_aggregated_select, but the candidates may lie between the group's

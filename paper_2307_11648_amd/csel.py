@@ -78,6 +78,10 @@ def load():
                                         _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp]
     lib.csel_partial_select.restype = ctypes.c_int
+    lib.csel_later_knn_workspace_size.argtypes = [_c.c_int64, _c.c_int32]
+    lib.csel_later_knn_workspace_size.restype = ctypes.c_int64
+    lib.csel_later_knn.argtypes = [_vp, _c.c_int64, _c.c_int32, _c.c_int32, _vp, _c.c_int64, _vp, _vp, _vp]
+    lib.csel_later_knn.restype = ctypes.c_int
     lib.csel_select_and_factor_list.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams),
                                                 _c.c_int64, _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                                 _vp, _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -713,6 +717,29 @@ def partial_select(points, kernel, group_ptr, members, max_members: int, pool, p
                                  _ptr(out.get("vals")), _ptr(out.get("member_log_condvar")), _ptr(out["status"]),
                                  _stream(stream))
     _check(rc)
+    return out
+
+
+def later_knn_pools(points, C: int, out=None, workspace=None, stream=None, check: bool = True):
+    """Later-ordered kNN pools on the GPU (csel_later_knn): (pool [n, C]
+    int32, pool_len [n] int32) for points [n, dim] FP64 in ordering-position
+    order.  With check, raises if a row could not be built (more than 2048
+    later points tied at one distance)."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    n, dim = points.shape
+    dev = points.device
+    if out is None:
+        out = (torch.empty((n, C), dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.int32, device=dev))
+    need = lib.csel_later_knn_workspace_size(n, dim)
+    if need < 0:
+        _check(-1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    _check(lib.csel_later_knn(points.data_ptr(), n, dim, int(C), workspace.data_ptr(), workspace.numel(),
+                              out[0].data_ptr(), out[1].data_ptr(), _stream(stream)))
+    if check and n > 0 and int(out[1].min().item()) < 0:
+        raise CselError(-4, "later_knn: more than 2048 later points tie at one distance")
     return out
 
 

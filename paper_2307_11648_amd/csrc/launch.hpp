@@ -170,6 +170,12 @@ int agg_factor_max_m();
 // the aggregated member columns (eq. L_col on s_q = {j in sort(T u S) : j >= q})
 hipError_t launch_agg_factor(const AggArgs& a, hipStream_t s);
 
+// later-ordered kNN pools (Sec. 4) on the GPU
+int64_t later_knn_workspace(int64_t n, int dim);
+int later_knn_max_pool();
+hipError_t launch_later_knn(const double* pts, int64_t n, int dim, int C, void* workspace, int32_t* pool,
+                            int32_t* pool_len, hipStream_t s);
+
 // partial (non-adjacent) aggregated selection, FP64, then (want_factor) the
 // member columns
 hipError_t launch_partial(const AggArgs& a, bool want_factor, hipStream_t s);

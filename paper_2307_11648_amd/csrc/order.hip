@@ -7,7 +7,7 @@
 // the target's coordinates quantised over the targets' bounding box
 // (30 bits: 10 per coordinate in 3-D, 15 in 2-D, 30 in 1-D), sorted with a
 // stable radix sort so equal codes keep increasing column order.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "launch.hpp"
 
@@ -107,9 +107,9 @@ static size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 static size_t sort_temp_bytes(int64_t T) {
     size_t bytes = 0;
-    const hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t*)nullptr,
-                                                            (uint32_t*)nullptr, (const int32_t*)nullptr,
-                                                            (int32_t*)nullptr, (int)T, 0, 30);
+    const hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                                   (const int32_t*)nullptr, (int32_t*)nullptr, (unsigned int)T,
+                                                   0u, 30u);
     return e == hipSuccess ? bytes : SIZE_MAX;
 }
 
@@ -141,7 +141,7 @@ hipError_t launch_spatial_order(const double* pts, int64_t n, int dim, int64_t T
                        (const uint64_t*)bb, keys_in, vals_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    return hipcub::DeviceRadixSort::SortPairs(w, temp, keys_in, keys_out, vals_in, order, (int)T, 0, 30, s);
+    return rocprim::radix_sort_pairs(w, temp, keys_in, keys_out, vals_in, order, (unsigned int)T, 0u, 30u, s);
 }
 
 }  // namespace csel

@@ -9,7 +9,7 @@
 // [T][k+1] layout), or not covered by any column, sort last and are dropped:
 // t_col_ptr[n] counts the kept entries and the slots past it get row -1 and
 // value 0.
-#include <hipcub/hipcub.hpp>
+#include <rocprim/device/device_radix_sort.hpp>
 
 #include "launch.hpp"
 
@@ -76,9 +76,9 @@ static int key_bits(int64_t n) {
 
 static size_t sort_temp(int64_t n_slots, int bits) {
     size_t bytes = 0;
-    const hipError_t e = hipcub::DeviceRadixSort::SortPairs(nullptr, bytes, (const uint32_t*)nullptr,
-                                                            (uint32_t*)nullptr, (const int32_t*)nullptr,
-                                                            (int32_t*)nullptr, (int)n_slots, 0, bits);
+    const hipError_t e = rocprim::radix_sort_pairs(nullptr, bytes, (const uint32_t*)nullptr, (uint32_t*)nullptr,
+                                                   (const int32_t*)nullptr, (int32_t*)nullptr,
+                                                   (unsigned int)n_slots, 0u, (unsigned int)bits);
     return e == hipSuccess ? bytes : SIZE_MAX;
 }
 
@@ -117,8 +117,8 @@ hipError_t launch_transpose_factor(int64_t n, const int64_t* col_ptr, const int3
                        keys_in, slots_in);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipcub::DeviceRadixSort::SortPairs(temp, temp_bytes, keys_in, keys_out, slots_in, perm, (int)n_slots, 0,
-                                           bits, s);
+    e = rocprim::radix_sort_pairs(temp, temp_bytes, keys_in, keys_out, slots_in, perm, (unsigned int)n_slots, 0u,
+                                  (unsigned int)bits, s);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(transposed_kernel, dim3(gb), dim3(256), 0, s, n, n_slots, (const uint32_t*)keys_out,
                        (const int32_t*)perm, (const int32_t*)colof, val, t_col_ptr, t_row_idx, t_val);
