@@ -162,7 +162,8 @@ def bench_groups(args):
                 f"m uniform in 8..32, union pools of 512 later points, k=64, {args.precision}, member columns")
     else:
         w = inputs.workload_gp(n_train=args.n or 500_000)
-        want_factor, want_post_var = False, True
+        # posterior variances are FP64-only (the mixed run is compared with FP64 below)
+        want_factor, want_post_var = False, args.precision == "fp64"
         desc = (f"GP prediction, {w.meta['n_train']} training points uniform in [0,1]^2, 4096 prediction points "
                 f"in 64 batches of 64, Matern 5/2, l=0.03, pools of 2048, k=128, {args.precision}, "
                 f"posterior variances")
@@ -209,7 +210,24 @@ def bench_groups(args):
                      "algorithmic_gflop_per_launch": float(np.sum(flops)) / 1e9,
                      "algorithmic_mb_per_launch": float(np.sum(byt)) / 1e6},
     }
-    if args.workload == "gp":
+    if args.workload == "gp" and args.precision == "mixed":
+        # the same batches in FP64: selections, posterior variances and time
+        o64 = csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, "fp64", want_post_var=True)
+        torch.cuda.synchronize()
+        ev64 = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+        ev64[0].record()
+        csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, "fp64", want_post_var=True, out=o64,
+                               workspace=o64["workspace"])
+        ev64[1].record()
+        torch.cuda.synchronize()
+        ld, ld64 = out["logdet"].cpu().numpy(), o64["logdet"].cpu().numpy()
+        res["config"]["mixed_vs_fp64"] = {
+            "fp64_ms": ev64[0].elapsed_time(ev64[1]),
+            "groups_identical": int(np.sum(np.all(out["sel"].cpu().numpy() == o64["sel"].cpu().numpy(), axis=1))),
+            "logdet_sum": float(ld.sum()), "logdet_sum_fp64": float(ld64.sum()),
+            "logdet_max_abs_difference": float(np.max(np.abs(ld - ld64))),
+            "note": "posterior variances are FP64-only (CSEL_EUNSUPPORTED in mixed precision)"}
+    if args.workload == "gp" and args.precision == "fp64":
         res["config"].update(gp_screened(args, w, pts, gp_t, mem_t, mm, pl, ln, out, ms))
     if args.cpu_seconds > 0:
         print("bench: cpu baseline", file=sys.stderr, flush=True)

@@ -218,8 +218,11 @@ int32_t csel_aggregated_max_block(void);
  *   max_members  bound on every m_g (groups above it get status 3)
  *   pool_idx     [n_groups][pool_stride] int32 candidate ids, pool_len [n_groups]
  *   k            0 <= k <= 256; pool_stride + max_members <= 4096
- *   precision    CSEL_FP64, or CSEL_MIXED (FP32 covariance evaluation and
- *                GEMVs, FP64 conditional variances and factor columns)
+ *   precision    CSEL_FP64, or CSEL_MIXED: FP64 conditional variances and
+ *                factor columns; the covariance evaluations and GEMVs of the
+ *                picks-only factor (var1) in FP32; those of the
+ *                target-conditioned factor (var2) in FP32 for pools <= 512,
+ *                groups <= 32, k <= 64 without post_var, in FP64 otherwise
  *   workspace    device scratch of csel_aggregated_workspace_size() bytes
  * Outputs:
  *   sel_idx      [n_groups][k] selected ids in selection order, -1 padded
@@ -229,7 +232,8 @@ int32_t csel_aggregated_max_block(void);
  *                (eq. obj_mult) (may be NULL)
  *   post_var     [sum m] Theta_qq | selected for every target: the posterior
  *                variances of GP prediction at the targets given the selected
- *                training points (Alg. infer_select) (may be NULL)
+ *                training points (Alg. infer_select) (may be NULL; CSEL_FP64
+ *                only, CSEL_EUNSUPPORTED with CSEL_MIXED)
  *   factor_val   (may be NULL) aggregated factor columns: member q gets
  *                s_q = {j in sort(T u selected) : j >= q} and the eq. L_col
  *                column on s_q, computed for the whole group from one reverse

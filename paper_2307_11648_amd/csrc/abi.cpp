@@ -399,6 +399,10 @@ CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, c
         return fail(CSEL_EINVAL, "a required array is NULL");
     if (want_factor && (!val_ptr || !factor_rows))
         return fail(CSEL_EINVAL, "factor output needs val_ptr, factor_rows and factor_val");
+    if (post_var && precision != CSEL_FP64)
+        return fail(CSEL_EUNSUPPORTED,
+                    "post_var needs CSEL_FP64: the FP32 factor of the picks does not resolve posterior variances "
+                    "far below the prior variance");
     const csel::AggPlan pl = csel::plan_aggregated(n_groups, pool_stride, max_members, k, precision);
     if (!workspace || workspace_bytes < pl.ws_bytes)
         return fail(CSEL_EINVAL, "workspace must hold csel_aggregated_workspace_size() = %lld bytes",
@@ -421,7 +425,7 @@ CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, c
     a.k = k;
     a.later_only = want_factor ? 1 : 0;
     a.ws = workspace;
-    a.slab_elems = pl.slab_elems;
+    a.slab_bytes = pl.slab_bytes;
     a.rmax = pl.rmax;
     a.sel = sel_idx;
     a.gap = top2_gap;

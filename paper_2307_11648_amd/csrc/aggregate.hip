@@ -46,15 +46,20 @@ __device__ __forceinline__ T matern_any(int two_nu, T r, T c, T s2) {
 
 constexpr int kAggMaxWaves = 16;
 
-template <typename T, int RPT>
+// TA: factor A (the selected points only) and its covariance evaluations;
+// TB: factor B (the targets, then the selected points).  FP64: both double.
+// Mixed: A in FP32, B in FP64 -- var2 = Theta_jj | T, I falls far below
+// the prior when many targets cluster (GP batches), below what an FP32
+// evaluation resolves, while var1 stays large.
+template <typename TA, typename TB, int RPT>
 __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
     extern __shared__ __align__(16) unsigned char agg_smem[];
-    // LDS layout: wave top-two [16], winner scalars, winner A row [k], B row [mmax+k]
+    // LDS layout: wave top-two [16], winner scalars, winner B row [mmax+k], A row [k]
     Top2* wtop = reinterpret_cast<Top2*>(agg_smem);
     double* wsc = reinterpret_cast<double*>(agg_smem + sizeof(Top2) * kAggMaxWaves);  // var1, var2, x0..x2
     int32_t* wid = reinterpret_cast<int32_t*>(wsc + 6);
-    T* rowA = reinterpret_cast<T*>(agg_smem + sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double));
-    T* rowB = rowA + p.k;
+    TB* rowB = reinterpret_cast<TB*>(agg_smem + sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double));
+    TA* rowA = reinterpret_cast<TA*>(rowB + p.max_members + p.k);
 
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
@@ -62,9 +67,11 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
     const int wave = tid >> 6;
     const int nwaves = NT >> 6;
     const int rmax = p.rmax;
-    T* slabA = reinterpret_cast<T*>(p.ws) + (int64_t)blockIdx.x * p.slab_elems;
-    T* slabB = slabA + (int64_t)p.k * rmax;
-    const T cnu = (T)p.c_nu, s2 = (T)p.s2;
+    // slab: B [(mmax + k) * rmax] of TB, then A [k * rmax] of TA
+    TB* slabB = reinterpret_cast<TB*>(reinterpret_cast<char*>(p.ws) + (int64_t)blockIdx.x * p.slab_bytes);
+    TA* slabA = reinterpret_cast<TA*>(slabB + (int64_t)(p.max_members + p.k) * rmax);
+    const TA cnuA = (TA)p.c_nu, s2A = (TA)p.s2;
+    const TB cnuB = (TB)p.c_nu, s2B = (TB)p.s2;
     const double prior = p.s2 + p.nugget;
     const double thr = 1e-12 * prior;
     const int dim = p.dim;
@@ -159,16 +166,16 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
             const int32_t idw = wid[0];
             ldT += log(piv);
             const double inv_sd = 1.0 / sqrt(piv);
-            const T inv_sd_t = (T)inv_sd;
+            const TB inv_sd_t = (TB)inv_sd;
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int r = i * NT + tid;
                 if (r < R) {
-                    const T e0 = (T)(x0[i] - y0), e1 = (T)(x1[i] - y1), e2 = (T)(x2[i] - y2);
-                    T acc = matern_any<T>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnu, s2);
-                    if (rid[i] == idw) acc += (T)p.nugget;
+                    const TB e0 = (TB)(x0[i] - y0), e1 = (TB)(x1[i] - y1), e2 = (TB)(x2[i] - y2);
+                    TB acc = matern_any<TB>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnuB, s2B);
+                    if (rid[i] == idw) acc += (TB)p.nugget;
                     for (int q = 0; q < c; ++q) acc -= slabB[(int64_t)q * rmax + r] * rowB[q];
-                    const T u = acc * inv_sd_t;
+                    const TB u = acc * inv_sd_t;
                     slabB[(int64_t)c * rmax + r] = u;
                     const double ud = (double)u;
                     v2[i] -= ud * ud;
@@ -226,18 +233,29 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     p.gap[g * p.k + t] = (w.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
                 }
             }
-            const T inv1 = (T)(1.0 / sqrt(w1)), inv2 = (T)(1.0 / sqrt(w2));
+            const TA inv1 = (TA)(1.0 / sqrt(w1));
+            const TB inv2 = (TB)(1.0 / sqrt(w2));
 #pragma unroll
             for (int i = 0; i < RPT; ++i) {
                 const int r = i * NT + tid;
                 if (r < R) {
-                    const T e0 = (T)(x0[i] - y0), e1 = (T)(x1[i] - y1), e2 = (T)(x2[i] - y2);
-                    T th = matern_any<T>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnu, s2);
-                    if (rid[i] == idw) th += (T)p.nugget;
-                    T a = th, bb = th;
+                    const TB e0 = (TB)(x0[i] - y0), e1 = (TB)(x1[i] - y1), e2 = (TB)(x2[i] - y2);
+                    TB thb = matern_any<TB>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnuB, s2B);
+                    if (rid[i] == idw) thb += (TB)p.nugget;
+                    TA tha;
+                    if constexpr (sizeof(TA) == sizeof(TB)) {
+                        tha = thb;
+                    } else {
+                        const TA f0 = (TA)(x0[i] - y0), f1 = (TA)(x1[i] - y1), f2 = (TA)(x2[i] - y2);
+                        tha = matern_any<TA>(p.two_nu, sqrt(f0 * f0 + f1 * f1 + f2 * f2), cnuA, s2A);
+                        if (rid[i] == idw) tha += (TA)p.nugget;
+                    }
+                    TA a = tha;
+                    TB bb = thb;
                     for (int q = 0; q < t; ++q) a -= slabA[(int64_t)q * rmax + r] * rowA[q];
                     for (int q = 0; q < m + t; ++q) bb -= slabB[(int64_t)q * rmax + r] * rowB[q];
-                    const T u1 = a * inv1, u2 = bb * inv2;
+                    const TA u1 = a * inv1;
+                    const TB u2 = bb * inv2;
                     slabA[(int64_t)t * rmax + r] = u1;
                     slabB[(int64_t)(m + t) * rmax + r] = u2;
                     const double d1 = (double)u1, d2 = (double)u2;
@@ -752,9 +770,9 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
     if (tid == 0 && bad_piv) p.status[g] = 2;
 }
 
-template <typename T, int RPT>
+template <typename TA, typename TB, int RPT>
 static hipError_t launch_sel(const AggArgs& a, int nt, unsigned grid, size_t smem, hipStream_t s) {
-    auto kern = agg_select_kernel<T, RPT>;
+    auto kern = agg_select_kernel<TA, TB, RPT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), smem, s, a);
@@ -767,14 +785,15 @@ AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, i
     pl.rpt = (pl.rmax + 1023) / 1024;
     pl.rpt = pl.rpt <= 1 ? 1 : pl.rpt <= 2 ? 2 : 4;
     pl.threads = std::min(1024, std::max(64, ((pl.rmax + pl.rpt - 1) / pl.rpt + 63) / 64 * 64));
-    const int64_t elem = precision == 0 ? 8 : 4;
-    pl.slab_elems = ((int64_t)k + max_members + k) * pl.rmax;
-    pl.slab_elems = (pl.slab_elems + 63) / 64 * 64;
+    // the slab kernel: factor B in FP64, factor A in FP64 or (mixed) FP32
+    const int64_t elemA = precision == 0 ? 8 : 4;
+    pl.slab_bytes = ((int64_t)max_members + k) * pl.rmax * 8 + (int64_t)k * pl.rmax * elemA;
+    pl.slab_bytes = (pl.slab_bytes + 255) / 256 * 256;
     // enough slots to fill the chip several times over, capped by the group count
     pl.slots = (int)std::min<int64_t>(n_groups, 1024);
     if (pl.slots < 1) pl.slots = 1;
-    pl.ws_bytes = pl.slab_elems * elem * pl.slots;
-    pl.smem = sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double) + ((size_t)k + max_members + k) * elem;
+    pl.ws_bytes = pl.slab_bytes * pl.slots;
+    pl.smem = sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double) + ((size_t)k + max_members) * 8 + (size_t)k * elemA;
     return pl;
 }
 
@@ -813,13 +832,13 @@ hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision,
         return e;
     }
     if (precision == 0) {
-        e = pl.rpt == 1 ? launch_sel<double, 1>(a, pl.threads, grid, pl.smem, s)
-            : pl.rpt == 2 ? launch_sel<double, 2>(a, pl.threads, grid, pl.smem, s)
-                          : launch_sel<double, 4>(a, pl.threads, grid, pl.smem, s);
+        e = pl.rpt == 1 ? launch_sel<double, double, 1>(a, pl.threads, grid, pl.smem, s)
+            : pl.rpt == 2 ? launch_sel<double, double, 2>(a, pl.threads, grid, pl.smem, s)
+                          : launch_sel<double, double, 4>(a, pl.threads, grid, pl.smem, s);
     } else {
-        e = pl.rpt == 1 ? launch_sel<float, 1>(a, pl.threads, grid, pl.smem, s)
-            : pl.rpt == 2 ? launch_sel<float, 2>(a, pl.threads, grid, pl.smem, s)
-                          : launch_sel<float, 4>(a, pl.threads, grid, pl.smem, s);
+        e = pl.rpt == 1 ? launch_sel<float, double, 1>(a, pl.threads, grid, pl.smem, s)
+            : pl.rpt == 2 ? launch_sel<float, double, 2>(a, pl.threads, grid, pl.smem, s)
+                          : launch_sel<float, double, 4>(a, pl.threads, grid, pl.smem, s);
     }
     if (e != hipSuccess) return e;
     if (want_factor) {

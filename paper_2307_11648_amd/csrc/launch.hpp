@@ -145,7 +145,7 @@ struct AggArgs {
     int32_t k;
     int32_t later_only;  // pool ids must exceed every member id (factor output)
     void* ws;
-    int64_t slab_elems;
+    int64_t slab_bytes;  // bytes of one workgroup's slab
     int32_t rmax;
     int32_t* sel;
     float* gap;
@@ -160,7 +160,7 @@ struct AggArgs {
 
 struct AggPlan {
     int rmax, rpt, threads, slots;
-    int64_t slab_elems, ws_bytes;
+    int64_t slab_bytes, ws_bytes;
     size_t smem;
 };
 
