@@ -236,6 +236,60 @@ def bench_groups(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_knn(args):
+    """Later-ordered kNN candidate pools on the GPU (csel_later_knn, Sec. 4)
+    for the default workload's cloud: N = 1e6 clustered points in [0,1]^3 in
+    reverse-maximin order (host set-up), pools of 512.  Timed: the whole call
+    (grids, Morton order, queries); checked: a seeded sample of rows against
+    the host definition; beside it the host C kd-tree on all of the box's
+    cores for the same pools."""
+    import numpy as np
+    import torch
+
+    from paper_2307_11648_amd import csel, inputs
+
+    n = args.n or 1_000_000
+    C = 512
+    print("bench: ordering the cloud (host)", file=sys.stderr, flush=True)
+    xo, _ = inputs.ordered_cloud(inputs.cluster_points(n, 3, 4))
+    pts = torch.from_numpy(xo).cuda()
+    pool, plen = csel.later_knn_pools(pts, C)
+    ws = torch.empty(max(csel.load().csel_later_knn_workspace_size(n, 3), 1), dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    times = []
+    for i in range(args.warmup + args.steps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        csel.later_knn_pools(pts, C, out=(pool, plen), workspace=ws, check=False)
+        e1.record()
+        torch.cuda.synchronize()
+        if i >= args.warmup:
+            times.append(e0.elapsed_time(e1))
+    ms = float(np.median(times))
+    rng = np.random.default_rng(77)
+    rows = np.sort(rng.choice(n, size=4096, replace=False)).astype(np.int32)
+    hp, hl = inputs.later_knn_pools_subset(xo, C, rows)
+    gp = pool[torch.from_numpy(rows).long().cuda()].cpu().numpy()
+    gl = plen.cpu().numpy()[rows]
+    identical = int(np.sum(np.all(gp == hp, axis=1) & (gl == hl)))
+    res = {"metric": "later-ordered kNN pools/s (C = 512)", "value": n / (ms * 1e-3), "unit": "pools/s",
+           "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"later-ordered 512-nearest pools of N={n} points in [0,1]^3 (20 Gaussian "
+                                  f"clusters sigma 0.03 + 20% uniform), reverse-maximin order; medians of "
+                                  f"{args.steps} calls", "rows_checked": len(rows),
+                      "rows_identical_to_host": identical, "min_pool_len": int(gl.min())}}
+    if args.cpu_seconds > 0:
+        print("bench: host kd-tree pools", file=sys.stderr, flush=True)
+        t0 = time.perf_counter()
+        inputs.later_knn_pools(xo, C)
+        dt = time.perf_counter() - t0
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0") or 0) or (os.cpu_count() or 1)
+        res["cpu_baseline"] = {"value": n / dt, "unit": "pools/s", "cores": threads, "kind": "host kd-tree",
+                               "sample": f"all {n} pools by the library's host C kd-trees (OpenMP), {dt:.1f} s"}
+    print(json.dumps(res), flush=True)
+
+
 def partial_work(group_ptr, members, pool, pool_len, sel, k, dim, two_nu):
     """Algorithmic flops of partial selection per group (numpy), from the
     picks the run made: per step t with ncol = m + t columns and the pick
@@ -1055,7 +1109,7 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="screened",
-                    choices=["screened", "plain", "aggregated", "gp", "apply", "pcg", "partial"])
+                    choices=["screened", "plain", "aggregated", "gp", "apply", "pcg", "partial", "knn"])
     ap.add_argument("--pcg-plain-iters", type=int, default=300,
                     help="pcg workload: iteration cap of the unpreconditioned run")
     ap.add_argument("--train-steps", type=int, default=3000, help="screened workload: Adam steps")
@@ -1109,6 +1163,8 @@ def main():
         return bench_pcg(args)
     if args.workload == "partial":
         return bench_partial(args)
+    if args.workload == "knn":
+        return bench_knn(args)
     if args.workload != "plain":
         return bench_groups(args)
     args.n = args.n or 100_000
