@@ -440,26 +440,68 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                     bc = reinterpret_cast<T*>(&sh_r[wib][0][0]);
                     bdx = bc + KMAX;
                 }
-                if (lane == ls) {
+                T dk0, dk1, dk2;
+                double vk, ck;
+                int32_t idk;
+                if constexpr (sizeof(T) == 8) {
+                    // FP64: the row through LDS (the GEMV reads it after the
+                    // evaluation); the scalars that gate the evaluation by
+                    // readlane from the winning lane, off the LDS round trip
+                    if (lane == ls) {
+#pragma unroll
+                        for (int rr = 0; rr < RPL; ++rr) {
+                            if (rr == rs) {
+#pragma unroll
+                                for (int q = 0; q < t; ++q) bc[q] = L[rr][q];
+                            }
+                        }
+                    }
+                    double wv = 0.0, wc = 0.0, w0 = 0.0, w1 = 0.0, w2 = 0.0;
+                    int32_t wp = -1;
 #pragma unroll
                     for (int rr = 0; rr < RPL; ++rr) {
                         if (rr == rs) {
-#pragma unroll
-                            for (int q = 0; q < t; ++q) bc[q] = L[rr][q];
-                            bdx[0] = dx[rr][0];
-                            bdx[1] = dx[rr][1];
-                            bdx[2] = dx[rr][2];
-                            bcd[0] = var[rr];
-                            bcd[1] = cov[rr];
-                            bcd[2] = (double)pid[rr];
+                            wv = var[rr];
+                            wc = cov[rr];
+                            w0 = dx[rr][0];
+                            w1 = dx[rr][1];
+                            w2 = dx[rr][2];
+                            wp = pid[rr];
                         }
                     }
+                    vk = bcast(wv, ls);
+                    ck = bcast(wc, ls);
+                    dk0 = bcast(w0, ls);
+                    dk1 = bcast(w1, ls);
+                    dk2 = bcast(w2, ls);
+                    idk = bcast(wp, ls);
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                } else {
+                    if (lane == ls) {
+#pragma unroll
+                        for (int rr = 0; rr < RPL; ++rr) {
+                            if (rr == rs) {
+#pragma unroll
+                                for (int q = 0; q < t; ++q) bc[q] = L[rr][q];
+                                bdx[0] = dx[rr][0];
+                                bdx[1] = dx[rr][1];
+                                bdx[2] = dx[rr][2];
+                                bcd[0] = var[rr];
+                                bcd[1] = cov[rr];
+                                bcd[2] = (double)pid[rr];
+                            }
+                        }
+                    }
+                    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+                    __builtin_amdgcn_wave_barrier();
+                    dk0 = bdx[0];
+                    dk1 = bdx[1];
+                    dk2 = bdx[2];
+                    vk = bcd[0];
+                    ck = bcd[1];
+                    idk = (int32_t)bcd[2];
                 }
-                __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-                __builtin_amdgcn_wave_barrier();
-                const T dk0 = bdx[0], dk1 = bdx[1], dk2 = bdx[2];
-                const double vk = bcd[0], ck = bcd[1];
-                const int32_t idk = (int32_t)bcd[2];
                 const double inv_sd = rsq64(vk);
                 const double ui = ck * inv_sd;
                 const T inv_sd_t = (T)inv_sd;
