@@ -198,26 +198,47 @@ def bench_groups(args):
     flops, byt = group_work(w.group_ptr, w.pool_len, k, w.points.shape[1], w.kernel.two_nu, want_factor)
     achieved = float(np.sum(flops)) / (ms * 1e-3) / 1e12
     st = out["status"].cpu().numpy()
+    # runs of at most 128 groups past 256 rows (without member columns, and
+    # outside the mixed register kernel's range) split each group's rows over
+    # several workgroups
+    reg = args.precision == "mixed" and not want_post_var and w.pool.shape[1] <= 512 and mm <= 32 and k <= 64
+    coop = (not want_factor and not reg and len(w.group_ptr) - 1 <= 128 and w.pool.shape[1] + mm > 256)
+    sel_kernel = ("agg_select_coop_kernel" if coop else "agg_select_kernel") + (" (+ agg_factor_kernel)"
+                                                                                   if want_factor else "")
     res = {
         "metric": METRIC, "value": cols / (ms * 1e-3), "unit": "columns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": desc, "groups": len(w.group_ptr) - 1, "columns": cols, "k": k,
                    "status_counts": {int(v): int((st == v).sum()) for v in np.unique(st)}},
-        "roofline": {"bound": "alu", "kernel": "agg_select_kernel (+ agg_factor_kernel)", "achieved": achieved,
+        "roofline": {"bound": "alu", "kernel": sel_kernel, "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": None, "kernel_ms": ms,
                      "algorithmic_gflop_per_launch": float(np.sum(flops)) / 1e9,
                      "algorithmic_mb_per_launch": float(np.sum(byt)) / 1e6},
     }
+    if coop:
+        # the left-looking updates stream each row's factor entries from the
+        # per-group slabs once per target column and per pick (8 bytes per
+        # FP64 fused multiply-add, 4 for the FP32 picks-only factor of mixed runs)
+        sa = 8 if args.precision == "fp64" else 4
+        gsz = np.diff(w.group_ptr).astype(np.int64)
+        rows = w.pool_len.astype(np.int64) + gsz
+        kk = np.minimum(k, w.pool_len).astype(np.int64)
+        per_row = (8 * gsz * (gsz - 1) // 2 + 8 * (gsz * kk + kk * (kk - 1) // 2) + sa * kk * (kk - 1) // 2
+                   + 8 * (gsz + kk) + sa * kk)
+        stream = float(np.sum(per_row * rows))
+        res["roofline"]["factor_stream_gb_per_launch"] = stream / 1e9
+        res["roofline"]["factor_stream_tb_per_s"] = stream / (ms * 1e-3) / 1e12
     if args.workload == "gp" and args.precision == "mixed":
         # the same batches in FP64: selections, posterior variances and time
-        o64 = csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, "fp64", want_post_var=True)
+        o64 = csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, "fp64", want_factor=False,
+                                     want_post_var=True)
         torch.cuda.synchronize()
         ev64 = (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
         ev64[0].record()
-        csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, "fp64", want_post_var=True, out=o64,
-                               workspace=o64["workspace"])
+        csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, "fp64", want_factor=False, want_post_var=True,
+                               out=o64, workspace=o64["workspace"])
         ev64[1].record()
         torch.cuda.synchronize()
         ld, ld64 = out["logdet"].cpu().numpy(), o64["logdet"].cpu().numpy()

@@ -248,7 +248,15 @@ int32_t csel_aggregated_max_block(void);
  *   status       [n_groups] per-group status: 0, 1 (stopped early), 2 (block
  *                not positive definite), 3 (bad input), 4 (pool precedes a
  *                member with factor output), 5 (pattern larger than
- *                csel_aggregated_max_block(); selection outputs are valid)
+ *                csel_aggregated_max_block(); selection outputs are valid),
+ *                6 (results lost: a barrier wait among the workgroups that
+ *                share the group ran out; not expected in a complete launch)
+ * Schedule: FP64 runs of at most 128 groups whose pool_stride + max_members
+ * exceeds 256, without factor output, split each group's rows over
+ * ceil((pool_stride + max_members) / 256) workgroups launched cooperatively
+ * (all resident at once); other runs, or when the device cannot hold that
+ * grid, give each group one workgroup.  Both schedules make the same
+ * selections up to rounding (near-tied steps may differ).
  */
 int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_groups,
                            const int32_t *group_ptr, const int32_t *members, int32_t max_members,

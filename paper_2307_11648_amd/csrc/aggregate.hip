@@ -793,6 +793,8 @@ AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, i
     pl.slots = (int)std::min<int64_t>(n_groups, 1024);
     if (pl.slots < 1) pl.slots = 1;
     pl.ws_bytes = pl.slab_bytes * pl.slots;
+    if (agg_coop_applies(n_groups, stride, max_members, k, precision))
+        pl.ws_bytes = std::max<int64_t>(pl.ws_bytes, agg_coop_workspace(n_groups, stride, max_members, k));
     pl.smem = sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double) + ((size_t)k + max_members) * 8 + (size_t)k * elemA;
     return pl;
 }
@@ -807,6 +809,14 @@ static hipError_t launch_reg(const AggArgs& a, hipStream_t s) {
     const unsigned grid = (unsigned)std::min<int64_t>(a.n_groups, 4096);
     hipLaunchKernelGGL(kern, dim3(grid), dim3(kAggRegThreads), smem, s, a);
     return hipGetLastError();
+}
+
+// few groups with pools past one workgroup's rows: each group's rows split
+// over several cooperatively launched workgroups (mixed runs the register
+// kernel covers stay there)
+bool agg_coop_applies(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision) {
+    return n_groups > 0 && n_groups <= 128 && k <= 256 && max_members <= 128 &&
+           (int64_t)stride + max_members > 256;
 }
 
 // the register-resident kernel applies to mixed precision without posterior
@@ -830,6 +840,18 @@ hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision,
             e = hipGetLastError();
         }
         return e;
+    }
+    if (agg_coop_applies(a.n_groups, a.stride, a.max_members, a.k, precision)) {
+        e = launch_aggregated_coop(a, precision, a.ws, s);
+        if (e == hipSuccess) {
+            if (want_factor) {
+                hipLaunchKernelGGL(agg_factor_kernel, dim3((unsigned)a.n_groups), dim3(kAggFacThreads), 0, s, a);
+                e = hipGetLastError();
+            }
+            return e;
+        }
+        if (e != hipErrorCooperativeLaunchTooLarge && e != hipErrorNotSupported) return e;
+        (void)hipGetLastError();  // the one-workgroup-per-group kernel instead
     }
     if (precision == 0) {
         e = pl.rpt == 1 ? launch_sel<double, double, 1>(a, pl.threads, grid, pl.smem, s)

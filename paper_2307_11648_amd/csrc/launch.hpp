@@ -167,6 +167,13 @@ struct AggPlan {
 AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision);
 hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s);
 int agg_factor_max_m();
+// multi-target selection with each group's rows over several workgroups
+// (cooperative launch; factor A in FP64 or, mixed, FP32);
+// hipErrorCooperativeLaunchTooLarge when the grid cannot be resident at once
+int64_t agg_coop_workspace(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k);
+hipError_t launch_aggregated_coop(const AggArgs& a, int precision, void* workspace, hipStream_t s);
+bool agg_coop_applies(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision);
+
 // the aggregated member columns (eq. L_col on s_q = {j in sort(T u S) : j >= q})
 hipError_t launch_agg_factor(const AggArgs& a, hipStream_t s);
 

@@ -141,6 +141,56 @@ def test_gp_posterior_variance():
             np.testing.assert_allclose(g["post_var"][b:e], o["post_var"][b:e], rtol=1e-7, atol=1e-13)
 
 
+def test_gp_split_rows_match_one_workgroup_per_group():
+    """FP64 runs with at most 128 groups and more than 256 rows a group split
+    each group's rows over several workgroups (cooperative launch; 1,024,
+    512 or 256 threads a workgroup depending on how many groups share the
+    chip); larger runs give each group one workgroup.  Groups are
+    independent, so the first H groups run alone must reproduce what the full
+    run of 144 gives them: picks up to the first top-two gap below 1e-9, log
+    det and posterior variances to 1e-10 relative.  H = 64, 50 and 20 take
+    the three block sizes (groups of 1,040 rows on 256 CUs).  The set
+    includes an out-of-range pool id (status 3), an empty pool and a pool
+    shorter than k."""
+    print("case: gp split rows n_train=30000 G=144 m=16 C=1024 k=48 fp64", flush=True)
+    w = inputs.workload_gp(n_train=30000, n_pred=2304, C=1024, k=48, n_strips=12, per_strip=12)
+    G = len(w.group_ptr) - 1
+    assert G == 144
+    pool = w.pool.copy()
+    plen = w.pool_len.copy()
+    pool[3, 5] = len(w.points) + 7
+    plen[5] = 0
+    plen[6] = 10
+    w.pool_len[:] = plen
+    full = run_gpu(w, w.k, "fp64", want_factor=False, pool=pool)
+    assert full["status"][3] == 3
+    for H in (64, 50, 20):
+        print(f"case: first {H} groups", flush=True)
+        sub = inputs.GroupWorkload(w.name, w.points, w.kernel, w.group_ptr[: H + 1].copy(),
+                                   w.members[: w.group_ptr[H]].copy(), pool[:H].copy(), plen[:H].copy(), w.k,
+                                   w.later_only, w.meta)
+        part = run_gpu(sub, w.k, "fp64", want_factor=False, pool=sub.pool,
+                       max_members=int(np.max(np.diff(w.group_ptr))))
+        np.testing.assert_array_equal(part["status"], full["status"][:H])
+        assert np.all(part["sel"][3] == -1) and np.isnan(part["logdet"][3])
+        assert np.all(part["sel"][5] == -1) and part["status"][5] == 0
+        assert np.sum(part["sel"][6] >= 0) == 10
+        same = 0
+        for gi in range(H):
+            if full["status"][gi] >= 2:
+                continue
+            p = decisive_prefix(full["gap"][gi], 1e-9)
+            assert np.array_equal(part["sel"][gi, :p], full["sel"][gi, :p]), gi
+            if not np.array_equal(part["sel"][gi], full["sel"][gi]):
+                continue
+            same += 1
+            assert part["logdet"][gi] == pytest.approx(full["logdet"][gi], rel=1e-10, abs=1e-10)
+            b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+            np.testing.assert_allclose(part["post_var"][b:e], full["post_var"][b:e], rtol=1e-10, atol=1e-14)
+        print(f"{same} of {H} groups identical", flush=True)
+        assert same >= H - 2
+
+
 def test_gp_mixed_selection_runs_to_k():
     """The same batches in mixed precision: 64 clustered targets under a
     smooth kernel drive var2 / prior to 1e-4..1e-7, below what an FP32
