@@ -141,6 +141,42 @@ def test_gp_posterior_variance():
             np.testing.assert_allclose(g["post_var"][b:e], o["post_var"][b:e], rtol=1e-7, atol=1e-13)
 
 
+def test_gp_full_shape_sample_matches_oracle():
+    """The GP prediction workload at its full shape: 500,000 training points,
+    64 batches of 64 prediction points, pools of 2,048, k = 128, FP64 (the
+    batches' rows split over cooperatively launched workgroups of 1,024
+    threads).  Four batches against the oracle: picks up to the first top-two
+    gap below 1e-6; on batches whose picks all agree, posterior variances to
+    1e-7 relative and log det to 1e-8 relative.  (64 clustered targets under
+    the smooth kernel drive their conditional variances to about 1e-7 of the
+    prior, where one FP64 rounding moves the log of a variance by about
+    1e-16 * 1e7 = 1e-9; log det sums some 200 such terms, about 800 in
+    magnitude.)"""
+    print("case: gp full shape n_train=500000 G=64 m=64 C=2048 k=128 fp64", flush=True)
+    w = inputs.workload_gp(n_train=500_000)
+    g = run_gpu(w, w.k, "fp64", want_factor=False)
+    assert np.all(g["status"] == 0)
+    same = 0
+    worst_pv = 0.0
+    sample = (0, 21, 42, 63)
+    for gi in sample:
+        b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+        o = oracle.aggregated_select(w.points, w.kernel, np.array([0, e - b], np.int32), w.members[b:e],
+                                     w.pool[gi: gi + 1], w.pool_len[gi: gi + 1], w.k, want_factor=False,
+                                     want_post_var=True)
+        p = decisive_prefix(o["gap"][0], THR)
+        assert np.array_equal(g["sel"][gi, :p], o["sel"][0, :p]), gi
+        if not np.array_equal(g["sel"][gi], o["sel"][0]):
+            continue
+        same += 1
+        assert g["logdet"][gi] == pytest.approx(o["logdet"][0], rel=1e-8, abs=1e-9)
+        pv = g["post_var"][b:e]
+        np.testing.assert_allclose(pv, o["post_var"], rtol=1e-7, atol=1e-13)
+        worst_pv = max(worst_pv, float(np.max(np.abs(pv - o["post_var"]) / o["post_var"])))
+    print(f"{same} of {len(sample)} batches identical; worst posterior variance error {worst_pv:.2e}", flush=True)
+    assert same >= len(sample) - 1
+
+
 def test_gp_split_rows_match_one_workgroup_per_group():
     """FP64 runs with at most 128 groups and more than 256 rows a group split
     each group's rows over several workgroups (cooperative launch; 1,024,
