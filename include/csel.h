@@ -251,12 +251,13 @@ int32_t csel_aggregated_max_block(void);
  *                csel_aggregated_max_block(); selection outputs are valid),
  *                6 (results lost: a barrier wait among the workgroups that
  *                share the group ran out; not expected in a complete launch)
- * Schedule: FP64 runs of at most 128 groups whose pool_stride + max_members
- * exceeds 256, without factor output, split each group's rows over
- * ceil((pool_stride + max_members) / 256) workgroups launched cooperatively
- * (all resident at once); other runs, or when the device cannot hold that
- * grid, give each group one workgroup.  Both schedules make the same
- * selections up to rounding (near-tied steps may differ).
+ * Schedule: runs of at most 128 groups whose pool_stride + max_members
+ * exceeds 256, without factor output (and in mixed precision outside the
+ * register kernel's range: pools <= 512, groups <= 32, k <= 64), split each
+ * group's rows over workgroups of 1024, 512 or 256 threads launched
+ * cooperatively (all resident at once); other runs, or when the device
+ * cannot hold that grid, give each group one workgroup.  Both schedules make
+ * the same selections up to rounding (near-tied steps may differ).
  */
 int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_groups,
                            const int32_t *group_ptr, const int32_t *members, int32_t max_members,
@@ -265,6 +266,30 @@ int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel
                            float *top2_gap, double *group_logdet, double *post_var, const int64_t *val_ptr,
                            int32_t *factor_rows, double *factor_val, double *member_log_condvar, uint8_t *status,
                            hipStream_t stream);
+
+/*
+ * csel_reverse_maximin -- the reverse-maximin ordering of Sec. 2.2 (eq.
+ * maximin, p = 1) on the GPU: the last position holds point 0, and each
+ * earlier position the remaining point farthest from every point placed
+ * after it (squared distances summed over the coordinates in order, products
+ * and sums rounded separately; ties to the smaller id); the same ordering as
+ * the host definition, bit for bit.
+ *   pts          [n][dim] FP64 in id order, 1 <= dim <= 3
+ *   workspace    device scratch of csel_reverse_maximin_workspace_size(n, dim)
+ *                bytes
+ *   order        [n] int32 out: order[pos] = the id placed at position pos
+ *   ell          [n] FP64 out: ell[pos] = distance of that point to the
+ *                points at later positions (+inf at position n-1)
+ *   rounds       host int32 out (may be NULL): rounds the GPU needed
+ * Several points are placed per round (a prefix of the remaining points by
+ * decreasing distance that no earlier point of it would change); the host
+ * launches the rounds in batches and reads a progress counter between them,
+ * so the call returns after the stream has drained.
+ * Errors: CSEL_EHIP if the rounds stop making progress (not expected).
+ */
+int64_t csel_reverse_maximin_workspace_size(int64_t n, int32_t dim);
+int csel_reverse_maximin(const double *pts, int64_t n, int32_t dim, void *workspace, int64_t workspace_bytes,
+                         int32_t *order, double *ell, int32_t *rounds, hipStream_t stream);
 
 /*
  * csel_later_knn -- the later-ordered candidate pools of Sec. 4 on the GPU:

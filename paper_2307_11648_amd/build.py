@@ -42,7 +42,13 @@ HIP_UNITS = [("abi.cpp", []), ("plan.cpp", []), ("select.hip", [])] + [
 ] + [
     (("select_mw_inst.hip", [f"-DCSEL_MW_T={t}", f"-DCSEL_MW_NU={nu}", f"-DCSEL_MW_W={w}", f"-DCSEL_MW_RPL={r}"]))
     for t in ("float", "double") for nu in (1, 3, 5) for (w, r) in ((2, 1), (4, 1), (4, 2))
-] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip", "global.hip", "pcg.hip", "partial.hip", "knn.hip", "agg_coop.hip")] + [
+] + [(s, []) for s in ("aggregate.hip", "apply.hip", "order.hip", "transpose.hip", "global.hip", "pcg.hip", "partial.hip",
+                        "agg_coop.hip")] + [
+    # the geometry kernels sum squared distances as the definition reads: the
+    # backend would otherwise fuse a product into the running sum (a source
+    # pragma does not stop that fusion once -ffp-contract=fast is on)
+    (s, ["-ffp-contract=off"]) for s in ("knn.hip", "maximin.hip")
+] + [
     # the screen's ReLU/min/max need no NaN handling: plain v_max/v_min without
     # the IEEE-mode quieting of their inputs; the max-ilp machine scheduler runs
     # the column screen 1% faster (identical results)

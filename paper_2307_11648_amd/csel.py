@@ -82,6 +82,11 @@ def load():
     lib.csel_later_knn_workspace_size.restype = ctypes.c_int64
     lib.csel_later_knn.argtypes = [_vp, _c.c_int64, _c.c_int32, _c.c_int32, _vp, _c.c_int64, _vp, _vp, _vp]
     lib.csel_later_knn.restype = ctypes.c_int
+    lib.csel_reverse_maximin_workspace_size.argtypes = [_c.c_int64, _c.c_int32]
+    lib.csel_reverse_maximin_workspace_size.restype = ctypes.c_int64
+    lib.csel_reverse_maximin.argtypes = [_vp, _c.c_int64, _c.c_int32, _vp, _c.c_int64, _vp, _vp,
+                                         ctypes.POINTER(_c.c_int32), _vp]
+    lib.csel_reverse_maximin.restype = ctypes.c_int
     lib.csel_select_and_factor_list.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams),
                                                 _c.c_int64, _vp, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                                 _vp, _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp]
@@ -741,6 +746,27 @@ def later_knn_pools(points, C: int, out=None, workspace=None, stream=None, check
     if check and n > 0 and int(out[1].min().item()) < 0:
         raise CselError(-4, "later_knn: more than 2048 later points tie at one distance")
     return out
+
+
+def reverse_maximin(points, out=None, workspace=None, stream=None):
+    """Reverse-maximin ordering on the GPU (csel_reverse_maximin): (order [n]
+    int32, ell [n] FP64, rounds) for points [n, dim] FP64 in id order;
+    order[pos] is the id at position pos.  Returns after the stream drained."""
+    lib = load()
+    _dev(points, torch.float64, "points")
+    n, dim = points.shape
+    dev = points.device
+    if out is None:
+        out = (torch.empty(n, dtype=torch.int32, device=dev), torch.empty(n, dtype=torch.float64, device=dev))
+    need = lib.csel_reverse_maximin_workspace_size(n, dim)
+    if need < 0:
+        _check(-1)
+    if workspace is None or workspace.numel() < need:
+        workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
+    rounds = _c.c_int32(0)
+    _check(lib.csel_reverse_maximin(points.data_ptr(), n, dim, workspace.data_ptr(), workspace.numel(),
+                                    out[0].data_ptr(), out[1].data_ptr(), ctypes.byref(rounds), _stream(stream)))
+    return out[0], out[1], int(rounds.value)
 
 
 def apply_factor(col_ptr, row_idx, val, x, transpose: bool, out=None, stream=None):

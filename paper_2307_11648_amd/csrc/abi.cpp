@@ -475,6 +475,40 @@ CSEL_API int csel_later_knn(const double* pts, int64_t n, int32_t dim, int32_t C
     return CSEL_OK;
 }
 
+CSEL_API int64_t csel_reverse_maximin_workspace_size(int64_t n, int32_t dim) {
+    g_err[0] = 0;
+    if (n < 0 || n > INT32_MAX) {
+        fail(CSEL_EINVAL, "n must be in [0, 2^31)");
+        return -1;
+    }
+    if (dim < 1 || dim > 3) {
+        fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+        return -1;
+    }
+    const int64_t b = csel::reverse_maximin_workspace(n, dim);
+    if (b < 0) fail(CSEL_EUNSUPPORTED, "reverse_maximin: cannot size the workspace");
+    return b;
+}
+
+CSEL_API int csel_reverse_maximin(const double* pts, int64_t n, int32_t dim, void* workspace, int64_t workspace_bytes,
+                                  int32_t* order, double* ell, int32_t* rounds, hipStream_t stream) {
+    g_err[0] = 0;
+    if (n < 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [0, 2^31) (got %lld)", (long long)n);
+    if (dim < 1 || dim > 3) return fail(CSEL_EINVAL, "dim must be 1, 2 or 3 (got %d)", dim);
+    if (rounds) *rounds = 0;
+    if (n == 0) return CSEL_OK;
+    if (!pts || !order || !ell) return fail(CSEL_EINVAL, "a required array is NULL");
+    const int64_t need = csel::reverse_maximin_workspace(n, dim);
+    if (need < 0) return fail(CSEL_EUNSUPPORTED, "reverse_maximin: cannot size the workspace");
+    if (!workspace || workspace_bytes < need)
+        return fail(CSEL_EINVAL, "workspace must hold csel_reverse_maximin_workspace_size() = %lld bytes",
+                    (long long)need);
+    hipError_t e = csel::launch_reverse_maximin(pts, n, dim, workspace, order, ell, stream, rounds);
+    if (e == hipErrorUnknown) return fail(CSEL_EHIP, "reverse_maximin: the rounds stopped making progress");
+    if (e != hipSuccess) return hip_fail(e, "reverse_maximin");
+    return CSEL_OK;
+}
+
 CSEL_API int csel_partial_select(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
                                  int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
                                  int32_t max_members, const int32_t* pool_idx, const int32_t* pool_len,

@@ -167,6 +167,11 @@ struct AggPlan {
 AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision);
 hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s);
 int agg_factor_max_m();
+// reverse-maximin ordering (Sec. 2.2, eq. maximin, p = 1); blocks until done
+int64_t reverse_maximin_workspace(int64_t n, int dim);
+hipError_t launch_reverse_maximin(const double* pts, int64_t n, int dim, void* workspace, int32_t* order, double* ell,
+                                  hipStream_t s, int32_t* rounds_out);
+
 // multi-target selection with each group's rows over several workgroups
 // (cooperative launch; factor A in FP64 or, mixed, FP32);
 // hipErrorCooperativeLaunchTooLarge when the grid cannot be resident at once

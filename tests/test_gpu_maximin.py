@@ -1,0 +1,68 @@
+"""GPU reverse-maximin ordering (csel_reverse_maximin; Sec. 2.2, eq. maximin,
+p = 1) against the host definition in the inputs module (itself checked
+against an O(n^2) brute force on the CPU): the order and the length scales
+must be identical, bit for bit (integer work, and the same rounding of every
+squared distance)."""
+import numpy as np
+import pytest
+import torch
+
+from paper_2307_11648_amd import csel, inputs
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    csel.load()
+
+
+def _check(x, name):
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    print(f"case: reverse-maximin {name} n={len(x)} d={x.shape[1]}", flush=True)
+    ho, hl = inputs.reverse_maximin(x)
+    go, gl, rounds = csel.reverse_maximin(torch.from_numpy(x).cuda())
+    go, gl = go.cpu().numpy(), gl.cpu().numpy()
+    bad = np.nonzero(go != ho)[0]
+    assert len(bad) == 0, f"{name}: first differing position {bad[-1]} of {len(x)} ({len(bad)} differ)"
+    assert np.array_equal(gl.view(np.uint64), hl.view(np.uint64)), name
+    print(f"{name}: identical, {rounds} rounds", flush=True)
+    return rounds
+
+
+def test_uniform_and_clustered_clouds():
+    _check(inputs.uniform_points(20000, 2, 1), "uniform 2-D")
+    _check(inputs.cluster_points(50000, 3, 4), "clustered 3-D")
+    _check(inputs.uniform_points(3000, 1, 2), "uniform 1-D")
+    _check(inputs.uniform_points(30000, 3, 7), "uniform 3-D")
+
+
+def test_exact_ties():
+    """A lattice (many exactly equal distances: ties go to the smaller id),
+    repeated points (distance 0) and a cloud of identical points."""
+    g = np.arange(100, dtype=np.float64)
+    lat = np.stack(np.meshgrid(g, g, indexing="ij"), axis=-1).reshape(-1, 2)
+    _check(lat, "lattice 100x100")
+    rng = np.random.default_rng(3)
+    base = rng.random((500, 3))
+    rep = np.concatenate([base, base, base])[rng.permutation(1500)]
+    _check(rep, "each point three times")
+    _check(np.full((100, 2), 0.25), "identical points")
+    _check(np.stack([np.arange(64.0), np.zeros(64)], axis=1), "points on a line in 2-D")
+
+
+def test_tiny_inputs():
+    for n in (1, 2, 3):
+        _check(inputs.uniform_points(n, 2, 5), f"n={n}")
+
+
+def test_full_size_cloud():
+    """The 1e6-point clustered cloud in 3-D of the selection workloads."""
+    rounds = _check(inputs.cluster_points(1_000_000, 3, 4), "clustered 3-D, 1e6 points")
+    assert rounds < 20000
+
+
+def test_abi_errors():
+    with pytest.raises(csel.CselError):
+        csel.reverse_maximin(torch.zeros((10, 4), dtype=torch.float64, device="cuda"))
