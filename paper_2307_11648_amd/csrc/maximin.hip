@@ -47,6 +47,8 @@ constexpr int kMmLastDigit = 8;         // digits 0..8 cover the 95 significant 
 constexpr int kMmMaxLevels = 25;
 constexpr int kMmStepsPerBatch = 32;    // rounds launched between two reads of the progress counter
 constexpr int kMmGridBlocks = 512;      // grid-stride kernels over all points
+constexpr int kMmHash = 4096;           // buckets of the round's conflict grid
+constexpr int kMmPassesPerStep = 2;     // histogram passes launched per round (a refill usually needs two)
 
 struct MmLevel {
     int32_t G;         // cells per dimension (2^l)
@@ -261,23 +263,64 @@ __global__ __launch_bounds__(256) void mm_fill_kernel(int32_t* v, int64_t m, int
         v[i] = value;
 }
 
+// Coarse levels (at most kMmLdsCells cells) count and place their points
+// through per-workgroup tallies in LDS, each workgroup taking a contiguous
+// chunk of the points: a million atomic increments of a handful of counters
+// would otherwise serialize.
+constexpr int kMmLdsCells = 4096;
+
 __global__ __launch_bounds__(256) void mm_count_kernel(MmArgs a, int l, int32_t* counts) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
-    const int64_t c = mm_cell(a.pts + j * a.dim, a.prm, l, a.dim, a.lev[l].G, a.nlev);
-    atomicAdd(&counts[c], 1);
+    __shared__ int32_t h[kMmLdsCells];
+    const MmLevel L = a.lev[l];
+    const bool lds = L.cells <= kMmLdsCells;
+    const int tid = threadIdx.x;
+    if (lds) {
+        for (int c = tid; c < L.cells; c += 256) h[c] = 0;
+        __syncthreads();
+    }
+    const int64_t chunk = (a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(a.n, j0 + chunk);
+    for (int64_t j = j0 + tid; j < j1; j += 256) {
+        const int64_t c = mm_cell(a.pts + j * a.dim, a.prm, l, a.dim, L.G, a.nlev);
+        if (lds)
+            atomicAdd(&h[c], 1);
+        else
+            atomicAdd(&counts[c], 1);
+    }
+    if (lds) {
+        __syncthreads();
+        for (int c = tid; c < L.cells; c += 256)
+            if (h[c]) atomicAdd(&counts[c], h[c]);
+    }
 }
 
 __global__ __launch_bounds__(256) void mm_scatter_kernel(MmArgs a, int l, int32_t* fill, int32_t* cell_ids,
                                                          double* cell_xyz) {
-    const int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (j >= a.n) return;
+    __shared__ int32_t h[kMmLdsCells];
     const MmLevel L = a.lev[l];
-    const double* x = a.pts + j * a.dim;
-    const int64_t c = mm_cell(x, a.prm, l, a.dim, L.G, a.nlev);
-    const int64_t at = L.pt_off + a.cell_start[L.cell_off + c] + atomicAdd(&fill[c], 1);
-    cell_ids[at] = (int32_t)j;
-    for (int k = 0; k < a.dim; ++k) cell_xyz[at * a.dim + k] = x[k];
+    const bool lds = L.cells <= kMmLdsCells;
+    const int tid = threadIdx.x;
+    const int64_t chunk = (a.n + gridDim.x - 1) / gridDim.x;
+    const int64_t j0 = (int64_t)blockIdx.x * chunk, j1 = min(a.n, j0 + chunk);
+    if (lds) {
+        // this chunk's count per cell, then one reservation per cell
+        for (int c = tid; c < L.cells; c += 256) h[c] = 0;
+        __syncthreads();
+        for (int64_t j = j0 + tid; j < j1; j += 256)
+            atomicAdd(&h[mm_cell(a.pts + j * a.dim, a.prm, l, a.dim, L.G, a.nlev)], 1);
+        __syncthreads();
+        for (int c = tid; c < L.cells; c += 256)
+            if (h[c]) h[c] = atomicAdd(&fill[c], h[c]);
+        __syncthreads();
+    }
+    for (int64_t j = j0 + tid; j < j1; j += 256) {
+        const double* x = a.pts + j * a.dim;
+        const int64_t c = mm_cell(x, a.prm, l, a.dim, L.G, a.nlev);
+        const int32_t slot = lds ? atomicAdd(&h[c], 1) : atomicAdd(&fill[c], 1);
+        const int64_t at = L.pt_off + a.cell_start[L.cell_off + c] + slot;
+        cell_ids[at] = (int32_t)j;
+        for (int k = 0; k < a.dim; ++k) cell_xyz[at * a.dim + k] = x[k];
+    }
 }
 
 // D_j = |x_j - x_0|^2; point 0 placed last
@@ -423,8 +466,11 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
     uint64_t* sk = reinterpret_cast<uint64_t*>(mm_smem);               // [kMmCap] D bits
     uint32_t* si = reinterpret_cast<uint32_t*>(sk + kMmCap);           // [kMmCap] ids (-1 pads)
     double* sx = reinterpret_cast<double*>(si + kMmCap);               // [kMmCap][3]
+    int32_t* hcnt = reinterpret_cast<int32_t*>(sx + 3 * kMmCap);         // [kMmHash + 1] bucket starts
+    int32_t* hfill = hcnt + (kMmHash + 1);                               // [kMmHash] fill counters
+    int32_t* hidx = hfill + kMmHash;                                     // [kMmCap] candidates by bucket
+    int32_t* hsum = hidx + kMmCap;                                       // [1024] per-thread totals
     __shared__ int sh_cnt, sh_first;
-    __shared__ int sh_conf[kMmRoundThreads / kWave];
     MmState* st = a.st;
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -458,50 +504,167 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
         si[t] = 0xFFFFFFFFu;
     }
     __syncthreads();
-    // bitonic sort, descending key
+    // bitonic sort, descending key: element i = tid + 1024 k (k = 0, 1) in
+    // registers; partners within a wave by shuffles, across waves through LDS
+    uint64_t kd[2];
+    uint32_t ki[2];
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = tid + k * kMmRoundThreads;
+        kd[k] = i < P ? sk[i] : 0ull;
+        ki[k] = i < P ? si[i] : 0xFFFFFFFFu;
+    }
     for (int size = 2; size <= P; size <<= 1) {
         for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = tid; t < P / 2; t += kMmRoundThreads) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool desc = (lo & size) == 0;
-                const bool sw = desc ? mm_before(sk[hi], si[hi], sk[lo], si[lo])
-                                     : mm_before(sk[lo], si[lo], sk[hi], si[hi]);
-                if (sw) {
-                    const uint64_t tk = sk[lo];
-                    sk[lo] = sk[hi];
-                    sk[hi] = tk;
-                    const uint32_t ti = si[lo];
-                    si[lo] = si[hi];
-                    si[hi] = ti;
+            if (stride >= kMmRoundThreads) {
+                // i and i + 1024 in one thread (size 2048: the lower index holds the larger key)
+                if (mm_before(kd[1], ki[1], kd[0], ki[0])) {
+                    const uint64_t tk = kd[0];
+                    kd[0] = kd[1];
+                    kd[1] = tk;
+                    const uint32_t ti = ki[0];
+                    ki[0] = ki[1];
+                    ki[1] = ti;
+                }
+                continue;
+            }
+            uint64_t od[2];
+            uint32_t oi[2];
+            if (stride >= kWave) {
+                __syncthreads();  // the previous exchange's reads are done
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int i = tid + k * kMmRoundThreads;
+                    if (i < P) {
+                        sk[i] = kd[k];
+                        si[i] = ki[k];
+                    }
+                }
+                __syncthreads();
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const int i = tid + k * kMmRoundThreads;
+                    od[k] = i < P ? sk[i ^ stride] : 0ull;
+                    oi[k] = i < P ? si[i ^ stride] : 0xFFFFFFFFu;
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < 2; ++k) {
+                    const uint32_t lo = __shfl_xor((uint32_t)kd[k], stride, kWave);
+                    const uint32_t hi = __shfl_xor((uint32_t)(kd[k] >> 32), stride, kWave);
+                    od[k] = ((uint64_t)hi << 32) | lo;
+                    oi[k] = __shfl_xor(ki[k], stride, kWave);
                 }
             }
-            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < 2; ++k) {
+                const int i = tid + k * kMmRoundThreads;
+                if (i >= P) continue;
+                const bool lower = (i & stride) == 0, desc = (i & size) == 0;
+                const bool keep = (lower == desc) ? !mm_before(od[k], oi[k], kd[k], ki[k])
+                                                  : !mm_before(kd[k], ki[k], od[k], oi[k]);
+                if (!keep) {
+                    kd[k] = od[k];
+                    ki[k] = oi[k];
+                }
+            }
         }
     }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < 2; ++k) {
+        const int i = tid + k * kMmRoundThreads;
+        if (i < P) {
+            sk[i] = kd[k];
+            si[i] = ki[k];
+        }
+    }
+    __syncthreads();
     for (int t = tid; t < nv; t += kMmRoundThreads)
         for (int k = 0; k < 3; ++k) sx[t * 3 + k] = k < dim ? a.pts[(int64_t)si[t] * dim + k] : 0.0;
     if (tid == 0) sh_first = nv;
-    __syncthreads();
-    // the first point that an earlier one lies closer to than sqrt(D)
-    for (int i0 = 1; i0 < nv; i0 += kWaves) {
-        const int i = i0 + wave;
-        bool conf = false;
-        if (i < nv) {
+    // the first point that an earlier one lies closer to than sqrt(D).  Two
+    // such points lie within sqrt(D_0) (the largest D) of each other, so the
+    // candidates are hashed by cells of that width and each one checks the
+    // earlier candidates of its own and the neighbouring cells only; a
+    // conflict found bounds the first one, and larger indices stop early.
+    const double D0 = __longlong_as_double((long long)sk[0]);
+    if (nv > 1 && D0 > 0.0) {
+        const double inv_w = 1.0 / (sqrt(D0) * (1.0 + 1e-9));
+        const double* lo = a.prm + a.nlev * 6;
+        for (int b = tid; b <= kMmHash; b += kMmRoundThreads) hcnt[b] = 0;
+        for (int b = tid; b < kMmHash; b += kMmRoundThreads) hfill[b] = 0;
+        __syncthreads();
+        // (clamped, so that a tiny width cannot overflow the conversion)
+        auto cell_of = [&](const double* x, int k) -> int64_t {
+            return k < dim ? (int64_t)fmin(fmax(floor((x[k] - lo[k]) * inv_w), -4e18), 4e18) : 0;
+        };
+        auto bucket = [&](int64_t c0, int64_t c1, int64_t c2) -> int {
+            const uint32_t h = (uint32_t)c0 * 73856093u ^ (uint32_t)c1 * 19349663u ^ (uint32_t)c2 * 83492791u;
+            return (int)(h & (kMmHash - 1));
+        };
+        for (int t = tid; t < nv; t += kMmRoundThreads)
+            atomicAdd(&hcnt[bucket(cell_of(sx + t * 3, 0), cell_of(sx + t * 3, 1), cell_of(sx + t * 3, 2))], 1);
+        __syncthreads();
+        // exclusive scan of the kMmHash counts (kMmHash / 1024 per thread)
+        constexpr int PER = kMmHash / kMmRoundThreads;
+        int loc[PER], run = 0;
+#pragma unroll
+        for (int q = 0; q < PER; ++q) {
+            loc[q] = run;
+            run += hcnt[tid * PER + q];
+        }
+        hsum[tid] = run;
+        __syncthreads();
+        if (tid < kWave) {
+            // the 1024 thread totals, scanned by one wave (16 per lane)
+            int v[16], acc = 0;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) {
+                v[q] = acc;
+                acc += hsum[tid * 16 + q];
+            }
+            int incl = acc;
+            for (int off = 1; off < kWave; off <<= 1) {
+                const int o = __shfl_up(incl, off, kWave);
+                if (lane >= off) incl += o;
+            }
+            const int excl = incl - acc;
+#pragma unroll
+            for (int q = 0; q < 16; ++q) hsum[tid * 16 + q] = excl + v[q];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int q = 0; q < PER; ++q) hcnt[tid * PER + q] = hsum[tid] + loc[q];
+        if (tid == 0) hcnt[kMmHash] = nv;
+        __syncthreads();
+        for (int t = tid; t < nv; t += kMmRoundThreads) {
+            const int b = bucket(cell_of(sx + t * 3, 0), cell_of(sx + t * 3, 1), cell_of(sx + t * 3, 2));
+            hidx[atomicAdd(&hfill[b], 1) + hcnt[b]] = t;
+        }
+        __syncthreads();
+        for (int i = 1 + tid; i < nv; i += kMmRoundThreads) {
+            if (__hip_atomic_load(&sh_first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i) break;
             const double Di = __longlong_as_double((long long)sk[i]);
-            for (int hh = lane; hh < i && !conf; hh += kWave) conf = mm_d2(sx + hh * 3, sx + i * 3, dim) < Di;
+            const double* q = sx + i * 3;
+            const int64_t c0 = cell_of(q, 0), c1 = cell_of(q, 1), c2 = cell_of(q, 2);
+            bool conf = false;
+            for (int d2i = (dim > 2 ? -1 : 0); d2i <= (dim > 2 ? 1 : 0) && !conf; ++d2i)
+                for (int d1i = (dim > 1 ? -1 : 0); d1i <= (dim > 1 ? 1 : 0) && !conf; ++d1i)
+                    for (int d0i = -1; d0i <= 1 && !conf; ++d0i) {
+                        const int b = bucket(c0 + d0i, c1 + d1i, c2 + d2i);
+                        for (int e = hcnt[b]; e < hcnt[b + 1] && !conf; ++e) {
+                            const int h = hidx[e];
+                            if (h < i) conf = mm_d2(sx + h * 3, q, dim) < Di;
+                            if ((e & 31) == 31 &&
+                                __hip_atomic_load(&sh_first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i)
+                                break;
+                        }
+                    }
+            if (conf) atomicMin(&sh_first, i);
         }
-        const bool any = __any(conf);
-        if (lane == 0) sh_conf[wave] = any ? i : nv;
-        __syncthreads();
-        if (tid == 0) {
-            int f = nv;
-            for (int w = 0; w < kWaves; ++w) f = min(f, sh_conf[w]);
-            sh_first = f;
-        }
-        __syncthreads();
-        if (sh_first < nv) break;
     }
+    __syncthreads();
     const int r = sh_first;
     const int pos0 = st->pos_next;
     for (int i = tid; i < r; i += kMmRoundThreads) {
@@ -704,12 +867,12 @@ hipError_t launch_reverse_maximin(const double* pts, int64_t n, int dim, void* w
     hipLaunchKernelGGL(mm_params_kernel, dim3(1), dim3(64), 0, s, (const uint64_t*)bb, a, prm);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const unsigned gp = (unsigned)((n + 255) / 256);
+    const unsigned gb = (unsigned)std::min<int64_t>((n + 255) / 256, 1024);
     for (int l = 0; l < y.nlev; ++l) {
         const MmLevel& L = y.lev[l];
         const unsigned gc = (unsigned)std::min<int64_t>((L.cells + 1 + 255) / 256, 4096);
         hipLaunchKernelGGL(mm_fill_kernel, dim3(gc), dim3(256), 0, s, fill, L.cells + 1, 0);
-        hipLaunchKernelGGL(mm_count_kernel, dim3(gp), dim3(256), 0, s, a, l, fill);
+        hipLaunchKernelGGL(mm_count_kernel, dim3(gb), dim3(256), 0, s, a, l, fill);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
         size_t sb = y.scan_bytes;
@@ -717,7 +880,7 @@ hipError_t launch_reverse_maximin(const double* pts, int64_t n, int dim, void* w
                                     rocprim::plus<int32_t>(), s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(mm_fill_kernel, dim3(gc), dim3(256), 0, s, fill, L.cells + 1, 0);
-        hipLaunchKernelGGL(mm_scatter_kernel, dim3(gp), dim3(256), 0, s, a, l, fill, const_cast<int32_t*>(a.cell_ids),
+        hipLaunchKernelGGL(mm_scatter_kernel, dim3(gb), dim3(256), 0, s, a, l, fill, const_cast<int32_t*>(a.cell_ids),
                            const_cast<double*>(a.cell_xyz));
         e = hipGetLastError();
         if (e != hipSuccess) return e;
@@ -726,18 +889,19 @@ hipError_t launch_reverse_maximin(const double* pts, int64_t n, int dim, void* w
                        0, s, a);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    const size_t smem = (size_t)kMmCap * (8 + 4 + 24);
+    const size_t smem = (size_t)kMmCap * (8 + 4 + 24) + (size_t)(2 * kMmHash + 1 + kMmCap + kMmRoundThreads) * 4;
     e = hipFuncSetAttribute((const void*)mm_round_kernel, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     const unsigned gh = (unsigned)std::min<int64_t>((n + 255) / 256, kMmGridBlocks);
-    // each step places at least one point, or advances a refill by three
-    // digits or runs its gather; a refill takes at most four steps, so every
+    // each step places at least one point, or advances a refill by two
+    // digits or runs its gather; a refill takes at most five steps, so every
     // batch of steps places points
     MmState hs{};
     int32_t left = (int32_t)(n - 1);
     for (;;) {
         for (int k = 0; k < kMmStepsPerBatch; ++k) {
-            for (int pass = 0; pass < 3; ++pass) hipLaunchKernelGGL(mm_hist_kernel, dim3(gh), dim3(256), 0, s, a);
+            for (int pass = 0; pass < kMmPassesPerStep; ++pass)
+                hipLaunchKernelGGL(mm_hist_kernel, dim3(gh), dim3(256), 0, s, a);
             hipLaunchKernelGGL(mm_gather_kernel, dim3(gh), dim3(256), 0, s, a);
             hipLaunchKernelGGL(mm_round_kernel, dim3(1), dim3(kMmRoundThreads), smem, s, a);
             hipLaunchKernelGGL(mm_update_kernel, dim3(1024), dim3(256), 0, s, a);
