@@ -217,29 +217,69 @@ __device__ __forceinline__ float matern_f32(float r, float c, float s2) {
 // Horner form, scaled by 2^k.  For a past ~745 the scaling underflows to 0.
 // The argument is never infinite or NaN here, so the special-value checks of
 // a general exp are left out.
-__device__ __forceinline__ double exp_neg64(double a) {
-    constexpr double kInvLn2 = 1.4426950408889634;
-    constexpr double kLn2Hi = 0x1.62e42ff000000p-1;
-    constexpr double kLn2Lo = -0x1.718432a1b0e26p-35;
+//
+// Its 64-bit constants (and the Matern 5/2 polynomial's 1/3) travel in an
+// ExpConsts.  A kernel that evaluates the covariance in a fully unrolled pick
+// loop builds them once with exp_consts_sgpr(), which pins each in a pair of
+// scalar registers for the whole kernel; written as literals, each use would
+// re-create its constant with two scalar moves (a thousand per column in the
+// FP64 kept-pool selection).  The arithmetic is the same either way.
+struct ExpConsts {
+    double inv_ln2, ln2_hi, ln2_lo, third;
+    double q[11];  // 1/12!, 1/11!, ..., 1/2! (the last two Horner steps add 1)
+};
+
+__device__ __forceinline__ ExpConsts exp_consts() {
+    ExpConsts K;
+    K.inv_ln2 = 1.4426950408889634;
+    K.ln2_hi = 0x1.62e42ff000000p-1;
+    K.ln2_lo = -0x1.718432a1b0e26p-35;
+    K.third = 1.0 / 3.0;
+    K.q[0] = 2.08767569878681e-09;
+    K.q[1] = 2.505210838544172e-08;
+    K.q[2] = 2.755731922398589e-07;
+    K.q[3] = 2.7557319223985893e-06;
+    K.q[4] = 2.48015873015873e-05;
+    K.q[5] = 0.0001984126984126984;
+    K.q[6] = 0.001388888888888889;
+    K.q[7] = 0.008333333333333333;
+    K.q[8] = 0.041666666666666664;
+    K.q[9] = 0.16666666666666666;
+    K.q[10] = 0.5;
+    return K;
+}
+
+// the value in scalar registers, opaque to the compiler (so kept, not re-made)
+__device__ __forceinline__ double pin_sgpr(double v) {
+    asm volatile("" : "+s"(v));
+    return v;
+}
+
+__device__ __forceinline__ ExpConsts exp_consts_sgpr() {
+    ExpConsts K = exp_consts();
+    K.inv_ln2 = pin_sgpr(K.inv_ln2);
+    K.ln2_hi = pin_sgpr(K.ln2_hi);
+    K.ln2_lo = pin_sgpr(K.ln2_lo);
+    K.third = pin_sgpr(K.third);
+#pragma unroll
+    for (int i = 0; i < 10; ++i) K.q[i] = pin_sgpr(K.q[i]);  // q[10] = 0.5 is an inline constant
+    return K;
+}
+
+__device__ __forceinline__ double exp_neg64(double a, const ExpConsts& K) {
     const double x = -a;
-    const double k = __builtin_rint(x * kInvLn2);
-    double r = fma(-k, kLn2Hi, x);
-    r = fma(-k, kLn2Lo, r);
-    double q = 2.08767569878681e-09;  // 1/12!
-    q = fma(q, r, 2.505210838544172e-08);
-    q = fma(q, r, 2.755731922398589e-07);
-    q = fma(q, r, 2.7557319223985893e-06);
-    q = fma(q, r, 2.48015873015873e-05);
-    q = fma(q, r, 0.0001984126984126984);
-    q = fma(q, r, 0.001388888888888889);
-    q = fma(q, r, 0.008333333333333333);
-    q = fma(q, r, 0.041666666666666664);
-    q = fma(q, r, 0.16666666666666666);
-    q = fma(q, r, 0.5);
+    const double k = __builtin_rint(x * K.inv_ln2);
+    double r = fma(-k, K.ln2_hi, x);
+    r = fma(-k, K.ln2_lo, r);
+    double q = K.q[0];
+#pragma unroll
+    for (int i = 1; i < 11; ++i) q = fma(q, r, K.q[i]);
     q = fma(q, r, 1.0);
     q = fma(q, r, 1.0);
     return __builtin_amdgcn_ldexp(q, (int)k);
 }
+
+__device__ __forceinline__ double exp_neg64(double a) { return exp_neg64(a, exp_consts()); }
 
 // sqrt(s) for s >= 0 in FP64, about 1 ulp: the hardware reciprocal square
 // root, one Goldschmidt step (g -> sqrt(s), h -> 1/(2 sqrt(s))) and one
@@ -259,12 +299,17 @@ __device__ __forceinline__ double dist64(double s) {
 // every kernel that inlines this rounds it the same way (with contraction
 // left to the compiler, a product with two uses may or may not be fused).
 template <int TWO_NU>
-__device__ __forceinline__ double matern_f64(double r, double c, double s2) {
+__device__ __forceinline__ double matern_f64(double r, double c, double s2, const ExpConsts& K) {
     const double a = c * r;
-    const double e = exp_neg64(a);
+    const double e = exp_neg64(a, K);
     if constexpr (TWO_NU == 1) return s2 * e;
     if constexpr (TWO_NU == 3) return s2 * fma(c, r, 1.0) * e;
-    return s2 * fma(a, fma(a, 1.0 / 3.0, 1.0), 1.0) * e;
+    return s2 * fma(a, fma(a, K.third, 1.0), 1.0) * e;
+}
+
+template <int TWO_NU>
+__device__ __forceinline__ double matern_f64(double r, double c, double s2) {
+    return matern_f64<TWO_NU>(r, c, s2, exp_consts());
 }
 
 // |e|^2 of a 3-vector with explicit fused multiply-adds (the same rounding

@@ -49,9 +49,17 @@ __device__ __forceinline__ T tsqrt(T x) {
 }
 
 template <typename T, int TWO_NU>
-__device__ __forceinline__ T matern(T r, T c, T s2) {
+__device__ __forceinline__ T matern(T r, T c, T s2, const ExpConsts& K) {
     if constexpr (sizeof(T) == 4) return matern_f32<TWO_NU>(r, c, s2);
-    else return matern_f64<TWO_NU>(r, c, s2);
+    else return matern_f64<TWO_NU>(r, c, s2, K);
+}
+
+// the FP64 exponential's constants: pinned in scalar registers for the FP64
+// kernels (built once instead of at every unrolled use), literals otherwise
+template <typename T>
+__device__ __forceinline__ ExpConsts kernel_exp_consts() {
+    if constexpr (sizeof(T) == 8) return exp_consts_sgpr();
+    else return exp_consts();
 }
 
 constexpr int kSelWavesPerBlock = 4;
@@ -289,6 +297,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         col = p.col_list[pos];
     }
     if (col < 0 || col >= p.n_targets) return;
+    const ExpConsts EK = kernel_exp_consts<T>();
 
     const int kout = p.k;
     int32_t* sel_out = p.sel + col * kout;
@@ -328,7 +337,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
             }
         }
         const T r = tsqrt(sqnorm3(dx[rr][0], dx[rr][1], dx[rr][2]));
-        cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
+        cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2, EK);
         // var = -1 marks a slot that can never be picked (empty, or selected)
         var[rr] = pid[rr] >= 0 ? prior : -1.0;
     }
@@ -510,7 +519,7 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 for (int rr = 0; rr < RPL; ++rr) {
                     const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
                     const T r = tsqrt(sqnorm3(e0, e1, e2));
-                    acc[rr] = matern<T, TWO_NU>(r, cnu, s2);
+                    acc[rr] = matern<T, TWO_NU>(r, cnu, s2, EK);
                     if (pid[rr] == idk) acc[rr] += nug;
                 }
                 // GEMV with the broadcast row, one LDS element at a time for all rows

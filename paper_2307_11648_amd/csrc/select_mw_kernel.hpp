@@ -72,6 +72,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
     // in all its waves, so no barrier is left waiting); one with at least one
     // column keeps every wave for the barriers
     if (!any_col) return;
+    const ExpConsts EK = kernel_exp_consts<T>();
     const int64_t col = column_of(cib);
     const bool has_col = col >= 0;
 
@@ -108,7 +109,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
             }
         }
         const T r = tsqrt(sqnorm3(dx[rr][0], dx[rr][1], dx[rr][2]));
-        cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2);
+        cov[rr] = (double)matern<T, TWO_NU>(r, cnu, s2, EK);
         // var = -1 marks a slot that can never be picked (empty, or selected)
         var[rr] = pid[rr] >= 0 ? prior : -1.0;
     }
@@ -219,7 +220,7 @@ __global__ __launch_bounds__(256) void select_factor_mw_kernel(SelectArgs p) {
             for (int rr = 0; rr < RPL; ++rr) {
                 const T e0 = dx[rr][0] - dk0, e1 = dx[rr][1] - dk1, e2 = dx[rr][2] - dk2;
                 const T r = tsqrt(sqnorm3(e0, e1, e2));
-                acc[rr] = matern<T, TWO_NU>(r, cnu, s2);
+                acc[rr] = matern<T, TWO_NU>(r, cnu, s2, EK);
                 if (pid[rr] == idk) acc[rr] += nug;
             }
             // GEMV with the broadcast row, one LDS element at a time for all rows
