@@ -54,6 +54,16 @@ typedef enum {
 
 enum { CSEL_FP64 = 0, CSEL_MIXED = 1 };
 
+/* Schedules of csel_aggregated_select_sched (see there). */
+enum {
+    CSEL_AGG_AUTO = 0,       /* the library's rule (csel_aggregated_select) */
+    CSEL_AGG_ONE_GROUP = 1,  /* one workgroup per group */
+    CSEL_AGG_REGISTER = 2,   /* the mixed register-resident kernel */
+    CSEL_AGG_SPLIT_256 = 3,  /* a group's rows over workgroups of 256 threads */
+    CSEL_AGG_SPLIT_512 = 4,  /* ... of 512 threads */
+    CSEL_AGG_SPLIT_1024 = 5  /* ... of 1024 threads */
+};
+
 /* Matern covariance K(x, y) = variance * m_nu(|x - y| / length_scale) with
  * nu = two_nu / 2 in {1/2, 3/2, 5/2}, plus `nugget` on the diagonal (by
  * index).  The paper uses the Matern family throughout (Sec. 6) without
@@ -233,7 +243,8 @@ int32_t csel_aggregated_max_block(void);
  *   post_var     [sum m] Theta_qq | selected for every target: the posterior
  *                variances of GP prediction at the targets given the selected
  *                training points (Alg. infer_select) (may be NULL; CSEL_FP64
- *                only, CSEL_EUNSUPPORTED with CSEL_MIXED)
+ *                only, CSEL_EUNSUPPORTED with CSEL_MIXED; NaN for a group with
+ *                status 4, left unwritten for status 3)
  *   factor_val   (may be NULL) aggregated factor columns: member q gets
  *                s_q = {j in sort(T u selected) : j >= q} and the eq. L_col
  *                column on s_q, computed for the whole group from one reverse
@@ -256,8 +267,8 @@ int32_t csel_aggregated_max_block(void);
  * register kernel's range: pools <= 512, groups <= 32, k <= 64), split each
  * group's rows over workgroups of 1024, 512 or 256 threads launched
  * cooperatively (all resident at once); other runs, or when the device
- * cannot hold that grid, give each group one workgroup.  Both schedules make
- * the same selections up to rounding (near-tied steps may differ).
+ * cannot hold that grid, give each group one workgroup.  The two schedules
+ * give bit-identical results.
  */
 int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel, int64_t n_groups,
                            const int32_t *group_ptr, const int32_t *members, int32_t max_members,
@@ -266,6 +277,30 @@ int csel_aggregated_select(const double *pts, int64_t n, int32_t dim, const csel
                            float *top2_gap, double *group_logdet, double *post_var, const int64_t *val_ptr,
                            int32_t *factor_rows, double *factor_val, double *member_log_condvar, uint8_t *status,
                            hipStream_t stream);
+
+/*
+ * csel_aggregated_select_sched -- csel_aggregated_select under an explicit
+ * schedule, for a caller that chooses by timing (the package's tuner does):
+ *   CSEL_AGG_AUTO        the rule csel_aggregated_select follows
+ *   CSEL_AGG_ONE_GROUP   one workgroup per group, factor columns in a slab
+ *   CSEL_AGG_REGISTER    the mixed register kernel (CSEL_MIXED, no post_var,
+ *                        pool_stride <= 512, max_members <= 32, k <= 64)
+ *   CSEL_AGG_SPLIT_256/512/1024  each group's rows over cooperatively launched
+ *                        workgroups of that many threads (no factor output,
+ *                        n_groups <= 1024, k <= 256, max_members <= 128)
+ * One workgroup per group and the split schedules give bit-identical results
+ * (the same expressions and summation orders); the register kernel evaluates
+ * the target-conditioned factor in FP32 and can differ in near-tied picks.
+ * Errors: CSEL_EUNSUPPORTED for a schedule outside its range, or when a split
+ * schedule's workgroups cannot all be resident at once.
+ */
+int csel_aggregated_select_sched(const double *pts, int64_t n, int32_t dim, const csel_kernel *kernel,
+                                 int64_t n_groups, const int32_t *group_ptr, const int32_t *members,
+                                 int32_t max_members, const int32_t *pool_idx, const int32_t *pool_len,
+                                 int32_t pool_stride, int32_t k, int32_t precision, void *workspace,
+                                 int64_t workspace_bytes, int32_t *sel_idx, float *top2_gap, double *group_logdet,
+                                 double *post_var, const int64_t *val_ptr, int32_t *factor_rows, double *factor_val,
+                                 double *member_log_condvar, uint8_t *status, int32_t schedule, hipStream_t stream);
 
 /*
  * csel_reverse_maximin -- the reverse-maximin ordering of Sec. 2.2 (eq.

@@ -16,6 +16,12 @@ cloud, so the first call for a shape class times each once on the stream it
 runs on and keeps the fastest; later calls of the class reuse the choice.
 Choices can persist in a JSON file, which a later process reads back.
 
+The multi-target selection (csel_aggregated_select_sched) is tuned the same
+way between one workgroup per group and a group's rows split over workgroups
+of 256, 512 or 1,024 threads: these give bit-identical results.  Mixed runs
+that the register-resident kernel covers keep it untuned (its FP32 arithmetic
+is its own, so a different choice could change a near-tied pick).
+
 The tuner only chooses between launches of the library's kernels; every step
 of the selection runs in them.
 """
@@ -28,6 +34,7 @@ import os
 from . import csel
 
 SCHEDULES = ("natural", "spatial", "natural/mw", "spatial/mw")
+AGG_SCHEDULES = ("one_group", "split256", "split512", "split1024")
 _FORMAT_VERSION = 2
 
 
@@ -39,6 +46,16 @@ def shape_key(dim: int, two_nu: int, n_targets: int, stride: int, k: int, precis
     kmax = 16 if k <= 16 else 32
     tb = max(0, int(math.ceil(math.log2(max(1, n_targets)))))
     return f"d{dim}/nu{two_nu}/pool{64 * rpl}/k{kmax}/{precision}/T2^{tb}"
+
+
+def agg_shape_key(dim: int, two_nu: int, n_groups: int, stride: int, max_members: int, k: int, precision: str,
+                  post_var: bool) -> str:
+    """Shape class of a multi-target selection: group count and rows per group
+    (pool + members) to the next power of two, members, picks, precision and
+    whether posterior variances are asked for."""
+    gb = max(0, int(math.ceil(math.log2(max(1, n_groups)))))
+    rb = max(0, int(math.ceil(math.log2(max(1, stride + max_members)))))
+    return f"agg/d{dim}/nu{two_nu}/G2^{gb}/rows2^{rb}/m{max_members}/k{k}/{precision}/pv{int(bool(post_var))}"
 
 
 def check_permutation(order, n: int) -> None:
@@ -97,7 +114,8 @@ class SelectTuner:
         if not isinstance(doc, dict) or doc.get("version") != _FORMAT_VERSION:
             return {}
         ch = doc.get("choices", {})
-        return {key: v for key, v in ch.items() if isinstance(v, dict) and v.get("schedule") in SCHEDULES}
+        return {key: v for key, v in ch.items()
+                if isinstance(v, dict) and v.get("schedule") in SCHEDULES + AGG_SCHEDULES}
 
     def save(self) -> None:
         if not self.path:
@@ -119,7 +137,8 @@ class SelectTuner:
             run()
             ms[name] = float(self._timer(run, stream))
         self.tuning_runs += 1
-        best = min(ms, key=lambda name: (ms[name], SCHEDULES.index(name)))
+        names = list(runners)
+        best = min(ms, key=lambda name: (ms[name], names.index(name)))
         self.choices[key] = {"schedule": best, "ms": ms}
         self.save()
         return best
@@ -175,5 +194,40 @@ class SelectTuner:
         if key not in self.choices or order.shape[0] != T:
             check_permutation(order, T)  # once per shape class (it reads the order back)
         runners = {"natural": natural, "spatial": spatial, "natural/mw": natural_mw, "spatial/mw": spatial_mw}
+        runners[self.choose(key, runners, stream)]()
+        return out
+
+    def aggregated_select(self, points, kernel, group_ptr, members, max_members: int, pool, pool_len, k: int,
+                          precision: str = "fp64", want_factor: bool = False, want_post_var: bool = False,
+                          want_gap: bool = False, out: dict | None = None, workspace=None, stream=None) -> dict:
+        """csel_aggregated_select under the tuned schedule of its shape class
+        (one workgroup per group, or split rows of 256, 512 or 1,024 threads;
+        split rows only without factor output and for at most 1,024 groups)."""
+        G = group_ptr.numel() - 1
+        stride = pool.shape[1] if pool.dim() == 2 else 0
+        args = (points, kernel, group_ptr, members, max_members, pool, pool_len, k, precision)
+        kw = dict(want_factor=want_factor, want_post_var=want_post_var, want_gap=want_gap, stream=stream)
+        register = (precision == "mixed" and not want_post_var and stride <= 512 and max_members <= 32 and k <= 64)
+        if register or G == 0:
+            return csel.aggregated_select(*args, out=out, workspace=workspace, **kw)
+        out = csel.aggregated_select(*args, out=out, workspace=workspace, schedule="one_group", **kw)
+        workspace = out["workspace"]
+        key = agg_shape_key(points.shape[1], int(kernel.two_nu), G, stride, max_members, k, precision,
+                            want_post_var)
+        names = ["one_group"]
+        if not want_factor and G <= 1024 and k <= 256 and max_members <= 128:
+            names += ["split256", "split512", "split1024"]
+        got = self.choices.get(key)
+        if got is not None and got["schedule"] in names:
+            return csel.aggregated_select(*args, out=out, workspace=workspace, schedule=got["schedule"], **kw)
+        runners = {}
+        for name in names:
+            def run(name=name):
+                csel.aggregated_select(*args, out=out, workspace=workspace, schedule=name, **kw)
+            try:
+                run()  # a split grid the device cannot hold is refused
+            except csel.CselError:
+                continue
+            runners[name] = run
         runners[self.choose(key, runners, stream)]()
         return out

@@ -74,6 +74,8 @@ def load():
                                            _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _c.c_int32,
                                            _vp, _c.c_int64, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp]
     lib.csel_aggregated_select.restype = ctypes.c_int
+    lib.csel_aggregated_select_sched.argtypes = lib.csel_aggregated_select.argtypes[:-1] + [_c.c_int32, _vp]
+    lib.csel_aggregated_select_sched.restype = ctypes.c_int
     lib.csel_partial_select.argtypes = [_vp, _c.c_int64, _c.c_int32, ctypes.POINTER(KernelParams), _c.c_int64,
                                         _vp, _vp, _c.c_int32, _vp, _vp, _c.c_int32, _c.c_int32, _vp, _vp, _vp, _vp,
                                         _vp, _vp, _vp, _vp, _vp]
@@ -638,10 +640,16 @@ def aggregated_val_ptr(group_ptr, pool_len, k: int):
     return vp
 
 
+AGG_SCHEDULES = {"auto": 0, "one_group": 1, "register": 2, "split256": 3, "split512": 4, "split1024": 5}
+
+
 def aggregated_select(points, kernel, group_ptr, members, max_members: int, pool, pool_len, k: int,
                       precision: str = "mixed", want_factor: bool = False, want_post_var: bool = False,
-                      want_gap: bool = False, out: dict | None = None, workspace=None, stream=None) -> dict:
-    """Multi-target (aggregated) greedy selection (csel_aggregated_select).
+                      want_gap: bool = False, out: dict | None = None, workspace=None, stream=None,
+                      schedule: str = "auto") -> dict:
+    """Multi-target (aggregated) greedy selection (csel_aggregated_select,
+    or csel_aggregated_select_sched for a schedule other than "auto": one of
+    AGG_SCHEDULES).
 
     group_ptr [G+1] int32 CSR offsets into members [sum m] int32; pool [G,
     stride] int32, pool_len [G] int32.  Returns GPU tensors: sel [G, k],
@@ -677,13 +685,16 @@ def aggregated_select(points, kernel, group_ptr, members, max_members: int, pool
         workspace = torch.empty(max(need, 1), dtype=torch.uint8, device=dev)
     out["workspace"] = workspace
     kp = kernel_struct(kernel)
-    rc = lib.csel_aggregated_select(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), G,
-                                    group_ptr.data_ptr(), members.data_ptr(), int(max_members), pool.data_ptr(),
-                                    pool_len.data_ptr(), stride, int(k), prec, workspace.data_ptr(),
-                                    workspace.numel(), _ptr(out["sel"]), _ptr(out.get("gap")),
-                                    _ptr(out.get("logdet")), _ptr(out.get("post_var")), _ptr(out.get("val_ptr")),
-                                    _ptr(out.get("rows")), _ptr(out.get("vals")),
-                                    _ptr(out.get("member_log_condvar")), _ptr(out["status"]), _stream(stream))
+    if schedule not in AGG_SCHEDULES:
+        raise ValueError(f"schedule must be one of {sorted(AGG_SCHEDULES)}")
+    rc = lib.csel_aggregated_select_sched(points.data_ptr(), points.shape[0], points.shape[1], ctypes.byref(kp), G,
+                                          group_ptr.data_ptr(), members.data_ptr(), int(max_members),
+                                          pool.data_ptr(), pool_len.data_ptr(), stride, int(k), prec,
+                                          workspace.data_ptr(), workspace.numel(), _ptr(out["sel"]),
+                                          _ptr(out.get("gap")), _ptr(out.get("logdet")), _ptr(out.get("post_var")),
+                                          _ptr(out.get("val_ptr")), _ptr(out.get("rows")), _ptr(out.get("vals")),
+                                          _ptr(out.get("member_log_condvar")), _ptr(out["status"]),
+                                          AGG_SCHEDULES[schedule], _stream(stream))
     _check(rc)
     return out
 

@@ -377,15 +377,17 @@ CSEL_API int64_t csel_aggregated_workspace_size(int64_t n_groups, int32_t pool_s
 
 CSEL_API int32_t csel_aggregated_max_block(void) { return csel::agg_factor_max_m(); }
 
-CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
-                                    int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
-                                    int32_t max_members, const int32_t* pool_idx, const int32_t* pool_len,
-                                    int32_t pool_stride, int32_t k, int32_t precision, void* workspace,
-                                    int64_t workspace_bytes, int32_t* sel_idx, float* top2_gap,
-                                    double* group_logdet, double* post_var, const int64_t* val_ptr,
-                                    int32_t* factor_rows, double* factor_val, double* member_log_condvar,
-                                    uint8_t* status, hipStream_t stream) {
+CSEL_API int csel_aggregated_select_sched(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                          int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
+                                          int32_t max_members, const int32_t* pool_idx, const int32_t* pool_len,
+                                          int32_t pool_stride, int32_t k, int32_t precision, void* workspace,
+                                          int64_t workspace_bytes, int32_t* sel_idx, float* top2_gap,
+                                          double* group_logdet, double* post_var, const int64_t* val_ptr,
+                                          int32_t* factor_rows, double* factor_val, double* member_log_condvar,
+                                          uint8_t* status, int32_t schedule, hipStream_t stream) {
     g_err[0] = 0;
+    if (schedule < CSEL_AGG_AUTO || schedule > CSEL_AGG_SPLIT_1024)
+        return fail(CSEL_EINVAL, "schedule must be one of the CSEL_AGG_ values (got %d)", schedule);
     int rc = check_kernel(kernel);
     if (rc) return rc;
     if (n <= 0 || n > INT32_MAX) return fail(CSEL_EINVAL, "n must be in [1, 2^31) (got %lld)", (long long)n);
@@ -436,9 +438,29 @@ CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, c
     a.fac_rows = factor_rows;
     a.fac_val = factor_val;
     a.member_logcv = member_log_condvar;
-    hipError_t e = csel::launch_aggregated(a, pl, precision, want_factor, stream);
+    hipError_t e = csel::launch_aggregated(a, pl, precision, want_factor, schedule, stream);
+    if (e == hipErrorNotSupported)
+        return fail(CSEL_EUNSUPPORTED, "schedule %d does not apply to this request (register: mixed, no post_var, "
+                    "pools <= 512, groups <= 32, k <= 64; split: no factor output, <= 1024 groups, k <= 256, "
+                    "groups <= 128)", schedule);
+    if (e == hipErrorCooperativeLaunchTooLarge)
+        return fail(CSEL_EUNSUPPORTED, "the split schedule's workgroups do not all fit on the device at once");
     if (e != hipSuccess) return hip_fail(e, "aggregated_select launch");
     return CSEL_OK;
+}
+
+CSEL_API int csel_aggregated_select(const double* pts, int64_t n, int32_t dim, const csel_kernel* kernel,
+                                    int64_t n_groups, const int32_t* group_ptr, const int32_t* members,
+                                    int32_t max_members, const int32_t* pool_idx, const int32_t* pool_len,
+                                    int32_t pool_stride, int32_t k, int32_t precision, void* workspace,
+                                    int64_t workspace_bytes, int32_t* sel_idx, float* top2_gap,
+                                    double* group_logdet, double* post_var, const int64_t* val_ptr,
+                                    int32_t* factor_rows, double* factor_val, double* member_log_condvar,
+                                    uint8_t* status, hipStream_t stream) {
+    return csel_aggregated_select_sched(pts, n, dim, kernel, n_groups, group_ptr, members, max_members, pool_idx,
+                                        pool_len, pool_stride, k, precision, workspace, workspace_bytes, sel_idx,
+                                        top2_gap, group_logdet, post_var, val_ptr, factor_rows, factor_val,
+                                        member_log_condvar, status, CSEL_AGG_AUTO, stream);
 }
 
 CSEL_API int64_t csel_later_knn_workspace_size(int64_t n, int32_t dim) {

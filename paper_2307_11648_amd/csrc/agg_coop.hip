@@ -3,7 +3,9 @@
 // few groups (GP prediction batches: 64 groups of 64 targets with pools of
 // 2,048) that one workgroup per group leaves on a quarter of the CUs.
 //
-// The computation is the slab kernel's (aggregate.hip), FP64: factor B
+// The computation is the slab kernel's (aggregate.hip), rounded the same way
+// (the same expressions, fused multiply-adds and summation orders), so the two
+// schedules give bit-identical results: factor B
 // conditions on the targets and then on every pick, factor A on the picks
 // only, both column-major in a per-group slab in global memory; every pick
 // maximizes 1 - var2 / var1.  W workgroups share a group, each owning a
@@ -183,10 +185,10 @@ __global__ __launch_bounds__(NT) void agg_select_coop_kernel(CoopArgs ca) {
         const double piv = pv[0], y0 = pv[1], y1 = pv[2], y2 = pv[3];
         const int32_t idw = (int32_t)pv[4];
         ldT += log(piv);
-        const double inv_sd = rsq64(piv);
+        const double inv_sd = 1.0 / sqrt(piv);
         if (r < R) {
             const double e0 = x0 - y0, e1 = x1 - y1, e2 = x2 - y2;
-            double acc = matern_f64_rt(p.two_nu, dist64(sqnorm3(e0, e1, e2)), cnu, s2);
+            double acc = matern_f64_rt(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnu, s2);
             if (rid == idw) acc += p.nugget;
             acc = dot_down<double>(acc, slabB + r, rmax, rowB, c);
             const double u = acc * inv_sd;
@@ -258,17 +260,17 @@ __global__ __launch_bounds__(NT) void agg_select_coop_kernel(CoopArgs ca) {
                 p.gap[g * p.k + t] = (best.k2 == 0ull) ? 1.0f : (sa == 0.0 ? 0.0f : (float)((sa - sb) / sa));
             }
         }
-        const double inv1 = rsq64(w1), inv2 = rsq64(w2);
+        const double inv1 = 1.0 / sqrt(w1), inv2 = 1.0 / sqrt(w2);
         if (r < R) {
             const double e0 = x0 - wr.x0, e1 = x1 - wr.x1, e2 = x2 - wr.x2;
-            double th = matern_f64_rt(p.two_nu, dist64(sqnorm3(e0, e1, e2)), cnu, s2);
+            double th = matern_f64_rt(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnu, s2);
             if (rid == wr.id) th += p.nugget;
             TA a;
             if constexpr (sizeof(TA) == 8) {
                 a = th;
             } else {
                 const float f0 = (float)e0, f1 = (float)e1, f2 = (float)e2;
-                a = matern_f32_rt(p.two_nu, sqrtf(sqnorm3(f0, f1, f2)), (float)cnu, (float)s2);
+                a = matern_f32_rt(p.two_nu, sqrt(sqnorm3(f0, f1, f2)), (float)cnu, (float)s2);
                 if (rid == wr.id) a += (float)p.nugget;
             }
             a = dot_down<TA>(a, slabA + r, rmax, rowA, t);
@@ -357,7 +359,7 @@ static hipError_t launch_coop(CoopArgs& ca, int cus, hipStream_t s) {
 // 2,112 rows run 3 workgroups of 1,024 threads each (6.5 ms for k = 128 on
 // MI355X, against 7.9 ms with 9 of 256), 8 such groups 9 of 256 (2.3 ms,
 // against 4.3 ms with 1,024).
-hipError_t launch_aggregated_coop(const AggArgs& a0, int precision, void* workspace, hipStream_t s) {
+hipError_t launch_aggregated_coop(const AggArgs& a0, int precision, int block_threads, void* workspace, hipStream_t s) {
     if (a0.n_groups == 0) return hipSuccess;
     // (the later-only check of factor-producing runs stays with the slab kernel)
     if (a0.k > kAggMaxSelectCoop || a0.max_members > kAggMaxMembersCoop || a0.later_only)
@@ -386,9 +388,10 @@ hipError_t launch_aggregated_coop(const AggArgs& a0, int precision, void* worksp
     e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
     if (e != hipSuccess) return e;
     if (!coop) return hipErrorCooperativeLaunchTooLarge;
-    const int nt = a0.n_groups * coop_split(rmax, 1024) >= cus / 2  ? 1024
-                   : a0.n_groups * coop_split(rmax, 512) >= cus / 2 ? 512
-                                                                     : 256;
+    const int nt = block_threads == 256 || block_threads == 512 || block_threads == 1024 ? block_threads
+                   : a0.n_groups * coop_split(rmax, 1024) >= cus / 2                    ? 1024
+                   : a0.n_groups * coop_split(rmax, 512) >= cus / 2                     ? 512
+                                                                                         : 256;
     if (precision == 0)
         return nt == 1024 ? launch_coop<double, 1024>(ca, cus, s)
                : nt == 512 ? launch_coop<double, 512>(ca, cus, s)

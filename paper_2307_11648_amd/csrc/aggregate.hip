@@ -172,7 +172,7 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                 const int r = i * NT + tid;
                 if (r < R) {
                     const TB e0 = (TB)(x0[i] - y0), e1 = (TB)(x1[i] - y1), e2 = (TB)(x2[i] - y2);
-                    TB acc = matern_any<TB>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnuB, s2B);
+                    TB acc = matern_any<TB>(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnuB, s2B);
                     if (rid[i] == idw) acc += (TB)p.nugget;
                     for (int q = 0; q < c; ++q) acc -= slabB[(int64_t)q * rmax + r] * rowB[q];
                     const TB u = acc * inv_sd_t;
@@ -240,14 +240,14 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                 const int r = i * NT + tid;
                 if (r < R) {
                     const TB e0 = (TB)(x0[i] - y0), e1 = (TB)(x1[i] - y1), e2 = (TB)(x2[i] - y2);
-                    TB thb = matern_any<TB>(p.two_nu, sqrt(e0 * e0 + e1 * e1 + e2 * e2), cnuB, s2B);
+                    TB thb = matern_any<TB>(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnuB, s2B);
                     if (rid[i] == idw) thb += (TB)p.nugget;
                     TA tha;
                     if constexpr (sizeof(TA) == sizeof(TB)) {
                         tha = thb;
                     } else {
                         const TA f0 = (TA)(x0[i] - y0), f1 = (TA)(x1[i] - y1), f2 = (TA)(x2[i] - y2);
-                        tha = matern_any<TA>(p.two_nu, sqrt(f0 * f0 + f1 * f1 + f2 * f2), cnuA, s2A);
+                        tha = matern_any<TA>(p.two_nu, sqrt(sqnorm3(f0, f1, f2)), cnuA, s2A);
                         if (rid[i] == idw) tha += (TA)p.nugget;
                     }
                     TA a = tha;
@@ -793,7 +793,7 @@ AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, i
     pl.slots = (int)std::min<int64_t>(n_groups, 1024);
     if (pl.slots < 1) pl.slots = 1;
     pl.ws_bytes = pl.slab_bytes * pl.slots;
-    if (agg_coop_applies(n_groups, stride, max_members, k, precision))
+    if (agg_split_possible(n_groups, max_members, k))
         pl.ws_bytes = std::max<int64_t>(pl.ws_bytes, agg_coop_workspace(n_groups, stride, max_members, k));
     pl.smem = sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double) + ((size_t)k + max_members) * 8 + (size_t)k * elemA;
     return pl;
@@ -821,15 +821,28 @@ bool agg_coop_applies(int64_t n_groups, int32_t stride, int32_t max_members, int
 
 // the register-resident kernel applies to mixed precision without posterior
 // variances, pools <= 512, groups <= 32 and k <= 64
+bool agg_split_possible(int64_t n_groups, int32_t max_members, int32_t k) {
+    return n_groups > 0 && n_groups <= 1024 && k <= 256 && max_members <= 128;
+}
+
 bool agg_reg_applies(int32_t stride, int32_t max_members, int32_t k, int precision, bool want_post_var) {
     return precision != 0 && !want_post_var && stride <= kAggRegThreads && max_members <= kAggRegMaxM && k <= 64;
 }
 
-hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s) {
+hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, int schedule,
+                             hipStream_t s) {
     if (a.n_groups == 0) return hipSuccess;
     hipError_t e;
     const unsigned grid = (unsigned)pl.slots;
-    if (agg_reg_applies(a.stride, a.max_members, a.k, precision, a.post_var != nullptr)) {
+    const bool reg_ok = agg_reg_applies(a.stride, a.max_members, a.k, precision, a.post_var != nullptr);
+    if (schedule == kAggRegister && !reg_ok) return hipErrorNotSupported;
+    if (schedule >= kAggSplit256) {
+        // explicit split rows: selection only, within the workspace's reach
+        if (want_factor || !agg_split_possible(a.n_groups, a.max_members, a.k)) return hipErrorNotSupported;
+        const int nt = schedule == kAggSplit256 ? 256 : schedule == kAggSplit512 ? 512 : 1024;
+        return launch_aggregated_coop(a, precision, nt, a.ws, s);
+    }
+    if (reg_ok && (schedule == kAggAuto || schedule == kAggRegister)) {
         const bool gap = a.gap != nullptr;
         e = a.k <= 16 ? (gap ? launch_reg<16, true>(a, s) : launch_reg<16, false>(a, s))
             : a.k <= 32 ? (gap ? launch_reg<32, true>(a, s) : launch_reg<32, false>(a, s))
@@ -841,8 +854,8 @@ hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision,
         }
         return e;
     }
-    if (agg_coop_applies(a.n_groups, a.stride, a.max_members, a.k, precision)) {
-        e = launch_aggregated_coop(a, precision, a.ws, s);
+    if (schedule == kAggAuto && agg_coop_applies(a.n_groups, a.stride, a.max_members, a.k, precision)) {
+        e = launch_aggregated_coop(a, precision, 0, a.ws, s);
         if (e == hipSuccess) {
             if (want_factor) {
                 hipLaunchKernelGGL(agg_factor_kernel, dim3((unsigned)a.n_groups), dim3(kAggFacThreads), 0, s, a);

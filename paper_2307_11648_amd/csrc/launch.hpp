@@ -165,7 +165,10 @@ struct AggPlan {
 };
 
 AggPlan plan_aggregated(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision);
-hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, hipStream_t s);
+// schedules of the multi-target selection (kAggAuto: the library's rule)
+enum AggSchedule { kAggAuto = 0, kAggOneGroup = 1, kAggRegister = 2, kAggSplit256 = 3, kAggSplit512 = 4, kAggSplit1024 = 5 };
+hipError_t launch_aggregated(const AggArgs& a, const AggPlan& pl, int precision, bool want_factor, int schedule,
+                             hipStream_t s);
 int agg_factor_max_m();
 // reverse-maximin ordering (Sec. 2.2, eq. maximin, p = 1); blocks until done
 int64_t reverse_maximin_workspace(int64_t n, int dim);
@@ -176,8 +179,12 @@ hipError_t launch_reverse_maximin(const double* pts, int64_t n, int dim, void* w
 // (cooperative launch; factor A in FP64 or, mixed, FP32);
 // hipErrorCooperativeLaunchTooLarge when the grid cannot be resident at once
 int64_t agg_coop_workspace(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k);
-hipError_t launch_aggregated_coop(const AggArgs& a, int precision, void* workspace, hipStream_t s);
+// (block_threads 256, 512 or 1024; 0 picks by the group count)
+hipError_t launch_aggregated_coop(const AggArgs& a, int precision, int block_threads, void* workspace, hipStream_t s);
 bool agg_coop_applies(int64_t n_groups, int32_t stride, int32_t max_members, int32_t k, int precision);
+// the workspace also holds the split-row schedule
+bool agg_split_possible(int64_t n_groups, int32_t max_members, int32_t k);
+bool agg_reg_applies(int32_t stride, int32_t max_members, int32_t k, int precision, bool want_post_var);
 
 // the aggregated member columns (eq. L_col on s_q = {j in sort(T u S) : j >= q})
 hipError_t launch_agg_factor(const AggArgs& a, hipStream_t s);

@@ -95,3 +95,20 @@ def test_four_schedules_fastest_wins_and_ties_go_to_the_earlier():
     g = _Fake({"natural": 10.0, "spatial": 12.0, "natural/mw": 10.0, "spatial/mw": 11.0})
     assert t.choose("n", g.runners()) == "natural"
     assert set(autotune.SCHEDULES) == {"natural", "spatial", "natural/mw", "spatial/mw"}
+
+
+def test_aggregated_shape_key_and_schedules(tmp_path):
+    """Multi-target shape classes round the group count and the rows per group
+    (pool + members) up to powers of two; the aggregated schedule names
+    survive the JSON cache, and the fastest of them wins."""
+    k1 = autotune.agg_shape_key(2, 5, 64, 2048, 64, 128, "fp64", True)
+    assert k1 == "agg/d2/nu5/G2^6/rows2^12/m64/k128/fp64/pv1"
+    assert autotune.agg_shape_key(2, 5, 60, 2000, 64, 128, "fp64", True) == k1
+    assert autotune.agg_shape_key(2, 5, 65, 2048, 64, 128, "fp64", True) != k1
+    assert autotune.agg_shape_key(2, 5, 64, 2048, 64, 128, "mixed", False) != k1
+    path = str(tmp_path / "tune.json")
+    f = _Fake({"one_group": 30.0, "split256": 8.0, "split512": 7.0, "split1024": 7.0})
+    t = autotune.SelectTuner(path=path, timer=f.timer)
+    assert t.choose(k1, f.runners()) == "split512"  # a tie goes to the earlier schedule
+    t2 = autotune.SelectTuner(path=path, timer=f.timer)
+    assert t2.choices[k1]["schedule"] == "split512"

@@ -181,13 +181,12 @@ def test_gp_split_rows_match_one_workgroup_per_group():
     """FP64 runs with at most 128 groups and more than 256 rows a group split
     each group's rows over several workgroups (cooperative launch; 1,024,
     512 or 256 threads a workgroup depending on how many groups share the
-    chip); larger runs give each group one workgroup.  Groups are
-    independent, so the first H groups run alone must reproduce what the full
-    run of 144 gives them: picks up to the first top-two gap below 1e-9, log
-    det and posterior variances to 1e-10 relative.  H = 64, 50 and 20 take
-    the three block sizes (groups of 1,040 rows on 256 CUs).  The set
-    includes an out-of-range pool id (status 3), an empty pool and a pool
-    shorter than k."""
+    chip); larger runs give each group one workgroup.  Both round alike and
+    groups are independent, so the first H groups run alone reproduce what
+    the full run of 144 gives them bit for bit: picks, gaps, log det and
+    posterior variances.  H = 64, 50 and 20 take the three block sizes
+    (groups of 1,040 rows on 256 CUs).  The set includes an out-of-range pool
+    id (status 3), an empty pool and a pool shorter than k."""
     print("case: gp split rows n_train=30000 G=144 m=16 C=1024 k=48 fp64", flush=True)
     w = inputs.workload_gp(n_train=30000, n_pred=2304, C=1024, k=48, n_strips=12, per_strip=12)
     G = len(w.group_ptr) - 1
@@ -211,20 +210,59 @@ def test_gp_split_rows_match_one_workgroup_per_group():
         assert np.all(part["sel"][3] == -1) and np.isnan(part["logdet"][3])
         assert np.all(part["sel"][5] == -1) and part["status"][5] == 0
         assert np.sum(part["sel"][6] >= 0) == 10
-        same = 0
+        np.testing.assert_array_equal(part["sel"], full["sel"][:H])
+        np.testing.assert_array_equal(part["gap"], full["gap"][:H])
+        np.testing.assert_array_equal(part["logdet"], full["logdet"][:H])
+        # (a status-3 group's posterior variances are left unwritten)
         for gi in range(H):
-            if full["status"][gi] >= 2:
-                continue
-            p = decisive_prefix(full["gap"][gi], 1e-9)
-            assert np.array_equal(part["sel"][gi, :p], full["sel"][gi, :p]), gi
-            if not np.array_equal(part["sel"][gi], full["sel"][gi]):
-                continue
-            same += 1
-            assert part["logdet"][gi] == pytest.approx(full["logdet"][gi], rel=1e-10, abs=1e-10)
-            b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
-            np.testing.assert_allclose(part["post_var"][b:e], full["post_var"][b:e], rtol=1e-10, atol=1e-14)
-        print(f"{same} of {H} groups identical", flush=True)
-        assert same >= H - 2
+            if full["status"][gi] < 2:
+                b, e = w.group_ptr[gi], w.group_ptr[gi + 1]
+                np.testing.assert_array_equal(part["post_var"][b:e], full["post_var"][b:e])
+
+
+def test_explicit_schedules_are_bit_identical():
+    """csel_aggregated_select_sched: one workgroup per group and the three
+    split-row block sizes give the same bits (FP64 with posterior variances
+    and gaps; mixed without); the tuner picks one of them and its result is
+    the same again.  Schedules outside their range are refused."""
+    from paper_2307_11648_amd import autotune
+
+    print("case: explicit schedules gp n_train=20000 G=16 m=64 C=1024 k=64", flush=True)
+    w = inputs.workload_gp(n_train=20000, n_pred=1024, C=1024, k=64, n_strips=4, per_strip=4)
+    dev = dict(pts=_t(w.points, torch.float64), gp=_t(w.group_ptr, torch.int32), mem=_t(w.members, torch.int32),
+               pl=_t(w.pool, torch.int32), ln=_t(w.pool_len, torch.int32))
+    mm = int(np.max(np.diff(w.group_ptr)))
+
+    def run(precision, schedule, post_var):
+        o = csel.aggregated_select(dev["pts"], w.kernel, dev["gp"], dev["mem"], mm, dev["pl"], dev["ln"], w.k,
+                                   precision, want_post_var=post_var, want_gap=True, schedule=schedule)
+        torch.cuda.synchronize()
+        return {key: v.cpu().numpy() for key, v in o.items() if key != "workspace"}
+
+    for precision, post_var in (("fp64", True), ("mixed", False)):
+        ref = run(precision, "one_group", post_var)
+        assert np.all(ref["status"] == 0)
+        for schedule in ("split256", "split512", "split1024", "auto"):
+            got = run(precision, schedule, post_var)
+            for key in ref:
+                np.testing.assert_array_equal(got[key], ref[key], err_msg=f"{precision} {schedule} {key}")
+        print(f"{precision}: one_group, split256/512/1024 and auto identical", flush=True)
+    tuner = autotune.SelectTuner()
+    t = tuner.aggregated_select(dev["pts"], w.kernel, dev["gp"], dev["mem"], mm, dev["pl"], dev["ln"], w.k, "fp64",
+                                want_post_var=True, want_gap=True)
+    torch.cuda.synchronize()
+    (key, choice), = tuner.choices.items()
+    print("tuned", key, choice, flush=True)
+    assert choice["schedule"] in autotune.AGG_SCHEDULES
+    ref = run("fp64", "one_group", True)
+    for k_ in ref:
+        np.testing.assert_array_equal(t[k_].cpu().numpy(), ref[k_])
+    # out of range: the register kernel with posterior variances; a split with factor output
+    with pytest.raises(csel.CselError):
+        run("mixed", "register", True)
+    with pytest.raises(csel.CselError):
+        csel.aggregated_select(dev["pts"], w.kernel, dev["gp"], dev["mem"], mm, dev["pl"], dev["ln"], w.k, "fp64",
+                               want_factor=True, schedule="split256")
 
 
 def test_gp_mixed_selection_runs_to_k():
