@@ -174,14 +174,22 @@ def bench_groups(args):
     gp_t, mem_t = t(w.group_ptr, torch.int32), t(w.members, torch.int32)
     pl, ln = t(w.pool, torch.int32), t(w.pool_len, torch.int32)
     mm = int(np.max(np.diff(w.group_ptr)))
-    out = csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, args.precision,
-                                 want_factor=want_factor, want_post_var=want_post_var)
+    # the schedule the tuner picks for this shape class (set-up: each candidate
+    # schedule timed once)
+    from paper_2307_11648_amd import autotune
+
+    tuner = autotune.SelectTuner()
+    out = tuner.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, args.precision,
+                                  want_factor=want_factor, want_post_var=want_post_var)
     torch.cuda.synchronize()
     ws = out["workspace"]
+    tuned = next(iter(tuner.choices.values()), None)
+    sched = tuned["schedule"] if tuned else "auto"
 
     def step():
         csel.aggregated_select(pts, w.kernel, gp_t, mem_t, mm, pl, ln, k, args.precision,
-                               want_factor=want_factor, want_post_var=want_post_var, out=out, workspace=ws)
+                               want_factor=want_factor, want_post_var=want_post_var, out=out, workspace=ws,
+                               schedule=sched)
 
     for _ in range(args.warmup):
         step()
@@ -198,19 +206,23 @@ def bench_groups(args):
     flops, byt = group_work(w.group_ptr, w.pool_len, k, w.points.shape[1], w.kernel.two_nu, want_factor)
     achieved = float(np.sum(flops)) / (ms * 1e-3) / 1e12
     st = out["status"].cpu().numpy()
-    # runs of at most 128 groups past 256 rows (without member columns, and
-    # outside the mixed register kernel's range) split each group's rows over
-    # several workgroups
+    # the kernel the chosen schedule runs
     reg = args.precision == "mixed" and not want_post_var and w.pool.shape[1] <= 512 and mm <= 32 and k <= 64
-    coop = (not want_factor and not reg and len(w.group_ptr) - 1 <= 128 and w.pool.shape[1] + mm > 256)
-    sel_kernel = ("agg_select_coop_kernel" if coop else "agg_select_kernel") + (" (+ agg_factor_kernel)"
-                                                                                   if want_factor else "")
+    if sched.startswith("split"):
+        coop = True
+    elif sched == "one_group":
+        coop = False
+    else:  # the library's rule
+        coop = (not want_factor and not reg and len(w.group_ptr) - 1 <= 128 and w.pool.shape[1] + mm > 256)
+    sel_kernel = ("agg_select_coop_kernel" if coop else "agg_select_reg_kernel" if reg else "agg_select_kernel") + (
+        " (+ agg_factor_kernel)" if want_factor else "")
     res = {
         "metric": METRIC, "value": cols / (ms * 1e-3), "unit": "columns/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
         "dtype": "f32+f64" if args.precision == "mixed" else "f64", "data": "synthetic",
         "config": {"workload": desc, "groups": len(w.group_ptr) - 1, "columns": cols, "k": k,
-                   "status_counts": {int(v): int((st == v).sum()) for v in np.unique(st)}},
+                   "status_counts": {int(v): int((st == v).sum()) for v in np.unique(st)},
+                   "schedule": sched, "schedule_tuning_ms": tuned["ms"] if tuned else None},
         "roofline": {"bound": "alu", "kernel": sel_kernel, "achieved": achieved,
                      "peak": PEAK_ALU_TFLOPS, "unit": "TFLOP/s", "frac": achieved / PEAK_ALU_TFLOPS,
                      "traffic": None, "kernel_ms": ms,

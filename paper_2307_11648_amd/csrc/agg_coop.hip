@@ -90,24 +90,6 @@ __device__ __forceinline__ void group_barrier(uint32_t* gs, uint32_t target, boo
     __syncthreads();
 }
 
-// acc - sum_{q < n} col[q * ld] * row[q], the fused multiply-adds in q order;
-// the strided column entries are loaded sixteen at a time, so that sixteen
-// global loads are in flight before the first is used
-template <typename T>
-__device__ __forceinline__ T dot_down(T acc, const T* __restrict__ col, int64_t ld, const T* row, int n) {
-    constexpr int U = 16;
-    int q = 0;
-    for (; q + U <= n; q += U) {
-        T v[U];
-#pragma unroll
-        for (int j = 0; j < U; ++j) v[j] = col[(int64_t)(q + j) * ld];
-#pragma unroll
-        for (int j = 0; j < U; ++j) acc = fma(-v[j], row[q + j], acc);
-    }
-    for (; q < n; ++q) acc = fma(-col[(int64_t)q * ld], row[q], acc);
-    return acc;
-}
-
 __device__ __forceinline__ float matern_f32_rt(int two_nu, float r, float c, float s2) {
     if (two_nu == 1) return matern_f32<1>(r, c, s2);
     if (two_nu == 3) return matern_f32<3>(r, c, s2);

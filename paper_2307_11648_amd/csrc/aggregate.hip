@@ -53,6 +53,9 @@ constexpr int kAggMaxWaves = 16;
 // evaluation resolves, while var1 stays large.
 template <typename TA, typename TB, int RPT>
 __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
+    // slab entries in flight per row in the left-looking updates: eight with one
+    // row per thread; with 2-4 rows per thread the registers are already short
+    constexpr int kUD = RPT == 1 ? 8 : 1;
     extern __shared__ __align__(16) unsigned char agg_smem[];
     // LDS layout: wave top-two [16], winner scalars, winner B row [mmax+k], A row [k]
     Top2* wtop = reinterpret_cast<Top2*>(agg_smem);
@@ -174,7 +177,7 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     const TB e0 = (TB)(x0[i] - y0), e1 = (TB)(x1[i] - y1), e2 = (TB)(x2[i] - y2);
                     TB acc = matern_any<TB>(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnuB, s2B);
                     if (rid[i] == idw) acc += (TB)p.nugget;
-                    for (int q = 0; q < c; ++q) acc -= slabB[(int64_t)q * rmax + r] * rowB[q];
+                    acc = dot_down<TB, kUD>(acc, slabB + r, rmax, rowB, c);
                     const TB u = acc * inv_sd_t;
                     slabB[(int64_t)c * rmax + r] = u;
                     const double ud = (double)u;
@@ -252,8 +255,8 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     }
                     TA a = tha;
                     TB bb = thb;
-                    for (int q = 0; q < t; ++q) a -= slabA[(int64_t)q * rmax + r] * rowA[q];
-                    for (int q = 0; q < m + t; ++q) bb -= slabB[(int64_t)q * rmax + r] * rowB[q];
+                    a = dot_down<TA, kUD>(a, slabA + r, rmax, rowA, t);
+                    bb = dot_down<TB, kUD>(bb, slabB + r, rmax, rowB, m + t);
                     const TA u1 = a * inv1;
                     const TB u2 = bb * inv2;
                     slabA[(int64_t)t * rmax + r] = u1;

@@ -319,6 +319,24 @@ __device__ __forceinline__ T sqnorm3(T e0, T e1, T e2) {
     return fma(e2, e2, fma(e1, e1, e0 * e0));
 }
 
+// acc - sum_{q < n} col[q * ld] * row[q], the fused multiply-adds in q order;
+// the strided column entries are loaded U at a time, so that U global loads
+// are in flight before the first is used (the multi-target
+// kernels' left-looking updates of a row from a column-major slab)
+template <typename T, int U = 16>
+__device__ __forceinline__ T dot_down(T acc, const T* __restrict__ col, int64_t ld, const T* row, int n) {
+    int q = 0;
+    for (; q + U <= n; q += U) {
+        T v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = col[(int64_t)(q + j) * ld];
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc = fma(-v[j], row[q + j], acc);
+    }
+    for (; q < n; ++q) acc = fma(-col[(int64_t)q * ld], row[q], acc);
+    return acc;
+}
+
 __device__ __forceinline__ double matern_f64_rt(int two_nu, double r, double c, double s2) {
     if (two_nu == 1) return matern_f64<1>(r, c, s2);
     if (two_nu == 3) return matern_f64<3>(r, c, s2);
