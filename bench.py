@@ -730,11 +730,8 @@ def _source_digest(*names):
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.0, in bytes; medians of
     # the launches of the default run (learned-screened workload, N = 1e6)
-    ("select_factor_kernel<double> (kept pools)", "spatial", "934c0e6346adbc2b"): (543896 * 1.9999 + 471925) * 1024,
-    ("screen_kernel", "spatial", "4730514d6a132cd8"): (2632670 * 1.9999 + 567916) * 1024,
-    # plain batched workload (N = 1e5, pools of 256): the mean of the timed launches
-    ("select_factor_kernel (plain batched)", "natural", "b927a454ec063414"): (63143 * 1.9999 + 39844) * 1024,
-    ("select_factor_kernel (plain batched)", "spatial", "b927a454ec063414"): (73595 * 1.9999 + 47877) * 1024,
+    ("select_factor_kernel<double> (kept pools)", "spatial", "c547143e34c255c5"): (540694 * 1.9999 + 471892) * 1024,
+    ("screen_kernel", "spatial", "0c719cb28005bc33"): (2639772 * 1.9999 + 567911) * 1024,
 }
 
 
