@@ -585,26 +585,42 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
     if (tid == 0) sh_first = nv;
     // the first point that an earlier one lies closer to than sqrt(D).  Two
     // such points lie within sqrt(D_0) (the largest D) of each other, so the
-    // candidates are hashed by cells of that width and each one checks the
-    // earlier candidates of its own and the neighbouring cells only; a
-    // conflict found bounds the first one, and larger indices stop early.
+    // candidates are hashed by cells twice that wide: the ball around a
+    // candidate reaches only the neighbour cell on the near side of each
+    // dimension, 2^dim cells in all.  Each candidate checks the earlier
+    // candidates of those cells; a conflict found bounds the first one, and
+    // larger indices stop early.  The widths carry a 1e-5 margin, so a cell
+    // coordinate t may err by up to 5e-6; past 2^30 cell widths across the box
+    // its rounding could exceed that, and every candidate shares one bucket
+    // instead.
     const double D0 = __longlong_as_double((long long)sk[0]);
     if (nv > 1 && D0 > 0.0) {
-        const double inv_w = 1.0 / (sqrt(D0) * (1.0 + 1e-9));
+        const double inv_w = 1.0 / (2.0 * sqrt(D0) * (1.0 + 1e-5));  // room for the rounding of t below
         const double* lo = a.prm + a.nlev * 6;
+        double ext = 0.0;
+        for (int k = 0; k < dim; ++k) ext = fmax(ext, a.prm[k * 2 + 1]);  // level 0: h = the extent
+        const bool one_bucket = ext * inv_w > 1073741824.0;
         for (int b = tid; b <= kMmHash; b += kMmRoundThreads) hcnt[b] = 0;
         for (int b = tid; b < kMmHash; b += kMmRoundThreads) hfill[b] = 0;
         __syncthreads();
-        // (clamped, so that a tiny width cannot overflow the conversion)
-        auto cell_of = [&](const double* x, int k) -> int64_t {
-            return k < dim ? (int64_t)fmin(fmax(floor((x[k] - lo[k]) * inv_w), -4e18), 4e18) : 0;
+        // cell coordinate of x along k, and the side (-1 or +1) of its nearer neighbour cell
+        auto cell_of = [&](const double* x, int k, int* side) -> int64_t {
+            if (k >= dim || one_bucket) {
+                if (side) *side = 0;
+                return 0;
+            }
+            const double t = (x[k] - lo[k]) * inv_w;
+            const double c = floor(t);
+            if (side) *side = t - c < 0.5 ? -1 : 1;
+            return (int64_t)c;
         };
         auto bucket = [&](int64_t c0, int64_t c1, int64_t c2) -> int {
             const uint32_t h = (uint32_t)c0 * 73856093u ^ (uint32_t)c1 * 19349663u ^ (uint32_t)c2 * 83492791u;
             return (int)(h & (kMmHash - 1));
         };
         for (int t = tid; t < nv; t += kMmRoundThreads)
-            atomicAdd(&hcnt[bucket(cell_of(sx + t * 3, 0), cell_of(sx + t * 3, 1), cell_of(sx + t * 3, 2))], 1);
+            atomicAdd(&hcnt[bucket(cell_of(sx + t * 3, 0, nullptr), cell_of(sx + t * 3, 1, nullptr),
+                                   cell_of(sx + t * 3, 2, nullptr))], 1);
         __syncthreads();
         // exclusive scan of the kMmHash counts (kMmHash / 1024 per thread)
         constexpr int PER = kMmHash / kMmRoundThreads;
@@ -639,7 +655,8 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
         if (tid == 0) hcnt[kMmHash] = nv;
         __syncthreads();
         for (int t = tid; t < nv; t += kMmRoundThreads) {
-            const int b = bucket(cell_of(sx + t * 3, 0), cell_of(sx + t * 3, 1), cell_of(sx + t * 3, 2));
+            const int b = bucket(cell_of(sx + t * 3, 0, nullptr), cell_of(sx + t * 3, 1, nullptr),
+                                 cell_of(sx + t * 3, 2, nullptr));
             hidx[atomicAdd(&hfill[b], 1) + hcnt[b]] = t;
         }
         __syncthreads();
@@ -647,20 +664,20 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
             if (__hip_atomic_load(&sh_first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i) break;
             const double Di = __longlong_as_double((long long)sk[i]);
             const double* q = sx + i * 3;
-            const int64_t c0 = cell_of(q, 0), c1 = cell_of(q, 1), c2 = cell_of(q, 2);
+            int s0, s1, s2;
+            const int64_t c0 = cell_of(q, 0, &s0), c1 = cell_of(q, 1, &s1), c2 = cell_of(q, 2, &s2);
             bool conf = false;
-            for (int d2i = (dim > 2 ? -1 : 0); d2i <= (dim > 2 ? 1 : 0) && !conf; ++d2i)
-                for (int d1i = (dim > 1 ? -1 : 0); d1i <= (dim > 1 ? 1 : 0) && !conf; ++d1i)
-                    for (int d0i = -1; d0i <= 1 && !conf; ++d0i) {
-                        const int b = bucket(c0 + d0i, c1 + d1i, c2 + d2i);
-                        for (int e = hcnt[b]; e < hcnt[b + 1] && !conf; ++e) {
-                            const int h = hidx[e];
-                            if (h < i) conf = mm_d2(sx + h * 3, q, dim) < Di;
-                            if ((e & 31) == 31 &&
-                                __hip_atomic_load(&sh_first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i)
-                                break;
-                        }
-                    }
+            const int ncell = one_bucket ? 1 : 1 << dim;
+            for (int cm = 0; cm < ncell && !conf; ++cm) {
+                const int b = bucket(c0 + ((cm & 1) ? s0 : 0), c1 + ((cm & 2) ? s1 : 0), c2 + ((cm & 4) ? s2 : 0));
+                for (int e = hcnt[b]; e < hcnt[b + 1] && !conf; ++e) {
+                    const int h = hidx[e];
+                    if (h < i) conf = mm_d2(sx + h * 3, q, dim) < Di;
+                    if ((e & 31) == 31 &&
+                        __hip_atomic_load(&sh_first, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <= i)
+                        break;
+                }
+            }
             if (conf) atomicMin(&sh_first, i);
         }
     }
@@ -715,7 +732,7 @@ __global__ __launch_bounds__(256) void mm_update_kernel(MmArgs a) {
         double q[3] = {0.0, 0.0, 0.0};
         for (int k = 0; k < dim; ++k) q[k] = a.pts[(int64_t)p * dim + k];
         // every point with d2 < D_j <= D_p lies within rho (with room for rounding)
-        const double rho = sqrt(__longlong_as_double((long long)Dp)) * (1.0 + 1e-9);
+        const double rho = sqrt(__longlong_as_double((long long)Dp)) * (1.0 + 1e-6);
         int l = a.nlev - 1;
         while (l > 0 && hmin[l] < rho) --l;
         const MmLevel L = a.lev[l];

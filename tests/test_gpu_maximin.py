@@ -52,6 +52,18 @@ def test_exact_ties():
     _check(np.stack([np.arange(64.0), np.zeros(64)], axis=1), "points on a line in 2-D")
 
 
+def test_near_duplicates():
+    """Points with twins and triplets 1e-13 apart: at the end the largest
+    remaining distance is ~1e-13 against a box of width ~1, more cell widths
+    than the round's conflict grid resolves, so it falls back to one bucket."""
+    rng = np.random.default_rng(11)
+    base = rng.random((2000, 2))
+    twins = base[:300] + 1e-13 * rng.standard_normal((300, 2))
+    trip = base[:100] - 1e-13 * rng.standard_normal((100, 2))
+    x = np.concatenate([base, twins, trip])[rng.permutation(2400)]
+    _check(x, "near-duplicate twins and triplets")
+
+
 def test_tiny_inputs():
     for n in (1, 2, 3):
         _check(inputs.uniform_points(n, 2, 5), f"n={n}")
