@@ -72,7 +72,7 @@ struct MmState {
     int32_t done_gather;
     int32_t overflow;   // set if a gather ever exceeded the buffer (not expected)
     int32_t rounds;     // rounds that placed points
-    int32_t pad;
+    int32_t sorted;     // the buffer is in key order with its keys in bufD (a round wrote it)
 };
 
 struct MmArgs {
@@ -88,6 +88,7 @@ struct MmArgs {
     uint64_t* D;              // [n] bits of the squared distance to the placed points
     int32_t* pos_of;          // [n] position of a placed point, -1 while remaining
     int32_t* buf;             // [kMmCap] candidate ids
+    uint64_t* bufD;           // [kMmCap] their D bits when a round last wrote the buffer
     int32_t* acc;             // [kMmCap] points placed by the last round
     uint64_t* accD;           // [kMmCap] their D bits
     uint32_t* hist;           // [kMmBins]
@@ -446,6 +447,7 @@ __global__ __launch_bounds__(256) void mm_gather_kernel(MmArgs a) {
     if (!sh_last || tid != 0) return;
     __threadfence();
     st->done_gather = 0;
+    st->sorted = 0;
     st->phase = 0;
     st->lvl = 0;
     st->prefix = 0;
@@ -461,51 +463,10 @@ __device__ __forceinline__ bool mm_before(uint64_t da, uint32_t ia, uint64_t db,
     return da > db || (da == db && ia < ib);
 }
 
-__global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
-    extern __shared__ __align__(16) unsigned char mm_smem[];
-    uint64_t* sk = reinterpret_cast<uint64_t*>(mm_smem);               // [kMmCap] D bits
-    uint32_t* si = reinterpret_cast<uint32_t*>(sk + kMmCap);           // [kMmCap] ids (-1 pads)
-    double* sx = reinterpret_cast<double*>(si + kMmCap);               // [kMmCap][3]
-    int32_t* hcnt = reinterpret_cast<int32_t*>(sx + 3 * kMmCap);         // [kMmHash + 1] bucket starts
-    int32_t* hfill = hcnt + (kMmHash + 1);                               // [kMmHash] fill counters
-    int32_t* hidx = hfill + kMmHash;                                     // [kMmCap] candidates by bucket
-    int32_t* hsum = hidx + kMmCap;                                       // [1024] per-thread totals
-    __shared__ int sh_cnt, sh_first;
-    MmState* st = a.st;
-    const int tid = threadIdx.x;
-    const int lane = lane_id();
-    const int wave = tid / kWave;
-    constexpr int kWaves = kMmRoundThreads / kWave;
-    const int phase = st->phase, nb = st->nb, remaining = st->remaining;
-    const u128 theta = st->theta;
-    const int dim = a.dim;
-    __syncthreads();
-    if (tid == 0) st->naccept = 0;
-    if (phase != 0 || nb == 0 || remaining == 0) return;
-    if (tid == 0) sh_cnt = 0;
-    __syncthreads();
-    // the buffer's points still remaining and at or above theta
-    for (int t = tid; t < nb; t += kMmRoundThreads) {
-        const int32_t id = a.buf[t];
-        if (a.pos_of[id] >= 0) continue;
-        const uint64_t d = a.D[id];
-        if (mm_key(d, id) >= theta) {
-            const int s = atomicAdd(&sh_cnt, 1);
-            sk[s] = d;
-            si[s] = (uint32_t)id;
-        }
-    }
-    __syncthreads();
-    const int nv = sh_cnt;
-    int P = 1;
-    while (P < nv) P <<= 1;
-    for (int t = nv + tid; t < P; t += kMmRoundThreads) {
-        sk[t] = 0ull;
-        si[t] = 0xFFFFFFFFu;
-    }
-    __syncthreads();
-    // bitonic sort, descending key: element i = tid + 1024 k (k = 0, 1) in
-    // registers; partners within a wave by shuffles, across waves through LDS
+// bitonic sort of sk/si[0 .. P) (P a power of two <= 2048) by descending key,
+// by the whole workgroup: element i = tid + 1024 k (k = 0, 1) in registers;
+// partners within a wave by shuffles, across waves through LDS
+__device__ void mm_sort_desc(uint64_t* sk, uint32_t* si, int P, int tid) {
     uint64_t kd[2];
     uint32_t ki[2];
 #pragma unroll
@@ -580,6 +541,168 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
         }
     }
     __syncthreads();
+}
+
+__global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
+    extern __shared__ __align__(16) unsigned char mm_smem[];
+    uint64_t* sk = reinterpret_cast<uint64_t*>(mm_smem);               // [kMmCap] D bits
+    uint32_t* si = reinterpret_cast<uint32_t*>(sk + kMmCap);           // [kMmCap] ids (-1 pads)
+    double* sx = reinterpret_cast<double*>(si + kMmCap);               // [kMmCap][3]
+    int32_t* hcnt = reinterpret_cast<int32_t*>(sx + 3 * kMmCap);         // [kMmHash + 1] bucket starts
+    int32_t* hfill = hcnt + (kMmHash + 1);                               // [kMmHash] fill counters
+    int32_t* hidx = hfill + kMmHash;                                     // [kMmCap] candidates by bucket
+    int32_t* hsum = hidx + kMmCap;                                       // [1024] per-thread totals
+    __shared__ int sh_cnt, sh_first, sh_nu, sh_nc;
+    __shared__ int sh_tot[2 * (kMmRoundThreads / kWave)][2];
+    MmState* st = a.st;
+    const int tid = threadIdx.x;
+    const int lane = lane_id();
+    const int wave = tid / kWave;
+    constexpr int kWaves = kMmRoundThreads / kWave;
+    const int phase = st->phase, nb = st->nb, remaining = st->remaining;
+    const bool sorted = st->sorted != 0;
+    const u128 theta = st->theta;
+    const int dim = a.dim;
+    __syncthreads();
+    if (tid == 0) st->naccept = 0;
+    if (phase != 0 || nb == 0 || remaining == 0) return;
+    int nv;
+    if (!sorted) {
+        // a freshly gathered buffer: its valid points, then a full sort
+        if (tid == 0) sh_cnt = 0;
+        __syncthreads();
+        for (int t = tid; t < nb; t += kMmRoundThreads) {
+            const int32_t id = a.buf[t];
+            if (a.pos_of[id] >= 0) continue;
+            const uint64_t d = a.D[id];
+            if (mm_key(d, id) >= theta) {
+                const int s = atomicAdd(&sh_cnt, 1);
+                sk[s] = d;
+                si[s] = (uint32_t)id;
+            }
+        }
+        __syncthreads();
+        nv = sh_cnt;
+        int P = 1;
+        while (P < nv) P <<= 1;
+        for (int t = nv + tid; t < P; t += kMmRoundThreads) {
+            sk[t] = 0ull;
+            si[t] = 0xFFFFFFFFu;
+        }
+        __syncthreads();
+        mm_sort_desc(sk, si, P, tid);
+    } else {
+        // the buffer as the last round left it, in key order: the entries
+        // whose D is unchanged keep that order (a stable compaction); the
+        // few whose D the update lowered are sorted apart and merged in by
+        // binary-search ranks.  (sx is free until the coordinates load.)
+        uint64_t* uk = reinterpret_cast<uint64_t*>(sx);
+        uint32_t* ui = reinterpret_cast<uint32_t*>(uk + kMmCap);
+        uint64_t* ck = reinterpret_cast<uint64_t*>(ui + kMmCap);
+        uint32_t* ci = reinterpret_cast<uint32_t*>(ck + kMmCap);
+        bool fu[2], fc[2];
+        uint64_t dk[2];
+        uint32_t ik[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            const int t = tid + k * kMmRoundThreads;
+            fu[k] = fc[k] = false;
+            dk[k] = 0ull;
+            ik[k] = 0u;
+            if (t < nb) {
+                const int32_t id = a.buf[t];
+                if (a.pos_of[id] < 0) {
+                    const uint64_t d = a.D[id];
+                    if (mm_key(d, id) >= theta) {
+                        dk[k] = d;
+                        ik[k] = (uint32_t)id;
+                        fu[k] = d == a.bufD[t];
+                        fc[k] = !fu[k];
+                    }
+                }
+            }
+        }
+        // positions in buffer order (t = tid, then tid + 1024): per wave and
+        // half a prefix of ballots, then the 32 (half, wave) totals in order
+        const uint64_t below = lane == 0 ? 0ull : (~0ull >> (kWave - lane));
+        uint64_t bu[2], bcm[2];
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            bu[k] = __ballot(fu[k]);
+            bcm[k] = __ballot(fc[k]);
+            if (lane == 0) {
+                sh_tot[k * kWaves + wave][0] = __popcll(bu[k]);
+                sh_tot[k * kWaves + wave][1] = __popcll(bcm[k]);
+            }
+        }
+        __syncthreads();
+        if (tid == 0) {
+            int au = 0, ac = 0;
+            for (int q = 0; q < 2 * kWaves; ++q) {
+                const int tu = sh_tot[q][0], tc = sh_tot[q][1];
+                sh_tot[q][0] = au;
+                sh_tot[q][1] = ac;
+                au += tu;
+                ac += tc;
+            }
+            sh_nu = au;
+            sh_nc = ac;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < 2; ++k) {
+            if (fu[k]) {
+                const int at = sh_tot[k * kWaves + wave][0] + __popcll(bu[k] & below);
+                uk[at] = dk[k];
+                ui[at] = ik[k];
+            }
+            if (fc[k]) {
+                const int at = sh_tot[k * kWaves + wave][1] + __popcll(bcm[k] & below);
+                ck[at] = dk[k];
+                ci[at] = ik[k];
+            }
+        }
+        const int nu = sh_nu, nc = sh_nc;
+        nv = nu + nc;
+        if (nc > 0) {
+            int Pc = 1;
+            while (Pc < nc) Pc <<= 1;
+            for (int t = nc + tid; t < Pc; t += kMmRoundThreads) {
+                ck[t] = 0ull;
+                ci[t] = 0xFFFFFFFFu;
+            }
+            __syncthreads();
+            mm_sort_desc(ck, ci, Pc, tid);
+        } else {
+            __syncthreads();
+        }
+        // ranks: own index plus the entries of the other list that come first
+        for (int q = tid; q < nu; q += kMmRoundThreads) {
+            int lo2 = 0, hi2 = nc;  // first c not before u_q
+            while (lo2 < hi2) {
+                const int mid = (lo2 + hi2) >> 1;
+                if (mm_before(ck[mid], ci[mid], uk[q], ui[q]))
+                    lo2 = mid + 1;
+                else
+                    hi2 = mid;
+            }
+            sk[q + lo2] = uk[q];
+            si[q + lo2] = ui[q];
+        }
+        for (int q = tid; q < nc; q += kMmRoundThreads) {
+            int lo2 = 0, hi2 = nu;  // first u not before c_q
+            while (lo2 < hi2) {
+                const int mid = (lo2 + hi2) >> 1;
+                if (mm_before(uk[mid], ui[mid], ck[q], ci[q]))
+                    lo2 = mid + 1;
+                else
+                    hi2 = mid;
+            }
+            sk[q + lo2] = ck[q];
+            si[q + lo2] = ci[q];
+        }
+        __syncthreads();
+    }
     for (int t = tid; t < nv; t += kMmRoundThreads)
         for (int k = 0; k < 3; ++k) sx[t * 3 + k] = k < dim ? a.pts[(int64_t)si[t] * dim + k] : 0.0;
     if (tid == 0) sh_first = nv;
@@ -694,13 +817,17 @@ __global__ __launch_bounds__(kMmRoundThreads) void mm_round_kernel(MmArgs a) {
         a.acc[i] = id;
         a.accD[i] = sk[i];
     }
-    for (int i = r + tid; i < nv; i += kMmRoundThreads) a.buf[i - r] = (int32_t)si[i];
+    for (int i = r + tid; i < nv; i += kMmRoundThreads) {
+        a.buf[i - r] = (int32_t)si[i];
+        a.bufD[i - r] = sk[i];
+    }
     __syncthreads();
     if (tid == 0) {
         st->naccept = r;
         st->pos_next = pos0 - r;
         st->remaining = remaining - r;
         st->nb = nv - r;
+        st->sorted = 1;
         if (r > 0) st->rounds += 1;
         if (nv - r == 0 && remaining - r > 0) {
             st->phase = 1;
@@ -806,7 +933,7 @@ struct MmLayout {
     int nlev;
     MmLevel lev[kMmMaxLevels];
     int64_t total_cells, max_cells;
-    size_t off_bb, off_prm, off_cs, off_fill, off_ids, off_xyz, off_D, off_pos, off_buf, off_acc, off_accD,
+    size_t off_bb, off_prm, off_cs, off_fill, off_ids, off_xyz, off_D, off_pos, off_buf, off_bufD, off_acc, off_accD,
         off_hist, off_st, off_scan;
     size_t scan_bytes, bytes;
 };
@@ -833,6 +960,7 @@ static bool mm_layout(int64_t n, int dim, MmLayout& y) {
     y.off_D = o; o += mm_align((size_t)n * 8);
     y.off_pos = o; o += mm_align((size_t)n * 4);
     y.off_buf = o; o += mm_align((size_t)kMmCap * 4);
+    y.off_bufD = o; o += mm_align((size_t)kMmCap * 8);
     y.off_acc = o; o += mm_align((size_t)kMmCap * 4);
     y.off_accD = o; o += mm_align((size_t)kMmCap * 8);
     y.off_hist = o; o += mm_align((size_t)kMmBins * 4);
@@ -872,6 +1000,7 @@ hipError_t launch_reverse_maximin(const double* pts, int64_t n, int dim, void* w
     a.D = reinterpret_cast<uint64_t*>(w + y.off_D);
     a.pos_of = reinterpret_cast<int32_t*>(w + y.off_pos);
     a.buf = reinterpret_cast<int32_t*>(w + y.off_buf);
+    a.bufD = reinterpret_cast<uint64_t*>(w + y.off_bufD);
     a.acc = reinterpret_cast<int32_t*>(w + y.off_acc);
     a.accD = reinterpret_cast<uint64_t*>(w + y.off_accD);
     a.hist = reinterpret_cast<uint32_t*>(w + y.off_hist);
