@@ -47,6 +47,7 @@ constexpr int kMmLastDigit = 8;         // digits 0..8 cover the 95 significant 
 constexpr int kMmMaxLevels = 25;
 constexpr int kMmStepsPerBatch = 32;    // rounds launched between two reads of the progress counter
 constexpr int kMmGridBlocks = 512;      // grid-stride kernels over all points
+constexpr int kMmLoadBatch = 8;         // points per thread whose loads a refill pass issues together
 constexpr int kMmHash = 4096;           // buckets of the round's conflict grid
 constexpr int kMmPassesPerStep = 2;     // histogram passes launched per round (a refill usually needs two)
 
@@ -350,6 +351,24 @@ __global__ __launch_bounds__(256) void mm_init_kernel(MmArgs a) {
 // refill: one histogram pass of the radix descent; the last workgroup to
 // finish reads the histogram and either fixes theta or descends one digit
 // ---------------------------------------------------------------------------
+// h[dig] += 1 for the active lanes of a wave (called by every lane): lanes
+// sharing a digit add once through their first lane (up to four distinct
+// digits), the rest one by one -- the first digits of the keys are mostly
+// equal, and thousands of increments of one LDS word would serialize
+__device__ __forceinline__ void mm_hist_add(uint32_t* h, int dig, bool act) {
+    const int lane = lane_id();
+    uint64_t pending = __ballot(act);
+    for (int it = 0; it < 4 && pending; ++it) {
+        const int leader = (int)__builtin_ctzll(pending);
+        const int dl = __shfl(dig, leader, kWave);
+        const uint64_t m = __ballot(act && dig == dl) & pending;
+        if (lane == leader) atomicAdd(&h[dl], (uint32_t)__popcll(m));
+        if ((m >> lane) & 1ull) act = false;
+        pending &= ~m;
+    }
+    if (act) atomicAdd(&h[dig], 1u);
+}
+
 __global__ __launch_bounds__(256) void mm_hist_kernel(MmArgs a) {
     __shared__ uint32_t h[kMmBins];
     __shared__ uint32_t tsum[256];
@@ -361,10 +380,25 @@ __global__ __launch_bounds__(256) void mm_hist_kernel(MmArgs a) {
     const int tid = threadIdx.x;
     for (int b = tid; b < kMmBins; b += 256) h[b] = 0u;
     __syncthreads();
-    for (int64_t j = (int64_t)blockIdx.x * 256 + tid; j < a.n; j += (int64_t)gridDim.x * 256) {
-        if (a.pos_of[j] >= 0) continue;
-        const u128 key = mm_key(a.D[j], (int32_t)j);
-        if (mm_prefix(key, lvl) == prefix) atomicAdd(&h[mm_digit(key, lvl)], 1u);
+    // kMmLoadBatch points per thread per pass, their loads issued together
+    // (a workgroup-uniform loop: every thread takes the same passes)
+    for (int64_t b0 = (int64_t)blockIdx.x * 256 * kMmLoadBatch; b0 < a.n; b0 += (int64_t)gridDim.x * 256 * kMmLoadBatch) {
+        const int64_t j0 = b0 + tid;
+        int32_t pv[kMmLoadBatch];
+        uint64_t dv[kMmLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kMmLoadBatch; ++u) {
+            const int64_t j = j0 + (int64_t)u * 256;
+            pv[u] = j < a.n ? a.pos_of[j] : 0;
+            dv[u] = j < a.n ? a.D[j] : 0ull;
+        }
+#pragma unroll
+        for (int u = 0; u < kMmLoadBatch; ++u) {
+            const int64_t j = j0 + (int64_t)u * 256;
+            const u128 key = mm_key(dv[u], (int32_t)j);
+            const bool act = j < a.n && pv[u] < 0 && mm_prefix(key, lvl) == prefix;
+            mm_hist_add(h, act ? mm_digit(key, lvl) : 0, act);
+        }
     }
     __syncthreads();
     for (int b = tid; b < kMmBins; b += 256)
@@ -425,20 +459,44 @@ __global__ __launch_bounds__(256) void mm_hist_kernel(MmArgs a) {
 
 // refill: every remaining point with key >= theta into the buffer
 __global__ __launch_bounds__(256) void mm_gather_kernel(MmArgs a) {
-    __shared__ int sh_last;
+    __shared__ int sh_last, sh_n, sh_base;
     MmState* st = a.st;
     if (st->phase != 2) return;
     const u128 theta = st->theta;
     const int tid = threadIdx.x;
-    for (int64_t j = (int64_t)blockIdx.x * 256 + tid; j < a.n; j += (int64_t)gridDim.x * 256) {
-        if (a.pos_of[j] >= 0) continue;
-        if (mm_key(a.D[j], (int32_t)j) >= theta) {
-            const int slot = atomicAdd(&st->nb, 1);
+    // (a workgroup-uniform loop: every thread takes the same passes)
+    for (int64_t b0 = (int64_t)blockIdx.x * 256 * kMmLoadBatch; b0 < a.n; b0 += (int64_t)gridDim.x * 256 * kMmLoadBatch) {
+        const int64_t j0 = b0 + tid;
+        int32_t pv[kMmLoadBatch];
+        uint64_t dv[kMmLoadBatch];
+#pragma unroll
+        for (int u = 0; u < kMmLoadBatch; ++u) {
+            const int64_t j = j0 + (int64_t)u * 256;
+            pv[u] = j < a.n ? a.pos_of[j] : 0;
+            dv[u] = j < a.n ? a.D[j] : 0ull;
+        }
+        // the workgroup's selected points take one range of the buffer
+        int loc[kMmLoadBatch];
+        if (tid == 0) sh_n = 0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMmLoadBatch; ++u) {
+            const int64_t j = j0 + (int64_t)u * 256;
+            loc[u] = (j < a.n && pv[u] < 0 && mm_key(dv[u], (int32_t)j) >= theta) ? atomicAdd(&sh_n, 1) : -1;
+        }
+        __syncthreads();
+        if (tid == 0) sh_base = sh_n > 0 ? atomicAdd(&st->nb, sh_n) : 0;
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kMmLoadBatch; ++u) {
+            if (loc[u] < 0) continue;
+            const int slot = sh_base + loc[u];
             if (slot < kMmCap)
-                a.buf[slot] = (int32_t)j;
+                a.buf[slot] = (int32_t)(j0 + (int64_t)u * 256);
             else
                 st->overflow = 1;
         }
+        __syncthreads();  // sh_n is reset for the next pass
     }
     __threadfence();
     __syncthreads();
