@@ -78,3 +78,28 @@ def test_full_size_cloud():
 def test_abi_errors():
     with pytest.raises(csel.CselError):
         csel.reverse_maximin(torch.zeros((10, 4), dtype=torch.float64, device="cuda"))
+
+
+def test_gpu_setup_feeds_the_selection():
+    """The whole path on the GPU: ordering, gather of the points into
+    ordering-position order, later-ordered pools, then FP64 selection and
+    factor columns.  The set-up equals the host's bit for bit, so every
+    output equals the run on host-built inputs bit for bit."""
+    print("case: GPU set-up + selection, clustered n=60000 d=3 C=128 k=16", flush=True)
+    x = inputs.cluster_points(60000, 3, 13)
+    kern = inputs.Kernel(3, 0.05)
+    host = inputs.single_target("host", x, kern, 128, 16)
+    xd = torch.from_numpy(np.ascontiguousarray(x)).cuda()
+    order, ell, _ = csel.reverse_maximin(xd)
+    xo = xd[order.long()].contiguous()
+    pool, plen = csel.later_knn_pools(xo, 128)
+    tg = torch.arange(len(x), dtype=torch.int32, device="cuda")
+    g = csel.select_and_factor(xo, kern, tg, pool, plen, 16, "fp64")
+    h = csel.select_and_factor(torch.from_numpy(host.points).cuda(), kern, tg, torch.from_numpy(host.pool).cuda(),
+                               torch.from_numpy(host.pool_len).cuda(), 16, "fp64")
+    torch.cuda.synchronize()
+    assert np.array_equal(xo.cpu().numpy(), host.points)
+    assert np.array_equal(pool.cpu().numpy(), host.pool)
+    for key in ("sel", "factor", "log_condvar", "status"):
+        np.testing.assert_array_equal(g[key].cpu().numpy(), h[key].cpu().numpy(), err_msg=key)
+    print("GPU set-up: selection outputs identical to the host-built run", flush=True)
