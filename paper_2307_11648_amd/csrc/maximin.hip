@@ -403,9 +403,15 @@ __global__ __launch_bounds__(256) void mm_hist_kernel(MmArgs a) {
     __syncthreads();
     for (int b = tid; b < kMmBins; b += 256)
         if (h[b]) atomicAdd(&a.hist[b], h[b]);
-    __threadfence();
+    // every wave's atomics complete, then one device-scope release per
+    // workgroup before it counts itself done (a fence from every thread would
+    // write back the L2 thousands of times per pass)
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0)
     __syncthreads();
-    if (tid == 0) sh_last = atomicAdd(&st->done_hist, 1) == (int)gridDim.x - 1;
+    if (tid == 0) {
+        __threadfence();
+        sh_last = atomicAdd(&st->done_hist, 1) == (int)gridDim.x - 1;
+    }
     __syncthreads();
     if (!sh_last) return;
     __threadfence();
@@ -498,9 +504,12 @@ __global__ __launch_bounds__(256) void mm_gather_kernel(MmArgs a) {
         }
         __syncthreads();  // sh_n is reset for the next pass
     }
-    __threadfence();
+    __builtin_amdgcn_s_waitcnt(0x0F70);  // vmcnt(0): this wave's buffer stores are done
     __syncthreads();
-    if (tid == 0) sh_last = atomicAdd(&st->done_gather, 1) == (int)gridDim.x - 1;
+    if (tid == 0) {
+        __threadfence();  // one release per workgroup
+        sh_last = atomicAdd(&st->done_gather, 1) == (int)gridDim.x - 1;
+    }
     __syncthreads();
     if (!sh_last || tid != 0) return;
     __threadfence();
