@@ -109,17 +109,40 @@ __device__ __forceinline__ uint32_t wave_max32(uint32_t v) {
     return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
-// Wave-wide max of a 64-bit key (uniform result).
+// Wave-wide sum of a float (uniform result): the DPP steps of wave_max32
+// leave each row's sum of 16 lanes in every lane of the row; the four row
+// sums are then added in a fixed order.  No lane-address registers (as a
+// shuffle through ds_bpermute needs) and no LDS traffic.
+template <int CTRL>
+__device__ __forceinline__ float dppf(float v) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float wave_sum_f32(float v) {
+    v += dppf<kDppQuadXor1>(v);
+    v += dppf<kDppQuadXor2>(v);
+    v += dppf<kDppRowRor4>(v);
+    v += dppf<kDppRowRor8>(v);
+    return (bcast(v, 0) + bcast(v, 16)) + (bcast(v, 32) + bcast(v, 48));
+}
+
+// Wave-wide max of a 64-bit key (uniform result): the steps of wave_max32 on
+// both 32-bit halves (rows outside a broadcast's row mask read 0, the
+// identity of the maximum), then lane 63's value.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ uint64_t dpp64_rows(uint64_t v) {
+    uint32_t lo = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)(uint32_t)v, CTRL, ROWS, 0xF, false);
+    uint32_t hi = (uint32_t)__builtin_amdgcn_update_dpp(0, (int32_t)(uint32_t)(v >> 32), CTRL, ROWS, 0xF, false);
+    return ((uint64_t)hi << 32) | lo;
+}
 __device__ __forceinline__ uint64_t wave_max64(uint64_t v) {
     uint64_t o;
     o = dpp64<kDppQuadXor1>(v); v = v > o ? v : o;
     o = dpp64<kDppQuadXor2>(v); v = v > o ? v : o;
     o = dpp64<kDppRowRor4>(v); v = v > o ? v : o;
     o = dpp64<kDppRowRor8>(v); v = v > o ? v : o;
-    uint64_t a = bcast(v, 0), b = bcast(v, 16), c = bcast(v, 32), d = bcast(v, 48);
-    a = a > b ? a : b;
-    c = c > d ? c : d;
-    return a > c ? a : c;
+    o = dpp64_rows<kDppRowBcast15, 0xA>(v); v = v > o ? v : o;
+    o = dpp64_rows<kDppRowBcast31, 0xC>(v); v = v > o ? v : o;
+    return bcast(v, 63);
 }
 
 // ---------------------------------------------------------------------------

@@ -599,7 +599,7 @@ __global__ __launch_bounds__(kScrWaves * 64, kScrWavesPerSimd) void screen_kerne
             base += __popcll(m);
             if (key[kk] != 0u && !k) drop += frcp(1.0f + __expf(-zz[kk]));
         }
-        for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+        drop = wave_sum_f32(drop);
         const bool fb = C > keep && drop > p.fb_thr;
         for (int q = base + lane; q < keep; q += 64) p.kept[col * keep + q] = -1;
         if (lane == 0) {
@@ -1132,7 +1132,7 @@ __global__ __launch_bounds__(kGrpThreads) void screen_group_kernel(GroupScreenAr
         kp[i] = key[i] > thr || (key[i] != 0u && key[i] == thr && rank < need);
         if (key[i] != 0u && !kp[i]) drop += frcp(1.0f + __expf(-zz[i]));
     }
-    for (int off = 32; off > 0; off >>= 1) drop += __shfl_xor(drop, off, 64);
+    drop = wave_sum_f32(drop);
     __syncthreads();
     if (lane == 0) sh_drop[wib] = drop;
     // kept candidates in slot order: a chunk's offset counts the kept slots of

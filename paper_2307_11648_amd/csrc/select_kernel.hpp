@@ -279,6 +279,11 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
     static_assert(KMAX + 1 <= kWave, "factor phase keeps one row of Theta_ss per lane");
     __shared__ __align__(16) double sh_r[kSelWavesPerBlock][KMAX + 1][KMAX + 2];
     __shared__ double sh_pt[kSelWavesPerBlock][KMAX + 1][4];  // points of s: x, y, z, id
+    // FP64 pools of up to 4 rows per lane: every slot's offset and point id
+    // (x, y, z, id), written once, so the winner's are read from one uniform
+    // LDS address as soon as its slot is known
+    constexpr bool kPxTable = sizeof(T) == 8 && RPL <= 4;
+    __shared__ __align__(16) double sh_px[kSelWavesPerBlock][kPxTable ? RPL * kWave : 1][4];
 
     const int lane = lane_id();
     const int wib = threadIdx.x >> 6;
@@ -342,6 +347,16 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
         var[rr] = pid[rr] >= 0 ? prior : -1.0;
     }
     bad = bad || __any(bad_idx);
+    if constexpr (kPxTable) {
+#pragma unroll
+        for (int rr = 0; rr < RPL; ++rr) {
+            double2* e = reinterpret_cast<double2*>(&sh_px[wib][rr * kWave + lane][0]);
+            e[0] = double2{(double)dx[rr][0], (double)dx[rr][1]};
+            e[1] = double2{(double)dx[rr][2], (double)pid[rr]};
+        }
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+    }
     if (bad) {
         for (int r = lane; r < kout; r += kWave) {
             sel_out[r] = -1;
@@ -472,18 +487,29 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                         if (rr == rs) {
                             wv = var[rr];
                             wc = cov[rr];
-                            w0 = dx[rr][0];
-                            w1 = dx[rr][1];
-                            w2 = dx[rr][2];
-                            wp = pid[rr];
+                            if constexpr (!kPxTable) {
+                                w0 = dx[rr][0];
+                                w1 = dx[rr][1];
+                                w2 = dx[rr][2];
+                                wp = pid[rr];
+                            }
                         }
                     }
                     vk = bcast(wv, ls);
                     ck = bcast(wc, ls);
-                    dk0 = bcast(w0, ls);
-                    dk1 = bcast(w1, ls);
-                    dk2 = bcast(w2, ls);
-                    idk = bcast(wp, ls);
+                    if constexpr (kPxTable) {
+                        const double2* px = reinterpret_cast<const double2*>(&sh_px[wib][slot][0]);
+                        const double2 a = px[0], b = px[1];
+                        dk0 = a.x;
+                        dk1 = a.y;
+                        dk2 = b.x;
+                        idk = (int32_t)b.y;
+                    } else {
+                        dk0 = bcast(w0, ls);
+                        dk1 = bcast(w1, ls);
+                        dk2 = bcast(w2, ls);
+                        idk = bcast(wp, ls);
+                    }
                     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
                     __builtin_amdgcn_wave_barrier();
                 } else {
