@@ -10,7 +10,8 @@
 //
 // One pick (Sec. 3.1, eq. cond_select / eq. obj_gp; App. C.1):
 //   score = cov^2 / var (FP64) -> wave top-two via DPP -> the winner's factor
-//   row, offset, var and cov are broadcast through LDS -> every lane
+//   row, offset, var and cov are broadcast (LDS; FP64: var and cov by
+//   readlane, the offset from a per-wave table of the pool) -> every lane
 //   evaluates Theta(row, winner), subtracts the GEMV L[row] . L[winner] and
 //   scales by 1/sqrt(var_winner) -> FP64 rank-one downdate of var and cov.
 // The target's own factor row is never formed: its entry for pick t is
@@ -469,8 +470,10 @@ __global__ __launch_bounds__(256) void select_factor_kernel(SelectArgs p) {
                 int32_t idk;
                 if constexpr (sizeof(T) == 8) {
                     // FP64: the row through LDS (the GEMV reads it after the
-                    // evaluation); the scalars that gate the evaluation by
-                    // readlane from the winning lane, off the LDS round trip
+                    // evaluation); var and cov by readlane from the winning
+                    // lane, off the LDS round trip; the offset and id from the
+                    // pool table (pools of up to 4 rows per lane), else by
+                    // readlane as well
                     if (lane == ls) {
 #pragma unroll
                         for (int rr = 0; rr < RPL; ++rr) {
