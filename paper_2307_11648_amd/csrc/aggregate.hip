@@ -46,6 +46,14 @@ __device__ __forceinline__ T matern_any(int two_nu, T r, T c, T s2) {
 
 constexpr int kAggMaxWaves = 16;
 
+// byte offset of the slab kernel's LDS column caches: past the wave top-two
+// records, the winner scalars and the winner's B and A rows
+inline __host__ __device__ size_t agg_cache_offset(int max_members, int k, size_t elem_a) {
+    const size_t b = sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double) + ((size_t)k + max_members) * sizeof(double) +
+                     (size_t)k * elem_a;
+    return (b + 15) / 16 * 16;
+}
+
 // TA: factor A (the selected points only) and its covariance evaluations;
 // TB: factor B (the targets, then the selected points).  FP64: both double.
 // Mixed: A in FP32, B in FP64 -- var2 = Theta_jj | T, I falls far below
@@ -63,6 +71,12 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
     int32_t* wid = reinterpret_cast<int32_t*>(wsc + 6);
     TB* rowB = reinterpret_cast<TB*>(agg_smem + sizeof(Top2) * kAggMaxWaves + 8 * sizeof(double));
     TA* rowA = reinterpret_cast<TA*>(rowB + p.max_members + p.k);
+    // LDS column caches (one row per thread): B's first nb columns, then A's
+    // first na, each column NT entries (row r at entry r)
+    const int nb = RPT == 1 ? p.cache_b : 0;
+    const int na = RPT == 1 ? p.cache_a : 0;
+    TB* cB = reinterpret_cast<TB*>(agg_smem + agg_cache_offset(p.max_members, p.k, sizeof(TA)));
+    TA* cA = reinterpret_cast<TA*>(cB + (size_t)nb * blockDim.x);
 
     const int tid = threadIdx.x;
     const int NT = blockDim.x;
@@ -162,7 +176,7 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     wsc[4] = x2[i];
                     wid[0] = rid[i];
                 }
-            for (int q = tid; q < c; q += NT) rowB[q] = slabB[(int64_t)q * rmax + prow];
+            for (int q = tid; q < c; q += NT) rowB[q] = q < nb ? cB[q * NT + prow] : slabB[(int64_t)q * rmax + prow];
             __syncthreads();
             const double piv = wsc[1];
             const double y0 = wsc[2], y1 = wsc[3], y2 = wsc[4];
@@ -177,9 +191,10 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     const TB e0 = (TB)(x0[i] - y0), e1 = (TB)(x1[i] - y1), e2 = (TB)(x2[i] - y2);
                     TB acc = matern_any<TB>(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnuB, s2B);
                     if (rid[i] == idw) acc += (TB)p.nugget;
-                    acc = dot_down<TB, kUD>(acc, slabB + r, rmax, rowB, c);
+                    acc = dot_down_cached<TB, kUD>(acc, cB + r, NT, nb, slabB + r, rmax, rowB, c);
                     const TB u = acc * inv_sd_t;
-                    slabB[(int64_t)c * rmax + r] = u;
+                    if (c < nb) cB[c * NT + r] = u;
+                    else slabB[(int64_t)c * rmax + r] = u;
                     const double ud = (double)u;
                     v2[i] -= ud * ud;
                 }
@@ -222,8 +237,9 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     wid[0] = rid[i];
                     live &= ~(1u << i);
                 }
-            for (int q = tid; q < t; q += NT) rowA[q] = slabA[(int64_t)q * rmax + slot];
-            for (int q = tid; q < m + t; q += NT) rowB[q] = slabB[(int64_t)q * rmax + slot];
+            for (int q = tid; q < t; q += NT) rowA[q] = q < na ? cA[q * NT + slot] : slabA[(int64_t)q * rmax + slot];
+            for (int q = tid; q < m + t; q += NT)
+                rowB[q] = q < nb ? cB[q * NT + slot] : slabB[(int64_t)q * rmax + slot];
             __syncthreads();
             const double w1 = wsc[0], w2 = wsc[1];
             const double y0 = wsc[2], y1 = wsc[3], y2 = wsc[4];
@@ -255,12 +271,14 @@ __global__ __launch_bounds__(1024) void agg_select_kernel(AggArgs p) {
                     }
                     TA a = tha;
                     TB bb = thb;
-                    a = dot_down<TA, kUD>(a, slabA + r, rmax, rowA, t);
-                    bb = dot_down<TB, kUD>(bb, slabB + r, rmax, rowB, m + t);
+                    a = dot_down_cached<TA, kUD>(a, cA + r, NT, na, slabA + r, rmax, rowA, t);
+                    bb = dot_down_cached<TB, kUD>(bb, cB + r, NT, nb, slabB + r, rmax, rowB, m + t);
                     const TA u1 = a * inv1;
                     const TB u2 = bb * inv2;
-                    slabA[(int64_t)t * rmax + r] = u1;
-                    slabB[(int64_t)(m + t) * rmax + r] = u2;
+                    if (t < na) cA[t * NT + r] = u1;
+                    else slabA[(int64_t)t * rmax + r] = u1;
+                    if (m + t < nb) cB[(m + t) * NT + r] = u2;
+                    else slabB[(int64_t)(m + t) * rmax + r] = u2;
                     const double d1 = (double)u1, d2 = (double)u2;
                     v1[i] -= d1 * d1;
                     v2[i] -= d2 * d2;
@@ -773,8 +791,30 @@ __global__ __launch_bounds__(kAggFacThreads) void agg_factor_kernel(AggArgs p) {
     if (tid == 0 && bad_piv) p.status[g] = 2;
 }
 
+// LDS of one CU, and the most one workgroup's column caches take
+constexpr size_t kCuLds = 160 * 1024;
+constexpr size_t kAggCacheLds = 152 * 1024;
+
 template <typename TA, typename TB, int RPT>
-static hipError_t launch_sel(const AggArgs& a, int nt, unsigned grid, size_t smem, hipStream_t s) {
+static hipError_t launch_sel(const AggArgs& a0, int nt, unsigned grid, size_t smem, hipStream_t s) {
+    AggArgs a = a0;
+    if (RPT == 1) {
+        // Column caches in the LDS that the workgroups resident on a CU leave
+        // free (their VGPRs allow 16 waves per CU): the first columns of B
+        // (the target columns and the first picks, re-read by every later
+        // step) take three quarters, A's first columns the rest.
+        const int waves = (nt + 63) / 64;
+        const size_t per_cu = (size_t)std::max(1, 16 / waves);
+        const size_t lds = std::min(kAggCacheLds, kCuLds / per_cu - 1024);
+        const size_t off = agg_cache_offset(a.max_members, a.k, sizeof(TA));
+        const size_t avail = lds > off ? lds - off : 0;
+        const size_t colB = (size_t)nt * sizeof(TB), colA = (size_t)nt * sizeof(TA);
+        const int nb = (int)std::min<size_t>(avail * 3 / 4 / colB, (size_t)a.max_members + a.k);
+        const int na = (int)std::min<size_t>((avail - nb * colB) / colA, (size_t)a.k);
+        a.cache_b = nb;
+        a.cache_a = na;
+        smem = std::max(smem, off + nb * colB + na * colA);
+    }
     auto kern = agg_select_kernel<TA, TB, RPT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;

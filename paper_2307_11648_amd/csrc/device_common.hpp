@@ -360,6 +360,33 @@ __device__ __forceinline__ T dot_down(T acc, const T* __restrict__ col, int64_t 
     return acc;
 }
 
+// dot_down over entries 0 .. n-1 of a column whose first nc entries sit in
+// LDS (entry q at cache[q * cld]) and the rest in global memory: the same
+// multiply-adds in the same order, so the same result as dot_down.
+template <typename T, int U = 16>
+__device__ __forceinline__ T dot_down_cached(T acc, const T* cache, int cld, int nc, const T* __restrict__ col,
+                                             int64_t ld, const T* row, int n) {
+    const int n1 = n < nc ? n : nc;
+    int q = 0;
+    for (; q + U <= n1; q += U) {
+        T v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = cache[(q + j) * cld];
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc = fma(-v[j], row[q + j], acc);
+    }
+    for (; q < n1; ++q) acc = fma(-cache[q * cld], row[q], acc);
+    for (; q + U <= n; q += U) {
+        T v[U];
+#pragma unroll
+        for (int j = 0; j < U; ++j) v[j] = col[(int64_t)(q + j) * ld];
+#pragma unroll
+        for (int j = 0; j < U; ++j) acc = fma(-v[j], row[q + j], acc);
+    }
+    for (; q < n; ++q) acc = fma(-col[(int64_t)q * ld], row[q], acc);
+    return acc;
+}
+
 __device__ __forceinline__ double matern_f64_rt(int two_nu, double r, double c, double s2) {
     if (two_nu == 1) return matern_f64<1>(r, c, s2);
     if (two_nu == 3) return matern_f64<3>(r, c, s2);

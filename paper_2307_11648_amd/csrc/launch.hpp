@@ -156,6 +156,10 @@ struct AggArgs {
     int32_t* fac_rows;
     double* fac_val;
     double* member_logcv;
+    // the slab kernel with one row per thread keeps the first cache_b columns
+    // of factor B and cache_a of factor A in LDS instead of the slab (set at
+    // its launch)
+    int32_t cache_a = 0, cache_b = 0;
 };
 
 struct AggPlan {

@@ -220,6 +220,35 @@ def test_gp_split_rows_match_one_workgroup_per_group():
                 np.testing.assert_array_equal(part["post_var"][b:e], full["post_var"][b:e])
 
 
+def test_group_slab_caches_keep_the_split_schedule_bits():
+    """Pools of 512 with groups of 8-32 (one 576-thread workgroup per group):
+    the slab kernel keeps the first columns of both factors in LDS column
+    caches, the split-row schedule keeps every column in global memory; both
+    take the same multiply-adds in the same order, so picks, gaps, log
+    determinants (and in FP64 posterior variances) agree bit for bit."""
+    print("case: slab caches vs split rows, aggregated n=2000 C=512 k=64 m=8..32", flush=True)
+    w = inputs.workload_aggregated(n=2000, C=512, k=64)
+    # few enough groups for the split schedule's cooperative launch
+    assert len(w.group_ptr) - 1 <= 128
+    dev = dict(pts=_t(w.points, torch.float64), gp=_t(w.group_ptr, torch.int32), mem=_t(w.members, torch.int32),
+               pl=_t(w.pool, torch.int32), ln=_t(w.pool_len, torch.int32))
+    mm = int(np.max(np.diff(w.group_ptr)))
+
+    def run(precision, schedule, post_var):
+        o = csel.aggregated_select(dev["pts"], w.kernel, dev["gp"], dev["mem"], mm, dev["pl"], dev["ln"], w.k,
+                                   precision, want_post_var=post_var, want_gap=True, schedule=schedule)
+        torch.cuda.synchronize()
+        return {key: v.cpu().numpy() for key, v in o.items() if key != "workspace"}
+
+    for precision, post_var in (("fp64", True), ("mixed", False)):
+        ref = run(precision, "split512", post_var)
+        got = run(precision, "one_group", post_var)
+        assert np.mean(ref["status"] == 0) > 0.9
+        for key in ref:
+            np.testing.assert_array_equal(got[key], ref[key], err_msg=f"{precision} {key}")
+        print(f"{precision}: slab with LDS caches == split rows ({len(w.group_ptr) - 1} groups)", flush=True)
+
+
 def test_explicit_schedules_are_bit_identical():
     """csel_aggregated_select_sched: one workgroup per group and the three
     split-row block sizes give the same bits (FP64 with posterior variances
