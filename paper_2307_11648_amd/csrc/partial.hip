@@ -337,10 +337,22 @@ __global__ __launch_bounds__(kPartThreads) void partial_select_kernel(AggArgs p)
                     L[c] = lc;
                 }
             }
+            // columns pk .. ncol - 1 move up by one and u enters at pk: pk and
+            // ncol are uniform, and the empty asm keeps each move behind a
+            // scalar branch (only the moved columns cost vector instructions)
 #pragma unroll
-            for (int c = kPartCols - 1; c >= 0; --c) {
-                if (c > pk) L[c] = L[c - 1 < 0 ? 0 : c - 1];
-                else if (c == pk) L[c] = u;
+            for (int c = kPartCols - 1; c >= 1; --c) {
+                if (c > pk && c <= ncol) {
+                    asm volatile("");
+                    L[c] = L[c - 1];
+                }
+            }
+#pragma unroll
+            for (int c = 0; c < kPartCols; ++c) {
+                if (c == pk) {
+                    asm volatile("");
+                    L[c] = u;
+                }
             }
             q += idk > my_id ? 1 : 0;
         }
