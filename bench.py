@@ -730,8 +730,8 @@ def _source_digest(*names):
 MEASURED_TRAFFIC = {
     # FETCH_SIZE x 1.9999 (a 1 GiB device copy reads as 524,315 KiB) + WRITE_SIZE x 1.0, in bytes; medians of
     # the launches of the default run (learned-screened workload, N = 1e6)
-    ("select_factor_kernel<double> (kept pools)", "spatial", "be838a9e8fb8936d"): (540572 * 1.9999 + 471876) * 1024,
-    ("screen_kernel", "spatial", "a75d43c4ccbf51f9"): (2114127 * 1.9999 + 564042) * 1024,
+    ("select_factor_kernel<double> (kept pools)", "spatial", "5b36f12868af78eb"): (540572 * 1.9999 + 471876) * 1024,
+    ("screen_kernel", "spatial", "a84e86504bb655a5"): (2114127 * 1.9999 + 564042) * 1024,
 }
 
 
