@@ -26,6 +26,8 @@
 // still reads the current step's.  Every workgroup of a group takes the same
 // steps (the group's size, pool length, validity and early stop are known to
 // all of them), so the groups need not wait for each other.
+#include <algorithm>
+
 #include "device_common.hpp"
 #include "launch.hpp"
 
@@ -47,6 +49,7 @@ struct CoopArgs {
     CoopPub* pub;       // [2][n_groups][W]
     double* piv;        // [2][n_groups][5]: pivot var2, coordinates, id
     uint32_t* sync;     // [n_groups][kSyncStride]: [0] arrivals, [1] invalid row seen, [2] wait abandoned
+    int32_t cache_b;    // factor B's first columns of the workgroup's own rows also kept in LDS
 };
 
 // one counter per 128-byte line
@@ -104,6 +107,11 @@ __global__ __launch_bounds__(NT) void agg_select_coop_kernel(CoopArgs ca) {
     __shared__ TA rowA[kAggMaxSelectCoop];
     __shared__ double rowB[kAggMaxSelectCoop + kAggMaxMembersCoop];
     __shared__ Top2 wtop[NT / kWave];
+    // the first nb columns of factor B for this workgroup's rows (entry tid of
+    // column c at cB[c * NT + tid]): the rows' own reads come from here, the
+    // slab keeps every column for the winner's and pivot's rows
+    extern __shared__ __align__(16) double cB[];
+    const int nb = ca.cache_b;
 
     const int tid = threadIdx.x;
     const int lane = lane_id();
@@ -172,9 +180,10 @@ __global__ __launch_bounds__(NT) void agg_select_coop_kernel(CoopArgs ca) {
             const double e0 = x0 - y0, e1 = x1 - y1, e2 = x2 - y2;
             double acc = matern_f64_rt(p.two_nu, sqrt(sqnorm3(e0, e1, e2)), cnu, s2);
             if (rid == idw) acc += p.nugget;
-            acc = dot_down<double>(acc, slabB + r, rmax, rowB, c);
+            acc = dot_down_cached<double>(acc, cB + threadIdx.x, NT, nb, slabB + r, rmax, rowB, c);
             const double u = acc * inv_sd;
             slabB[(int64_t)c * rmax + r] = u;
+            if (c < nb) cB[c * NT + threadIdx.x] = u;
             v2 = fma(-u, u, v2);
         }
         __syncthreads();  // rowB is rewritten at the next column
@@ -256,11 +265,12 @@ __global__ __launch_bounds__(NT) void agg_select_coop_kernel(CoopArgs ca) {
                 if (rid == wr.id) a += (float)p.nugget;
             }
             a = dot_down<TA>(a, slabA + r, rmax, rowA, t);
-            const double bb = dot_down<double>(th, slabB + r, rmax, rowB, m + t);
+            const double bb = dot_down_cached<double>(th, cB + threadIdx.x, NT, nb, slabB + r, rmax, rowB, m + t);
             const TA u1 = a * (TA)inv1;
             const double u2 = bb * inv2;
             slabA[(int64_t)t * rmax + r] = u1;
             slabB[(int64_t)(m + t) * rmax + r] = u2;
+            if (m + t < nb) cB[(m + t) * NT + threadIdx.x] = u2;
             const double d1 = (double)u1;
             v1 = fma(-d1, d1, v1);
             v2 = fma(-u2, u2, v2);
@@ -314,23 +324,46 @@ int64_t agg_coop_workspace(int64_t n_groups, int32_t stride, int32_t max_members
            n_groups * kSyncStride * 4;
 }
 
+// LDS of one CU, and the most one workgroup's column cache takes
+constexpr size_t kCoopCuLds = 160 * 1024;
+constexpr size_t kCoopCacheLds = 152 * 1024;
+
 template <typename TA, int NT>
 static hipError_t launch_coop(CoopArgs& ca, int cus, hipStream_t s) {
     ca.W = coop_split(ca.a.rmax, NT);
     ca.rows_wg = NT;
     const int64_t nblocks = ca.a.n_groups * ca.W;
+    const void* kern = (const void*)agg_select_coop_kernel<TA, NT>;
     int per_cu = 0;
-    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, (const void*)agg_select_coop_kernel<TA, NT>, NT, 0);
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, NT, 0);
     if (e != hipSuccess) return e;
     if (nblocks > (int64_t)per_cu * cus || nblocks > INT32_MAX) return hipErrorCooperativeLaunchTooLarge;
+    // B's first columns in the LDS the resident workgroups leave free (as
+    // many workgroups per CU as without them)
+    hipFuncAttributes fa;
+    e = hipFuncGetAttributes(&fa, kern);
+    if (e != hipSuccess) return e;
+    const size_t lds = std::min<size_t>(kCoopCacheLds, kCoopCuLds / (size_t)std::max(1, per_cu));
+    const size_t avail = lds > fa.sharedSizeBytes + 1024 ? lds - fa.sharedSizeBytes - 1024 : 0;
+    ca.cache_b = (int)std::min<size_t>(avail / ((size_t)NT * sizeof(double)), (size_t)ca.a.max_members + ca.a.k);
+    size_t smem = (size_t)ca.cache_b * NT * sizeof(double);
+    if (smem > 0) {
+        e = hipFuncSetAttribute(kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
+        int per_cu2 = 0;
+        if (e == hipSuccess) e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu2, kern, NT, smem);
+        if (e != hipSuccess || per_cu2 < per_cu) {  // keep the residency: no caches
+            (void)hipGetLastError();
+            ca.cache_b = 0;
+            smem = 0;
+        }
+    }
     // counters start at zero (a fill kernel: no memset node if the caller captures the stream)
     const int64_t ns = ca.a.n_groups * kSyncStride;
     hipLaunchKernelGGL(agg_coop_clear_kernel, dim3((unsigned)((ns + 255) / 256)), dim3(256), 0, s, ca.sync, ns);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     void* args[] = {&ca};
-    return hipLaunchCooperativeKernel((const void*)agg_select_coop_kernel<TA, NT>, dim3((unsigned)nblocks), dim3(NT),
-                                      args, 0, s);
+    return hipLaunchCooperativeKernel(kern, dim3((unsigned)nblocks), dim3(NT), args, (unsigned)smem, s);
 }
 
 // the cooperative launch, when every workgroup fits on the device at once;
