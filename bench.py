@@ -230,9 +230,10 @@ def bench_groups(args):
                      "algorithmic_mb_per_launch": float(np.sum(byt)) / 1e6},
     }
     if coop:
-        # the left-looking updates stream each row's factor entries from the
-        # per-group slabs once per target column and per pick (8 bytes per
-        # FP64 fused multiply-add, 4 for the FP32 picks-only factor of mixed runs)
+        # the left-looking updates read each row's factor entries once per
+        # target column and per pick (8 bytes per FP64 fused multiply-add, 4
+        # for the FP32 picks-only factor of mixed runs): factor B's first
+        # columns from LDS, the rest from the per-group slabs
         sa = 8 if args.precision == "fp64" else 4
         gsz = np.diff(w.group_ptr).astype(np.int64)
         rows = w.pool_len.astype(np.int64) + gsz
