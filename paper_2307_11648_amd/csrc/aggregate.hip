@@ -798,13 +798,16 @@ constexpr size_t kAggCacheLds = 152 * 1024;
 template <typename TA, typename TB, int RPT>
 static hipError_t launch_sel(const AggArgs& a0, int nt, unsigned grid, size_t smem, hipStream_t s) {
     AggArgs a = a0;
+    auto kern = agg_select_kernel<TA, TB, RPT>;
     if (RPT == 1) {
         // Column caches in the LDS that the workgroups resident on a CU leave
-        // free (their VGPRs allow 16 waves per CU): the first columns of B
-        // (the target columns and the first picks, re-read by every later
-        // step) take three quarters, A's first columns the rest.
-        const int waves = (nt + 63) / 64;
-        const size_t per_cu = (size_t)std::max(1, 16 / waves);
+        // free (as many as its registers allow without the caches): the first
+        // columns of B (the target columns and the first picks, re-read by
+        // every later step) take three quarters, A's first columns the rest.
+        int res = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&res, (const void*)kern, nt, smem);
+        if (e != hipSuccess) return e;
+        const size_t per_cu = (size_t)std::max(1, res);
         const size_t lds = std::min(kAggCacheLds, kCuLds / per_cu - 1024);
         const size_t off = agg_cache_offset(a.max_members, a.k, sizeof(TA));
         const size_t avail = lds > off ? lds - off : 0;
@@ -815,7 +818,6 @@ static hipError_t launch_sel(const AggArgs& a0, int nt, unsigned grid, size_t sm
         a.cache_a = na;
         smem = std::max(smem, off + nb * colB + na * colA);
     }
-    auto kern = agg_select_kernel<TA, TB, RPT>;
     hipError_t e = hipFuncSetAttribute((const void*)kern, hipFuncAttributeMaxDynamicSharedMemorySize, (int)smem);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(kern, dim3(grid), dim3(nt), smem, s, a);
