@@ -226,27 +226,31 @@ def test_group_slab_caches_keep_the_split_schedule_bits():
     caches, the split-row schedule keeps every column in global memory; both
     take the same multiply-adds in the same order, so picks, gaps, log
     determinants (and in FP64 posterior variances) agree bit for bit."""
-    print("case: slab caches vs split rows, aggregated n=2000 C=512 k=64 m=8..32", flush=True)
-    w = inputs.workload_aggregated(n=2000, C=512, k=64)
-    # few enough groups for the split schedule's cooperative launch
-    assert len(w.group_ptr) - 1 <= 128
-    dev = dict(pts=_t(w.points, torch.float64), gp=_t(w.group_ptr, torch.int32), mem=_t(w.members, torch.int32),
-               pl=_t(w.pool, torch.int32), ln=_t(w.pool_len, torch.int32))
-    mm = int(np.max(np.diff(w.group_ptr)))
+    # pools of 512 (part of each factor cached), and pools of 64 with k = 4,
+    # where the caches hold every column and the slab is never touched
+    for name, w, split in (("n=2000 C=512 k=64 m=8..32", inputs.workload_aggregated(n=2000, C=512, k=64), "split512"),
+                           ("n=500 C=64 k=4 m=2..8",
+                            inputs.workload_aggregated(n=500, seed=7, C=64, k=4, mmin=2, mmax=8), "split256")):
+        print(f"case: slab caches vs split rows, aggregated {name}", flush=True)
+        # few enough groups for the split schedule's cooperative launch
+        assert len(w.group_ptr) - 1 <= 128
+        dev = dict(pts=_t(w.points, torch.float64), gp=_t(w.group_ptr, torch.int32), mem=_t(w.members, torch.int32),
+                   pl=_t(w.pool, torch.int32), ln=_t(w.pool_len, torch.int32))
+        mm = int(np.max(np.diff(w.group_ptr)))
 
-    def run(precision, schedule, post_var):
-        o = csel.aggregated_select(dev["pts"], w.kernel, dev["gp"], dev["mem"], mm, dev["pl"], dev["ln"], w.k,
-                                   precision, want_post_var=post_var, want_gap=True, schedule=schedule)
-        torch.cuda.synchronize()
-        return {key: v.cpu().numpy() for key, v in o.items() if key != "workspace"}
+        def run(precision, schedule, post_var):
+            o = csel.aggregated_select(dev["pts"], w.kernel, dev["gp"], dev["mem"], mm, dev["pl"], dev["ln"], w.k,
+                                       precision, want_post_var=post_var, want_gap=True, schedule=schedule)
+            torch.cuda.synchronize()
+            return {key: v.cpu().numpy() for key, v in o.items() if key != "workspace"}
 
-    for precision, post_var in (("fp64", True), ("mixed", False)):
-        ref = run(precision, "split512", post_var)
-        got = run(precision, "one_group", post_var)
-        assert np.mean(ref["status"] == 0) > 0.9
-        for key in ref:
-            np.testing.assert_array_equal(got[key], ref[key], err_msg=f"{precision} {key}")
-        print(f"{precision}: slab with LDS caches == split rows ({len(w.group_ptr) - 1} groups)", flush=True)
+        for precision, post_var in (("fp64", True), ("mixed", False)):
+            ref = run(precision, split, post_var)
+            got = run(precision, "one_group", post_var)
+            assert np.mean(ref["status"] == 0) > 0.9
+            for key in ref:
+                np.testing.assert_array_equal(got[key], ref[key], err_msg=f"{name} {precision} {key}")
+            print(f"{precision}: slab with LDS caches == split rows ({len(w.group_ptr) - 1} groups)", flush=True)
 
 
 def test_explicit_schedules_are_bit_identical():
